@@ -1,0 +1,425 @@
+"""Pins of the FP64 oracle against facts fixed by mathematics and physics, not by the
+oracle's own formulas: closed forms, special cases reducing to library or stdlib routines
+that are independent of scipy's Faddeeva code (math.erfc, mpmath, QUADPACK), invariants,
+and brute force on tiny inputs. The paper prints no worked example or value to pin to.
+"""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import xsec_oracle as O
+
+SQPI = math.sqrt(math.pi)
+
+
+# ------------------------------------------------------------------ profile: w(z)
+def test_peak_w0_is_one():
+    # w(0) = 1, so a pure Gaussian line peaks at 1/(b_D sqrt(pi))
+    for bD in (1e-4, 0.02, 1.7):
+        assert O.voigt(0.0, bD, 0.0) == pytest.approx(1.0 / (bD * SQPI), rel=1e-15, abs=0)
+
+
+@pytest.mark.parametrize("y", [1e-7, 1e-4, 0.01, 0.3, 1.0, 2.5, 5.0])
+def test_peak_is_erfcx_stdlib(y):
+    # Re w(iy) = erfcx(y) = exp(y^2) erfc(y); math.erfc is the C library's routine
+    bD = 0.013
+    v = O.voigt(0.0, bD, y * bD) * bD * SQPI
+    assert v == pytest.approx(math.exp(y * y) * math.erfc(y), rel=2e-14, abs=0)
+
+
+@pytest.mark.parametrize("y", [8.0, 50.0, 3e3, 3.5e4])
+def test_peak_is_erfcx_mpmath_large_y(y):
+    bD = 0.5
+    v = O.voigt(0.0, bD, y * bD) * bD * SQPI
+    mpmath.mp.dps = 40
+    ref = float(mpmath.exp(mpmath.mpf(y) ** 2) * mpmath.erfc(mpmath.mpf(y)))
+    assert v == pytest.approx(ref, rel=1e-13, abs=0)
+
+
+def test_gaussian_limit_closed_form():
+    # gamma_L = 0: K(x, 0) = exp(-x^2)
+    bD = 0.021
+    d = np.linspace(-6 * bD, 6 * bD, 241)
+    v = O.voigt(d, bD, 0.0)
+    ref = np.exp(-(d / bD) ** 2) / (bD * SQPI)
+    np.testing.assert_allclose(v, ref, rtol=1e-13, atol=0)
+
+
+def test_lorentzian_limit():
+    # b_D << gamma_L: V -> (gamma/pi)/(d^2 + gamma^2); the deviation is O((b_D/gamma)^2)
+    g = 0.07
+    for bD in (1e-3, 1e-4):
+        d = np.linspace(-5 * g, 5 * g, 101)
+        v = O.voigt(d, bD, g)
+        lor = (g / math.pi) / (d * d + g * g)
+        dev = np.max(np.abs(v / lor - 1.0))
+        assert dev < 2.0 * (bD / g) ** 2
+        assert dev > 0.01 * (bD / g) ** 2  # the Doppler part is really there
+
+
+def _mp_w(z):
+    # Faddeeva function from mpmath: w(z) = exp(-z^2) erfc(-iz)
+    return mpmath.exp(-z * z) * mpmath.erfc(-1j * z)
+
+
+def test_voigt_vs_mpmath_faddeeva():
+    rng = np.random.default_rng(7)
+    mpmath.mp.dps = 40
+    xs = 10 ** rng.uniform(-3, 5, 150)
+    ys = 10 ** rng.uniform(np.log10(5e-7), np.log10(3.5e4), 150)
+    # include the core and its neighbourhood densely
+    xs = np.concatenate([xs, rng.uniform(0, 8, 100)])
+    ys = np.concatenate([ys, 10 ** rng.uniform(-6.3, 1, 100)])
+    worst = 0.0
+    for x, y in zip(xs, ys):
+        ref = float(_mp_w(mpmath.mpc(x, y)).real)
+        bD = 0.03
+        v = float(O.voigt(x * bD, bD, y * bD)) * bD * SQPI
+        worst = max(worst, abs(v - ref) / ref)
+    assert worst < 1e-12
+
+
+@pytest.mark.parametrize("d,bD,g", [(0.0, 0.02, 0.01), (0.013, 0.02, 0.01),
+                                    (0.1, 0.02, 0.001), (0.5, 0.01, 0.05),
+                                    (0.004, 0.002, 0.0005), (3.0, 0.5, 0.2),
+                                    (0.0, 0.001, 0.3), (0.07, 0.05, 0.05)])
+def test_convolution_quadpack(d, bD, g):
+    # V = Gaussian (*) Lorentzian, integrated by QUADPACK, independent of wofz
+    def G(t):
+        return math.exp(-(t / bD) ** 2) / (bD * SQPI)
+
+    def L(t):
+        return (g / math.pi) / (t * t + g * g)
+
+    f = lambda t: G(t) * L(d - t)
+    lim = 12 * bD
+    pts = sorted({-lim, 0.0, d, lim} if -lim < d < lim else {-lim, 0.0, lim})
+    total = 0.0
+    for a, b in zip(pts[:-1], pts[1:]):
+        total += integrate.quad(f, a, b, epsabs=0, epsrel=1e-12, limit=400)[0]
+    # tails of the Gaussian beyond 12 b_D are below exp(-144)
+    assert O.voigt(d, bD, g) == pytest.approx(total, rel=1e-9, abs=0)
+
+
+@pytest.mark.parametrize("bD,g", [(0.02, 0.0), (0.02, 0.005), (0.001, 0.05)])
+def test_unit_area(bD, g):
+    f = lambda t: float(O.voigt(t, bD, g))
+    pts = [-1e4, -10 * max(bD, g), 0.0, 10 * max(bD, g), 1e4]
+    tot = sum(integrate.quad(f, a, b, limit=800, epsrel=1e-12)[0]
+              for a, b in zip(pts[:-1], pts[1:]))
+    # Lorentz tails beyond 1e4 cm^-1 hold 2 g / (pi 1e4)
+    tail = 2 * g / (math.pi * 1e4)
+    assert tot + tail == pytest.approx(1.0, rel=1e-8, abs=0)
+
+
+def test_fwhm_olivero_limits_and_accuracy():
+    # pure limits
+    bD = 0.02
+    fG = 2 * bD * math.sqrt(math.log(2))
+    assert O.voigt_fwhm(0.0, bD) == pytest.approx(fG, rel=1e-15, abs=0)
+    assert O.voigt_fwhm(0.1, 0.0) == pytest.approx(0.2, rel=1e-4, abs=0)  # 0.5346 + sqrt(.2166)
+    # against the true half-width of the oracle's own profile (root finding):
+    # Olivero & Longbothum quote 0.02 % accuracy
+    from scipy.optimize import brentq
+    for g in (1e-4, 0.005, 0.02, 0.1):
+        peak = O.voigt(0.0, bD, g)
+        h = brentq(lambda t: O.voigt(t, bD, g) - 0.5 * peak, 0.0, 10 * (bD + g), xtol=1e-15)
+        assert O.voigt_fwhm(g, bD) == pytest.approx(2 * h, rel=3e-4, abs=0)
+
+
+# ------------------------------------------------------------------ widths
+def test_doppler_width_matches_maxwell_velocity_variance():
+    # the Doppler profile's variance is nu0^2 k T /(m c^2) (1-D Maxwellian velocity),
+    # integrated here numerically from the oracle's own Gaussian profile
+    nu0, T, m = 2000.0, 1200.0, 28.0
+    bD = float(O.doppler_width(nu0, T, m))
+    var = integrate.quad(lambda t: t * t * float(O.voigt(t, bD, 0.0)), -20 * bD, 20 * bD,
+                         epsrel=1e-13, limit=200)[0]
+    kT_over_mc2 = 1.380649e-23 * T / (m * 1.66053906660e-27 * 299792458.0 ** 2)
+    assert var == pytest.approx(nu0 ** 2 * kT_over_mc2, rel=1e-10, abs=0)
+
+
+def test_doppler_scaling():
+    a = O.doppler_width(1000.0, 300.0, 16.0)
+    assert O.doppler_width(3000.0, 300.0, 16.0) == pytest.approx(3 * a, rel=1e-15, abs=0)
+    assert O.doppler_width(1000.0, 1200.0, 16.0) == pytest.approx(2 * a, rel=1e-15, abs=0)
+    assert O.doppler_width(1000.0, 300.0, 64.0) == pytest.approx(a / 2, rel=1e-15, abs=0)
+
+
+def test_lorentz_special_cases():
+    assert O.lorentz_width(0.07, 0.6, 1.0, 296.0) == pytest.approx(0.07, rel=1e-15, abs=0)
+    assert O.lorentz_width(0.07, 0.6, 3.0, 296.0) == pytest.approx(0.21, rel=1e-15, abs=0)
+    # n = 0.5 and T = 4 T_ref halves the width
+    assert O.lorentz_width(0.07, 0.5, 1.0, 4 * 296.0) == pytest.approx(0.035, rel=1e-15, abs=0)
+    # n = 0: no temperature dependence
+    assert O.lorentz_width(0.05, 0.0, 2.0, 1500.0) == pytest.approx(0.1, rel=1e-15, abs=0)
+
+
+# ------------------------------------------------------------------ strengths
+def test_strength_from_einstein_b_route():
+    """The integrated absorption cross-section from the Einstein-B coefficient, in SI,
+    frequency space: int sigma dnu_Hz = (h nu/c) B_lu (n_l/N) (1 - exp(-h nu/kT)), with
+    B_lu = (g_u/g_l) c^3 A /(8 pi h nu^3) and n_l/N = g_l exp(-E_l/kT)/Q. Dividing by c
+    converts to wavenumber space (cm/molecule after m -> cm). A different route from the
+    ExoMol expression that catches a dropped 8 pi, a wrong power of nu or of c."""
+    h, c, k = 6.62607015e-34, 299792458.0, 1.380649e-23
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        nu_cm = rng.uniform(100, 30000)
+        A = 10 ** rng.uniform(-6, 2)
+        E_cm = rng.exponential(3000)
+        g_u = int(rng.integers(1, 51))
+        g_l = 7  # cancels
+        T = rng.uniform(300, 3000)
+        Q = 0.0343 * T ** 1.5
+        nu_hz = c * 100 * nu_cm
+        E_J = h * c * 100 * E_cm
+        B = (g_u / g_l) * c ** 3 * A / (8 * math.pi * h * nu_hz ** 3)
+        pop = g_l * math.exp(-E_J / (k * T)) / Q
+        s_hz = (h * nu_hz / c) * B * pop * (1 - math.exp(-h * nu_hz / (k * T)))  # m^2 Hz
+        s_cm = s_hz / c * 100.0   # m^2 Hz -> m^2 / m  -> m -> cm (per molecule)
+        S = O.strength_einstein(nu_cm, A, E_cm, g_u, T, Q)
+        assert float(S) == pytest.approx(s_cm, rel=1e-12, abs=0)
+
+
+def test_strength_reference_form_equals_einstein_form():
+    """S_ref := S_einstein(T_ref) makes the HITRAN-form scaling reproduce the ExoMol
+    form at every T (two different expressions of the same temperature dependence)."""
+    rng = np.random.default_rng(11)
+    nu = rng.uniform(100, 30000, 50)
+    A = 10 ** rng.uniform(-6, 2, 50)
+    E = rng.exponential(3000, 50)
+    g = rng.integers(1, 51, 50)
+    Qref = O.partition_function(O.T_REF)
+    Sref = O.strength_einstein(nu, A, E, g, O.T_REF, Qref)
+    for T in (300.0, 800.0, 2500.0, 3000.0):
+        QT = O.partition_function(T)
+        a = O.strength_einstein(nu, A, E, g, T, QT)
+        b = O.strength_reference(nu, Sref, E, T, QT, Qref)
+        np.testing.assert_allclose(b, a, rtol=1e-12)
+
+
+def test_strength_invariants():
+    # S scales with g' A; S*Q does not depend on the partition-function amplitude;
+    # E'' = 0 and c2 nu0/T -> 0 gives S -> g' A c2 /(8 pi c nu0 T Q)
+    S1 = O.strength_einstein(1500.0, 2.0, 100.0, 3, 1000.0, 50.0)
+    assert O.strength_einstein(1500.0, 4.0, 100.0, 3, 1000.0, 50.0) == pytest.approx(2 * S1, rel=1e-15, abs=0)
+    assert O.strength_einstein(1500.0, 2.0, 100.0, 6, 1000.0, 25.0) == pytest.approx(4 * S1, rel=1e-15, abs=0)
+    nu, T = 1e-3, 3000.0
+    s = O.strength_einstein(nu, 1.0, 0.0, 1, T, 1.0)
+    c_cgs, c2 = 2.99792458e10, 1.4387768775039338
+    assert float(s) == pytest.approx(c2 / (8 * math.pi * c_cgs * nu * T), rel=1e-6, abs=0)
+
+
+def test_partition_function_table_interpolation():
+    Tt, Qt = [100.0, 1000.0, 3000.0], [10.0, 200.0, 1000.0]
+    assert O.partition_function(1000.0, table_T=Tt, table_Q=Qt) == 200.0
+    assert O.partition_function(550.0, table_T=Tt, table_Q=Qt) == pytest.approx(105.0, abs=0)
+    assert O.partition_function(2000.0, table_T=Tt, table_Q=Qt) == pytest.approx(600.0, abs=0)
+    assert O.partition_function(296.0) == pytest.approx(0.0343 * 296 ** 1.5, abs=0)
+
+
+def test_stored_rounding_is_what_the_oracle_consumes():
+    # float32/uint16 arrays are upcast exactly: identical to passing their float64 copies
+    rng = np.random.default_rng(5)
+    L = {"nu0": np.sort(rng.uniform(1000, 1010, 50)),
+         "A": (10 ** rng.uniform(-6, 2, 50)).astype(np.float32),
+         "E_low": rng.exponential(3000, 50).astype(np.float32),
+         "gamma": rng.uniform(0.03, 0.1, 50).astype(np.float32),
+         "n_T": rng.uniform(0.4, 0.8, 50).astype(np.float32),
+         "g_up": rng.integers(1, 51, 50).astype(np.uint16)}
+    L64 = {k: v.astype(np.float64) for k, v in L.items()}
+    grid = np.linspace(1000, 1010, 300)
+    a = O.sigma(L, grid, 0.5, 900.0, 18.0, cut_cm1=3.0)
+    b = O.sigma(L64, grid, 0.5, 900.0, 18.0, cut_cm1=3.0)
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ cutoff and sum
+def _one_line(nu0=1000.0, A=1.0, E=500.0, g=5, gam=0.05, n=0.6):
+    return {"nu0": np.array([nu0]), "A": np.array([A], np.float32),
+            "E_low": np.array([E], np.float32), "gamma": np.array([gam], np.float32),
+            "n_T": np.array([n], np.float32), "g_up": np.array([g], np.uint16)}
+
+
+def test_single_line_equals_strength_times_profile():
+    L = _one_line()
+    grid = np.linspace(990, 1010, 2001)
+    P, T, m = 0.3, 1200.0, 18.0
+    sig = O.sigma(L, grid, P, T, m, cut_cm1=5.0)
+    par = O.line_parameters(L, P, T, m, cut_cm1=5.0)
+    d = grid - 1000.0
+    expect = np.where(np.abs(d) <= 5.0, par["S"][0] * O.voigt(d, par["b_D"][0], par["gamma_L"][0]), 0.0)
+    np.testing.assert_allclose(sig, expect, rtol=1e-15, atol=0)
+
+
+def test_cut_edge_is_inclusive_and_exact():
+    L = _one_line(nu0=1000.0)
+    cut = 0.5
+    edge_hi, edge_lo = 1000.5, 999.5          # exactly representable
+    grid = np.array([np.nextafter(edge_lo, 0), edge_lo, 1000.0, edge_hi,
+                     np.nextafter(edge_hi, 2000)])
+    sig = O.sigma(L, grid, 1.0, 1000.0, 18.0, cut_cm1=cut)
+    assert sig[0] == 0.0 and sig[4] == 0.0
+    assert sig[1] > 0 and sig[3] > 0 and sig[2] > sig[3]
+
+
+def test_window_reaching_in_from_outside_counts():
+    # a line left of the grid contributes through its wing; windows clip at grid edges
+    L = _one_line(nu0=995.0)
+    grid = np.linspace(1000, 1001, 11)
+    sig = O.sigma(L, grid, 1.0, 1000.0, 18.0, cut_cm1=5.5)
+    assert (sig[:6] > 0).all() and (sig[6:] == 0).all()
+
+
+@pytest.mark.parametrize("kind", ["gauss", "lorentz", "voigt"])
+def test_profile_integral_within_cutoff(kind):
+    """Sum_j sigma_j dnu on a fine grid = S * F(cut), F = int_{-cut}^{cut} V."""
+    L = _one_line(nu0=1000.0, gam=0.05, n=0.0)
+    m = 18.0
+    if kind == "gauss":
+        P, T = 0.0, 1000.0
+    elif kind == "lorentz":
+        P, T = 50.0, 1000.0
+    else:
+        P, T = 0.4, 1000.0
+    par = O.line_parameters(L, P, T, m, cut_cm1=1.0)
+    bD, gL, S = par["b_D"][0], par["gamma_L"][0], par["S"][0]
+    cut = 0.125                       # the window ends and grid points are exact binaries
+    dnu = 2.0 ** -14                  # <= b_D / 50 here
+    assert dnu <= bD / 40
+    n = int(round(2 * cut / dnu))
+    grid = 1000.0 - cut + dnu * np.arange(n + 1)
+    sig = O.sigma(L, grid, P, T, m, cut_cm1=cut)
+    # trapezoid over the closed window [-cut, cut]
+    integ = dnu * (sig.sum() - 0.5 * (sig[0] + sig[-1]))
+    if kind == "gauss":
+        F = math.erf(cut / bD)
+    else:
+        F = integrate.quad(lambda t: float(O.voigt(t, bD, gL)), -cut, cut, points=[0.0],
+                           epsrel=1e-12, limit=400)[0]
+        if kind == "lorentz":
+            # close to (2/pi) arctan(cut/gamma), the pure Lorentz mass
+            assert F == pytest.approx(2 / math.pi * math.atan(cut / gL), rel=5e-3, abs=0)
+    assert integ == pytest.approx(S * F, rel=2e-5, abs=0)
+
+
+def test_superposition_and_permutation():
+    rng = np.random.default_rng(2)
+    n = 400
+    L = {"nu0": np.sort(rng.uniform(1000, 1020, n)),
+         "A": (10 ** rng.uniform(-6, 2, n)).astype(np.float32),
+         "E_low": rng.exponential(3000, n).astype(np.float32),
+         "gamma": rng.uniform(0.03, 0.1, n).astype(np.float32),
+         "n_T": rng.uniform(0.4, 0.8, n).astype(np.float32),
+         "g_up": rng.integers(1, 51, n).astype(np.uint16)}
+    grid = np.linspace(1000, 1020, 2001)
+    kw = dict(P=0.2, T=1100.0, mass_amu=16.0, cut_kind="min_fwhm", cut_cm1=25.0,
+              fwhm_mult=100.0)
+    full = O.sigma(L, grid, **kw)
+    half = rng.random(n) < 0.5
+    a = O.sigma({k: v[half] for k, v in L.items()}, grid, **kw)
+    b = O.sigma({k: v[~half] for k, v in L.items()}, grid, **kw)
+    np.testing.assert_allclose(a + b, full, rtol=1e-13, atol=1e-30)
+    perm = rng.permutation(n)
+    c = O.sigma({k: v[perm] for k, v in L.items()}, grid, **kw)
+    np.testing.assert_allclose(c, full, rtol=1e-14, atol=0)
+
+
+def test_brute_force_mpmath_tiny():
+    """Pure-Python double loop, Faddeeva from mpmath, every term written out."""
+    rng = np.random.default_rng(9)
+    n = 6
+    L = {"nu0": np.sort(rng.uniform(2000, 2001, n)),
+         "A": (10 ** rng.uniform(-2, 2, n)).astype(np.float32),
+         "E_low": rng.exponential(1000, n).astype(np.float32),
+         "gamma": rng.uniform(0.03, 0.1, n).astype(np.float32),
+         "n_T": rng.uniform(0.4, 0.8, n).astype(np.float32),
+         "g_up": rng.integers(1, 51, n).astype(np.uint16)}
+    grid = np.linspace(1999.5, 2001.5, 23)
+    P, T, m, cut = 0.05, 700.0, 28.0, 0.6
+    sig = O.sigma(L, grid, P, T, m, cut_cm1=cut)
+    mpmath.mp.dps = 30
+    h, c, k, amu = 6.62607015e-34, 299792458.0, 1.380649e-23, 1.66053906660e-27
+    c2 = 100 * h * c / k
+    Q = 0.0343 * T ** 1.5
+    for j, nu in enumerate(grid):
+        tot = 0.0
+        for i in range(n):
+            nu0 = float(L["nu0"][i])
+            d = nu - nu0
+            if abs(d) > cut:
+                continue
+            A, E, g = float(L["A"][i]), float(L["E_low"][i]), float(L["g_up"][i])
+            gam, nT = float(L["gamma"][i]), float(L["n_T"][i])
+            S = g * A / (8 * math.pi * c * 100 * nu0 ** 2) * math.exp(-c2 * E / T) \
+                * (1 - math.exp(-c2 * nu0 / T)) / Q
+            bD = nu0 / c * math.sqrt(2 * k * T / (m * amu))
+            gL = gam * P * (296.0 / T) ** nT
+            w = _mp_w(mpmath.mpc(d / bD, gL / bD))
+            tot += S * float(w.real) / (bD * SQPI)
+        assert sig[j] == pytest.approx(tot, rel=1e-12, abs=0)
+
+
+def test_count_evals_matches_definition():
+    rng = np.random.default_rng(4)
+    n = 300
+    L = {"nu0": np.sort(rng.uniform(100, 110, n)),
+         "A": np.ones(n, np.float32), "E_low": np.zeros(n, np.float32),
+         "gamma": rng.uniform(0.03, 0.1, n).astype(np.float32),
+         "n_T": rng.uniform(0.4, 0.8, n).astype(np.float32),
+         "g_up": np.ones(n, np.uint16)}
+    grid = np.linspace(100, 110, 777)
+    for kind, kw in (("fixed", dict(cut_cm1=1.3)),
+                     ("min_fwhm", dict(cut_cm1=25.0, fwhm_mult=100.0))):
+        par = O.line_parameters(L, 1e-3, 500.0, 16.0, cut_kind=kind, **kw)
+        brute = int(np.sum(np.abs(grid[:, None] - L["nu0"][None, :]) <= par["cut"][None, :]))
+        assert O.count_evals(L, grid, 1e-3, 500.0, 16.0, cut_kind=kind, **kw) == brute
+
+
+def test_compare_metric():
+    ref = np.array([1.0, 0.5, 1e-9, 1e-12])
+    ok = O.compare(ref * (1 + 5e-5), ref)
+    assert ok["violations"] == 0
+    bad = ref.copy()
+    bad[1] *= 1 + 2e-4
+    assert O.compare(bad, ref)["violations"] == 1
+    small = ref.copy()
+    small[3] += 2e-8
+    assert O.compare(small, ref)["violations"] == 1
+
+
+def test_planted_mistakes_are_caught(monkeypatch):
+    """Plant plausible mistakes in the oracle on the CPU and check that a pin fails."""
+    # (1) wrong sign of the Lorentz term inside z
+    orig = O.voigt
+
+    def bad_voigt(dnu, b_D, gamma_L):
+        z = (np.asarray(dnu) - 1j * np.asarray(gamma_L)) / np.asarray(b_D)
+        from scipy.special import wofz
+        return wofz(z).real / (np.asarray(b_D) * SQPI)
+
+    monkeypatch.setattr(O, "voigt", bad_voigt)
+    with pytest.raises(AssertionError):
+        test_peak_is_erfcx_stdlib(0.3)
+    monkeypatch.setattr(O, "voigt", orig)
+    # (2) nu0 instead of nu0^2 in the strength
+    orig_s = O.strength_einstein
+
+    def bad_s(nu0, A, E_low, g_up, T, Q_T):
+        return orig_s(nu0, A, E_low, g_up, T, Q_T) * np.asarray(nu0, float)
+
+    monkeypatch.setattr(O, "strength_einstein", bad_s)
+    with pytest.raises(AssertionError):
+        test_strength_from_einstein_b_route()
+    monkeypatch.setattr(O, "strength_einstein", orig_s)
+    # (3) Doppler width from the FWHM instead of the 1/e half-width
+    orig_d = O.doppler_width
+    monkeypatch.setattr(O, "doppler_width",
+                        lambda nu0, T, m: orig_d(nu0, T, m) * 2 * math.sqrt(math.log(2)))
+    with pytest.raises(AssertionError):
+        test_doppler_width_matches_maxwell_velocity_variance()
+    monkeypatch.setattr(O, "doppler_width", orig_d)
