@@ -1,0 +1,189 @@
+"""Benchmark: Voigt line-point evaluations per second on one MI355X.
+
+Workload (default): 1e7 synthetic lines over 500-10000 cm^-1 (mass 16 amu), a uniform
+0.01 cm^-1 grid of 9.5e5 points, one (P, T) = (0.1 bar, 1500 K), fixed 25 cm^-1 cutoff,
+FP32 Voigt evaluation with Kahan-compensated sums and FP64 centres/offsets. One step is one
+full xs_compute of that cross-section with the line list and grid resident in HBM.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
+
+Prints one JSON line. The plain FP64 GPU path is timed beside it ("fp64_path"), the FP64
+CPU oracle is timed on a bounded sample of the same workload on this host's cores
+("cpu_baseline"), and the GPU result is checked against the oracle on that sample
+("max_rel_err"). Kernel duration for the roofline comes from HIP events recorded on the
+stream the kernel runs on.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# per-eval algorithmic FP32 work of the far-tier evaluation (FMA = 2 FLOPs):
+# offset 1, cut test 1, x 1, r^2 2, 1/r^2 1, v 1, v^2 1, (1 - u/2) 2, 2v^2 1, d 2,
+# numerator 2, 1/d 1, three products 3, scale 1, Kahan add 4  -> 25
+FLOPS_PER_EVAL = 25.0
+PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (published)
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mid")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-points", type=int, default=8192,
+                    help="grid points in the oracle sample (16 windows)")
+    ap.add_argument("--pts-per-lane", type=int, default=0)
+    ap.add_argument("--split", type=int, default=0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_20870_amd import synth, xsec
+
+    W = synth.WORKLOADS[args.workload]
+    if len(W.pts) != 1:
+        raise SystemExit("bench workload must have one (P, T) point")
+    P, T = W.pts[0]
+    t0 = time.time()
+    L = synth.make_lines(W.lines, workers=synth.default_workers())
+    grid = W.grid()
+    log(f"generated {W.lines.n} lines, {len(grid)} grid points in {time.time() - t0:.1f} s")
+
+    ctx = xsec.Context(0)
+    info = ctx.device_info()
+    h = ctx.load_lines(L, W.mass_amu)
+    g = ctx.set_grid(grid)
+    kind = xsec.XS_CUT_FIXED if W.cut_kind == "fixed" else xsec.XS_CUT_MIN_FWHM
+    o32 = ctx.opts(kind, W.cut_cm1, W.fwhm_mult, xsec.XS_FP32_KAHAN, args.pts_per_lane, args.split)
+    o64 = ctx.opts(kind, W.cut_cm1, W.fwhm_mult, xsec.XS_FP64, args.pts_per_lane, args.split)
+
+    evals = int(ctx.count_evals(h, g, [(P, T)], o32)[0])
+    if W.cut_kind == "fixed":
+        # independent count from the sorted centres (searchsorted), the harness's rule
+        nu0 = L["nu0"]
+        lo = np.searchsorted(nu0, grid - W.cut_cm1, "left")
+        hi = np.searchsorted(nu0, grid + W.cut_cm1, "right")
+        host_count = int(np.sum(hi - lo))
+        if abs(host_count - evals) > 1e-6 * evals:
+            raise SystemExit(f"eval count mismatch: device {evals}, host {host_count}")
+    log(f"line-point evals per step: {evals:.4e}")
+
+    stream = torch.cuda.current_stream()
+    out = torch.empty((1, len(grid)), dtype=torch.float64, device="cuda")
+
+    def run(opts, steps, warmup):
+        for _ in range(warmup):
+            ctx.compute(h, g, [(P, T)], opts, out=out, stream=stream)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for a, b in evs:
+            a.record(stream)
+            ctx.compute(h, g, [(P, T)], opts, out=out, stream=stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        kms = [a.elapsed_time(b) for a, b in evs]
+        return wall, float(np.mean(kms)), float(np.min(kms))
+
+    wall32, k32, kmin32 = run(o32, args.steps, args.warmup)
+    sig32 = out.cpu().numpy()[0].copy()
+    ms = wall32 / args.steps * 1e3
+    value = evals * args.steps / wall32
+    log(f"fp32+kahan: {ms:.3f} ms/step, kernel {k32:.3f} ms (min {kmin32:.3f}), "
+        f"{value:.4e} evals/s")
+
+    fp64 = None
+    if not args.no_fp64:
+        steps64 = max(3, args.steps // 4)
+        wall64, k64, _ = run(o64, steps64, 1)
+        v64 = evals * steps64 / wall64
+        fp64 = {"value": v64, "unit": "evals/s", "ms_per_step": wall64 / steps64 * 1e3,
+                "kernel_ms": k64, "steps": steps64, "fp32_speedup": value / v64}
+        log(f"fp64 path: {wall64 / steps64 * 1e3:.3f} ms/step, {v64:.4e} evals/s")
+
+    # oracle on a bounded sample: 16 windows of contiguous points
+    cpu = None
+    max_rel = None
+    if not args.no_cpu:
+        from oracle import xsec_oracle as O
+        rng = np.random.default_rng(2024)
+        win = max(1, args.cpu_points // 16)
+        starts = np.sort(rng.choice(len(grid) - win, 16, replace=False))
+        idx = np.unique(np.concatenate([np.arange(s, s + win) for s in starts]))
+        n_eval_sample = O.count_evals(L, grid, P, T, W.mass_amu, W.cut_kind, W.cut_cm1,
+                                      W.fwhm_mult, points=idx)
+        workers = synth.default_workers()
+        t = time.perf_counter()
+        ref = O.sigma_parallel(L, grid, workers=workers, chunk=max(32, win // 4), points=idx,
+                               P=P, T=T, mass_amu=W.mass_amu, cut_kind=W.cut_kind,
+                               cut_cm1=W.cut_cm1, fwhm_mult=W.fwhm_mult)
+        tc = time.perf_counter() - t
+        st = O.compare(sig32[idx], ref, ref_max=float(sig32.max()))
+        max_rel = st["max_rel"]
+        cpu = {"value": n_eval_sample / tc, "unit": "evals/s", "cores": workers,
+               "kind": "oracle",
+               "sample": f"{len(idx)} grid points in 16 windows of {win} ({n_eval_sample:.3e} "
+                         f"line-point evals) of the same workload, {tc:.1f} s"}
+        log(f"oracle: {n_eval_sample / tc:.4e} evals/s on {workers} cores; "
+            f"parity max_rel {st['max_rel']:.3e} violations {st['violations']}")
+        if st["violations"]:
+            log("PARITY VIOLATIONS", st)
+
+    achieved = evals * FLOPS_PER_EVAL / (k32 * 1e-3) / 1e12
+    res = {
+        "metric": "Voigt line-point evals/s at <=1e-4 rel err vs FP64",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{W.name}: {W.lines.n:.0e} lines {W.lines.nu_lo:g}-"
+                               f"{W.lines.nu_hi:g} cm^-1, {len(grid)} grid points, "
+                               f"P={P} bar T={T} K, cut {W.cut_cm1} cm^-1",
+                   "lines": W.lines.n, "grid_points": len(grid), "pt_points": 1,
+                   "evals_per_step": evals, "precision": "fp32 voigt + kahan, fp64 offsets",
+                   "device": info},
+        "max_rel_err": max_rel,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": None, "kernel_ms": k32,
+                     "flops_per_eval": FLOPS_PER_EVAL},
+        "fp64_path": fp64,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,182 @@
+/* xsec.h - C ABI of libxsec.so: line-by-line opacity cross-sections on one MI355X.
+ *
+ * The operations follow the paper's statement of the method (arXiv 2510.20870, section
+ * "Functionality of pyROX"): read a line list with its partition function and broadening
+ * coefficients (bullet "Download and read files"), compute line strengths and widths at
+ * the user's pressure and temperature (bullet "Compute line-strengths and -widths"), the
+ * Voigt profile as the real part of the Faddeeva function (bullet "Compute line
+ * profiles"), and sum the profiles into a cross-section per temperature-pressure point
+ * (bullet "Combine and save") on any user grid (section "Similar tools").
+ *
+ * Physics conventions (the paper gives no formulas; these textbook forms are used):
+ *   S (Einstein A form)  = g' A /(8 pi c nu0^2) exp(-c2 E''/T) (1 - exp(-c2 nu0/T)) / Q(T)
+ *   S (reference form)   = S_ref Q(T_ref)/Q(T) exp(-c2 E''/T)/exp(-c2 E''/T_ref)
+ *                            (1 - exp(-c2 nu0/T))/(1 - exp(-c2 nu0/T_ref))
+ *   b_D (1/e half-width) = (nu0/c) sqrt(2 k_B T / m)
+ *   gamma_L (HWHM)       = gamma_ref (P/P_ref) (T_ref/T)^n_T      (no natural width)
+ *   V(d)                 = Re w((d + i gamma_L)/b_D) / (b_D sqrt(pi))
+ *   sigma(nu_j)          = sum over lines with |nu_j - nu0_i| <= cut_i of S_i V_i
+ * with the cut either fixed, or min(cap, mult * f_V) with f_V the Olivero-Longbothum
+ * Voigt FWHM 0.5346 f_L + sqrt(0.2166 f_L^2 + f_G^2), f_L = 2 gamma_L,
+ * f_G = 2 b_D sqrt(ln 2). The difference nu_j - nu0_i and the cut test are FP64.
+ *
+ * Units: wavenumber cm^-1, pressure bar, temperature K, mass amu, sigma cm^2/molecule.
+ *
+ * Conventions of every call:
+ *   - returns an xs_status (0 = XS_OK, negative = error); no exception or abort crosses
+ *     the ABI; xs_last_error() gives a message for the calling thread's last failure;
+ *   - inputs are copied before the call returns; the caller keeps ownership of every
+ *     pointer it passes; outputs are written into caller-owned memory;
+ *   - handles become invalid after unload/free; a context is used from one thread at a
+ *     time, except the serving calls (xs_submit .. xs_release), which are thread-safe.
+ */
+#ifndef XSEC_H
+#define XSEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XS_ABI_VERSION 1
+
+typedef enum {
+  XS_OK = 0,
+  XS_EINVAL = -1,      /* bad argument (null pointer, NaN, P <= 0, unknown enum, ...) */
+  XS_ENOMEM = -2,      /* the request does not fit the context's HBM budget            */
+  XS_EDEVICE = -3,     /* a HIP runtime call failed                                    */
+  XS_ENOTFOUND = -4,   /* unknown handle                                               */
+  XS_EUNSORTED = -5,   /* grid not strictly increasing                                 */
+  XS_EBUSY = -6,       /* handle still referenced by pending requests                  */
+  XS_ECANCELLED = -7,  /* request was cancelled                                        */
+  XS_ETIMEOUT = -8     /* xs_wait timed out                                            */
+} xs_status;
+
+enum { XS_EINSTEIN_A = 0, XS_REF_STRENGTH = 1 };  /* strength form                   */
+enum { XS_Q_POWER = 0, XS_Q_TABLE = 1 };          /* partition-function form         */
+enum { XS_CUT_FIXED = 0, XS_CUT_MIN_FWHM = 1 };   /* line-wing cutoff rule           */
+enum { XS_FP32_KAHAN = 0, XS_FP64 = 1 };          /* arithmetic of the profile sum   */
+
+typedef struct xs_ctx xs_ctx;     /* opaque; one per device                              */
+typedef uint64_t xs_lines_t;      /* resident line list                                  */
+typedef uint64_t xs_grid_t;       /* resident wavenumber grid                            */
+typedef uint64_t xs_req_t;        /* serving request                                     */
+typedef struct xs_graph xs_graph; /* captured batched computation                        */
+
+int xs_abi_version(void);
+
+/* Create a context on HIP device `device` that may hold at most `hbm_budget_bytes` of
+ * device memory (line lists + grids + scratch + request outputs); 0 = 90% of free
+ * memory. *out receives the context. Errors: XS_EINVAL, XS_EDEVICE. */
+int xs_create(int device, size_t hbm_budget_bytes, xs_ctx **out);
+/* Free every resource of the context (waits for its device work). NULL is a no-op. */
+void xs_destroy(xs_ctx *ctx);
+/* Message of the calling thread's last failed call ("" if none). Never NULL. */
+const char *xs_last_error(const xs_ctx *ctx);
+/* Device facts: compute units, LDS bytes per workgroup, arch name ("gfx950"). */
+int xs_device_info(xs_ctx *ctx, int *n_cu, size_t *lds_bytes, char *arch, size_t arch_len);
+/* Bytes of device memory the context currently accounts against its budget. */
+int xs_memory_used(xs_ctx *ctx, size_t *used, size_t *budget);
+
+/* A line list as a host structure of arrays, n records (paper: "Download and read
+ * files"). nu0 float64 [cm^-1]; A_or_Sref float32 (Einstein A [s^-1], or the strength at
+ * T_ref [cm/molecule] for XS_REF_STRENGTH); E_low float32 [cm^-1]; gamma_ref float32
+ * [cm^-1/bar] at T_ref; n_T float32; g_up uint16 (>= 1; unused by the reference form).
+ * The arrays need not be sorted: the library keeps a stable sort by nu0 (ties keep the
+ * input order). n = 0 is allowed (every sigma is then 0). */
+typedef struct {
+  size_t n;
+  const double *nu0;
+  const float *A_or_Sref;
+  const float *E_low;
+  const float *gamma_ref;
+  const float *n_T;
+  const uint16_t *g_up;
+} xs_lines_desc;
+
+/* The species: strength form, molecular mass [amu], T_ref [K] (296 when 0),
+ * P_ref [bar] (1 when 0), and Q(T) = q_a * T^q_b (XS_Q_POWER) or the linear
+ * interpolation of the q_n nodes (q_T ascending, q_val) clamped at the ends
+ * (XS_Q_TABLE; the table is copied). */
+typedef struct {
+  int strength_form;
+  double mass_amu;
+  double T_ref;
+  double P_ref;
+  int q_kind;
+  double q_a, q_b;
+  const double *q_T;
+  const double *q_val;
+  size_t q_n;
+} xs_species_desc;
+
+/* Copy a line list into HBM (26 bytes per line, sorted by nu0). Errors: XS_EINVAL
+ * (NaN/negative fields, g_up = 0 with the Einstein form, bad species), XS_ENOMEM. */
+int xs_load_lines(xs_ctx *ctx, const xs_lines_desc *lines, const xs_species_desc *species,
+                  xs_lines_t *out);
+/* Release a line list. XS_EBUSY while serving requests still reference it. */
+int xs_unload_lines(xs_ctx *ctx, xs_lines_t lines);
+/* Number of lines and resident bytes of a list. */
+int xs_lines_info(xs_ctx *ctx, xs_lines_t lines, size_t *n, size_t *bytes);
+
+/* Copy a wavenumber grid of n points into HBM. It must be finite and strictly increasing
+ * (else XS_EUNSORTED); n >= 1. A wavelength grid is converted by the caller. */
+int xs_set_grid(xs_ctx *ctx, const double *nu_cm1, size_t n, xs_grid_t *out);
+int xs_free_grid(xs_ctx *ctx, xs_grid_t grid);
+/* Number of points of a resident grid. */
+int xs_grid_info(xs_ctx *ctx, xs_grid_t grid, size_t *n);
+
+typedef struct { double P_bar, T_K; } xs_pt;
+
+/* Options of a computation. cut_cm1 is the fixed cut (XS_CUT_FIXED) or the cap of
+ * min(cap, fwhm_mult * f_V) (XS_CUT_MIN_FWHM). pts_per_lane (0 = autotuned, else 1, 2, 4
+ * or 8) sets the grid tile of one wavefront to 64 * pts_per_lane points; split (0 =
+ * autotuned, else 1..256) divides each tile's line window into that many independent
+ * work items whose partial sums are added in a fixed order. */
+typedef struct {
+  int cutoff_kind;
+  double cut_cm1;
+  double fwhm_mult;
+  int precision;
+  int pts_per_lane;
+  int split;
+} xs_opts;
+
+/* sigma(nu_j; P_k, T_k) for k < npts on every point of `grid`, written to
+ * sigma_out[k * n_grid + j] (float64, row-major [npts][n_grid]). With out_on_device != 0,
+ * sigma_out is device memory, the work is enqueued on `stream` (a hipStream_t, NULL =
+ * the null stream) and the call returns without waiting; otherwise sigma_out is host
+ * memory and the call returns when it is filled. Each output element is produced by one
+ * work item in a fixed line order, so repeated calls give bitwise identical results.
+ * Errors: XS_EINVAL (P or T <= 0 or not finite, bad options), XS_ENOTFOUND, XS_ENOMEM,
+ * XS_EDEVICE. */
+int xs_compute(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts, size_t npts,
+               const xs_opts *opts, double *sigma_out, int out_on_device, void *stream);
+
+/* Number of (line, grid point) pairs inside the cutoff, per (P, T) point, counted on the
+ * device with the same FP64 rule as xs_compute: counts_out[k] (host memory). */
+int xs_count_evals(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts,
+                   size_t npts, const xs_opts *opts, uint64_t *counts_out);
+
+/* Batched computation captured once in a hipGraph (its point table and scratch are owned
+ * by the graph) and replayed by xs_graph_launch on any stream; sigma_dev is device memory
+ * of npts * n_grid float64. */
+int xs_graph_create(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts,
+                    size_t npts, const xs_opts *opts, double *sigma_dev, xs_graph **out);
+int xs_graph_launch(xs_graph *g, void *stream);
+void xs_graph_destroy(xs_graph *g);
+
+/* The Voigt function K(x, y) = Re w(x + iy) as the kernels evaluate it, for n host
+ * points: on the device (xs_eval_voigt) or compiled for the host (xs_eval_voigt_host).
+ * precision: XS_FP32_KAHAN (FP32 tiers) or XS_FP64. */
+int xs_eval_voigt(xs_ctx *ctx, const double *x, const double *y, size_t n, int precision,
+                  double *K_out);
+int xs_eval_voigt_host(const double *x, const double *y, size_t n, int precision,
+                       double *K_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XSEC_H */

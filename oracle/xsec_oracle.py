@@ -238,9 +238,13 @@ def count_evals(lines: Dict[str, np.ndarray], grid: np.ndarray, P: float, T: flo
 
 
 # ------------------------------------------------------------- process-pool driver
+_POOL_DATA = {}
+
+
 def _sigma_job(args):
-    lines, grid, kw, pts = args
-    return sigma(lines, grid, points=pts, **kw)
+    # the line list and grid are inherited from the parent through fork, not pickled
+    kw, pts = args
+    return sigma(_POOL_DATA["lines"], _POOL_DATA["grid"], points=pts, **kw)
 
 
 def sigma_parallel(lines, grid, workers: Optional[int] = None, chunk: int = 256,
@@ -253,8 +257,12 @@ def sigma_parallel(lines, grid, workers: Optional[int] = None, chunk: int = 256,
     if workers <= 1 or len(blocks) == 1:
         return sigma(lines, grid, points=idx, **kw)
     import multiprocessing as mp
-    with mp.get_context("fork").Pool(workers) as pool:
-        parts = pool.map(_sigma_job, [(lines, grid, kw, b) for b in blocks])
+    _POOL_DATA["lines"], _POOL_DATA["grid"] = lines, grid
+    try:
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_sigma_job, [(kw, b) for b in blocks])
+    finally:
+        _POOL_DATA.clear()
     return np.concatenate(parts)
 
 
@@ -271,8 +279,9 @@ def compare(sig: np.ndarray, ref: np.ndarray, rel_tol: float = 1e-4,
     rel = np.zeros_like(ref)
     rel[big] = np.abs(sig[big] - ref[big]) / ref[big]
     absdev = np.abs(sig - ref)
-    viol = int(np.count_nonzero(rel[big] > rel_tol)) + int(
-        np.count_nonzero(absdev[~big] > floor * m))
+    # written as "not within" so that NaN or inf results count as violations
+    viol = int(np.count_nonzero(~(rel[big] <= rel_tol))) + int(
+        np.count_nonzero(~(absdev[~big] <= floor * m)))
     return {"max_rel": float(rel[big].max()) if big.any() else 0.0,
             "p99_rel": float(np.quantile(rel[big], 0.99)) if big.any() else 0.0,
             "n_big": int(big.sum()), "violations": viol,

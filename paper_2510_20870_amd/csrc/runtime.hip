@@ -1,0 +1,774 @@
+// Host runtime behind the C ABI of include/xsec.h: contexts, HBM budget, resident line
+// lists and grids, argument validation, work planning, launches and hipGraph capture.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/xsec.h"
+#include "kernel_args.h"
+#include "runtime_internal.h"
+#include "voigt.h"
+
+namespace xs {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(XS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Weideman (1994) coefficients a_1..a_N of the rational series for w(z):
+// a_n = (1/2M) sum_{k=-M+1}^{M-1} f(t_k) exp(-i pi n k / M), with M = 2N,
+// t_k = L tan(k pi / 2M), f(t) = exp(-t^2)(L^2 + t^2); f is even in k, so the sum is real.
+void weideman_coefficients(int N, double* a) {
+  const int M = 2 * N;
+  const double L = sqrt(N / sqrt(2.0));
+  std::vector<double> f(M);
+  for (int k = 0; k < M; ++k) {
+    const double t = L * tan(k * M_PI / (2.0 * M));
+    f[k] = exp(-t * t) * (L * L + t * t);
+  }
+  for (int n = 1; n <= N; ++n) {
+    double acc = f[0];
+    for (int k = 1; k < M; ++k) acc += 2.0 * f[k] * cos(M_PI * (double)n * k / M);
+    a[n - 1] = acc / (2.0 * M);
+  }
+}
+
+const double* host_weideman() {
+  static double a[kWeidN];
+  static std::once_flag once;
+  std::call_once(once, [] { weideman_coefficients(kWeidN, a); });
+  return a;
+}
+
+}  // namespace xs
+
+using xs::fail;
+
+bool xs_ctx::reserve(size_t bytes) {
+  size_t cur = used.load();
+  do {
+    if (cur + bytes > budget) return false;
+  } while (!used.compare_exchange_weak(cur, cur + bytes));
+  return true;
+}
+
+void xs_ctx::release(size_t bytes) { used.fetch_sub(bytes); }
+
+int xs_ctx::dev_alloc(void** p, size_t bytes, const char* what) {
+  if (bytes == 0) bytes = 256;
+  if (!reserve(bytes))
+    return fail(XS_ENOMEM, "%s: %zu bytes exceed the HBM budget (%zu of %zu in use)", what,
+                bytes, used.load(), budget);
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    release(bytes);
+    (void)hipGetLastError();
+    return fail(XS_ENOMEM, "%s: hipMalloc(%zu) failed: %s", what, bytes, hipGetErrorString(e));
+  }
+  return XS_OK;
+}
+
+void xs_ctx::dev_free(void* p, size_t bytes) {
+  if (!p) return;
+  if (bytes == 0) bytes = 256;
+  (void)hipFree(p);
+  release(bytes);
+}
+
+// Grow-only device scratch buffer.
+int xs_ctx::scratch(xs::Scratch& s, size_t bytes, const char* what) {
+  if (s.cap >= bytes && s.ptr) return XS_OK;
+  if (s.ptr) dev_free(s.ptr, s.cap);
+  s.ptr = nullptr;
+  s.cap = 0;
+  size_t want = std::max(bytes, (size_t)4096);
+  int rc = dev_alloc(&s.ptr, want, what);
+  if (rc) return rc;
+  s.cap = want;
+  return XS_OK;
+}
+
+xs::LinesRes* xs_ctx::find_lines(xs_lines_t h) {
+  auto it = lines.find(h);
+  return it == lines.end() ? nullptr : it->second;
+}
+
+xs::GridRes* xs_ctx::find_grid(xs_grid_t h) {
+  auto it = grids.find(h);
+  return it == grids.end() ? nullptr : it->second;
+}
+
+namespace xs {
+
+int validate_opts(const xs_opts* o) {
+  if (!o) return fail(XS_EINVAL, "opts is NULL");
+  if (o->cutoff_kind != XS_CUT_FIXED && o->cutoff_kind != XS_CUT_MIN_FWHM)
+    return fail(XS_EINVAL, "unknown cutoff_kind %d", o->cutoff_kind);
+  if (!(o->cut_cm1 > 0.0) || !isfinite(o->cut_cm1))
+    return fail(XS_EINVAL, "cut_cm1 must be finite and > 0 (got %g)", o->cut_cm1);
+  if (o->cutoff_kind == XS_CUT_MIN_FWHM && (!(o->fwhm_mult > 0.0) || !isfinite(o->fwhm_mult)))
+    return fail(XS_EINVAL, "fwhm_mult must be finite and > 0 (got %g)", o->fwhm_mult);
+  if (o->precision != XS_FP32_KAHAN && o->precision != XS_FP64)
+    return fail(XS_EINVAL, "unknown precision %d", o->precision);
+  const int P = o->pts_per_lane;
+  if (P != 0 && P != 1 && P != 2 && P != 4 && P != 8)
+    return fail(XS_EINVAL, "pts_per_lane must be 0, 1, 2, 4 or 8 (got %d)", P);
+  if (o->split < 0 || o->split > kMaxSplit)
+    return fail(XS_EINVAL, "split must be in [0, %d] (got %d)", kMaxSplit, o->split);
+  return XS_OK;
+}
+
+int validate_pts(const xs_pt* pts, size_t npts) {
+  if (npts == 0) return fail(XS_EINVAL, "npts must be >= 1");
+  if (!pts) return fail(XS_EINVAL, "pts is NULL");
+  if (npts > (size_t)1 << 20) return fail(XS_EINVAL, "npts %zu too large", npts);
+  for (size_t k = 0; k < npts; ++k) {
+    if (!(pts[k].P_bar > 0.0) || !isfinite(pts[k].P_bar) || !(pts[k].T_K > 0.0) ||
+        !isfinite(pts[k].T_K))
+      return fail(XS_EINVAL, "pts[%zu] = (P %g bar, T %g K): both must be finite and > 0", k,
+                  pts[k].P_bar, pts[k].T_K);
+  }
+  return XS_OK;
+}
+
+Plan make_plan(const Ctx& c, size_t n_grid, size_t npts, const xs_opts& o, int64_t n_lines) {
+  Plan p;
+  p.P = o.pts_per_lane ? o.pts_per_lane : 4;
+  const int64_t tile = (int64_t)kWave * p.P;
+  p.n_tiles = ((int64_t)n_grid + tile - 1) / tile;
+  const int64_t base = p.n_tiles * (int64_t)npts;
+  if (o.split) {
+    p.split = o.split;
+  } else {
+    // enough wavefronts to give every SIMD (4 per CU) four of them
+    const int64_t target = (int64_t)c.n_cu * 16;
+    int64_t s = (target + base - 1) / base;
+    s = std::max<int64_t>(1, std::min<int64_t>(s, 64));
+    // no point in splits much shorter than one 64-line chunk
+    const int64_t cap = std::max<int64_t>(1, n_lines / 64);
+    p.split = (int)std::min<int64_t>(s, cap);
+  }
+  p.n_items = base * p.split;
+  p.n_wg = (p.n_items + kWavesPerWG - 1) / kWavesPerWG;
+  p.per_xcd = (p.n_wg + 7) / 8;
+  p.phys_wg = p.per_xcd * 8;
+  return p;
+}
+
+TileArgs make_args(const Ctx& c, const LinesRes& L, const GridRes& G, const xs_opts& o,
+                   const Plan& p, const double* pts_dev, int npts) {
+  TileArgs A;
+  memset(&A, 0, sizeof A);
+  A.L = L.dev;
+  A.sp = L.sp;
+  A.cut.kind = o.cutoff_kind == XS_CUT_FIXED ? kCutFixed : kCutMinFwhm;
+  A.cut.cut = o.cut_cm1;
+  A.cut.mult = o.fwhm_mult;
+  A.grid = G.d;
+  A.n_grid = (int64_t)G.n;
+  A.pts = pts_dev;
+  A.n_pts = npts;
+  A.split = p.split;
+  A.n_tiles = p.n_tiles;
+  A.n_items = p.n_items;
+  A.n_wg = p.n_wg;
+  A.per_xcd = p.per_xcd;
+  A.wc = c.wc;
+  return A;
+}
+
+// Enqueue the tile kernel (and the reduction when split > 1) writing sigma to out_dev.
+int enqueue_compute(Ctx& c, const TileArgs& A0, const Plan& p, bool f64, double* out_dev,
+                    double* part_dev, hipStream_t st) {
+  TileArgs A = A0;
+  A.out = (p.split == 1) ? out_dev : part_dev;
+  hipError_t e = launch_tile(A, p.P, f64, st, p.phys_wg);
+  if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
+  if (p.split > 1) {
+    e = launch_reduce(part_dev, out_dev, A.n_grid, A.n_pts, p.split, st);
+    if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
+  }
+  return XS_OK;
+}
+
+// Upload the (P, T) table into the context's device buffer, waiting first for the last
+// launch that read it unless the content is unchanged.
+int upload_pts(Ctx& c, const xs_pt* pts, size_t npts, hipStream_t st) {
+  const size_t bytes = npts * 2 * sizeof(double);
+  std::vector<double> h(2 * npts);
+  for (size_t k = 0; k < npts; ++k) {
+    h[2 * k] = pts[k].P_bar;
+    h[2 * k + 1] = pts[k].T_K;
+  }
+  if (c.pts_host == h && c.pts_buf.ptr && c.pts_buf.cap >= bytes) return XS_OK;
+  if (c.pts_event_valid) {
+    hipError_t e = hipEventSynchronize(c.pts_event);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  }
+  int rc = c.scratch(c.pts_buf, bytes, "point table");
+  if (rc) return rc;
+  if (c.pts_pinned_cap < bytes) {
+    if (c.pts_pinned) (void)hipHostFree(c.pts_pinned);
+    c.pts_pinned = nullptr;
+    hipError_t e = hipHostMalloc(&c.pts_pinned, std::max(bytes, (size_t)4096), 0);
+    if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
+    c.pts_pinned_cap = std::max(bytes, (size_t)4096);
+  }
+  memcpy(c.pts_pinned, h.data(), bytes);
+  hipError_t e = hipMemcpyAsync(c.pts_buf.ptr, c.pts_pinned, bytes, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "point table upload");
+  c.pts_host = std::move(h);
+  return XS_OK;
+}
+
+}  // namespace xs
+
+using namespace xs;
+
+extern "C" {
+
+int xs_abi_version(void) { return XS_ABI_VERSION; }
+
+const char* xs_last_error(const xs_ctx*) { return g_last_error.c_str(); }
+
+int xs_create(int device, size_t hbm_budget_bytes, xs_ctx** out) {
+  if (!out) return fail(XS_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) return fail(XS_EDEVICE, "no HIP device available");
+  if (device < 0 || device >= ndev) return fail(XS_EINVAL, "device %d out of range", device);
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  size_t free_b = 0, total_b = 0;
+  e = hipMemGetInfo(&free_b, &total_b);
+  if (e != hipSuccess) return hip_fail(e, "hipMemGetInfo");
+  Ctx* c = new Ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
+  c->n_cu = prop.multiProcessorCount;
+  c->lds = prop.sharedMemPerBlock;
+  c->arch = prop.gcnArchName;
+  void* wc = nullptr;
+  int rc = c->dev_alloc(&wc, kWeidN * sizeof(double), "Weideman coefficients");
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  c->wc = (double*)wc;
+  e = hipMemcpy(c->wc, host_weideman(), kWeidN * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    xs_destroy(c);
+    return hip_fail(e, "coefficient upload");
+  }
+  e = hipEventCreateWithFlags(&c->pts_event, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    xs_destroy(c);
+    return hip_fail(e, "hipEventCreate");
+  }
+  *out = c;
+  return XS_OK;
+}
+
+void xs_destroy(xs_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  serve_shutdown(c);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : c->lines) free_lines_res(*c, kv.second);
+  for (auto& kv : c->grids) {
+    c->dev_free(kv.second->d, kv.second->bytes);
+    delete kv.second;
+  }
+  c->dev_free(c->wc, kWeidN * sizeof(double));
+  for (Scratch* s : {&c->pts_buf, &c->part_buf, &c->out_buf, &c->count_buf})
+    if (s->ptr) c->dev_free(s->ptr, s->cap);
+  if (c->pts_pinned) (void)hipHostFree(c->pts_pinned);
+  if (c->pts_event) (void)hipEventDestroy(c->pts_event);
+  delete c;
+}
+
+int xs_device_info(xs_ctx* c, int* n_cu, size_t* lds_bytes, char* arch, size_t arch_len) {
+  if (!c) return fail(XS_EINVAL, "ctx is NULL");
+  if (n_cu) *n_cu = c->n_cu;
+  if (lds_bytes) *lds_bytes = c->lds;
+  if (arch && arch_len) {
+    strncpy(arch, c->arch.c_str(), arch_len - 1);
+    arch[arch_len - 1] = 0;
+  }
+  return XS_OK;
+}
+
+int xs_memory_used(xs_ctx* c, size_t* used, size_t* budget) {
+  if (!c) return fail(XS_EINVAL, "ctx is NULL");
+  if (used) *used = c->used.load();
+  if (budget) *budget = c->budget;
+  return XS_OK;
+}
+
+int xs_load_lines(xs_ctx* c, const xs_lines_desc* d, const xs_species_desc* sp, xs_lines_t* out) {
+  if (!c || !d || !sp || !out) return fail(XS_EINVAL, "NULL argument");
+  const size_t n = d->n;
+  if (n > 0 && (!d->nu0 || !d->A_or_Sref || !d->E_low || !d->gamma_ref || !d->n_T || !d->g_up))
+    return fail(XS_EINVAL, "line arrays must be non-NULL when n > 0");
+  if (sp->strength_form != XS_EINSTEIN_A && sp->strength_form != XS_REF_STRENGTH)
+    return fail(XS_EINVAL, "unknown strength_form %d", sp->strength_form);
+  if (!(sp->mass_amu > 0.0) || !isfinite(sp->mass_amu))
+    return fail(XS_EINVAL, "mass_amu must be finite and > 0");
+  const double T_ref = sp->T_ref > 0 ? sp->T_ref : 296.0;
+  const double P_ref = sp->P_ref > 0 ? sp->P_ref : 1.0;
+  if (!isfinite(T_ref) || !isfinite(P_ref)) return fail(XS_EINVAL, "T_ref/P_ref not finite");
+  if (sp->q_kind == XS_Q_POWER) {
+    if (!(sp->q_a > 0.0) || !isfinite(sp->q_a) || !isfinite(sp->q_b))
+      return fail(XS_EINVAL, "Q(T) = a T^b needs finite a > 0 and finite b");
+  } else if (sp->q_kind == XS_Q_TABLE) {
+    if (!sp->q_T || !sp->q_val || sp->q_n < 1)
+      return fail(XS_EINVAL, "Q table needs q_T, q_val and q_n >= 1");
+    for (size_t k = 0; k < sp->q_n; ++k) {
+      if (!isfinite(sp->q_T[k]) || !(sp->q_val[k] > 0.0) || !isfinite(sp->q_val[k]))
+        return fail(XS_EINVAL, "Q table node %zu invalid", k);
+      if (k && !(sp->q_T[k] > sp->q_T[k - 1]))
+        return fail(XS_EINVAL, "Q table temperatures must increase");
+    }
+  } else {
+    return fail(XS_EINVAL, "unknown q_kind %d", sp->q_kind);
+  }
+  // validate records; find whether they are sorted
+  bool sorted = true;
+  double gmax = 0.0, nmin = 0.0, nmax = 0.0;
+  for (size_t i = 0; i < n; ++i) {
+    const double nu = d->nu0[i];
+    const float A = d->A_or_Sref[i], E = d->E_low[i], g = d->gamma_ref[i], nt = d->n_T[i];
+    if (!(nu > 0.0) || !isfinite(nu)) return fail(XS_EINVAL, "nu0[%zu] = %g invalid", i, nu);
+    if (!(A >= 0.0f) || !isfinite(A)) return fail(XS_EINVAL, "A_or_Sref[%zu] invalid", i);
+    if (!(E >= 0.0f) || !isfinite(E)) return fail(XS_EINVAL, "E_low[%zu] invalid", i);
+    if (!(g >= 0.0f) || !isfinite(g)) return fail(XS_EINVAL, "gamma_ref[%zu] invalid", i);
+    if (!isfinite(nt)) return fail(XS_EINVAL, "n_T[%zu] invalid", i);
+    if (sp->strength_form == XS_EINSTEIN_A && d->g_up[i] == 0)
+      return fail(XS_EINVAL, "g_up[%zu] = 0", i);
+    if (i && nu < d->nu0[i - 1]) sorted = false;
+    gmax = std::max(gmax, (double)g);
+    if (i == 0) nmin = nmax = nt;
+    nmin = std::min(nmin, (double)nt);
+    nmax = std::max(nmax, (double)nt);
+  }
+  std::vector<size_t> order;
+  if (!sorted) {
+    order.resize(n);
+    std::iota(order.begin(), order.end(), (size_t)0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return d->nu0[a] < d->nu0[b]; });
+  }
+  LinesRes* L = new LinesRes();
+  L->n = n;
+  // one allocation, 256-byte aligned sub-arrays
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t b_nu = al(n * 8), b_f = al(n * 4), b_g = al(n * 2);
+  const size_t qn = sp->q_kind == XS_Q_TABLE ? sp->q_n : 0;
+  const size_t b_q = al(qn * 8);
+  L->bytes = b_nu + 4 * b_f + b_g + 2 * b_q;
+  int rc = c->dev_alloc(&L->base, L->bytes, "line list");
+  if (rc) {
+    delete L;
+    return rc;
+  }
+  char* p = (char*)L->base;
+  double* nu_d = (double*)p; p += b_nu;
+  float* A_d = (float*)p; p += b_f;
+  float* E_d = (float*)p; p += b_f;
+  float* g_d = (float*)p; p += b_f;
+  float* n_d = (float*)p; p += b_f;
+  uint16_t* u_d = (uint16_t*)p; p += b_g;
+  double* qT_d = (double*)p; p += b_q;
+  double* qV_d = (double*)p;
+  auto put = [&](void* dst, const void* src, size_t esz) -> hipError_t {
+    if (n == 0) return hipSuccess;
+    if (sorted) return hipMemcpy(dst, src, n * esz, hipMemcpyHostToDevice);
+    std::vector<char> tmp(n * esz);
+    const char* s = (const char*)src;
+    for (size_t i = 0; i < n; ++i) memcpy(&tmp[i * esz], s + order[i] * esz, esz);
+    return hipMemcpy(dst, tmp.data(), n * esz, hipMemcpyHostToDevice);
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = put(nu_d, d->nu0, 8);
+  if (e == hipSuccess) e = put(A_d, d->A_or_Sref, 4);
+  if (e == hipSuccess) e = put(E_d, d->E_low, 4);
+  if (e == hipSuccess) e = put(g_d, d->gamma_ref, 4);
+  if (e == hipSuccess) e = put(n_d, d->n_T, 4);
+  if (e == hipSuccess) e = put(u_d, d->g_up, 2);
+  if (e == hipSuccess && qn) e = hipMemcpy(qT_d, sp->q_T, qn * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess && qn) e = hipMemcpy(qV_d, sp->q_val, qn * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    c->dev_free(L->base, L->bytes);
+    delete L;
+    return hip_fail(e, "line list upload");
+  }
+  L->dev.nu0 = nu_d;
+  L->dev.A = A_d;
+  L->dev.E = E_d;
+  L->dev.gam = g_d;
+  L->dev.nT = n_d;
+  L->dev.g = u_d;
+  L->dev.n = (int64_t)n;
+  L->sp.form = sp->strength_form == XS_EINSTEIN_A ? kEinstein : kReference;
+  L->sp.q_kind = sp->q_kind == XS_Q_POWER ? kQPower : kQTable;
+  L->sp.mass_amu = sp->mass_amu;
+  L->sp.T_ref = T_ref;
+  L->sp.P_ref = P_ref;
+  L->sp.q_a = sp->q_a;
+  L->sp.q_b = sp->q_b;
+  L->sp.q_T = qn ? qT_d : nullptr;
+  L->sp.q_val = qn ? qV_d : nullptr;
+  L->sp.q_n = (int)qn;
+  L->sp.gam_max = gmax;
+  L->sp.n_min = nmin;
+  L->sp.n_max = nmax;
+  // host copy of the species for host-side Q evaluation (tables on the host)
+  L->q_T_host.assign(sp->q_T ? sp->q_T : nullptr, sp->q_T ? sp->q_T + qn : nullptr);
+  L->q_val_host.assign(sp->q_val ? sp->q_val : nullptr, sp->q_val ? sp->q_val + qn : nullptr);
+  std::lock_guard<std::mutex> lk(c->mu);
+  const uint64_t h = c->next_handle++;
+  c->lines[h] = L;
+  *out = h;
+  return XS_OK;
+}
+
+int xs_unload_lines(xs_ctx* c, xs_lines_t h) {
+  if (!c) return fail(XS_EINVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  LinesRes* L = c->find_lines(h);
+  if (!L) return fail(XS_ENOTFOUND, "unknown line list %llu", (unsigned long long)h);
+  if (L->refs.load() > 0)
+    return fail(XS_EBUSY, "line list %llu is referenced by %d pending request(s)",
+                (unsigned long long)h, L->refs.load());
+  c->lines.erase(h);
+  (void)hipDeviceSynchronize();
+  free_lines_res(*c, L);
+  return XS_OK;
+}
+
+int xs_lines_info(xs_ctx* c, xs_lines_t h, size_t* n, size_t* bytes) {
+  if (!c) return fail(XS_EINVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  LinesRes* L = c->find_lines(h);
+  if (!L) return fail(XS_ENOTFOUND, "unknown line list %llu", (unsigned long long)h);
+  if (n) *n = L->n;
+  if (bytes) *bytes = L->bytes;
+  return XS_OK;
+}
+
+int xs_set_grid(xs_ctx* c, const double* nu, size_t n, xs_grid_t* out) {
+  if (!c || !out) return fail(XS_EINVAL, "NULL argument");
+  if (n == 0 || !nu) return fail(XS_EINVAL, "grid needs n >= 1 points");
+  if ((int64_t)n < 0) return fail(XS_EINVAL, "grid too large");
+  for (size_t j = 0; j < n; ++j) {
+    if (!isfinite(nu[j])) return fail(XS_EUNSORTED, "grid[%zu] is not finite", j);
+    if (j && !(nu[j] > nu[j - 1]))
+      return fail(XS_EUNSORTED, "grid is not strictly increasing at %zu", j);
+  }
+  GridRes* G = new GridRes();
+  G->n = n;
+  G->bytes = n * sizeof(double);
+  int rc = c->dev_alloc((void**)&G->d, G->bytes, "grid");
+  if (rc) {
+    delete G;
+    return rc;
+  }
+  hipError_t e = hipMemcpy(G->d, nu, G->bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    c->dev_free(G->d, G->bytes);
+    delete G;
+    return hip_fail(e, "grid upload");
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  const uint64_t h = c->next_handle++;
+  c->grids[h] = G;
+  *out = h;
+  return XS_OK;
+}
+
+int xs_free_grid(xs_ctx* c, xs_grid_t h) {
+  if (!c) return fail(XS_EINVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  GridRes* G = c->find_grid(h);
+  if (!G) return fail(XS_ENOTFOUND, "unknown grid %llu", (unsigned long long)h);
+  if (G->refs.load() > 0) return fail(XS_EBUSY, "grid %llu is referenced by pending requests",
+                                      (unsigned long long)h);
+  c->grids.erase(h);
+  (void)hipDeviceSynchronize();
+  c->dev_free(G->d, G->bytes);
+  delete G;
+  return XS_OK;
+}
+
+int xs_grid_info(xs_ctx* c, xs_grid_t h, size_t* n) {
+  if (!c || !n) return fail(XS_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(c->mu);
+  GridRes* G = c->find_grid(h);
+  if (!G) return fail(XS_ENOTFOUND, "unknown grid %llu", (unsigned long long)h);
+  *n = G->n;
+  return XS_OK;
+}
+
+int xs_compute(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t npts,
+               const xs_opts* opts, double* sigma_out, int out_on_device, void* stream) {
+  if (!c) return fail(XS_EINVAL, "ctx is NULL");
+  if (!sigma_out) return fail(XS_EINVAL, "sigma_out is NULL");
+  int rc = validate_opts(opts);
+  if (rc) return rc;
+  rc = validate_pts(pts, npts);
+  if (rc) return rc;
+  LinesRes* L;
+  GridRes* G;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    L = c->find_lines(lh);
+    G = c->find_grid(gh);
+  }
+  if (!L) return fail(XS_ENOTFOUND, "unknown line list %llu", (unsigned long long)lh);
+  if (!G) return fail(XS_ENOTFOUND, "unknown grid %llu", (unsigned long long)gh);
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  const Plan p = make_plan(*c, G->n, npts, *opts, L->dev.n);
+  if (c->pts_event_valid && st != c->last_stream) {
+    // scratch buffers are reused: order this call after the previous one
+    e = hipEventSynchronize(c->pts_event);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  }
+  rc = upload_pts(*c, pts, npts, st);
+  if (rc) return rc;
+  const size_t out_bytes = npts * G->n * sizeof(double);
+  double* part = nullptr;
+  if (p.split > 1) {
+    rc = c->scratch(c->part_buf, out_bytes * p.split, "split partials");
+    if (rc) return rc;
+    part = (double*)c->part_buf.ptr;
+  }
+  double* out_dev = sigma_out;
+  if (!out_on_device) {
+    rc = c->scratch(c->out_buf, out_bytes, "output staging");
+    if (rc) return rc;
+    out_dev = (double*)c->out_buf.ptr;
+  }
+  const TileArgs A = make_args(*c, *L, *G, *opts, p, (const double*)c->pts_buf.ptr, (int)npts);
+  rc = enqueue_compute(*c, A, p, opts->precision == XS_FP64, out_dev, part, st);
+  if (rc) return rc;
+  e = hipEventRecord(c->pts_event, st);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  c->pts_event_valid = true;
+  c->last_stream = st;
+  if (!out_on_device) {
+    e = hipMemcpyAsync(sigma_out, out_dev, out_bytes, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "result download");
+  }
+  return XS_OK;
+}
+
+int xs_count_evals(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t npts,
+                   const xs_opts* opts, uint64_t* counts_out) {
+  if (!c || !counts_out) return fail(XS_EINVAL, "NULL argument");
+  int rc = validate_opts(opts);
+  if (rc) return rc;
+  rc = validate_pts(pts, npts);
+  if (rc) return rc;
+  LinesRes* L;
+  GridRes* G;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    L = c->find_lines(lh);
+    G = c->find_grid(gh);
+  }
+  if (!L || !G) return fail(XS_ENOTFOUND, "unknown line list or grid");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t st = nullptr;
+  if (c->pts_event_valid) {
+    e = hipEventSynchronize(c->pts_event);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  }
+  xs_opts o = *opts;
+  o.split = 1;
+  const Plan p = make_plan(*c, G->n, npts, o, L->dev.n);
+  rc = upload_pts(*c, pts, npts, st);
+  if (rc) return rc;
+  rc = c->scratch(c->count_buf, npts * sizeof(uint64_t), "counters");
+  if (rc) return rc;
+  e = hipMemsetAsync(c->count_buf.ptr, 0, npts * sizeof(uint64_t), st);
+  if (e != hipSuccess) return hip_fail(e, "counter clear");
+  TileArgs A = make_args(*c, *L, *G, o, p, (const double*)c->pts_buf.ptr, (int)npts);
+  A.counts = (unsigned long long*)c->count_buf.ptr;
+  e = launch_count(A, p.P, st, p.phys_wg);
+  if (e != hipSuccess) return hip_fail(e, "count kernel launch");
+  e = hipMemcpyAsync(counts_out, c->count_buf.ptr, npts * sizeof(uint64_t),
+                     hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "count download");
+  e = hipEventRecord(c->pts_event, st);
+  c->pts_event_valid = (e == hipSuccess);
+  c->last_stream = st;
+  return XS_OK;
+}
+
+struct xs_graph {
+  xs_ctx* ctx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* pts = nullptr;
+  size_t pts_bytes = 0;
+  void* part = nullptr;
+  size_t part_bytes = 0;
+};
+
+int xs_graph_create(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t npts,
+                    const xs_opts* opts, double* sigma_dev, xs_graph** out) {
+  if (!c || !out || !sigma_dev) return fail(XS_EINVAL, "NULL argument");
+  *out = nullptr;
+  int rc = validate_opts(opts);
+  if (rc) return rc;
+  rc = validate_pts(pts, npts);
+  if (rc) return rc;
+  LinesRes* L;
+  GridRes* G;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    L = c->find_lines(lh);
+    G = c->find_grid(gh);
+  }
+  if (!L || !G) return fail(XS_ENOTFOUND, "unknown line list or grid");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  const Plan p = make_plan(*c, G->n, npts, *opts, L->dev.n);
+  xs_graph* g = new xs_graph();
+  g->ctx = c;
+  g->pts_bytes = npts * 2 * sizeof(double);
+  rc = c->dev_alloc(&g->pts, g->pts_bytes, "graph point table");
+  if (rc) {
+    delete g;
+    return rc;
+  }
+  std::vector<double> h(2 * npts);
+  for (size_t k = 0; k < npts; ++k) {
+    h[2 * k] = pts[k].P_bar;
+    h[2 * k + 1] = pts[k].T_K;
+  }
+  e = hipMemcpy(g->pts, h.data(), g->pts_bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    xs_graph_destroy(g);
+    return hip_fail(e, "graph point table upload");
+  }
+  if (p.split > 1) {
+    g->part_bytes = npts * G->n * sizeof(double) * p.split;
+    rc = c->dev_alloc(&g->part, g->part_bytes, "graph partials");
+    if (rc) {
+      xs_graph_destroy(g);
+      return rc;
+    }
+  }
+  hipStream_t cs = nullptr;
+  e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    xs_graph_destroy(g);
+    return hip_fail(e, "hipStreamCreate");
+  }
+  const TileArgs A = make_args(*c, *L, *G, *opts, p, (const double*)g->pts, (int)npts);
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    rc = enqueue_compute(*c, A, p, opts->precision == XS_FP64, sigma_dev, (double*)g->part, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
+    if (rc == XS_OK && e2 != hipSuccess) rc = hip_fail(e2, "hipStreamEndCapture");
+  } else {
+    rc = hip_fail(e, "hipStreamBeginCapture");
+  }
+  (void)hipStreamDestroy(cs);
+  if (rc == XS_OK) {
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) rc = hip_fail(e, "hipGraphInstantiate");
+  }
+  if (rc) {
+    xs_graph_destroy(g);
+    return rc;
+  }
+  *out = g;
+  return XS_OK;
+}
+
+int xs_graph_launch(xs_graph* g, void* stream) {
+  if (!g || !g->exec) return fail(XS_EINVAL, "graph is NULL");
+  hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return XS_OK;
+}
+
+void xs_graph_destroy(xs_graph* g) {
+  if (!g) return;
+  (void)hipDeviceSynchronize();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->pts) g->ctx->dev_free(g->pts, g->pts_bytes);
+  if (g->part) g->ctx->dev_free(g->part, g->part_bytes);
+  delete g;
+}
+
+int xs_eval_voigt(xs_ctx* c, const double* x, const double* y, size_t n, int precision,
+                  double* K_out) {
+  if (!c || (n && (!x || !y || !K_out))) return fail(XS_EINVAL, "NULL argument");
+  if (precision != XS_FP32_KAHAN && precision != XS_FP64)
+    return fail(XS_EINVAL, "unknown precision %d", precision);
+  if (n == 0) return XS_OK;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  void* buf = nullptr;
+  const size_t b = n * sizeof(double);
+  int rc = c->dev_alloc(&buf, 3 * b, "voigt evaluation buffers");
+  if (rc) return rc;
+  double* dx = (double*)buf;
+  double* dy = dx + n;
+  double* dk = dy + n;
+  e = hipMemcpy(dx, x, b, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dy, y, b, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_eval_voigt(dx, dy, (int64_t)n, precision == XS_FP64, c->wc, dk, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(K_out, dk, b, hipMemcpyDeviceToHost);
+  c->dev_free(buf, 3 * b);
+  if (e != hipSuccess) return hip_fail(e, "voigt evaluation");
+  return XS_OK;
+}
+
+int xs_eval_voigt_host(const double* x, const double* y, size_t n, int precision, double* K_out) {
+  if (n && (!x || !y || !K_out)) return fail(XS_EINVAL, "NULL argument");
+  if (precision != XS_FP32_KAHAN && precision != XS_FP64)
+    return fail(XS_EINVAL, "unknown precision %d", precision);
+  const double* wc = host_weideman();
+  for (size_t i = 0; i < n; ++i)
+    K_out[i] = precision == XS_FP64 ? voigt_k64(x[i], y[i], wc)
+                                    : (double)voigt_k32(x[i], (float)y[i], wc);
+  return XS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,311 @@
+"""ctypes binding of libxsec.so (include/xsec.h). Argument marshalling only: every step of
+the computation runs in the library's HIP kernels. PyTorch is used by callers for device
+memory and streams; this module accepts raw device pointers or torch tensors.
+
+The library is loaded from this package directory; if it is missing, LibraryMissing is
+raised (there is no fallback implementation)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libxsec.so")
+
+XS_OK, XS_EINVAL, XS_ENOMEM, XS_EDEVICE, XS_ENOTFOUND = 0, -1, -2, -3, -4
+XS_EUNSORTED, XS_EBUSY, XS_ECANCELLED, XS_ETIMEOUT = -5, -6, -7, -8
+XS_EINSTEIN_A, XS_REF_STRENGTH = 0, 1
+XS_Q_POWER, XS_Q_TABLE = 0, 1
+XS_CUT_FIXED, XS_CUT_MIN_FWHM = 0, 1
+XS_FP32_KAHAN, XS_FP64 = 0, 1
+
+_STATUS = {0: "XS_OK", -1: "XS_EINVAL", -2: "XS_ENOMEM", -3: "XS_EDEVICE",
+           -4: "XS_ENOTFOUND", -5: "XS_EUNSORTED", -6: "XS_EBUSY", -7: "XS_ECANCELLED",
+           -8: "XS_ETIMEOUT"}
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class XsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class LinesDesc(C.Structure):
+    _fields_ = [("n", C.c_size_t), ("nu0", C.c_void_p), ("A_or_Sref", C.c_void_p),
+                ("E_low", C.c_void_p), ("gamma_ref", C.c_void_p), ("n_T", C.c_void_p),
+                ("g_up", C.c_void_p)]
+
+
+class SpeciesDesc(C.Structure):
+    _fields_ = [("strength_form", C.c_int), ("mass_amu", C.c_double), ("T_ref", C.c_double),
+                ("P_ref", C.c_double), ("q_kind", C.c_int), ("q_a", C.c_double),
+                ("q_b", C.c_double), ("q_T", C.c_void_p), ("q_val", C.c_void_p),
+                ("q_n", C.c_size_t)]
+
+
+class Pt(C.Structure):
+    _fields_ = [("P_bar", C.c_double), ("T_K", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("cutoff_kind", C.c_int), ("cut_cm1", C.c_double), ("fwhm_mult", C.c_double),
+                ("precision", C.c_int), ("pts_per_lane", C.c_int), ("split", C.c_int)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+_SIGS = {
+    "xs_abi_version": ([], C.c_int),
+    "xs_create": ([C.c_int, C.c_size_t, C.POINTER(C.c_void_p)], C.c_int),
+    "xs_destroy": ([C.c_void_p], None),
+    "xs_last_error": ([C.c_void_p], C.c_char_p),
+    "xs_device_info": ([C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_size_t), C.c_char_p,
+                        C.c_size_t], C.c_int),
+    "xs_memory_used": ([C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)], C.c_int),
+    "xs_load_lines": ([C.c_void_p, C.POINTER(LinesDesc), C.POINTER(SpeciesDesc),
+                       C.POINTER(C.c_uint64)], C.c_int),
+    "xs_unload_lines": ([C.c_void_p, C.c_uint64], C.c_int),
+    "xs_lines_info": ([C.c_void_p, C.c_uint64, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)],
+                      C.c_int),
+    "xs_set_grid": ([C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_uint64)], C.c_int),
+    "xs_free_grid": ([C.c_void_p, C.c_uint64], C.c_int),
+    "xs_grid_info": ([C.c_void_p, C.c_uint64, C.POINTER(C.c_size_t)], C.c_int),
+    "xs_compute": ([C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(Pt), C.c_size_t,
+                    C.POINTER(Opts), C.c_void_p, C.c_int, C.c_void_p], C.c_int),
+    "xs_count_evals": ([C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(Pt), C.c_size_t,
+                        C.POINTER(Opts), C.c_void_p], C.c_int),
+    "xs_graph_create": ([C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(Pt), C.c_size_t,
+                         C.POINTER(Opts), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "xs_graph_launch": ([C.c_void_p, C.c_void_p], C.c_int),
+    "xs_graph_destroy": ([C.c_void_p], None),
+    "xs_eval_voigt": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p],
+                      C.c_int),
+    "xs_eval_voigt_host": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p],
+                           C.c_int),
+}
+
+
+def lib():
+    """The loaded library (raises LibraryMissing when it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise LibraryMissing(
+                    f"{LIB_PATH} is missing: build it with `python -m paper_2510_20870_amd.build`")
+            L = C.CDLL(LIB_PATH)
+            for name, (args, res) in _SIGS.items():
+                f = getattr(L, name)
+                f.argtypes = args
+                f.restype = res
+            _lib = L
+        return _lib
+
+
+def exported_symbols() -> Sequence[str]:
+    return tuple(_SIGS)
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def eval_voigt_host(x, y, precision: int = XS_FP32_KAHAN) -> np.ndarray:
+    """K(x, y) as the kernels compute it, evaluated by the same source compiled for the host."""
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    out = np.empty_like(x)
+    rc = lib().xs_eval_voigt_host(_ptr(x), _ptr(y), x.size, precision, _ptr(out))
+    if rc:
+        raise XsError(rc, lib().xs_last_error(None).decode())
+    return out
+
+
+def _dev_ptr(t) -> int:
+    if hasattr(t, "data_ptr"):
+        return int(t.data_ptr())
+    return int(t)
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return int(stream.cuda_stream)
+    return int(stream)
+
+
+class Context:
+    """One xs_ctx on one device. Closes on close()/__exit__/garbage collection."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self._L = lib()
+        h = C.c_void_p()
+        self._check(self._L.xs_create(device, hbm_budget_bytes, C.byref(h)))
+        self.h = h.value
+        self.device = device
+
+    # ------------------------------------------------------------------ plumbing
+    def _check(self, rc: int):
+        if rc != XS_OK:
+            raise XsError(rc, self._L.xs_last_error(None).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.xs_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ queries
+    def device_info(self) -> Dict[str, object]:
+        n_cu = C.c_int()
+        lds = C.c_size_t()
+        arch = C.create_string_buffer(64)
+        self._check(self._L.xs_device_info(self.h, C.byref(n_cu), C.byref(lds), arch, 64))
+        return {"n_cu": n_cu.value, "lds_bytes": lds.value, "arch": arch.value.decode()}
+
+    def memory_used(self):
+        u, b = C.c_size_t(), C.c_size_t()
+        self._check(self._L.xs_memory_used(self.h, C.byref(u), C.byref(b)))
+        return u.value, b.value
+
+    # ------------------------------------------------------------------ residency
+    def load_lines(self, lines: Dict[str, np.ndarray], mass_amu: float,
+                   strength_form: int = XS_EINSTEIN_A, q_a: float = 0.0343, q_b: float = 1.5,
+                   q_table: Optional[Sequence[Sequence[float]]] = None,
+                   T_ref: float = 296.0, P_ref: float = 1.0) -> int:
+        arrs = {
+            "nu0": np.ascontiguousarray(lines["nu0"], np.float64),
+            "A": np.ascontiguousarray(lines["A"], np.float32),
+            "E_low": np.ascontiguousarray(lines["E_low"], np.float32),
+            "gamma": np.ascontiguousarray(lines["gamma"], np.float32),
+            "n_T": np.ascontiguousarray(lines["n_T"], np.float32),
+            "g_up": np.ascontiguousarray(lines["g_up"], np.uint16),
+        }
+        n = len(arrs["nu0"])
+        d = LinesDesc(n, _ptr(arrs["nu0"]), _ptr(arrs["A"]), _ptr(arrs["E_low"]),
+                      _ptr(arrs["gamma"]), _ptr(arrs["n_T"]), _ptr(arrs["g_up"]))
+        if q_table is not None:
+            qT = np.ascontiguousarray(q_table[0], np.float64)
+            qV = np.ascontiguousarray(q_table[1], np.float64)
+            sp = SpeciesDesc(strength_form, mass_amu, T_ref, P_ref, XS_Q_TABLE, 0.0, 0.0,
+                             _ptr(qT), _ptr(qV), len(qT))
+        else:
+            sp = SpeciesDesc(strength_form, mass_amu, T_ref, P_ref, XS_Q_POWER, q_a, q_b,
+                             None, None, 0)
+        h = C.c_uint64()
+        self._check(self._L.xs_load_lines(self.h, C.byref(d), C.byref(sp), C.byref(h)))
+        return h.value
+
+    def unload_lines(self, h: int):
+        self._check(self._L.xs_unload_lines(self.h, h))
+
+    def lines_info(self, h: int):
+        n, b = C.c_size_t(), C.c_size_t()
+        self._check(self._L.xs_lines_info(self.h, h, C.byref(n), C.byref(b)))
+        return n.value, b.value
+
+    def set_grid(self, nu: np.ndarray) -> int:
+        nu = np.ascontiguousarray(nu, np.float64)
+        h = C.c_uint64()
+        self._check(self._L.xs_set_grid(self.h, _ptr(nu), nu.size, C.byref(h)))
+        return h.value
+
+    def free_grid(self, h: int):
+        self._check(self._L.xs_free_grid(self.h, h))
+
+    # ------------------------------------------------------------------ compute
+    @staticmethod
+    def opts(cutoff_kind: int = XS_CUT_FIXED, cut_cm1: float = 25.0, fwhm_mult: float = 100.0,
+             precision: int = XS_FP32_KAHAN, pts_per_lane: int = 0, split: int = 0) -> Opts:
+        return Opts(cutoff_kind, cut_cm1, fwhm_mult, precision, pts_per_lane, split)
+
+    @staticmethod
+    def _pts(pts) -> C.Array:
+        pts = np.asarray(pts, np.float64).reshape(-1, 2)
+        arr = (Pt * len(pts))()
+        for k, (p, t) in enumerate(pts):
+            arr[k] = Pt(float(p), float(t))
+        return arr
+
+    def compute(self, lines: int, grid: int, pts, opts: Opts, out=None, stream=None):
+        """sigma[npts, n_grid]. With `out` a device tensor (or pointer) the work is enqueued
+        on `stream` and `out` is returned; otherwise a host numpy array is returned."""
+        p = self._pts(pts)
+        if out is None:
+            n_grid = self.grid_len(grid)
+            host = np.empty((len(p), n_grid), np.float64)
+            self._check(self._L.xs_compute(self.h, lines, grid, p, len(p), C.byref(opts),
+                                           _ptr(host), 0, None))
+            return host
+        self._check(self._L.xs_compute(self.h, lines, grid, p, len(p), C.byref(opts),
+                                       _dev_ptr(out), 1, _stream_handle(stream)))
+        return out
+
+    def count_evals(self, lines: int, grid: int, pts, opts: Opts) -> np.ndarray:
+        p = self._pts(pts)
+        out = np.zeros(len(p), np.uint64)
+        self._check(self._L.xs_count_evals(self.h, lines, grid, p, len(p), C.byref(opts),
+                                           _ptr(out)))
+        return out
+
+    def grid_len(self, grid: int) -> int:
+        n = C.c_size_t()
+        self._check(self._L.xs_grid_info(self.h, grid, C.byref(n)))
+        return n.value
+
+    def eval_voigt(self, x, y, precision: int = XS_FP32_KAHAN) -> np.ndarray:
+        x = np.ascontiguousarray(x, np.float64)
+        y = np.ascontiguousarray(y, np.float64)
+        out = np.empty_like(x)
+        self._check(self._L.xs_eval_voigt(self.h, _ptr(x), _ptr(y), x.size, precision,
+                                          _ptr(out)))
+        return out
+
+    # ------------------------------------------------------------------ graphs
+    def graph_create(self, lines: int, grid: int, pts, opts: Opts, out) -> "Graph":
+        p = self._pts(pts)
+        g = C.c_void_p()
+        self._check(self._L.xs_graph_create(self.h, lines, grid, p, len(p), C.byref(opts),
+                                            _dev_ptr(out), C.byref(g)))
+        return Graph(self, g.value)
+
+
+class Graph:
+    def __init__(self, ctx: Context, h: int):
+        self.ctx = ctx
+        self.h = h
+
+    def launch(self, stream=None):
+        self.ctx._check(self.ctx._L.xs_graph_launch(self.h, _stream_handle(stream)))
+
+    def close(self):
+        if self.h:
+            self.ctx._L.xs_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,337 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, element by element
+on seeded inputs, plus determinism, edge cases and error paths.
+
+Tolerance (the acceptance rule of the method's target): per spectrum, with m = max(ref),
+|sigma - ref|/ref <= 1e-4 where ref > 1e-8 m, |sigma - ref| <= 1e-8 m elsewhere. The
+FP32 error budget (Voigt approximation <= 1.3e-6, argument rounding, FP32 strength scale,
+Kahan summation) is below 1e-5, so the tests also assert that tighter bound where noted.
+"""
+import numpy as np
+import pytest
+
+from oracle import xsec_oracle as O
+from paper_2510_20870_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2510_20870_amd import xsec
+    c = xsec.Context(0)
+    yield c
+    c.close()
+
+
+def _xsec():
+    from paper_2510_20870_amd import xsec
+    return xsec
+
+
+def _opts(kind="fixed", cut=25.0, mult=100.0, f64=False, P=0, split=0):
+    X = _xsec()
+    return X.Context.opts(X.XS_CUT_FIXED if kind == "fixed" else X.XS_CUT_MIN_FWHM, cut, mult,
+                          X.XS_FP64 if f64 else X.XS_FP32_KAHAN, P, split)
+
+
+def _check(sig, ref, tol=TOL, label=""):
+    st = O.compare(sig, ref, rel_tol=tol)
+    print(f"[parity] {label} max_rel={st['max_rel']:.3e} p99={st['p99_rel']:.3e} "
+          f"n_big={st['n_big']} violations={st['violations']}", flush=True)
+    assert st["violations"] == 0, st
+    return st
+
+
+def test_device_is_gfx950(ctx):
+    info = ctx.device_info()
+    print("[device]", info, flush=True)
+    assert info["arch"].startswith("gfx950")
+    assert info["n_cu"] >= 1
+
+
+def test_voigt_device_error_map(ctx):
+    from scipy.special import wofz
+    X = _xsec()
+    rng = np.random.default_rng(0)
+    n = 300_000
+    x = np.concatenate([10 ** rng.uniform(-3, np.log10(1.1e5), n), rng.uniform(0, 10, n)])
+    y = np.concatenate([10 ** rng.uniform(np.log10(5e-7), np.log10(3.5e4), n),
+                        10 ** rng.uniform(np.log10(5e-7), 1.5, n)])
+    ref = wofz(x + 1j * y).real
+    k32 = ctx.eval_voigt(x, y, X.XS_FP32_KAHAN)
+    k64 = ctx.eval_voigt(x, y, X.XS_FP64)
+    r32 = np.abs(k32 - ref) / ref
+    r64 = np.abs(k64 - ref) / ref
+    print(f"[voigt] fp32 max {r32.max():.3e}  fp64 max {r64.max():.3e}", flush=True)
+    assert r32.max() < 2e-6
+    assert r64.max() < 3e-8
+
+
+def _tiny():
+    W = synth.WORKLOADS["tiny"]
+    return W, synth.make_lines(W.lines), W.grid()
+
+
+@pytest.mark.parametrize("f64", [False, True])
+def test_tiny_full_grid(ctx, f64):
+    W, L, grid = _tiny()
+    P, T = W.pts[0]
+    ref = O.sigma(L, grid, P, T, W.mass_amu, cut_cm1=W.cut_cm1)
+    h = ctx.load_lines(L, W.mass_amu)
+    g = ctx.set_grid(grid)
+    sig = ctx.compute(h, g, [(P, T)], _opts(cut=W.cut_cm1, f64=f64))[0]
+    st = _check(sig, ref, label=f"tiny f64={f64}")
+    assert st["max_rel"] < (1e-7 if f64 else 1e-5)
+    # bitwise repeatable
+    for _ in range(2):
+        again = ctx.compute(h, g, [(P, T)], _opts(cut=W.cut_cm1, f64=f64))[0]
+        assert np.array_equal(again, sig)
+    ctx.unload_lines(h)
+    ctx.free_grid(g)
+
+
+@pytest.mark.parametrize("P,split", [(1, 1), (2, 3), (4, 1), (8, 7), (4, 64)])
+def test_tiny_launch_shapes(ctx, P, split):
+    """Every tile width and line split gives the same answer (to the FP32 budget)."""
+    W, L, grid = _tiny()
+    grid = grid[:7777]            # ragged tail: not a multiple of any tile width
+    ref = O.sigma(L, grid, 0.3, 700.0, W.mass_amu, cut_cm1=W.cut_cm1)
+    h = ctx.load_lines(L, W.mass_amu)
+    g = ctx.set_grid(grid)
+    sig = ctx.compute(h, g, [(0.3, 700.0)], _opts(cut=W.cut_cm1, P=P, split=split))[0]
+    _check(sig, ref, tol=1e-5, label=f"P={P} split={split}")
+    ctx.unload_lines(h)
+    ctx.free_grid(g)
+
+
+def test_tiny_many_pt_and_fwhm_cut(ctx):
+    W, L, grid = _tiny()
+    pts = synth.pt_table(1e-5, 1e2, 4, 300.0, 3000.0, 3)
+    h = ctx.load_lines(L, W.mass_amu)
+    g = ctx.set_grid(grid)
+    sig = ctx.compute(h, g, pts, _opts("min_fwhm", 25.0, 100.0))
+    cnt = ctx.count_evals(h, g, pts, _opts("min_fwhm", 25.0, 100.0))
+    for k, (P, T) in enumerate(pts):
+        ref = O.sigma(L, grid, P, T, W.mass_amu, cut_kind="min_fwhm", cut_cm1=25.0,
+                      fwhm_mult=100.0)
+        _check(sig[k], ref, tol=1e-5, label=f"fwhm P={P:.1e} T={T:.0f}")
+        n_ref = O.count_evals(L, grid, P, T, W.mass_amu, "min_fwhm", 25.0, 100.0)
+        assert int(cnt[k]) == n_ref
+    ctx.unload_lines(h)
+    ctx.free_grid(g)
+
+
+def test_count_evals_fixed(ctx):
+    W, L, grid = _tiny()
+    h = ctx.load_lines(L, W.mass_amu)
+    g = ctx.set_grid(grid)
+    cnt = ctx.count_evals(h, g, [(1.0, 1000.0)], _opts(cut=10.0))
+    assert int(cnt[0]) == O.count_evals(L, grid, 1.0, 1000.0, W.mass_amu, cut_cm1=10.0)
+    ctx.unload_lines(h)
+    ctx.free_grid(g)
+
+
+def _small_list(n, lo, hi, seed):
+    return synth.make_lines(synth.ListSpec(n, lo, hi, seed))
+
+
+def test_reference_form_and_q_table(ctx):
+    X = _xsec()
+    L = _small_list(3000, 2000.0, 2030.0, 5)
+    # a strength column for the reference form
+    L = dict(L)
+    L["A"] = (L["A"].astype(np.float64) * 1e-21).astype(np.float32)
+    grid = synth.uniform_grid(1995.0, 2035.0, 0.005)
+    qT = np.array([100.0, 500.0, 1000.0, 2000.0, 4000.0])
+    qV = 0.0343 * qT ** 1.5 * (1 + 0.1 * np.sin(qT / 700.0))
+    for P, T in ((0.01, 450.0), (3.0, 2500.0)):
+        ref = O.sigma(L, grid, P, T, 28.0, cut_cm1=5.0, strength_form="reference",
+                      table_T=qT, table_Q=qV)
+        h = ctx.load_lines(L, 28.0, strength_form=X.XS_REF_STRENGTH, q_table=(qT, qV))
+        g = ctx.set_grid(grid)
+        sig = ctx.compute(h, g, [(P, T)], _opts(cut=5.0))[0]
+        _check(sig, ref, tol=1e-5, label=f"reference form P={P} T={T}")
+        ctx.unload_lines(h)
+        ctx.free_grid(g)
+
+
+@pytest.mark.parametrize("factor", [1e30, 1e-30])
+def test_extreme_magnitudes(ctx, factor):
+    """sigma is linear in A: results of any absolute size stay inside the FP32 path's range
+    (adaptive power-of-two scale) and match the oracle."""
+    L = dict(_small_list(5000, 1500.0, 1520.0, 4))
+    L["A"] = (L["A"].astype(np.float64) * factor).astype(np.float32)
+    grid = synth.uniform_grid(1499.0, 1521.0, 0.004)
+    ref = O.sigma(L, grid, 0.02, 800.0, 20.0, cut_cm1=3.0)
+    h = ctx.load_lines(L, 20.0)
+    g = ctx.set_grid(grid)
+    sig = ctx.compute(h, g, [(0.02, 800.0)], _opts(cut=3.0))[0]
+    assert np.all(np.isfinite(sig))
+    _check(sig, ref, tol=1e-5, label=f"magnitude x{factor:g}")
+    ctx.unload_lines(h)
+    ctx.free_grid(g)
+
+
+def test_unsorted_and_duplicate_centres(ctx):
+    L = _small_list(4000, 3000.0, 3010.0, 8)
+    L = {k: v.copy() for k, v in L.items()}
+    L["nu0"][100:110] = L["nu0"][100]          # ties
+    rng = np.random.default_rng(1)
+    perm = rng.permutation(len(L["nu0"]))
+    Lp = {k: v[perm] for k, v in L.items()}
+    grid = synth.uniform_grid(2999.0, 3011.0, 0.003)
+    ref = O.sigma(Lp, grid, 0.05, 900.0, 17.0, cut_cm1=2.0)
+    h = ctx.load_lines(Lp, 17.0)
+    g = ctx.set_grid(grid)
+    sig = ctx.compute(h, g, [(0.05, 900.0)], _opts(cut=2.0))[0]
+    _check(sig, ref, tol=1e-5, label="unsorted")
+    ctx.unload_lines(h)
+    ctx.free_grid(g)
+
+
+def test_edge_cases(ctx):
+    X = _xsec()
+    L = _small_list(2000, 1000.0, 1005.0, 3)
+    # empty line list: sigma == 0
+    empty = {k: v[:0] for k, v in L.items()}
+    h0 = ctx.load_lines(empty, 18.0)
+    g = ctx.set_grid(synth.uniform_grid(1000.0, 1001.0, 0.01))
+    assert np.all(ctx.compute(h0, g, [(1.0, 300.0)], _opts(cut=1.0)) == 0.0)
+    ctx.unload_lines(h0)
+    # single grid point; lines entirely outside the grid
+    h = ctx.load_lines(L, 18.0)
+    g1 = ctx.set_grid(np.array([1002.5]))
+    ref = O.sigma(L, np.array([1002.5]), 1.0, 300.0, 18.0, cut_cm1=1.0)
+    s1 = ctx.compute(h, g1, [(1.0, 300.0)], _opts(cut=1.0))[0]
+    _check(s1, ref, tol=1e-5, label="single point")
+    gfar = ctx.set_grid(synth.uniform_grid(2000.0, 2001.0, 0.01))
+    assert np.all(ctx.compute(h, gfar, [(1.0, 300.0)], _opts(cut=25.0)) == 0.0)
+    # a single line: sigma = S V exactly, cut edges inclusive
+    one = {k: v[:1].copy() for k, v in L.items()}
+    one["nu0"][:] = 1000.0
+    h1 = ctx.load_lines(one, 18.0)
+    ge = ctx.set_grid(np.array([np.nextafter(999.5, 0), 999.5, 1000.0, 1000.5,
+                                np.nextafter(1000.5, 2000)]))
+    se = ctx.compute(h1, ge, [(1.0, 1000.0)], _opts(cut=0.5))[0]
+    assert se[0] == 0.0 and se[4] == 0.0 and se[1] > 0 and se[3] > 0
+    refe = O.sigma(one, np.array([999.5, 1000.0, 1000.5]), 1.0, 1000.0, 18.0, cut_cm1=0.5)
+    np.testing.assert_allclose(se[1:4], refe, rtol=1e-5)
+    for hh in (h, h1):
+        ctx.unload_lines(hh)
+    for gg in (g, g1, gfar, ge):
+        ctx.free_grid(gg)
+
+
+def test_error_paths(ctx):
+    X = _xsec()
+    L = _small_list(100, 1000.0, 1001.0, 0)
+    h = ctx.load_lines(L, 18.0)
+    g = ctx.set_grid(np.array([1000.0, 1000.5]))
+    with pytest.raises(X.XsError) as e:
+        ctx.compute(h, g, [(0.0, 300.0)], _opts(cut=1.0))
+    assert e.value.code == X.XS_EINVAL
+    with pytest.raises(X.XsError) as e:
+        ctx.compute(h, g, [(1.0, float("nan"))], _opts(cut=1.0))
+    assert e.value.code == X.XS_EINVAL
+    with pytest.raises(X.XsError) as e:
+        ctx.compute(h, g, [(1.0, 300.0)], _opts(cut=-1.0))
+    assert e.value.code == X.XS_EINVAL
+    with pytest.raises(X.XsError) as e:
+        ctx.compute(h, g, [(1.0, 300.0)], _opts(cut=1.0, P=3))
+    assert e.value.code == X.XS_EINVAL
+    with pytest.raises(X.XsError) as e:
+        ctx.set_grid(np.array([1.0, 1.0, 2.0]))
+    assert e.value.code == X.XS_EUNSORTED
+    with pytest.raises(X.XsError) as e:
+        ctx.compute(h, 987654, [(1.0, 300.0)], _opts(cut=1.0))
+    assert e.value.code == X.XS_ENOTFOUND
+    bad = {k: v.copy() for k, v in L.items()}
+    bad["g_up"][3] = 0
+    with pytest.raises(X.XsError) as e:
+        ctx.load_lines(bad, 18.0)
+    assert e.value.code == X.XS_EINVAL
+    # a budget too small for the list
+    small = X.Context(0, hbm_budget_bytes=1 << 16)
+    big = _small_list(20000, 1000.0, 1010.0, 0)
+    with pytest.raises(X.XsError) as e:
+        small.load_lines(big, 18.0)
+    assert e.value.code == X.XS_ENOMEM
+    small.close()
+    ctx.unload_lines(h)
+    ctx.free_grid(g)
+
+
+def test_graph_replay_matches_compute(ctx):
+    import torch
+    W, L, grid = _tiny()
+    h = ctx.load_lines(L, W.mass_amu)
+    g = ctx.set_grid(grid)
+    pts = [(1.0, 1000.0), (0.01, 500.0)]
+    o = _opts(cut=W.cut_cm1, split=4)
+    eager = ctx.compute(h, g, pts, o)
+    out = torch.zeros((2, len(grid)), dtype=torch.float64, device="cuda")
+    gr = ctx.graph_create(h, g, pts, o, out)
+    for rep in range(3):
+        out.zero_()
+        gr.launch(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager), rep
+        # eager work between replays
+        _ = ctx.compute(h, g, [(5.0, 2000.0)], o)
+    gr.close()
+    ctx.unload_lines(h)
+    ctx.free_grid(g)
+
+
+def test_device_output_on_torch_stream(ctx):
+    import torch
+    W, L, grid = _tiny()
+    h = ctx.load_lines(L, W.mass_amu)
+    g = ctx.set_grid(grid)
+    o = _opts(cut=W.cut_cm1)
+    host = ctx.compute(h, g, [(1.0, 1000.0)], o)
+    s = torch.cuda.Stream()
+    out = torch.empty((1, len(grid)), dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(s):
+        ctx.compute(h, g, [(1.0, 1000.0)], o, out=out, stream=s)
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy(), host)
+    ctx.unload_lines(h)
+    ctx.free_grid(g)
+
+
+def _sample_points(n_grid, n_windows, width, seed):
+    rng = np.random.default_rng(seed)
+    starts = np.sort(rng.choice(n_grid - width, n_windows, replace=False))
+    return np.unique(np.concatenate([np.arange(s, s + width) for s in starts]))
+
+
+@pytest.mark.parametrize("f64", [False, True])
+def test_mid_full_size_sampled(ctx, f64):
+    """1e7 lines, 9.5e5-point grid, one (P, T), launched as the benchmark launches it;
+    the oracle recomputes sampled windows of the output."""
+    import torch
+    W = synth.WORKLOADS["mid"]
+    L = synth.make_lines(W.lines, workers=synth.default_workers())
+    grid = W.grid()
+    P, T = W.pts[0]
+    h = ctx.load_lines(L, W.mass_amu)
+    g = ctx.set_grid(grid)
+    out = torch.empty((1, len(grid)), dtype=torch.float64, device="cuda")
+    ctx.compute(h, g, [(P, T)], _opts(cut=W.cut_cm1, f64=f64), out=out)
+    torch.cuda.synchronize()
+    sig = out.cpu().numpy()[0]
+    idx = _sample_points(len(grid), 6, 96, seed=11)
+    idx = np.concatenate([idx, [0, 1, len(grid) - 2, len(grid) - 1]])
+    ref = O.sigma_parallel(L, grid, workers=synth.default_workers(), chunk=96, points=idx,
+                           P=P, T=T, mass_amu=W.mass_amu, cut_cm1=W.cut_cm1)
+    # max over the full spectrum from the GPU result (a sample has no global max)
+    _check(sig[idx], ref, label=f"mid f64={f64}", )
+    assert np.all(np.isfinite(sig)) and np.all(sig > 0)
+    ctx.unload_lines(h)
+    ctx.free_grid(g)

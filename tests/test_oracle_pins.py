@@ -390,6 +390,14 @@ def test_compare_metric():
     small = ref.copy()
     small[3] += 2e-8
     assert O.compare(small, ref)["violations"] == 1
+    # non-finite results are violations, in either regime
+    for k in (0, 3):
+        nan = ref.copy()
+        nan[k] = np.nan
+        assert O.compare(nan, ref)["violations"] == 1
+        inf = ref.copy()
+        inf[k] = np.inf
+        assert O.compare(inf, ref)["violations"] == 1
 
 
 def test_planted_mistakes_are_caught(monkeypatch):
