@@ -50,6 +50,7 @@ def main():
                     help="grid points in the oracle sample (16 windows)")
     ap.add_argument("--pts-per-lane", type=int, default=0)
     ap.add_argument("--split", type=int, default=0)
+    ap.add_argument("--waves-per-simd", type=int, default=0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -75,8 +76,10 @@ def main():
     h = ctx.load_lines(L, W.mass_amu)
     g = ctx.set_grid(grid)
     kind = xsec.XS_CUT_FIXED if W.cut_kind == "fixed" else xsec.XS_CUT_MIN_FWHM
-    o32 = ctx.opts(kind, W.cut_cm1, W.fwhm_mult, xsec.XS_FP32_KAHAN, args.pts_per_lane, args.split)
-    o64 = ctx.opts(kind, W.cut_cm1, W.fwhm_mult, xsec.XS_FP64, args.pts_per_lane, args.split)
+    o32 = ctx.opts(kind, W.cut_cm1, W.fwhm_mult, xsec.XS_FP32_KAHAN, args.pts_per_lane,
+                   args.split, args.waves_per_simd)
+    o64 = ctx.opts(kind, W.cut_cm1, W.fwhm_mult, xsec.XS_FP64, args.pts_per_lane, args.split,
+                   args.waves_per_simd)
 
     evals = int(ctx.count_evals(h, g, [(P, T)], o32)[0])
     if W.cut_kind == "fixed":

@@ -131,10 +131,12 @@ int xs_grid_info(xs_ctx *ctx, xs_grid_t grid, size_t *n);
 typedef struct { double P_bar, T_K; } xs_pt;
 
 /* Options of a computation. cut_cm1 is the fixed cut (XS_CUT_FIXED) or the cap of
- * min(cap, fwhm_mult * f_V) (XS_CUT_MIN_FWHM). pts_per_lane (0 = autotuned, else 1, 2, 4
- * or 8) sets the grid tile of one wavefront to 64 * pts_per_lane points; split (0 =
- * autotuned, else 1..256) divides each tile's line window into that many independent
- * work items whose partial sums are added in a fixed order. */
+ * min(cap, fwhm_mult * f_V) (XS_CUT_MIN_FWHM). Launch shape (each 0 = autotuned):
+ * pts_per_lane (1, 2, 4 or 8) sets the grid tile of one wavefront to 64 * pts_per_lane
+ * points; split (1..256) divides each tile's line window into that many independent work
+ * items whose partial sums are added in a fixed order; waves_per_simd (2, 3 or 4) is the
+ * occupancy the tile kernel is compiled for. The result does not depend on the launch
+ * shape beyond FP32 rounding (bitwise for a fixed shape). */
 typedef struct {
   int cutoff_kind;
   double cut_cm1;
@@ -142,6 +144,7 @@ typedef struct {
   int precision;
   int pts_per_lane;
   int split;
+  int waves_per_simd;
 } xs_opts;
 
 /* sigma(nu_j; P_k, T_k) for k < npts on every point of `grid`, written to

@@ -23,30 +23,51 @@ struct LinesDev {
   int64_t n;
 };
 
+// Per (line, P-T point) parameters written by the parameter kernel: the cutoff half-width,
+// 1/b_D, the profile scale S/(b_D sqrt(pi)) and y = gamma_L/b_D (all FP64, 32 bytes).
+struct LineRec {
+  double cut, ib, sc, y;
+};
+
+struct ParamArgs {
+  LinesDev L;
+  SpeciesDev sp;
+  CutDev cut;
+  const double* pts;      // [n_pts][2] = (P bar, T K), whole table
+  int pt0, n_pt;          // this batch: points pt0 .. pt0 + n_pt - 1
+  int64_t lo, n;          // line range [lo, lo + n)
+  LineRec* out;           // [n_pt][n]
+};
+
 struct TileArgs {
   LinesDev L;
   SpeciesDev sp;
   CutDev cut;
   const double* grid;
   int64_t n_grid;
-  const double* pts;      // [n_pts][2] = (P bar, T K)
-  int n_pts;
+  const double* pts;      // [n_pts][2], whole table
+  int pt0, n_pt;          // this batch
   int split;
   int64_t n_tiles;
-  int64_t n_items;        // n_tiles * n_pts * split
+  int64_t n_items;        // n_tiles * n_pt * split
   int64_t n_wg;           // logical workgroups (ceil(n_items / 4))
   int64_t per_xcd;        // ceil(n_wg / 8)
-  double* out;            // [n_pts][n_grid], or partials [n_pts][split][n_grid]
+  const LineRec* recs;    // [n_pt][rec_n] records of lines [rec_lo, rec_lo + rec_n)
+  int64_t rec_lo, rec_n;
+  double* out;            // split == 1: sigma rows [n_pts][n_grid] (row pt0 + k);
+                          // else partials [n_pt][split][n_grid] of this batch
   unsigned long long* counts;  // count kernel only: [n_pts]
-  const double* wc;       // Weideman coefficients a_1..a_40
 };
 
 // Launchers (kernels.hip). phys_wg = number of workgroups launched (a multiple of 8).
-hipError_t launch_tile(const TileArgs& A, int P, bool f64, hipStream_t st, int64_t phys_wg);
+hipError_t launch_params(const ParamArgs& A, hipStream_t st);
+hipError_t launch_tile(const TileArgs& A, int P, bool f64, int W, hipStream_t st,
+                       int64_t phys_wg);
 hipError_t launch_count(const TileArgs& A, int P, hipStream_t st, int64_t phys_wg);
 hipError_t launch_reduce(const double* part, double* out, int64_t n_grid, int n_pts, int split,
                          hipStream_t st);
 hipError_t launch_eval_voigt(const double* x, const double* y, int64_t n, int f64,
-                             const double* wc, double* out, hipStream_t st);
+                             double* out, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);
 
 }  // namespace xs

@@ -1,31 +1,40 @@
-// gfx950 kernels of the cross-section sum (paper, "Functionality of pyROX": the Voigt
-// profiles of all lines "are summed into ... cross-sections for each temperature-pressure
-// point").
+// gfx950 kernels of the cross-section sum: the Voigt profiles of all lines are summed into
+// a cross-section for each temperature-pressure point (paper, "Functionality of pyROX",
+// bullets "Compute line-strengths and -widths", "Compute line profiles", "Combine and
+// save").
 //
-// Work decomposition. One work item = (grid tile, (P, T) point, line split). A tile is
-// 64 * P consecutive grid points owned by ONE wavefront: lane l holds points
-// j0 + 64 p + l for p < P, so each of the P rows is 64 consecutive points and the
-// cutoff/core branches diverge only inside the one or two rows a line's core touches.
-// Waves are independent: no workgroup barrier, no atomics on results.
+// Two kernels carry the path:
 //
-// Per item the wave
-//   1. bounds the cutoff of every line that can reach the tile (cut_bound),
-//   2. finds the line window [lo, hi) by a 64-ary search on the sorted centres (one load
-//      per lane per level, five levels for 1e9 lines),
-//   3. walks the window in chunks of 64 lines: each lane loads one line (coalesced
-//      structure-of-arrays loads), derives its FP64 parameters and writes a 32-byte record
-//      to the wave's LDS slice; after a wave-level fence every lane reads the records back
-//      as LDS broadcasts and evaluates all its points against each line,
-//   4. writes its sums: the final value, or a partial for the fixed-order reduction.
+// 1. xs_params_kernel (HBM-bound): for every line in the range a grid can reach and every
+//    (P, T) point of a batch, the FP64 line parameters (cutoff, 1/b_D, S/(b_D sqrt(pi)),
+//    y = gamma_L/b_D) as one 32-byte record. Each line is derived once per (P, T) instead
+//    of once per tile that visits it, and the transcendental FP64 code stays out of the
+//    register budget of the tile kernel.
 //
-// Arithmetic of one (line, point) pair: d = nu_j - nu0 (FP64), the cut test |d| <= cut
-// (FP64), x = d / b_D (FP64, rounded once to FP32), K(x, y) in FP32 outside the core and
-// FP64 inside it, then a Kahan-compensated FP32 add (or a plain FP64 add for the FP64
-// path). FP32 contributions carry a power-of-two scale chosen per wavefront: whenever a
-// staged chunk holds a line stronger than any before, the scale is lowered so the
-// strongest contribution is about 2^97 and the running sums are rescaled exactly (a
-// power-of-two multiply), so any absolute magnitude of sigma stays inside FP32 range; the
-// scale is removed exactly when the FP64 result is stored.
+// 2. xs_tile_kernel (VALU-bound). One work item = (grid tile, (P, T) point, line split).
+//    A tile is 64 * P consecutive grid points owned by ONE wavefront: lane l holds points
+//    j0 + 64 p + l for p < P, so each of the P rows is 64 consecutive points. Waves are
+//    independent: no workgroup barrier and no atomics on results. Per item the wave
+//      a. bounds the cutoff of every line that can reach the tile (cut_bound),
+//      b. finds the line window [lo, hi) by a 64-ary search on the sorted centres (one
+//         load per lane per level, five levels for 1e9 lines),
+//      c. walks the window in chunks of 64 lines: each lane loads one line's centre and
+//         record (coalesced), classifies the line against each row and writes a record to
+//         the wave's LDS slice; after a wave-level fence every lane reads the records back
+//         as LDS broadcasts and evaluates its points against each line,
+//      d. writes its sums: the final value, or a partial for the fixed-order reduction.
+//
+// Arithmetic of one (line, point) pair on the general path: d = nu_j - nu0 (FP64), the cut
+// test |d| <= cut (FP64), x = d / b_D (FP64, rounded once to FP32), K(x, y) in FP32 outside
+// |z| = 8 and FP64 inside, then a Kahan-compensated FP32 add (or a plain FP64 add on the
+// FP64 path). Rows that lie entirely inside the cut and entirely in the far tier of a line
+// (the large majority) skip the FP64 offset and test: x = (nu_j - nu_end) / b_D + x_end from
+// the row's nearer end, in FP32 (relative error a few ulps since x does not change sign
+// along the row). FP32 contributions carry a power-of-two scale chosen per wavefront:
+// whenever a staged chunk holds a line stronger than any before, the scale is lowered so
+// the strongest contribution is about 2^97 and the running sums are rescaled exactly, so
+// any absolute magnitude of sigma stays inside FP32 range; the scale is removed exactly
+// when the FP64 result is stored.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -41,20 +50,55 @@ namespace xs {
 constexpr int kScaleTarget = 96;   // exponent of the strongest FP32 contribution scale
 constexpr int kNoScale = -(1 << 28);
 
-// Record of one staged line in LDS.
-template <bool F64> struct Rec;
-template <> struct alignas(16) Rec<false> {
+// ------------------------------------------------------------------ parameter kernel
+__global__ __launch_bounds__(256) void xs_params_kernel(ParamArgs A) {
+  const int k = blockIdx.y;
+  const PtConst pc = make_pt(A.sp, A.pts[2 * (A.pt0 + k)], A.pts[2 * (A.pt0 + k) + 1]);
+  LineRec* out = A.out + (int64_t)k * A.n;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < A.n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = A.lo + t;
+    const double nu0 = A.L.nu0[i];
+    const LineParams lp = line_params(A.sp, pc, A.cut, nu0, A.L.A[i], A.L.E[i], A.L.gam[i],
+                                      A.L.nT[i], A.L.g[i]);
+    LineRec r;
+    r.cut = lp.cut;
+    r.ib = 1.0 / lp.bD;
+    r.sc = lp.S * r.ib * (1.0 / kSqrtPiD);
+    r.y = lp.gL * r.ib;
+    out[t] = r;
+  }
+}
+
+// ------------------------------------------------------------------ tile kernel
+// Record of one staged line in LDS. cls holds 2 bits per row p of the wave's tile:
+// 0 = no point of the row is inside the cut, 1 = general path, 2 / 3 = every point of the
+// row is inside the cut and in the far tier, the line lying left / right of the row; xr[p]
+// is then x at the row's nearest end (first / last point).
+template <bool F64, int P> struct Rec;
+template <int P> struct alignas(16) Rec<false, P> {
   double nu0, cut, ib;
-  float y, sc;
+  float y, y2, sc, scy;   // scy = sc * y / sqrt(pi): scale of the far-tier kernel
+  float ib32;
+  int cls;
+  float xr[P];
 };
-template <> struct alignas(16) Rec<true> {
-  double nu0, cut, ib, y, sc, pad;
+template <int P> struct alignas(16) Rec<true, P> {
+  double nu0, cut, ib, y, sc;
+  int cls;
+  int pad;
 };
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+  return v;
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; map them so that each XCD (and
@@ -91,10 +135,9 @@ __device__ int64_t wave_search(const double* __restrict__ a, int64_t n, double k
 
 struct ItemInfo {
   int64_t j0;        // first grid index of the tile
-  int pt;            // (P, T) index
+  int k;             // (P, T) index within the batch
   int s;             // split index
-  int64_t b, e;      // line range of this item
-  PtConst pc;
+  int64_t b, e;      // line range of this item (global line indices)
 };
 
 template <int P>
@@ -105,69 +148,119 @@ __device__ __forceinline__ bool decode_item(const TileArgs& A, int lane, ItemInf
   if (wg >= A.n_wg || item >= A.n_items) return false;
   it.s = (int)(item % A.split);
   const int64_t r = item / A.split;
-  it.pt = (int)(r % A.n_pts);
-  const int64_t tile = r / A.n_pts;
+  it.k = (int)(r % A.n_pt);
+  const int64_t tile = r / A.n_pt;
   it.j0 = tile * (int64_t)(kWave * P);
   const int64_t jl = min(it.j0 + (int64_t)(kWave * P), A.n_grid) - 1;
-  const double P_bar = A.pts[2 * it.pt], T_K = A.pts[2 * it.pt + 1];
-  it.pc = make_pt(A.sp, P_bar, T_K);
+  const int pt = A.pt0 + it.k;
+  const PtConst pc = make_pt(A.sp, A.pts[2 * pt], A.pts[2 * pt + 1]);
   const double nu_first = A.grid[it.j0];
   const double nu_last = A.grid[jl];
-  const double cb = cut_bound(A.sp, it.pc, A.cut, nu_last);
+  const double cb = cut_bound(A.sp, pc, A.cut, nu_last);
   // widen the keys by a few ulps of nu so that rounding of nu -+ cb never drops a line
   const double lk = nu_first - cb - fabs(nu_first) * 0x1p-48;
   const double hk = nu_last + cb + fabs(nu_last) * 0x1p-48;
-  const int64_t lo = wave_search<false>(A.L.nu0, A.L.n, lk, lane);
-  const int64_t hi = wave_search<true>(A.L.nu0, A.L.n, hk, lane);
+  // search inside the record range only (the host sized it to cover every tile)
+  const double* base = A.L.nu0 + A.rec_lo;
+  const int64_t lo = A.rec_lo + wave_search<false>(base, A.rec_n, lk, lane);
+  const int64_t hi = A.rec_lo + wave_search<true>(base, A.rec_n, hk, lane);
   const int64_t cnt = hi > lo ? hi - lo : 0;
   it.b = lo + cnt * it.s / A.split;
   it.e = lo + cnt * (it.s + 1) / A.split;
   return true;
 }
 
-// Stages line i: fills the record except the FP32 scale and returns the FP64 profile
-// scale S / (b_D sqrt(pi)) in *sc64.
-template <bool F64>
-__device__ __forceinline__ Rec<F64> stage_line(const TileArgs& A, const PtConst& pc, int64_t i,
-                                               double* sc64) {
+// Row bounds of a wave's tile: row p holds points j0 + 64p + lane; ra/rb are its first and
+// last valid grid values (wave-uniform).
+template <int P>
+struct Rows {
+  double ra[P], rb[P];
+  bool valid[P];
+};
+
+// Stages line i: the record (except the FP32 scales, set once the chunk's scale is known)
+// with the row classes; returns the FP64 profile scale in *sc64.
+template <bool F64, int P>
+__device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, const Rows<P>& rows,
+                                                  int64_t i, double* sc64) {
   const double nu0 = A.L.nu0[i];
-  const LineParams lp = line_params(A.sp, pc, A.cut, nu0, A.L.A[i], A.L.E[i], A.L.gam[i],
-                                    A.L.nT[i], A.L.g[i]);
-  Rec<F64> r;
+  const LineRec lr = A.recs[(int64_t)k * A.rec_n + (i - A.rec_lo)];
+  Rec<F64, P> r;
   r.nu0 = nu0;
-  r.cut = lp.cut;
-  r.ib = 1.0 / lp.bD;
-  *sc64 = lp.S / (lp.bD * kSqrtPiD);
+  r.cut = lr.cut;
+  r.ib = lr.ib;
+  *sc64 = lr.sc;
+  const float y = (float)lr.y;
+  // Classify each row with the same FP64 difference and test the per-point path uses;
+  // the difference is monotone in nu_j, so the row's two ends decide for every point.
+  int cls = 0;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    int c = 0;
+    float xr = 0.0f;
+    if (rows.valid[p]) {
+      const double da = rows.ra[p] - nu0, db = rows.rb[p] - nu0;
+      const bool none = (da > lr.cut) || (db < -lr.cut);
+      const bool all = (fabs(da) <= lr.cut) && (fabs(db) <= lr.cut);
+      if (!none) {
+        c = 1;
+        if (!F64 && all && (da > 0.0 || db < 0.0)) {
+          const float x = (float)((da > 0.0 ? da : db) * lr.ib);
+          if (fmaf(y, y, x * x) >= kFarR2) {
+            c = da > 0.0 ? 2 : 3;
+            xr = x;
+          }
+        }
+      }
+    }
+    cls |= c << (2 * p);
+    if constexpr (!F64) r.xr[p] = xr;
+  }
+  r.cls = cls;
   if constexpr (F64) {
-    r.y = lp.gL / lp.bD;
-    r.sc = *sc64;
-    r.pad = 0.0;
+    r.y = lr.y;
+    r.sc = lr.sc;
+    r.pad = 0;
   } else {
-    r.y = (float)(lp.gL / lp.bD);
+    r.y = y;
+    r.y2 = y * y;
+    r.ib32 = (float)lr.ib;
     r.sc = 0.0f;
+    r.scy = 0.0f;
   }
   return r;
 }
 
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
-  return v;
+__device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
+  const float yk = v - c;
+  const float t = s + yk;
+  c = (t - s) - yk;
+  s = t;
 }
 
-template <int P, bool F64>
-__global__ __launch_bounds__(kBlock) void xs_tile_kernel(TileArgs A) {
-  __shared__ Rec<F64> recs[kWavesPerWG][kWave];
+// W > 0 asks the compiler for at least W waves per SIMD (capping VGPRs at 512/W).
+template <int P, bool F64, int W>
+__global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileArgs A) {
+  __shared__ Rec<F64, P> recs[kWavesPerWG][kWave];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x >> 6;
   ItemInfo it;
   if (!decode_item<P>(A, lane, it)) return;
 
+  Rows<P> rows;
   double nu[P];
+  float da32[P], db32[P];   // offsets of this lane's points from the row ends
 #pragma unroll
   for (int p = 0; p < P; ++p) {
-    const int64_t j = it.j0 + kWave * p + lane;
+    const int64_t ja = it.j0 + kWave * p;
+    rows.valid[p] = ja < A.n_grid;
+    const int64_t jb = min(ja + kWave - 1, A.n_grid - 1);
+    rows.ra[p] = rows.valid[p] ? A.grid[ja] : 0.0;
+    rows.rb[p] = rows.valid[p] ? A.grid[jb] : 0.0;
+    const int64_t j = ja + lane;
     nu[p] = (j < A.n_grid) ? A.grid[j] : __builtin_nan("");
+    da32[p] = (float)(nu[p] - rows.ra[p]);
+    db32[p] = (float)(nu[p] - rows.rb[p]);
   }
   using acc_t = typename std::conditional<F64, double, float>::type;
   acc_t s[P], c[P];
@@ -177,12 +270,12 @@ __global__ __launch_bounds__(kBlock) void xs_tile_kernel(TileArgs A) {
 
   for (int64_t base = it.b; base < it.e; base += kWave) {
     const int64_t i = base + lane;
-    Rec<F64> r;
+    Rec<F64, P> r;
     double sc64 = 0.0;
     if (i < it.e) {
-      r = stage_line<F64>(A, it.pc, i, &sc64);
+      r = stage_line<F64, P>(A, it.k, rows, i, &sc64);
     } else {
-      r.nu0 = 0.0; r.cut = -1.0; r.ib = 0.0; r.y = 0; r.sc = 0;
+      r.cls = 0;
     }
     if constexpr (!F64) {
       const int ex = wave_max(sc64 > 0.0 ? ilogb(sc64) : kNoScale);
@@ -196,35 +289,66 @@ __global__ __launch_bounds__(kBlock) void xs_tile_kernel(TileArgs A) {
         }
         e_ref = ex;
       }
-      r.sc = (float)ldexp(sc64, kScaleTarget - e_ref);
+      const double scd = ldexp(sc64, kScaleTarget - e_ref);
+      r.sc = (float)scd;
+      r.scy = (float)(scd * (double)r.y * (double)kInvSqrtPi);
     }
     recs[wv][lane] = r;
     wave_sync();
     const int nk = (int)min((int64_t)kWave, it.e - base);
-    for (int k = 0; k < nk; ++k) {
-      const Rec<F64> q = recs[wv][k];
+    for (int kk = 0; kk < nk; ++kk) {
+      const Rec<F64, P>& q = recs[wv][kk];
+      const int cls = __builtin_amdgcn_readfirstlane(q.cls);
+      if (cls == 0) continue;
+      if constexpr (!F64) {
+        // Common case: the line lies left (or right) of the whole tile and every row is
+        // inside the cut and in the far tier. One branch-free block for all rows lets
+        // the P independent dependency chains interleave.
+        constexpr int kAllLeft = (int)(0xAAAAAAAAu & ((1u << (2 * P)) - 1u));
+        constexpr int kAllRight = (int)(0xFFFFFFFFu & ((1u << (2 * P)) - 1u));
+        if (cls == kAllLeft || cls == kAllRight) {
+          const bool left = (cls == kAllLeft);
+          float v[P];
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            const float x = fmaf(left ? da32[p] : db32[p], q.ib32, q.xr[p]);
+            const float x2 = x * x;
+            v[p] = q.scy * voigt_far32_scaled(x2, x2 + q.y2);
+          }
+#pragma unroll
+          for (int p = 0; p < P; ++p) kahan_add(s[p], c[p], v[p]);
+          continue;
+        }
+      }
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        const double d = nu[p] - q.nu0;
-        if (fabs(d) <= q.cut) {
-          const double xd = d * q.ib;
-          if constexpr (F64) {
-            s[p] += q.sc * voigt_k64(xd, q.y, A.wc);
+        const int cp = (cls >> (2 * p)) & 3;
+        if (cp == 0) continue;
+        if constexpr (F64) {
+          const double d = nu[p] - q.nu0;
+          if (fabs(d) <= q.cut) s[p] += q.sc * voigt_k64(d * q.ib, q.y);
+        } else {
+          float v;
+          if (cp == 1) {
+            // general: FP64 offset and cut test, tier chosen per point
+            const double d = nu[p] - q.nu0;
+            if (!(fabs(d) <= q.cut)) continue;
+            v = q.sc * voigt_k32(d * q.ib, q.y);
           } else {
-            const float v = q.sc * voigt_k32(xd, q.y, A.wc);
-            const float yk = v - c[p];
-            const float t = s[p] + yk;
-            c[p] = (t - s[p]) - yk;
-            s[p] = t;
+            // whole row inside the cut and in the far tier
+            const float x = fmaf(cp == 2 ? da32[p] : db32[p], q.ib32, q.xr[p]);
+            const float x2 = x * x;
+            v = q.scy * voigt_far32_scaled(x2, x2 + q.y2);
           }
+          kahan_add(s[p], c[p], v);
         }
       }
     }
     wave_sync();
   }
 
-  double* out = A.out;
-  const int64_t row = (A.split == 1) ? (int64_t)it.pt : ((int64_t)it.pt * A.split + it.s);
+  const int64_t row = (A.split == 1) ? (int64_t)(A.pt0 + it.k)
+                                     : ((int64_t)it.k * A.split + it.s);
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const int64_t j = it.j0 + kWave * p + lane;
@@ -232,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void xs_tile_kernel(TileArgs A) {
       double v;
       if constexpr (F64) v = s[p];
       else v = ldexp((double)s[p] - (double)c[p], e_ref - kScaleTarget);
-      out[row * A.n_grid + j] = v;
+      A.out[row * A.n_grid + j] = v;
     }
   }
 }
@@ -273,15 +397,14 @@ __global__ __launch_bounds__(kBlock) void xs_count_kernel(TileArgs A) {
     double c0 = 0.0, ct = -1.0;
     if (i < it.e) {
       c0 = A.L.nu0[i];
-      ct = line_params(A.sp, it.pc, A.cut, c0, A.L.A[i], A.L.E[i], A.L.gam[i], A.L.nT[i],
-                       A.L.g[i]).cut;
+      ct = A.recs[(int64_t)it.k * A.rec_n + (i - A.rec_lo)].cut;
     }
     cen[wv][lane] = c0;
     cut[wv][lane] = ct;
     wave_sync();
     const int nk = (int)min((int64_t)kWave, it.e - base);
-    for (int k = 0; k < nk; ++k) {
-      const double q0 = cen[wv][k], qc = cut[wv][k];
+    for (int kk = 0; kk < nk; ++kk) {
+      const double q0 = cen[wv][kk], qc = cut[wv][kk];
 #pragma unroll
       for (int p = 0; p < P; ++p) cnt += (fabs(nu[p] - q0) <= qc) ? 1ull : 0ull;
     }
@@ -289,38 +412,53 @@ __global__ __launch_bounds__(kBlock) void xs_count_kernel(TileArgs A) {
   }
   // wave reduction, then one 64-bit integer atomic per wave (exact, order-free)
   for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
-  if (lane == 0) atomicAdd(A.counts + it.pt, cnt);
+  if (lane == 0) atomicAdd(A.counts + A.pt0 + it.k, cnt);
+}
+
+__global__ void xs_fill_u64_kernel(unsigned long long* p, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = 0ull;
 }
 
 __global__ void xs_eval_voigt_kernel(const double* __restrict__ x, const double* __restrict__ y,
-                                     int64_t n, int f64, const double* __restrict__ wc,
-                                     double* __restrict__ out) {
+                                     int64_t n, int f64, double* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  out[t] = f64 ? voigt_k64(x[t], y[t], wc) : (double)voigt_k32(x[t], (float)y[t], wc);
+  out[t] = f64 ? voigt_k64(x[t], y[t]) : (double)voigt_k32(x[t], (float)y[t]);
 }
 
-}  // namespace xs
-
 // --------------------------------------------------------------------------- launchers
-namespace xs {
+hipError_t launch_params(const ParamArgs& A, hipStream_t st) {
+  if (A.n <= 0 || A.n_pt <= 0) return hipSuccess;
+  int64_t blocks = (A.n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(xs_params_kernel, dim3((unsigned)blocks, (unsigned)A.n_pt), dim3(256), 0,
+                     st, A);
+  return hipGetLastError();
+}
 
-hipError_t launch_tile(const TileArgs& A, int P, bool f64, hipStream_t st, int64_t phys_wg) {
-  const dim3 grid((unsigned)phys_wg), block(kBlock);
-#define XS_TILE_CASE(PP)                                                             \
-  case PP:                                                                           \
-    if (f64) hipLaunchKernelGGL((xs_tile_kernel<PP, true>), grid, block, 0, st, A);  \
-    else hipLaunchKernelGGL((xs_tile_kernel<PP, false>), grid, block, 0, st, A);     \
-    break;
-  switch (P) {
-    XS_TILE_CASE(1)
-    XS_TILE_CASE(2)
-    XS_TILE_CASE(4)
-    XS_TILE_CASE(8)
+template <int P, bool F64>
+static hipError_t launch_tile_w(const TileArgs& A, int W, hipStream_t st, dim3 grid) {
+  const dim3 block(kBlock);
+  switch (W) {
+    case 0: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 0>), grid, block, 0, st, A); break;
+    case 3: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 3>), grid, block, 0, st, A); break;
+    case 4: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 4>), grid, block, 0, st, A); break;
     default: return hipErrorInvalidValue;
   }
-#undef XS_TILE_CASE
   return hipGetLastError();
+}
+
+hipError_t launch_tile(const TileArgs& A, int P, bool f64, int W, hipStream_t st,
+                       int64_t phys_wg) {
+  const dim3 grid((unsigned)phys_wg);
+  switch (P) {
+    case 1: return f64 ? launch_tile_w<1, true>(A, W, st, grid) : launch_tile_w<1, false>(A, W, st, grid);
+    case 2: return f64 ? launch_tile_w<2, true>(A, W, st, grid) : launch_tile_w<2, false>(A, W, st, grid);
+    case 4: return f64 ? launch_tile_w<4, true>(A, W, st, grid) : launch_tile_w<4, false>(A, W, st, grid);
+    case 8: return f64 ? launch_tile_w<8, true>(A, W, st, grid) : launch_tile_w<8, false>(A, W, st, grid);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_count(const TileArgs& A, int P, hipStream_t st, int64_t phys_wg) {
@@ -346,12 +484,19 @@ hipError_t launch_reduce(const double* part, double* out, int64_t n_grid, int n_
   return hipGetLastError();
 }
 
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(xs_fill_u64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     p, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_eval_voigt(const double* x, const double* y, int64_t n, int f64,
-                             const double* wc, double* out, hipStream_t st) {
+                             double* out, hipStream_t st) {
   const int64_t blocks = (n + 255) / 256;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(xs_eval_voigt_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, y, n,
-                     f64, wc, out);
+                     f64, out);
   return hipGetLastError();
 }
 

@@ -37,31 +37,6 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(XS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Weideman (1994) coefficients a_1..a_N of the rational series for w(z):
-// a_n = (1/2M) sum_{k=-M+1}^{M-1} f(t_k) exp(-i pi n k / M), with M = 2N,
-// t_k = L tan(k pi / 2M), f(t) = exp(-t^2)(L^2 + t^2); f is even in k, so the sum is real.
-void weideman_coefficients(int N, double* a) {
-  const int M = 2 * N;
-  const double L = sqrt(N / sqrt(2.0));
-  std::vector<double> f(M);
-  for (int k = 0; k < M; ++k) {
-    const double t = L * tan(k * M_PI / (2.0 * M));
-    f[k] = exp(-t * t) * (L * L + t * t);
-  }
-  for (int n = 1; n <= N; ++n) {
-    double acc = f[0];
-    for (int k = 1; k < M; ++k) acc += 2.0 * f[k] * cos(M_PI * (double)n * k / M);
-    a[n - 1] = acc / (2.0 * M);
-  }
-}
-
-const double* host_weideman() {
-  static double a[kWeidN];
-  static std::once_flag once;
-  std::call_once(once, [] { weideman_coefficients(kWeidN, a); });
-  return a;
-}
-
 }  // namespace xs
 
 using xs::fail;
@@ -137,6 +112,9 @@ int validate_opts(const xs_opts* o) {
     return fail(XS_EINVAL, "pts_per_lane must be 0, 1, 2, 4 or 8 (got %d)", P);
   if (o->split < 0 || o->split > kMaxSplit)
     return fail(XS_EINVAL, "split must be in [0, %d] (got %d)", kMaxSplit, o->split);
+  if (o->waves_per_simd != 0 && o->waves_per_simd != 2 && o->waves_per_simd != 3 &&
+      o->waves_per_simd != 4)
+    return fail(XS_EINVAL, "waves_per_simd must be 0, 2, 3 or 4 (got %d)", o->waves_per_simd);
   return XS_OK;
 }
 
@@ -153,62 +131,114 @@ int validate_pts(const xs_pt* pts, size_t npts) {
   return XS_OK;
 }
 
-Plan make_plan(const Ctx& c, size_t n_grid, size_t npts, const xs_opts& o, int64_t n_lines) {
+// Lines that can reach the grid: nu0 within the largest possible cut of its ends. The
+// host index holds every kSampleStride-th centre, so the range is found to within a block
+// and errs on the inclusive side.
+static void line_range(const LinesRes& L, const GridRes& G, const xs_opts& o, int64_t* lo,
+                       int64_t* hi) {
+  const int64_t n = (int64_t)L.n;
+  const double reach = o.cut_cm1 * (1.0 + 1e-9);
+  const double klo = G.first - reach - fabs(G.first) * 1e-12;
+  const double khi = G.last + reach + fabs(G.last) * 1e-12;
+  const std::vector<double>& sm = L.sample;
+  // largest sample index k with sm[k] < klo: lines before k * stride are all < klo
+  int64_t k0 = (int64_t)(std::lower_bound(sm.begin(), sm.end(), klo) - sm.begin()) - 1;
+  int64_t k1 = (int64_t)(std::upper_bound(sm.begin(), sm.end(), khi) - sm.begin());
+  *lo = k0 < 0 ? 0 : std::min(n, k0 * kSampleStride);
+  *hi = k1 >= (int64_t)sm.size() ? n : std::min(n, k1 * kSampleStride);
+  if (*hi < *lo) *hi = *lo;
+}
+
+Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const xs_opts& o) {
   Plan p;
   p.P = o.pts_per_lane ? o.pts_per_lane : 4;
+  p.W = o.waves_per_simd == 2 ? 0 : o.waves_per_simd;
   const int64_t tile = (int64_t)kWave * p.P;
-  p.n_tiles = ((int64_t)n_grid + tile - 1) / tile;
-  const int64_t base = p.n_tiles * (int64_t)npts;
+  p.n_tiles = ((int64_t)G.n + tile - 1) / tile;
+  p.npts = (int)npts;
+  int64_t hi = 0;
+  line_range(L, G, o, &p.rec_lo, &hi);
+  p.rec_n = hi - p.rec_lo;
   if (o.split) {
     p.split = o.split;
   } else {
     // enough wavefronts to give every SIMD (4 per CU) four of them
+    const int64_t base = p.n_tiles * (int64_t)npts;
     const int64_t target = (int64_t)c.n_cu * 16;
-    int64_t s = (target + base - 1) / base;
-    s = std::max<int64_t>(1, std::min<int64_t>(s, 64));
-    // no point in splits much shorter than one 64-line chunk
-    const int64_t cap = std::max<int64_t>(1, n_lines / 64);
-    p.split = (int)std::min<int64_t>(s, cap);
+    int64_t sp = (target + base - 1) / base;
+    sp = std::max<int64_t>(1, std::min<int64_t>(sp, 64));
+    // no point in splits much shorter than one 64-line chunk per tile window
+    const int64_t per_tile = std::max<int64_t>(1, p.rec_n / std::max<int64_t>(1, p.n_tiles));
+    sp = std::min<int64_t>(sp, std::max<int64_t>(1, per_tile / 64));
+    p.split = (int)sp;
   }
-  p.n_items = base * p.split;
-  p.n_wg = (p.n_items + kWavesPerWG - 1) / kWavesPerWG;
-  p.per_xcd = (p.n_wg + 7) / 8;
-  p.phys_wg = p.per_xcd * 8;
+  // (P, T) points per batch: the records of a batch (32 B per line and point) and its
+  // partials stay under a quarter of the free budget and 16 GiB
+  const size_t used = c.used.load();
+  const size_t free_b = c.budget > used ? c.budget - used : 0;
+  const size_t cap = std::min<size_t>((size_t)16 << 30, free_b / 4);
+  const size_t per_pt = std::max<size_t>(
+      1, (size_t)p.rec_n * 32 + (p.split > 1 ? (size_t)p.split * G.n * 8 : 0));
+  p.pt_batch = (int)std::max<size_t>(1, std::min<size_t>(npts, cap / per_pt));
   return p;
 }
 
-TileArgs make_args(const Ctx& c, const LinesRes& L, const GridRes& G, const xs_opts& o,
-                   const Plan& p, const double* pts_dev, int npts) {
-  TileArgs A;
-  memset(&A, 0, sizeof A);
-  A.L = L.dev;
-  A.sp = L.sp;
-  A.cut.kind = o.cutoff_kind == XS_CUT_FIXED ? kCutFixed : kCutMinFwhm;
-  A.cut.cut = o.cut_cm1;
-  A.cut.mult = o.fwhm_mult;
-  A.grid = G.d;
-  A.n_grid = (int64_t)G.n;
-  A.pts = pts_dev;
-  A.n_pts = npts;
-  A.split = p.split;
-  A.n_tiles = p.n_tiles;
-  A.n_items = p.n_items;
-  A.n_wg = p.n_wg;
-  A.per_xcd = p.per_xcd;
-  A.wc = c.wc;
-  return A;
-}
-
-// Enqueue the tile kernel (and the reduction when split > 1) writing sigma to out_dev.
-int enqueue_compute(Ctx& c, const TileArgs& A0, const Plan& p, bool f64, double* out_dev,
-                    double* part_dev, hipStream_t st) {
-  TileArgs A = A0;
-  A.out = (p.split == 1) ? out_dev : part_dev;
-  hipError_t e = launch_tile(A, p.P, f64, st, p.phys_wg);
-  if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
-  if (p.split > 1) {
-    e = launch_reduce(part_dev, out_dev, A.n_grid, A.n_pts, p.split, st);
-    if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
+int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Plan& p,
+                 const double* pts_dev, double* out_dev, void* rec_dev, void* part_dev,
+                 hipStream_t st, unsigned long long* counts) {
+  const bool f64 = o.precision == XS_FP64;
+  CutDev cut;
+  cut.kind = o.cutoff_kind == XS_CUT_FIXED ? kCutFixed : kCutMinFwhm;
+  cut.cut = o.cut_cm1;
+  cut.mult = o.fwhm_mult;
+  for (int pt0 = 0; pt0 < p.npts; pt0 += p.pt_batch) {
+    const int nb = std::min(p.pt_batch, p.npts - pt0);
+    ParamArgs PA;
+    memset(&PA, 0, sizeof PA);
+    PA.L = L.dev;
+    PA.sp = L.sp;
+    PA.cut = cut;
+    PA.pts = pts_dev;
+    PA.pt0 = pt0;
+    PA.n_pt = nb;
+    PA.lo = p.rec_lo;
+    PA.n = p.rec_n;
+    PA.out = (LineRec*)rec_dev;
+    hipError_t e = launch_params(PA, st);
+    if (e != hipSuccess) return hip_fail(e, "parameter kernel launch");
+    TileArgs A;
+    memset(&A, 0, sizeof A);
+    A.L = L.dev;
+    A.sp = L.sp;
+    A.cut = cut;
+    A.grid = G.d;
+    A.n_grid = (int64_t)G.n;
+    A.pts = pts_dev;
+    A.pt0 = pt0;
+    A.n_pt = nb;
+    A.split = counts ? 1 : p.split;
+    A.n_tiles = p.n_tiles;
+    A.n_items = p.n_tiles * nb * A.split;
+    A.n_wg = (A.n_items + kWavesPerWG - 1) / kWavesPerWG;
+    A.per_xcd = (A.n_wg + 7) / 8;
+    A.recs = (const LineRec*)rec_dev;
+    A.rec_lo = p.rec_lo;
+    A.rec_n = p.rec_n;
+    const int64_t phys = A.per_xcd * 8;
+    if (counts) {
+      A.counts = counts;
+      e = launch_count(A, p.P, st, phys);
+      if (e != hipSuccess) return hip_fail(e, "count kernel launch");
+      continue;
+    }
+    A.out = (A.split == 1) ? out_dev : (double*)part_dev;
+    e = launch_tile(A, p.P, f64, p.W, st, phys);
+    if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
+    if (A.split > 1) {
+      e = launch_reduce((const double*)part_dev, out_dev + (int64_t)pt0 * A.n_grid, A.n_grid,
+                        nb, A.split, st);
+      if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
+    }
   }
   return XS_OK;
 }
@@ -274,18 +304,6 @@ int xs_create(int device, size_t hbm_budget_bytes, xs_ctx** out) {
   c->n_cu = prop.multiProcessorCount;
   c->lds = prop.sharedMemPerBlock;
   c->arch = prop.gcnArchName;
-  void* wc = nullptr;
-  int rc = c->dev_alloc(&wc, kWeidN * sizeof(double), "Weideman coefficients");
-  if (rc) {
-    delete c;
-    return rc;
-  }
-  c->wc = (double*)wc;
-  e = hipMemcpy(c->wc, host_weideman(), kWeidN * sizeof(double), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    xs_destroy(c);
-    return hip_fail(e, "coefficient upload");
-  }
   e = hipEventCreateWithFlags(&c->pts_event, hipEventDisableTiming);
   if (e != hipSuccess) {
     xs_destroy(c);
@@ -305,8 +323,7 @@ void xs_destroy(xs_ctx* c) {
     c->dev_free(kv.second->d, kv.second->bytes);
     delete kv.second;
   }
-  c->dev_free(c->wc, kWeidN * sizeof(double));
-  for (Scratch* s : {&c->pts_buf, &c->part_buf, &c->out_buf, &c->count_buf})
+  for (Scratch* s : {&c->pts_buf, &c->part_buf, &c->out_buf, &c->count_buf, &c->rec_buf})
     if (s->ptr) c->dev_free(s->ptr, s->cap);
   if (c->pts_pinned) (void)hipHostFree(c->pts_pinned);
   if (c->pts_event) (void)hipEventDestroy(c->pts_event);
@@ -448,6 +465,9 @@ int xs_load_lines(xs_ctx* c, const xs_lines_desc* d, const xs_species_desc* sp, 
   L->sp.gam_max = gmax;
   L->sp.n_min = nmin;
   L->sp.n_max = nmax;
+  // host index: every kSampleStride-th centre of the sorted list
+  for (size_t i = 0; i < n; i += (size_t)kSampleStride)
+    L->sample.push_back(sorted ? d->nu0[i] : d->nu0[order[i]]);
   // host copy of the species for host-side Q evaluation (tables on the host)
   L->q_T_host.assign(sp->q_T ? sp->q_T : nullptr, sp->q_T ? sp->q_T + qn : nullptr);
   L->q_val_host.assign(sp->q_val ? sp->q_val : nullptr, sp->q_val ? sp->q_val + qn : nullptr);
@@ -494,6 +514,8 @@ int xs_set_grid(xs_ctx* c, const double* nu, size_t n, xs_grid_t* out) {
   GridRes* G = new GridRes();
   G->n = n;
   G->bytes = n * sizeof(double);
+  G->first = nu[0];
+  G->last = nu[n - 1];
   int rc = c->dev_alloc((void**)&G->d, G->bytes, "grid");
   if (rc) {
     delete G;
@@ -555,20 +577,22 @@ int xs_compute(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t 
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
-  const Plan p = make_plan(*c, G->n, npts, *opts, L->dev.n);
   if (c->pts_event_valid && st != c->last_stream) {
     // scratch buffers are reused: order this call after the previous one
     e = hipEventSynchronize(c->pts_event);
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
   }
+  const Plan p = make_plan(*c, *L, *G, npts, *opts);
   rc = upload_pts(*c, pts, npts, st);
   if (rc) return rc;
   const size_t out_bytes = npts * G->n * sizeof(double);
-  double* part = nullptr;
+  rc = c->scratch(c->rec_buf, p.rec_bytes(), "line records");
+  if (rc) return rc;
+  void* part = nullptr;
   if (p.split > 1) {
-    rc = c->scratch(c->part_buf, out_bytes * p.split, "split partials");
+    rc = c->scratch(c->part_buf, p.part_bytes(G->n), "split partials");
     if (rc) return rc;
-    part = (double*)c->part_buf.ptr;
+    part = c->part_buf.ptr;
   }
   double* out_dev = sigma_out;
   if (!out_on_device) {
@@ -576,8 +600,8 @@ int xs_compute(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t 
     if (rc) return rc;
     out_dev = (double*)c->out_buf.ptr;
   }
-  const TileArgs A = make_args(*c, *L, *G, *opts, p, (const double*)c->pts_buf.ptr, (int)npts);
-  rc = enqueue_compute(*c, A, p, opts->precision == XS_FP64, out_dev, part, st);
+  rc = enqueue_path(*L, *G, *opts, p, (const double*)c->pts_buf.ptr, out_dev, c->rec_buf.ptr,
+                    part, st);
   if (rc) return rc;
   e = hipEventRecord(c->pts_event, st);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -615,17 +639,18 @@ int xs_count_evals(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, siz
   }
   xs_opts o = *opts;
   o.split = 1;
-  const Plan p = make_plan(*c, G->n, npts, o, L->dev.n);
+  const Plan p = make_plan(*c, *L, *G, npts, o);
   rc = upload_pts(*c, pts, npts, st);
   if (rc) return rc;
   rc = c->scratch(c->count_buf, npts * sizeof(uint64_t), "counters");
   if (rc) return rc;
-  e = hipMemsetAsync(c->count_buf.ptr, 0, npts * sizeof(uint64_t), st);
+  rc = c->scratch(c->rec_buf, p.rec_bytes(), "line records");
+  if (rc) return rc;
+  e = launch_fill_u64((unsigned long long*)c->count_buf.ptr, (int64_t)npts, st);
   if (e != hipSuccess) return hip_fail(e, "counter clear");
-  TileArgs A = make_args(*c, *L, *G, o, p, (const double*)c->pts_buf.ptr, (int)npts);
-  A.counts = (unsigned long long*)c->count_buf.ptr;
-  e = launch_count(A, p.P, st, p.phys_wg);
-  if (e != hipSuccess) return hip_fail(e, "count kernel launch");
+  rc = enqueue_path(*L, *G, o, p, (const double*)c->pts_buf.ptr, nullptr, c->rec_buf.ptr,
+                    nullptr, st, (unsigned long long*)c->count_buf.ptr);
+  if (rc) return rc;
   e = hipMemcpyAsync(counts_out, c->count_buf.ptr, npts * sizeof(uint64_t),
                      hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -644,6 +669,8 @@ struct xs_graph {
   size_t pts_bytes = 0;
   void* part = nullptr;
   size_t part_bytes = 0;
+  void* rec = nullptr;
+  size_t rec_bytes = 0;
 };
 
 int xs_graph_create(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t npts,
@@ -664,7 +691,7 @@ int xs_graph_create(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, si
   if (!L || !G) return fail(XS_ENOTFOUND, "unknown line list or grid");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  const Plan p = make_plan(*c, G->n, npts, *opts, L->dev.n);
+  const Plan p = make_plan(*c, *L, *G, npts, *opts);
   xs_graph* g = new xs_graph();
   g->ctx = c;
   g->pts_bytes = npts * 2 * sizeof(double);
@@ -684,12 +711,18 @@ int xs_graph_create(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, si
     return hip_fail(e, "graph point table upload");
   }
   if (p.split > 1) {
-    g->part_bytes = npts * G->n * sizeof(double) * p.split;
+    g->part_bytes = p.part_bytes(G->n);
     rc = c->dev_alloc(&g->part, g->part_bytes, "graph partials");
     if (rc) {
       xs_graph_destroy(g);
       return rc;
     }
+  }
+  g->rec_bytes = p.rec_bytes();
+  rc = c->dev_alloc(&g->rec, g->rec_bytes, "graph line records");
+  if (rc) {
+    xs_graph_destroy(g);
+    return rc;
   }
   hipStream_t cs = nullptr;
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -697,10 +730,9 @@ int xs_graph_create(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, si
     xs_graph_destroy(g);
     return hip_fail(e, "hipStreamCreate");
   }
-  const TileArgs A = make_args(*c, *L, *G, *opts, p, (const double*)g->pts, (int)npts);
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    rc = enqueue_compute(*c, A, p, opts->precision == XS_FP64, sigma_dev, (double*)g->part, cs);
+    rc = enqueue_path(*L, *G, *opts, p, (const double*)g->pts, sigma_dev, g->rec, g->part, cs);
     hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
     if (rc == XS_OK && e2 != hipSuccess) rc = hip_fail(e2, "hipStreamEndCapture");
   } else {
@@ -733,6 +765,7 @@ void xs_graph_destroy(xs_graph* g) {
   if (g->graph) (void)hipGraphDestroy(g->graph);
   if (g->pts) g->ctx->dev_free(g->pts, g->pts_bytes);
   if (g->part) g->ctx->dev_free(g->part, g->part_bytes);
+  if (g->rec) g->ctx->dev_free(g->rec, g->rec_bytes);
   delete g;
 }
 
@@ -753,7 +786,7 @@ int xs_eval_voigt(xs_ctx* c, const double* x, const double* y, size_t n, int pre
   double* dk = dy + n;
   e = hipMemcpy(dx, x, b, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(dy, y, b, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = launch_eval_voigt(dx, dy, (int64_t)n, precision == XS_FP64, c->wc, dk, nullptr);
+  if (e == hipSuccess) e = launch_eval_voigt(dx, dy, (int64_t)n, precision == XS_FP64, dk, nullptr);
   if (e == hipSuccess) e = hipMemcpy(K_out, dk, b, hipMemcpyDeviceToHost);
   c->dev_free(buf, 3 * b);
   if (e != hipSuccess) return hip_fail(e, "voigt evaluation");
@@ -764,10 +797,9 @@ int xs_eval_voigt_host(const double* x, const double* y, size_t n, int precision
   if (n && (!x || !y || !K_out)) return fail(XS_EINVAL, "NULL argument");
   if (precision != XS_FP32_KAHAN && precision != XS_FP64)
     return fail(XS_EINVAL, "unknown precision %d", precision);
-  const double* wc = host_weideman();
   for (size_t i = 0; i < n; ++i)
-    K_out[i] = precision == XS_FP64 ? voigt_k64(x[i], y[i], wc)
-                                    : (double)voigt_k32(x[i], (float)y[i], wc);
+    K_out[i] = precision == XS_FP64 ? voigt_k64(x[i], y[i])
+                                    : (double)voigt_k32(x[i], (float)y[i]);
   return XS_OK;
 }
 

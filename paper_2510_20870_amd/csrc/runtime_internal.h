@@ -27,23 +27,32 @@ struct LinesRes {
   size_t n = 0;
   std::atomic<int> refs{0}; // pending serving requests
   std::vector<double> q_T_host, q_val_host;
+  std::vector<double> sample;   // nu0 of every kSampleStride-th line (host index)
 };
+
+constexpr int64_t kSampleStride = 1024;
 
 struct GridRes {
   double* d = nullptr;
   size_t n = 0;
   size_t bytes = 0;
+  double first = 0.0, last = 0.0;   // host copies of the end points
   std::atomic<int> refs{0};
 };
 
 struct Plan {
   int P = 4;               // grid points per lane (tile = 64 P points)
   int split = 1;           // line splits per tile
+  int W = 0;               // occupancy target of the tile kernel (0, 3 or 4 waves/SIMD)
   int64_t n_tiles = 0;
-  int64_t n_items = 0;
-  int64_t n_wg = 0;
-  int64_t per_xcd = 0;
-  int64_t phys_wg = 0;
+  int64_t rec_lo = 0;      // lines [rec_lo, rec_lo + rec_n) can reach the grid
+  int64_t rec_n = 0;
+  int npts = 0;
+  int pt_batch = 1;        // (P, T) points per parameter/tile launch pair
+  size_t rec_bytes() const { return (size_t)rec_n * pt_batch * 32; }
+  size_t part_bytes(size_t n_grid) const {
+    return split > 1 ? (size_t)pt_batch * split * n_grid * sizeof(double) : 0;
+  }
 };
 
 struct Server;  // serving loop (serve.hip)
@@ -61,9 +70,8 @@ struct xs_ctx {
   uint64_t next_handle = 1;
   std::unordered_map<uint64_t, xs::LinesRes*> lines;
   std::unordered_map<uint64_t, xs::GridRes*> grids;
-  double* wc = nullptr;                  // Weideman coefficients on the device
   // scratch of xs_compute / xs_count_evals (single caller thread)
-  xs::Scratch pts_buf, part_buf, out_buf, count_buf;
+  xs::Scratch pts_buf, part_buf, out_buf, count_buf, rec_buf;
   void* pts_pinned = nullptr;
   size_t pts_pinned_cap = 0;
   std::vector<double> pts_host;          // content of pts_buf
@@ -86,14 +94,15 @@ using Ctx = xs_ctx;
 
 int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
-const double* host_weideman();
 int validate_opts(const xs_opts* o);
 int validate_pts(const xs_pt* pts, size_t npts);
-Plan make_plan(const Ctx& c, size_t n_grid, size_t npts, const xs_opts& o, int64_t n_lines);
-TileArgs make_args(const Ctx& c, const LinesRes& L, const GridRes& G, const xs_opts& o,
-                   const Plan& p, const double* pts_dev, int npts);
-int enqueue_compute(Ctx& c, const TileArgs& A0, const Plan& p, bool f64, double* out_dev,
-                    double* part_dev, hipStream_t st);
+Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const xs_opts& o);
+// Enqueue the whole path on `st`: per batch of (P, T) points the parameter kernel, the
+// tile kernel and (split > 1) the fixed-order reduction; with counts != nullptr the count
+// kernel instead of tile + reduction.
+int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Plan& p,
+                 const double* pts_dev, double* out_dev, void* rec_dev, void* part_dev,
+                 hipStream_t st, unsigned long long* counts = nullptr);
 
 inline void free_lines_res(Ctx& c, LinesRes* L) {
   c.dev_free(L->base, L->bytes);

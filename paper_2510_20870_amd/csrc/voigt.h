@@ -5,14 +5,17 @@
 // GPU-side approximations, written once as __host__ __device__ code so the same source is
 // compiled into the gfx950 kernels and into a host entry point used to map its error.
 //
-// Regions, chosen on r^2 = x^2 + y^2 (all are written for x >= 0 or either sign):
+// Regions, chosen on r^2 = x^2 + y^2 (x may have either sign):
 //
-//  * far  (r^2 >= 1600): 2-node Gauss-Hermite quadrature of
+//  * far  (r^2 >= 400): the asymptotic expansion w(z) ~ (i/sqrt(pi)) (1/z)(1 + 1/(2z^2)
+//    + 3/(4z^4)). With u = 1/r^2 and c = x^2 u its real part is
+//        K = (y u / sqrt(pi)) (1 + u (2c - 1/2) + u^2 (12c^2 - 9c + 3/4)),
+//    every term proportional to y (no cancellation); the next term is below 2.1e-7
+//    relative at |z| = 20. One reciprocal.
+//  * mid  (64 <= r^2 < 400): 4-node Gauss-Hermite quadrature of
 //        w(z) = (i/pi) int exp(-t^2)/(z - t) dt,
 //    whose real part (y/pi) sum_k w_k / ((x - t_k)^2 + y^2) is a sum of positive terms:
-//    it has no cancellation, so FP32 keeps its relative accuracy (quadrature error
-//    <= 1e-6 relative at |z| >= 40).
-//  * mid  (64 <= r^2 < 1600): the same with 4 nodes (<= 1e-6 relative at |z| >= 8).
+//    no cancellation, so FP32 keeps its relative accuracy (<= 1e-6 at |z| >= 8).
 //  * core (r^2 < 64): Weideman's (1994) rational series with N = 40 terms,
 //        w(z) ~ 2 p(Z)/(L - iz)^2 + pi^{-1/2}/(L - iz),  Z = (L + iz)/(L - iz),
 //    L = 2^{-1/4} sqrt(N), evaluated in FP64: near the real axis Re w is tiny beside
@@ -27,6 +30,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "weideman_coef.h"
 
 #define XS_HD __host__ __device__ __forceinline__
 
@@ -46,7 +51,8 @@ constexpr double kGH8_t[4] = {0.38118699020732211685, 1.15719371244678019472,
 constexpr double kGH8_w[4] = {0.66114701255824129103, 0.20780232581489187955,
                               0.01707798300741347546, 0.00019960407221136762};
 
-constexpr float kFarR2 = 1600.0f;   // |z| >= 40
+constexpr float kFarR2 = 400.0f;    // |z| >= 20 (FP32 far tier)
+constexpr double kFarR2_64 = 1600.0; // |z| >= 40 (FP64 far tier)
 constexpr float kMidR2 = 64.0f;     // |z| >= 8
 constexpr int kWeidN = 40;
 
@@ -75,15 +81,18 @@ XS_HD double rcp64(double a) {
 // ---------------------------------------------------------------- FP32 tiers
 // Every tier returns K itself, given r2 = x^2 + y^2 and y.
 
-// far tier, one node pair
-XS_HD float voigt_far32(float r2, float y) {
+// far tier: returns K sqrt(pi) / y = u (1 + u (2c - 1/2 + u (12c^2 - 9c + 3/4)))
+XS_HD float voigt_far32_scaled(float x2, float r2) {
   const float u = rcp32(r2);
-  const float v = y * u;
-  const float q = v * v;
-  const float a = fmaf(-0.5f, u, 1.0f);                        // 1 - t^2 u, t^2 = 1/2
-  const float d = fmaf(a, a, 2.0f * q);                        // + 4 t^2 v^2
-  const float n = fmaf((float)(kSqrtPi * 0.5), u, (float)kSqrtPi);  // 2w (1 + t^2 u)
-  return (float)(1.0 / kPi) * v * n * rcp32(d);
+  const float c = x2 * u;
+  const float q2 = fmaf(fmaf(12.0f, c, -9.0f), c, 0.75f);
+  const float q1 = fmaf(2.0f, c, -0.5f);
+  const float s = fmaf(u, fmaf(u, q2, q1), 1.0f);
+  return u * s;
+}
+
+XS_HD float voigt_far32(float x2, float r2, float y) {
+  return (float)kInvSqrtPi * y * voigt_far32_scaled(x2, r2);
 }
 
 // mid tier, two node pairs
@@ -107,6 +116,7 @@ XS_HD float voigt_mid32(float r2, float y) {
 }
 
 // ---------------------------------------------------------------- FP64 tiers
+// FP64 path: 4-node quadrature for |z| >= 40, 8 nodes for 8 <= |z| < 40, Weideman core.
 XS_HD double voigt_far64(double r2, double y) {
   // 4 nodes (<= 2e-12 relative at |z| >= 40)
   const double t1s = kGH4_t1 * kGH4_t1, t2s = kGH4_t2 * kGH4_t2;
@@ -137,9 +147,10 @@ XS_HD double voigt_mid64(double r2, double y) {
   return (1.0 / kPi) * v * fma(n01, d23, n23 * d01) * rcp64(d01 * d23);
 }
 
-// core: Weideman N = 40 in FP64. `a` holds a_1..a_N (a[n-1] multiplies Z^(n-1)).
-XS_HD double voigt_core64(double x, double y, const double* __restrict__ a) {
-  const double L = 5.31829589694498834;           // 2^{-1/4} sqrt(40)
+// core: Weideman N = 40 in FP64 (kWeidA[n-1] multiplies Z^(n-1)).
+XS_HD double voigt_core64(double x, double y) {
+  const double* a = kWeidA;
+  const double L = kWeidL;
   const double lpy = L + y;
   const double D = fma(lpy, lpy, x * x);
   const double iD = rcp64(D);
@@ -160,19 +171,20 @@ XS_HD double voigt_core64(double x, double y, const double* __restrict__ a) {
 
 // Full K in FP32 arithmetic for the far/mid tiers and FP64 for the core. x may be
 // negative (K is even in x).
-XS_HD float voigt_k32(double xd, float y, const double* __restrict__ wc) {
+XS_HD float voigt_k32(double xd, float y) {
   const float x = (float)xd;
-  const float r2 = fmaf(x, x, y * y);
-  if (r2 >= kFarR2) return voigt_far32(r2, y);
+  const float x2 = x * x;
+  const float r2 = fmaf(y, y, x2);
+  if (r2 >= kFarR2) return voigt_far32(x2, r2, y);
   if (r2 >= kMidR2) return voigt_mid32(r2, y);
-  return (float)voigt_core64(xd, (double)y, wc);
+  return (float)voigt_core64(xd, (double)y);
 }
 
-XS_HD double voigt_k64(double x, double y, const double* __restrict__ wc) {
+XS_HD double voigt_k64(double x, double y) {
   const double r2 = fma(x, x, y * y);
-  if (r2 >= (double)kFarR2) return voigt_far64(r2, y);
+  if (r2 >= kFarR2_64) return voigt_far64(r2, y);
   if (r2 >= (double)kMidR2) return voigt_mid64(r2, y);
-  return voigt_core64(x, y, wc);
+  return voigt_core64(x, y);
 }
 
 }  // namespace xs

@@ -57,7 +57,8 @@ class Pt(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("cutoff_kind", C.c_int), ("cut_cm1", C.c_double), ("fwhm_mult", C.c_double),
-                ("precision", C.c_int), ("pts_per_lane", C.c_int), ("split", C.c_int)]
+                ("precision", C.c_int), ("pts_per_lane", C.c_int), ("split", C.c_int),
+                ("waves_per_simd", C.c_int)]
 
 
 _lib = None
@@ -237,8 +238,10 @@ class Context:
     # ------------------------------------------------------------------ compute
     @staticmethod
     def opts(cutoff_kind: int = XS_CUT_FIXED, cut_cm1: float = 25.0, fwhm_mult: float = 100.0,
-             precision: int = XS_FP32_KAHAN, pts_per_lane: int = 0, split: int = 0) -> Opts:
-        return Opts(cutoff_kind, cut_cm1, fwhm_mult, precision, pts_per_lane, split)
+             precision: int = XS_FP32_KAHAN, pts_per_lane: int = 0, split: int = 0,
+             waves_per_simd: int = 0) -> Opts:
+        return Opts(cutoff_kind, cut_cm1, fwhm_mult, precision, pts_per_lane, split,
+                    waves_per_simd)
 
     @staticmethod
     def _pts(pts) -> C.Array:
