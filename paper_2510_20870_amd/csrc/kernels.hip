@@ -48,6 +48,7 @@
 namespace xs {
 
 constexpr int kScaleTarget = 96;   // exponent of the strongest FP32 contribution scale
+enum { kSkip = 0, kRows = 1, kLeftFar = 2, kLeftVFar = 3, kRightFar = 4, kRightVFar = 5 };
 constexpr int kNoScale = -(1 << 28);
 
 // ------------------------------------------------------------------ parameter kernel
@@ -74,19 +75,23 @@ __global__ __launch_bounds__(256) void xs_params_kernel(ParamArgs A) {
 // Record of one staged line in LDS. cls holds 2 bits per row p of the wave's tile:
 // 0 = no point of the row is inside the cut, 1 = general path, 2 / 3 = every point of the
 // row is inside the cut and in the far tier, the line lying left / right of the row; xr[p]
-// is then x at the row's nearest end (first / last point).
+// is then x at the row's nearest end (first / last point). mode selects the hot-loop path
+// of the line: kSkip (no row inside the cut), kRows (per-row classes), or one of the
+// whole-tile far blocks when every row is of class 2 (kLeft*) or of class 3 (kRight*),
+// with the two-term series (k*VFar) when the whole tile is at |z| >= 80.
 template <bool F64, int P> struct Rec;
 template <int P> struct alignas(16) Rec<false, P> {
   double nu0, cut, ib;
   float y, y2, sc, scy;   // scy = sc * y / sqrt(pi): scale of the far-tier kernel
   float ib32;
   int cls;
+  int mode;
   float xr[P];
 };
 template <int P> struct alignas(16) Rec<true, P> {
   double nu0, cut, ib, y, sc;
   int cls;
-  int pad;
+  int mode;
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -144,7 +149,9 @@ template <int P>
 __device__ __forceinline__ bool decode_item(const TileArgs& A, int lane, ItemInfo& it) {
   const int64_t phys = blockIdx.x;
   const int64_t wg = xcd_logical_wg(phys, A.per_xcd);
-  const int64_t item = wg * kWavesPerWG + (threadIdx.x >> 6);
+  // the wave index is wave-uniform; say so, so that everything derived from it is scalar
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t item = wg * kWavesPerWG + wave;
   if (wg >= A.n_wg || item >= A.n_items) return false;
   it.s = (int)(item % A.split);
   const int64_t r = item / A.split;
@@ -216,11 +223,23 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
     cls |= c << (2 * p);
     if constexpr (!F64) r.xr[p] = xr;
   }
+  int mode = cls == 0 ? kSkip : kRows;
+  if constexpr (!F64) {
+    // whole-tile far blocks; the two-term series when the point nearest to the line is
+    // already at |z| >= 80
+    constexpr int kAllLeft = (int)(0xAAAAAAAAu & ((1u << (2 * P)) - 1u));
+    constexpr int kAllRight = (int)(0xFFFFFFFFu & ((1u << (2 * P)) - 1u));
+    if (cls == kAllLeft) {
+      mode = fmaf(y, y, r.xr[0] * r.xr[0]) >= kVFarR2 ? kLeftVFar : kLeftFar;
+    } else if (cls == kAllRight) {
+      mode = fmaf(y, y, r.xr[P - 1] * r.xr[P - 1]) >= kVFarR2 ? kRightVFar : kRightFar;
+    }
+  }
   r.cls = cls;
+  r.mode = mode;
   if constexpr (F64) {
     r.y = lr.y;
     r.sc = lr.sc;
-    r.pad = 0;
   } else {
     r.y = y;
     r.y2 = y * y;
@@ -236,6 +255,20 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
   const float t = s + yk;
   c = (t - s) - yk;
   s = t;
+}
+
+// Contributions of one line to all P rows when every row is in the far tier (VFAR: the
+// two-term series), x from the row end.
+template <int P, bool VFAR>
+__device__ __forceinline__ void far_values(const Rec<false, P>& q, const float (&off)[P],
+                                           float (&v)[P]) {
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const float x = fmaf(off[p], q.ib32, q.xr[p]);
+    const float x2 = x * x;
+    const float r2 = x2 + q.y2;
+    v[p] = q.scy * (VFAR ? voigt_vfar32_scaled(x2, r2) : voigt_far32_scaled(x2, r2));
+  }
 }
 
 // W > 0 asks the compiler for at least W waves per SIMD (capping VGPRs at 512/W).
@@ -276,6 +309,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       r = stage_line<F64, P>(A, it.k, rows, i, &sc64);
     } else {
       r.cls = 0;
+      r.mode = kSkip;
     }
     if constexpr (!F64) {
       const int ex = wave_max(sc64 > 0.0 ? ilogb(sc64) : kNoScale);
@@ -298,50 +332,47 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     const int nk = (int)min((int64_t)kWave, it.e - base);
     for (int kk = 0; kk < nk; ++kk) {
       const Rec<F64, P>& q = recs[wv][kk];
-      const int cls = __builtin_amdgcn_readfirstlane(q.cls);
-      if (cls == 0) continue;
-      if constexpr (!F64) {
-        // Common case: the line lies left (or right) of the whole tile and every row is
-        // inside the cut and in the far tier. One branch-free block for all rows lets
-        // the P independent dependency chains interleave.
-        constexpr int kAllLeft = (int)(0xAAAAAAAAu & ((1u << (2 * P)) - 1u));
-        constexpr int kAllRight = (int)(0xFFFFFFFFu & ((1u << (2 * P)) - 1u));
-        if (cls == kAllLeft || cls == kAllRight) {
-          const bool left = (cls == kAllLeft);
-          float v[P];
+      const int mode = __builtin_amdgcn_readfirstlane(q.mode);
+      if (mode == kSkip) continue;
+      if constexpr (F64) {
+        const int cls = __builtin_amdgcn_readfirstlane(q.cls);
 #pragma unroll
-          for (int p = 0; p < P; ++p) {
-            const float x = fmaf(left ? da32[p] : db32[p], q.ib32, q.xr[p]);
-            const float x2 = x * x;
-            v[p] = q.scy * voigt_far32_scaled(x2, x2 + q.y2);
-          }
-#pragma unroll
-          for (int p = 0; p < P; ++p) kahan_add(s[p], c[p], v[p]);
-          continue;
-        }
-      }
-#pragma unroll
-      for (int p = 0; p < P; ++p) {
-        const int cp = (cls >> (2 * p)) & 3;
-        if (cp == 0) continue;
-        if constexpr (F64) {
+        for (int p = 0; p < P; ++p) {
+          if (((cls >> (2 * p)) & 3) == 0) continue;
           const double d = nu[p] - q.nu0;
           if (fabs(d) <= q.cut) s[p] += q.sc * voigt_k64(d * q.ib, q.y);
-        } else {
-          float v;
-          if (cp == 1) {
-            // general: FP64 offset and cut test, tier chosen per point
-            const double d = nu[p] - q.nu0;
-            if (!(fabs(d) <= q.cut)) continue;
-            v = q.sc * voigt_k32(d * q.ib, q.y);
-          } else {
-            // whole row inside the cut and in the far tier
-            const float x = fmaf(cp == 2 ? da32[p] : db32[p], q.ib32, q.xr[p]);
-            const float x2 = x * x;
-            v = q.scy * voigt_far32_scaled(x2, x2 + q.y2);
-          }
-          kahan_add(s[p], c[p], v);
         }
+      } else {
+        // Every path only produces the P contributions of this line; one shared Kahan
+        // update follows, so the sums live in fixed registers.
+        float v[P];
+        if (mode >= kLeftFar) {
+          // The line lies left (or right) of the whole tile and every row is inside the
+          // cut and in the far tier: one branch-free block over the P independent rows.
+          if (mode == kLeftVFar) far_values<P, true>(q, da32, v);
+          else if (mode == kRightVFar) far_values<P, true>(q, db32, v);
+          else if (mode == kLeftFar) far_values<P, false>(q, da32, v);
+          else far_values<P, false>(q, db32, v);
+        } else {
+          const int cls = __builtin_amdgcn_readfirstlane(q.cls);
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            const int cp = (cls >> (2 * p)) & 3;
+            v[p] = 0.0f;
+            if (cp == 1) {
+              // general: FP64 offset and cut test, tier chosen per point
+              const double d = nu[p] - q.nu0;
+              if (fabs(d) <= q.cut) v[p] = q.sc * voigt_k32(d * q.ib, q.y);
+            } else if (cp >= 2) {
+              // whole row inside the cut and in the far tier
+              const float x = fmaf(cp == 2 ? da32[p] : db32[p], q.ib32, q.xr[p]);
+              const float x2 = x * x;
+              v[p] = q.scy * voigt_far32_scaled(x2, x2 + q.y2);
+            }
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) kahan_add(s[p], c[p], v[p]);
       }
     }
     wave_sync();

@@ -151,7 +151,7 @@ static void line_range(const LinesRes& L, const GridRes& G, const xs_opts& o, in
 
 Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const xs_opts& o) {
   Plan p;
-  p.P = o.pts_per_lane ? o.pts_per_lane : 4;
+  p.P = o.pts_per_lane ? o.pts_per_lane : 2;
   p.W = o.waves_per_simd == 2 ? 0 : o.waves_per_simd;
   const int64_t tile = (int64_t)kWave * p.P;
   p.n_tiles = ((int64_t)G.n + tile - 1) / tile;
@@ -162,9 +162,10 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
   if (o.split) {
     p.split = o.split;
   } else {
-    // enough wavefronts to give every SIMD (4 per CU) four of them
+    // about four work items per resident wavefront slot (4 SIMDs x 7 waves per CU), so
+    // the last round of waves is short
     const int64_t base = p.n_tiles * (int64_t)npts;
-    const int64_t target = (int64_t)c.n_cu * 16;
+    const int64_t target = (int64_t)c.n_cu * 112;
     int64_t sp = (target + base - 1) / base;
     sp = std::max<int64_t>(1, std::min<int64_t>(sp, 64));
     // no point in splits much shorter than one 64-line chunk per tile window

@@ -52,6 +52,7 @@ constexpr double kGH8_w[4] = {0.66114701255824129103, 0.20780232581489187955,
                               0.01707798300741347546, 0.00019960407221136762};
 
 constexpr float kFarR2 = 400.0f;    // |z| >= 20 (FP32 far tier)
+constexpr float kVFarR2 = 6400.0f;  // |z| >= 80 (FP32 two-term far tier)
 constexpr double kFarR2_64 = 1600.0; // |z| >= 40 (FP64 far tier)
 constexpr float kMidR2 = 64.0f;     // |z| >= 8
 constexpr int kWeidN = 40;
@@ -89,6 +90,14 @@ XS_HD float voigt_far32_scaled(float x2, float r2) {
   const float q1 = fmaf(2.0f, c, -0.5f);
   const float s = fmaf(u, fmaf(u, q2, q1), 1.0f);
   return u * s;
+}
+
+// two-term far tier for |z| >= 80 (the dropped u^2 term is below 9.2e-8 relative there):
+// returns K sqrt(pi) / y = u (1 + u (2c - 1/2))
+XS_HD float voigt_vfar32_scaled(float x2, float r2) {
+  const float u = rcp32(r2);
+  const float c = x2 * u;
+  return u * fmaf(u, fmaf(2.0f, c, -0.5f), 1.0f);
 }
 
 XS_HD float voigt_far32(float x2, float r2, float y) {
