@@ -51,6 +51,8 @@ def main():
     ap.add_argument("--pts-per-lane", type=int, default=0)
     ap.add_argument("--split", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
+    ap.add_argument("--gen-workers", type=int, default=0,
+                    help="processes generating the synthetic list (0 = one per core, max 16)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -67,7 +69,7 @@ def main():
         raise SystemExit("bench workload must have one (P, T) point")
     P, T = W.pts[0]
     t0 = time.time()
-    L = synth.make_lines(W.lines, workers=synth.default_workers())
+    L = synth.make_lines(W.lines, workers=args.gen_workers or synth.default_workers())
     grid = W.grid()
     log(f"generated {W.lines.n} lines, {len(grid)} grid points in {time.time() - t0:.1f} s")
 

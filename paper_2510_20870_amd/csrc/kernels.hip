@@ -74,8 +74,9 @@ __global__ __launch_bounds__(256) void xs_params_kernel(ParamArgs A) {
 // ------------------------------------------------------------------ tile kernel
 // Record of one staged line in LDS. cls holds 2 bits per row p of the wave's tile:
 // 0 = no point of the row is inside the cut, 1 = general path, 2 / 3 = every point of the
-// row is inside the cut and in the far tier, the line lying left / right of the row; xr[p]
-// is then x at the row's nearest end (first / last point). mode selects the hot-loop path
+// row is in the far tier, the line lying left / right of the row; xr[p] is then x at the
+// row's nearest end (first / last point), and the points inside the cut are the lanes
+// <= bnd[p] (class 2) or >= bnd[p] (class 3), found exactly at staging time. mode selects the hot-loop path
 // of the line: kSkip (no row inside the cut), kRows (per-row classes), or one of the
 // whole-tile far blocks when every row is of class 2 (kLeft*) or of class 3 (kRight*),
 // with the two-term series (k*VFar) when the whole tile is at |z| >= 80.
@@ -84,9 +85,11 @@ template <int P> struct alignas(16) Rec<false, P> {
   double nu0, cut, ib;
   float y, y2, sc, scy;   // scy = sc * y / sqrt(pi): scale of the far-tier kernel
   float ib32;
+  float m2y2;             // -2 y^2
   int cls;
   int mode;
   float xr[P];
+  signed char bnd[P];
 };
 template <int P> struct alignas(16) Rec<true, P> {
   double nu0, cut, ib, y, sc;
@@ -183,13 +186,15 @@ template <int P>
 struct Rows {
   double ra[P], rb[P];
   bool valid[P];
+  int last[P];          // lane of the last valid point of the row
 };
 
 // Stages line i: the record (except the FP32 scales, set once the chunk's scale is known)
 // with the row classes; returns the FP64 profile scale in *sc64.
 template <bool F64, int P>
 __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, const Rows<P>& rows,
-                                                  int64_t i, double* sc64) {
+                                                  const double* rowv, int64_t i,
+                                                  double* sc64) {
   const double nu0 = A.L.nu0[i];
   const LineRec lr = A.recs[(int64_t)k * A.rec_n + (i - A.rec_lo)];
   Rec<F64, P> r;
@@ -199,29 +204,54 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
   *sc64 = lr.sc;
   const float y = (float)lr.y;
   // Classify each row with the same FP64 difference and test the per-point path uses;
-  // the difference is monotone in nu_j, so the row's two ends decide for every point.
+  // the difference is monotone in nu_j, so the row's two ends decide for every point, and
+  // a binary search over the row's grid values (rowv, LDS) finds the cut boundary.
   int cls = 0;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     int c = 0;
     float xr = 0.0f;
+    int bnd = 0;
     if (rows.valid[p]) {
       const double da = rows.ra[p] - nu0, db = rows.rb[p] - nu0;
       const bool none = (da > lr.cut) || (db < -lr.cut);
-      const bool all = (fabs(da) <= lr.cut) && (fabs(db) <= lr.cut);
       if (!none) {
         c = 1;
-        if (!F64 && all && (da > 0.0 || db < 0.0)) {
-          const float x = (float)((da > 0.0 ? da : db) * lr.ib);
+        if (!F64 && (da > 0.0 || db < 0.0)) {
+          const bool left = da > 0.0;   // the line lies left of the row
+          const float x = (float)((left ? da : db) * lr.ib);
           if (fmaf(y, y, x * x) >= kFarR2) {
-            c = da > 0.0 ? 2 : 3;
+            c = left ? 2 : 3;
             xr = x;
+            const double* rv = rowv + kWave * p;
+            if (left) {
+              // last lane with nu - nu0 <= cut (lane 0 qualifies: da <= cut)
+              int lo = 0, hi = rows.last[p] + 1;
+              if (db <= lr.cut) lo = rows.last[p];
+              while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (rv[mid] - nu0 <= lr.cut) lo = mid; else hi = mid;
+              }
+              bnd = lo == rows.last[p] ? kWave - 1 : lo;
+            } else {
+              // first lane with nu - nu0 >= -cut (the last lane qualifies: db >= -cut)
+              int lo = -1, hi = rows.last[p];
+              if (da >= -lr.cut) hi = 0;
+              while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (rv[mid] - nu0 >= -lr.cut) hi = mid; else lo = mid;
+              }
+              bnd = hi;
+            }
           }
         }
       }
     }
     cls |= c << (2 * p);
-    if constexpr (!F64) r.xr[p] = xr;
+    if constexpr (!F64) {
+      r.xr[p] = xr;
+      r.bnd[p] = (signed char)bnd;
+    }
   }
   int mode = cls == 0 ? kSkip : kRows;
   if constexpr (!F64) {
@@ -229,9 +259,13 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
     // already at |z| >= 80
     constexpr int kAllLeft = (int)(0xAAAAAAAAu & ((1u << (2 * P)) - 1u));
     constexpr int kAllRight = (int)(0xFFFFFFFFu & ((1u << (2 * P)) - 1u));
-    if (cls == kAllLeft) {
+    bool full = true;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+      full = full && (r.bnd[p] == (cls == kAllLeft ? kWave - 1 : 0));
+    if (cls == kAllLeft && full) {
       mode = fmaf(y, y, r.xr[0] * r.xr[0]) >= kVFarR2 ? kLeftVFar : kLeftFar;
-    } else if (cls == kAllRight) {
+    } else if (cls == kAllRight && full) {
       mode = fmaf(y, y, r.xr[P - 1] * r.xr[P - 1]) >= kVFarR2 ? kRightVFar : kRightFar;
     }
   }
@@ -243,6 +277,7 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
   } else {
     r.y = y;
     r.y2 = y * y;
+    r.m2y2 = -2.0f * r.y2;
     r.ib32 = (float)lr.ib;
     r.sc = 0.0f;
     r.scy = 0.0f;
@@ -265,9 +300,8 @@ __device__ __forceinline__ void far_values(const Rec<false, P>& q, const float (
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const float x = fmaf(off[p], q.ib32, q.xr[p]);
-    const float x2 = x * x;
-    const float r2 = x2 + q.y2;
-    v[p] = q.scy * (VFAR ? voigt_vfar32_scaled(x2, r2) : voigt_far32_scaled(x2, r2));
+    const float r2 = fmaf(x, x, q.y2);
+    v[p] = q.scy * (VFAR ? voigt_vfar32_scaled(q.m2y2, r2) : voigt_far32_scaled(q.y2, r2));
   }
 }
 
@@ -275,6 +309,7 @@ __device__ __forceinline__ void far_values(const Rec<false, P>& q, const float (
 template <int P, bool F64, int W>
 __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileArgs A) {
   __shared__ Rec<F64, P> recs[kWavesPerWG][kWave];
+  __shared__ double rowvals[kWavesPerWG][kWave * P];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x >> 6;
   ItemInfo it;
@@ -290,11 +325,14 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     const int64_t jb = min(ja + kWave - 1, A.n_grid - 1);
     rows.ra[p] = rows.valid[p] ? A.grid[ja] : 0.0;
     rows.rb[p] = rows.valid[p] ? A.grid[jb] : 0.0;
+    rows.last[p] = rows.valid[p] ? (int)(jb - ja) : 0;
     const int64_t j = ja + lane;
     nu[p] = (j < A.n_grid) ? A.grid[j] : __builtin_nan("");
     da32[p] = (float)(nu[p] - rows.ra[p]);
     db32[p] = (float)(nu[p] - rows.rb[p]);
+    rowvals[wv][kWave * p + lane] = nu[p];
   }
+  wave_sync();
   using acc_t = typename std::conditional<F64, double, float>::type;
   acc_t s[P], c[P];
 #pragma unroll
@@ -306,7 +344,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     Rec<F64, P> r;
     double sc64 = 0.0;
     if (i < it.e) {
-      r = stage_line<F64, P>(A, it.k, rows, i, &sc64);
+      r = stage_line<F64, P>(A, it.k, rows, rowvals[wv], i, &sc64);
     } else {
       r.cls = 0;
       r.mode = kSkip;
@@ -364,10 +402,11 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
               const double d = nu[p] - q.nu0;
               if (fabs(d) <= q.cut) v[p] = q.sc * voigt_k32(d * q.ib, q.y);
             } else if (cp >= 2) {
-              // whole row inside the cut and in the far tier
+              // whole row in the far tier; the lanes inside the cut are one side of bnd
               const float x = fmaf(cp == 2 ? da32[p] : db32[p], q.ib32, q.xr[p]);
-              const float x2 = x * x;
-              v[p] = q.scy * voigt_far32_scaled(x2, x2 + q.y2);
+              const float f = q.scy * voigt_far32_scaled(q.y2, fmaf(x, x, q.y2));
+              const bool in = cp == 2 ? (lane <= q.bnd[p]) : (lane >= q.bnd[p]);
+              v[p] = in ? f : 0.0f;
             }
           }
         }

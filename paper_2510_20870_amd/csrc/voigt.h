@@ -8,10 +8,11 @@
 // Regions, chosen on r^2 = x^2 + y^2 (x may have either sign):
 //
 //  * far  (r^2 >= 400): the asymptotic expansion w(z) ~ (i/sqrt(pi)) (1/z)(1 + 1/(2z^2)
-//    + 3/(4z^4)). With u = 1/r^2 and c = x^2 u its real part is
-//        K = (y u / sqrt(pi)) (1 + u (2c - 1/2) + u^2 (12c^2 - 9c + 3/4)),
+//    + 3/(4z^4)). With u = 1/r^2 and w = y^2 u (so that x^2 u = 1 - w) its real part is
+//        K = (y u / sqrt(pi)) (1 + u (3/2 - 2w) + u^2 (15/4 - 15w + 12w^2)),
 //    every term proportional to y (no cancellation); the next term is below 2.1e-7
-//    relative at |z| = 20. One reciprocal.
+//    relative at |z| = 20. For r^2 >= 6400 the u^2 term is dropped (<= 9.2e-8). x enters
+//    only through r^2 = fma(x, x, y^2); one reciprocal.
 //  * mid  (64 <= r^2 < 400): 4-node Gauss-Hermite quadrature of
 //        w(z) = (i/pi) int exp(-t^2)/(z - t) dt,
 //    whose real part (y/pi) sum_k w_k / ((x - t_k)^2 + y^2) is a sum of positive terms:
@@ -82,26 +83,25 @@ XS_HD double rcp64(double a) {
 // ---------------------------------------------------------------- FP32 tiers
 // Every tier returns K itself, given r2 = x^2 + y^2 and y.
 
-// far tier: returns K sqrt(pi) / y = u (1 + u (2c - 1/2 + u (12c^2 - 9c + 3/4)))
-XS_HD float voigt_far32_scaled(float x2, float r2) {
+// far tier: returns K sqrt(pi) / y = u (1 + u (3/2 - 2w + u (15/4 - 15w + 12w^2))),
+// w = y^2 u
+XS_HD float voigt_far32_scaled(float y2, float r2) {
   const float u = rcp32(r2);
-  const float c = x2 * u;
-  const float q2 = fmaf(fmaf(12.0f, c, -9.0f), c, 0.75f);
-  const float q1 = fmaf(2.0f, c, -0.5f);
-  const float s = fmaf(u, fmaf(u, q2, q1), 1.0f);
-  return u * s;
+  const float w = y2 * u;
+  const float q2 = fmaf(fmaf(12.0f, w, -15.0f), w, 3.75f);
+  const float q1 = fmaf(-2.0f, w, 1.5f);
+  return u * fmaf(u, fmaf(u, q2, q1), 1.0f);
 }
 
-// two-term far tier for |z| >= 80 (the dropped u^2 term is below 9.2e-8 relative there):
-// returns K sqrt(pi) / y = u (1 + u (2c - 1/2))
-XS_HD float voigt_vfar32_scaled(float x2, float r2) {
+// two-term far tier for |z| >= 80: returns K sqrt(pi) / y = u (1 + u (3/2 - 2w)); with
+// m2y2 = -2 y^2 precomputed per line this is three operations after the reciprocal
+XS_HD float voigt_vfar32_scaled(float m2y2, float r2) {
   const float u = rcp32(r2);
-  const float c = x2 * u;
-  return u * fmaf(u, fmaf(2.0f, c, -0.5f), 1.0f);
+  return u * fmaf(u, fmaf(m2y2, u, 1.5f), 1.0f);
 }
 
-XS_HD float voigt_far32(float x2, float r2, float y) {
-  return (float)kInvSqrtPi * y * voigt_far32_scaled(x2, r2);
+XS_HD float voigt_far32(float r2, float y) {
+  return (float)kInvSqrtPi * y * voigt_far32_scaled(y * y, r2);
 }
 
 // mid tier, two node pairs
@@ -182,9 +182,8 @@ XS_HD double voigt_core64(double x, double y) {
 // negative (K is even in x).
 XS_HD float voigt_k32(double xd, float y) {
   const float x = (float)xd;
-  const float x2 = x * x;
-  const float r2 = fmaf(y, y, x2);
-  if (r2 >= kFarR2) return voigt_far32(x2, r2, y);
+  const float r2 = fmaf(x, x, y * y);
+  if (r2 >= kFarR2) return voigt_far32(r2, y);
   if (r2 >= kMidR2) return voigt_mid32(r2, y);
   return (float)voigt_core64(xd, (double)y);
 }

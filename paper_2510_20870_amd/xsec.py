@@ -14,7 +14,8 @@ from typing import Dict, Optional, Sequence
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libxsec.so")
+# XSEC_LIB selects another build of the same library (same ABI)
+LIB_PATH = os.environ.get("XSEC_LIB") or os.path.join(PKG, "libxsec.so")
 
 XS_OK, XS_EINVAL, XS_ENOMEM, XS_EDEVICE, XS_ENOTFOUND = 0, -1, -2, -3, -4
 XS_EUNSORTED, XS_EBUSY, XS_ECANCELLED, XS_ETIMEOUT = -5, -6, -7, -8
