@@ -51,7 +51,7 @@ struct TileArgs {
   int64_t n_tiles;
   int64_t n_items;        // n_tiles * n_pt * split
   int64_t n_wg;           // logical workgroups (ceil(n_items / 4))
-  int64_t per_xcd;        // ceil(n_wg / 8)
+  const int* tile_order;  // issue order of the tiles (nullptr: ascending)
   const LineRec* recs;    // [n_pt][rec_n] records of lines [rec_lo, rec_lo + rec_n)
   int64_t rec_lo, rec_n;
   double* out;            // split == 1: sigma rows [n_pts][n_grid] (row pt0 + k);
@@ -59,7 +59,9 @@ struct TileArgs {
   unsigned long long* counts;  // count kernel only: [n_pts]
 };
 
-// Launchers (kernels.hip). phys_wg = number of workgroups launched (a multiple of 8).
+// Launchers (kernels.hip). phys_wg = number of workgroups launched: n_wg rounded up to a
+// multiple of 8 * 16 (whole XCD blocks).
+inline int64_t phys_workgroups(int64_t n_wg) { return (n_wg + 127) / 128 * 128; }
 hipError_t launch_params(const ParamArgs& A, hipStream_t st);
 hipError_t launch_tile(const TileArgs& A, int P, bool f64, int W, hipStream_t st,
                        int64_t phys_wg);

@@ -25,12 +25,13 @@
 //      d. writes its sums: the final value, or a partial for the fixed-order reduction.
 //
 // Arithmetic of one (line, point) pair on the general path: d = nu_j - nu0 (FP64), the cut
-// test |d| <= cut (FP64), x = d / b_D (FP64, rounded once to FP32), K(x, y) in FP32 outside
-// |z| = 8 and FP64 inside, then a Kahan-compensated FP32 add (or a plain FP64 add on the
-// FP64 path). Rows that lie entirely inside the cut and entirely in the far tier of a line
-// (the large majority) skip the FP64 offset and test: x = (nu_j - nu_end) / b_D + x_end from
-// the row's nearer end, in FP32 (relative error a few ulps since x does not change sign
-// along the row). FP32 contributions carry a power-of-two scale chosen per wavefront:
+// test |d| <= cut (FP64), x = d / b_D (FP64, rounded once to FP32), K(x, y) from the FP32
+// asymptotic series outside |z| = 7 and in FP64 inside, then a Kahan-compensated FP32 add
+// (or a plain FP64 add on the FP64 path). Rows that lie entirely in the series region of a
+// line (the large majority) skip the FP64 offset and test: x = (nu_j - nu_end) / b_D + x_end
+// from the row's nearer end, in FP32 (relative error a few ulps since x does not change
+// sign along the row), with the shortest series the row's nearest point allows and the cut
+// applied as a lane bound found at staging time. FP32 contributions carry a power-of-two scale chosen per wavefront:
 // whenever a staged chunk holds a line stronger than any before, the scale is lowered so
 // the strongest contribution is about 2^97 and the running sums are rescaled exactly, so
 // any absolute magnitude of sigma stays inside FP32 range; the scale is removed exactly
@@ -48,7 +49,7 @@
 namespace xs {
 
 constexpr int kScaleTarget = 96;   // exponent of the strongest FP32 contribution scale
-enum { kSkip = 0, kRows = 1, kLeftFar = 2, kLeftVFar = 3, kRightFar = 4, kRightVFar = 5 };
+enum { kSkip = 0, kRows = 1, kLeft = 2, kRight = 6 };   // kLeft/kRight + variant 0..3
 constexpr int kNoScale = -(1 << 28);
 
 // ------------------------------------------------------------------ parameter kernel
@@ -74,22 +75,22 @@ __global__ __launch_bounds__(256) void xs_params_kernel(ParamArgs A) {
 // ------------------------------------------------------------------ tile kernel
 // Record of one staged line in LDS. cls holds 2 bits per row p of the wave's tile:
 // 0 = no point of the row is inside the cut, 1 = general path, 2 / 3 = every point of the
-// row is in the far tier, the line lying left / right of the row; xr[p] is then x at the
-// row's nearest end (first / last point), and the points inside the cut are the lanes
-// <= bnd[p] (class 2) or >= bnd[p] (class 3), found exactly at staging time. mode selects the hot-loop path
-// of the line: kSkip (no row inside the cut), kRows (per-row classes), or one of the
-// whole-tile far blocks when every row is of class 2 (kLeft*) or of class 3 (kRight*),
-// with the two-term series (k*VFar) when the whole tile is at |z| >= 80.
+// row is in the FP32 series region (|z| >= 7), the line lying left / right of the row; xr[p]
+// is then x at the row's nearest end (first / last point), rinfo[p] & 63 = bnd: the points
+// inside the cut are the lanes <= bnd (class 2) or >= bnd (class 3), found exactly at
+// staging time, and rinfo[p] >> 6 is the series variant the row's nearest point needs.
+// mode selects the hot-loop path of the line: kSkip (no row inside the cut), kRows
+// (per-row classes), or one whole-tile series block when every row is of class 2
+// (kLeft + variant) or of class 3 (kRight + variant) with every point inside the cut.
 template <bool F64, int P> struct Rec;
 template <int P> struct alignas(16) Rec<false, P> {
   double nu0, cut, ib;
-  float y, y2, sc, scy;   // scy = sc * y / sqrt(pi): scale of the far-tier kernel
+  float y, y2, sc, scy;   // scy = sc * y / sqrt(pi): scale of the series blocks
   float ib32;
-  float m2y2;             // -2 y^2
   int cls;
   int mode;
   float xr[P];
-  signed char bnd[P];
+  unsigned char rinfo[P];
 };
 template <int P> struct alignas(16) Rec<true, P> {
   double nu0, cut, ib, y, sc;
@@ -109,10 +110,14 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs; map them so that each XCD (and
-// its L2) works on a contiguous range of tiles, which share most of their line windows.
-__device__ __forceinline__ int64_t xcd_logical_wg(int64_t phys, int64_t per_xcd) {
-  return (phys & 7) * per_xcd + (phys >> 3);
+// Workgroups are dispatched round-robin over the 8 XCDs. Logical workgroups are grouped in
+// blocks of kXcdBlock consecutive ones (neighbouring tiles, which share most of their line
+// windows, so they reuse one XCD's L2), and the blocks are dealt round-robin to the XCDs,
+// so every XCD gets a share of cheap and expensive tiles.
+constexpr int64_t kXcdBlock = 16;
+__device__ __forceinline__ int64_t xcd_logical_wg(int64_t phys) {
+  const int64_t xcd = phys & 7, slot = phys >> 3;
+  return (slot / kXcdBlock) * (8 * kXcdBlock) + xcd * kXcdBlock + (slot % kXcdBlock);
 }
 
 // First index i in [0, n) with a[i] >= key (n if none); LE selects a[i] > key instead.
@@ -151,7 +156,7 @@ struct ItemInfo {
 template <int P>
 __device__ __forceinline__ bool decode_item(const TileArgs& A, int lane, ItemInfo& it) {
   const int64_t phys = blockIdx.x;
-  const int64_t wg = xcd_logical_wg(phys, A.per_xcd);
+  const int64_t wg = xcd_logical_wg(phys);
   // the wave index is wave-uniform; say so, so that everything derived from it is scalar
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t item = wg * kWavesPerWG + wave;
@@ -159,7 +164,8 @@ __device__ __forceinline__ bool decode_item(const TileArgs& A, int lane, ItemInf
   it.s = (int)(item % A.split);
   const int64_t r = item / A.split;
   it.k = (int)(r % A.n_pt);
-  const int64_t tile = r / A.n_pt;
+  // tiles are issued in the order the host chose (most expensive first)
+  const int64_t tile = A.tile_order ? (int64_t)A.tile_order[r / A.n_pt] : r / A.n_pt;
   it.j0 = tile * (int64_t)(kWave * P);
   const int64_t jl = min(it.j0 + (int64_t)(kWave * P), A.n_grid) - 1;
   const int pt = A.pt0 + it.k;
@@ -211,7 +217,7 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
   for (int p = 0; p < P; ++p) {
     int c = 0;
     float xr = 0.0f;
-    int bnd = 0;
+    int bnd = 0, var = 0;
     if (rows.valid[p]) {
       const double da = rows.ra[p] - nu0, db = rows.rb[p] - nu0;
       const bool none = (da > lr.cut) || (db < -lr.cut);
@@ -220,9 +226,11 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
         if (!F64 && (da > 0.0 || db < 0.0)) {
           const bool left = da > 0.0;   // the line lies left of the row
           const float x = (float)((left ? da : db) * lr.ib);
-          if (fmaf(y, y, x * x) >= kFarR2) {
+          const float r2n = fmaf(x, x, y * y);
+          if (r2n >= kFarR2) {
             c = left ? 2 : 3;
             xr = x;
+            var = asym_variant(r2n);
             const double* rv = rowv + kWave * p;
             if (left) {
               // last lane with nu - nu0 <= cut (lane 0 qualifies: da <= cut)
@@ -250,24 +258,21 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
     cls |= c << (2 * p);
     if constexpr (!F64) {
       r.xr[p] = xr;
-      r.bnd[p] = (signed char)bnd;
+      r.rinfo[p] = (unsigned char)(bnd | (var << 6));
     }
   }
   int mode = cls == 0 ? kSkip : kRows;
   if constexpr (!F64) {
-    // whole-tile far blocks; the two-term series when the point nearest to the line is
-    // already at |z| >= 80
+    // whole-tile series blocks: every row on one side with every point inside the cut;
+    // the variant is that of the tile's point nearest to the line
     constexpr int kAllLeft = (int)(0xAAAAAAAAu & ((1u << (2 * P)) - 1u));
     constexpr int kAllRight = (int)(0xFFFFFFFFu & ((1u << (2 * P)) - 1u));
     bool full = true;
 #pragma unroll
     for (int p = 0; p < P; ++p)
-      full = full && (r.bnd[p] == (cls == kAllLeft ? kWave - 1 : 0));
-    if (cls == kAllLeft && full) {
-      mode = fmaf(y, y, r.xr[0] * r.xr[0]) >= kVFarR2 ? kLeftVFar : kLeftFar;
-    } else if (cls == kAllRight && full) {
-      mode = fmaf(y, y, r.xr[P - 1] * r.xr[P - 1]) >= kVFarR2 ? kRightVFar : kRightFar;
-    }
+      full = full && ((r.rinfo[p] & 63) == (cls == kAllLeft ? kWave - 1 : 0));
+    if (cls == kAllLeft && full) mode = kLeft + (r.rinfo[0] >> 6);
+    else if (cls == kAllRight && full) mode = kRight + (r.rinfo[P - 1] >> 6);
   }
   r.cls = cls;
   r.mode = mode;
@@ -277,7 +282,6 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
   } else {
     r.y = y;
     r.y2 = y * y;
-    r.m2y2 = -2.0f * r.y2;
     r.ib32 = (float)lr.ib;
     r.sc = 0.0f;
     r.scy = 0.0f;
@@ -292,16 +296,15 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
   s = t;
 }
 
-// Contributions of one line to all P rows when every row is in the far tier (VFAR: the
-// two-term series), x from the row end.
-template <int P, bool VFAR>
-__device__ __forceinline__ void far_values(const Rec<false, P>& q, const float (&off)[P],
-                                           float (&v)[P]) {
+// Contributions of one line to all P rows when every row is in the series region with
+// NT terms, x from the row end.
+template <int P, int NT>
+__device__ __forceinline__ void series_values(const Rec<false, P>& q, const float (&off)[P],
+                                              float (&v)[P]) {
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const float x = fmaf(off[p], q.ib32, q.xr[p]);
-    const float r2 = fmaf(x, x, q.y2);
-    v[p] = q.scy * (VFAR ? voigt_vfar32_scaled(q.m2y2, r2) : voigt_far32_scaled(q.y2, r2));
+    v[p] = q.scy * asym_scaled<NT>(q.y2, fmaf(x, x, q.y2));
   }
 }
 
@@ -384,13 +387,19 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
         // Every path only produces the P contributions of this line; one shared Kahan
         // update follows, so the sums live in fixed registers.
         float v[P];
-        if (mode >= kLeftFar) {
-          // The line lies left (or right) of the whole tile and every row is inside the
-          // cut and in the far tier: one branch-free block over the P independent rows.
-          if (mode == kLeftVFar) far_values<P, true>(q, da32, v);
-          else if (mode == kRightVFar) far_values<P, true>(q, db32, v);
-          else if (mode == kLeftFar) far_values<P, false>(q, da32, v);
-          else far_values<P, false>(q, db32, v);
+        if (mode >= kLeft) {
+          // The line lies left (or right) of the whole tile and every point is inside the
+          // cut and in the series region: one branch-free block over the P rows.
+          switch (mode) {
+            case kLeft + 0: series_values<P, 2>(q, da32, v); break;
+            case kLeft + 1: series_values<P, 3>(q, da32, v); break;
+            case kLeft + 2: series_values<P, 4>(q, da32, v); break;
+            case kLeft + 3: series_values<P, 6>(q, da32, v); break;
+            case kRight + 0: series_values<P, 2>(q, db32, v); break;
+            case kRight + 1: series_values<P, 3>(q, db32, v); break;
+            case kRight + 2: series_values<P, 4>(q, db32, v); break;
+            default: series_values<P, 6>(q, db32, v); break;
+          }
         } else {
           const int cls = __builtin_amdgcn_readfirstlane(q.cls);
 #pragma unroll
@@ -398,14 +407,16 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
             const int cp = (cls >> (2 * p)) & 3;
             v[p] = 0.0f;
             if (cp == 1) {
-              // general: FP64 offset and cut test, tier chosen per point
+              // general: FP64 offset and cut test, series or core per point
               const double d = nu[p] - q.nu0;
               if (fabs(d) <= q.cut) v[p] = q.sc * voigt_k32(d * q.ib, q.y);
             } else if (cp >= 2) {
-              // whole row in the far tier; the lanes inside the cut are one side of bnd
+              // whole row in the series region; the lanes inside the cut are one side of bnd
+              const int info = __builtin_amdgcn_readfirstlane((int)q.rinfo[p]);
               const float x = fmaf(cp == 2 ? da32[p] : db32[p], q.ib32, q.xr[p]);
-              const float f = q.scy * voigt_far32_scaled(q.y2, fmaf(x, x, q.y2));
-              const bool in = cp == 2 ? (lane <= q.bnd[p]) : (lane >= q.bnd[p]);
+              const float f = q.scy * asym_scaled_v(info >> 6, q.y2, fmaf(x, x, q.y2));
+              const int bnd = info & 63;
+              const bool in = cp == 2 ? (lane <= bnd) : (lane >= bnd);
               v[p] = in ? f : 0.0f;
             }
           }

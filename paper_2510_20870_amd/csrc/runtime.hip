@@ -181,12 +181,48 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
   const size_t per_pt = std::max<size_t>(
       1, (size_t)p.rec_n * 32 + (p.split > 1 ? (size_t)p.split * G.n * 8 : 0));
   p.pt_batch = (int)std::max<size_t>(1, std::min<size_t>(npts, cap / per_pt));
+  // issue order: tiles by decreasing number of lines within the largest cut (from the
+  // sampled index), so the most expensive work items start first
+  std::vector<int64_t> cost(p.n_tiles);
+  const std::vector<double>& sm = L.sample;
+  for (int64_t t = 0; t < p.n_tiles; ++t) {
+    const int64_t j0 = t * tile, j1 = std::min<int64_t>(j0 + tile, (int64_t)G.n) - 1;
+    const double lo = G.host[j0] - o.cut_cm1, hi = G.host[j1] + o.cut_cm1;
+    cost[t] = (int64_t)(std::upper_bound(sm.begin(), sm.end(), hi) -
+                        std::lower_bound(sm.begin(), sm.end(), lo));
+  }
+  // coarse cost classes (ratio 2^(1/4)) keep neighbouring tiles of similar cost together,
+  // so that they still share their line windows in one XCD's L2
+  std::vector<int> cls(p.n_tiles);
+  for (int64_t t = 0; t < p.n_tiles; ++t)
+    cls[t] = (int)std::floor(4.0 * std::log2(1.0 + (double)cost[t]));
+  p.tile_order.resize(p.n_tiles);
+  std::iota(p.tile_order.begin(), p.tile_order.end(), 0);
+  std::stable_sort(p.tile_order.begin(), p.tile_order.end(),
+                   [&](int a, int b) { return cls[a] > cls[b]; });
   return p;
 }
 
+int upload_order(Ctx& c, const Plan& p, hipStream_t st) {
+  const size_t bytes = p.tile_order.size() * sizeof(int);
+  if (c.order_host == p.tile_order && c.order_buf.ptr) return XS_OK;
+  if (c.pts_event_valid) {
+    hipError_t e = hipEventSynchronize(c.pts_event);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  }
+  int rc = c.scratch(c.order_buf, bytes, "tile order");
+  if (rc) return rc;
+  hipError_t e = hipMemcpy(c.order_buf.ptr, p.tile_order.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "tile order upload");
+  c.order_host = p.tile_order;
+  (void)st;
+  return XS_OK;
+}
+
 int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Plan& p,
-                 const double* pts_dev, double* out_dev, void* rec_dev, void* part_dev,
-                 hipStream_t st, unsigned long long* counts) {
+                 const double* pts_dev, const int* order_dev, double* out_dev, void* rec_dev,
+                 void* part_dev, hipStream_t st, unsigned long long* counts) {
+  const int* tile_order = order_dev;
   const bool f64 = o.precision == XS_FP64;
   CutDev cut;
   cut.kind = o.cutoff_kind == XS_CUT_FIXED ? kCutFixed : kCutMinFwhm;
@@ -221,11 +257,11 @@ int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Pl
     A.n_tiles = p.n_tiles;
     A.n_items = p.n_tiles * nb * A.split;
     A.n_wg = (A.n_items + kWavesPerWG - 1) / kWavesPerWG;
-    A.per_xcd = (A.n_wg + 7) / 8;
+    A.tile_order = tile_order;
     A.recs = (const LineRec*)rec_dev;
     A.rec_lo = p.rec_lo;
     A.rec_n = p.rec_n;
-    const int64_t phys = A.per_xcd * 8;
+    const int64_t phys = phys_workgroups(A.n_wg);
     if (counts) {
       A.counts = counts;
       e = launch_count(A, p.P, st, phys);
@@ -324,7 +360,8 @@ void xs_destroy(xs_ctx* c) {
     c->dev_free(kv.second->d, kv.second->bytes);
     delete kv.second;
   }
-  for (Scratch* s : {&c->pts_buf, &c->part_buf, &c->out_buf, &c->count_buf, &c->rec_buf})
+  for (Scratch* s : {&c->pts_buf, &c->part_buf, &c->out_buf, &c->count_buf, &c->rec_buf,
+                     &c->order_buf})
     if (s->ptr) c->dev_free(s->ptr, s->cap);
   if (c->pts_pinned) (void)hipHostFree(c->pts_pinned);
   if (c->pts_event) (void)hipEventDestroy(c->pts_event);
@@ -517,6 +554,7 @@ int xs_set_grid(xs_ctx* c, const double* nu, size_t n, xs_grid_t* out) {
   G->bytes = n * sizeof(double);
   G->first = nu[0];
   G->last = nu[n - 1];
+  G->host.assign(nu, nu + n);
   int rc = c->dev_alloc((void**)&G->d, G->bytes, "grid");
   if (rc) {
     delete G;
@@ -601,8 +639,10 @@ int xs_compute(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t 
     if (rc) return rc;
     out_dev = (double*)c->out_buf.ptr;
   }
-  rc = enqueue_path(*L, *G, *opts, p, (const double*)c->pts_buf.ptr, out_dev, c->rec_buf.ptr,
-                    part, st);
+  rc = upload_order(*c, p, st);
+  if (rc) return rc;
+  rc = enqueue_path(*L, *G, *opts, p, (const double*)c->pts_buf.ptr,
+                    (const int*)c->order_buf.ptr, out_dev, c->rec_buf.ptr, part, st);
   if (rc) return rc;
   e = hipEventRecord(c->pts_event, st);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -649,8 +689,11 @@ int xs_count_evals(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, siz
   if (rc) return rc;
   e = launch_fill_u64((unsigned long long*)c->count_buf.ptr, (int64_t)npts, st);
   if (e != hipSuccess) return hip_fail(e, "counter clear");
-  rc = enqueue_path(*L, *G, o, p, (const double*)c->pts_buf.ptr, nullptr, c->rec_buf.ptr,
-                    nullptr, st, (unsigned long long*)c->count_buf.ptr);
+  rc = upload_order(*c, p, st);
+  if (rc) return rc;
+  rc = enqueue_path(*L, *G, o, p, (const double*)c->pts_buf.ptr,
+                    (const int*)c->order_buf.ptr, nullptr, c->rec_buf.ptr, nullptr, st,
+                    (unsigned long long*)c->count_buf.ptr);
   if (rc) return rc;
   e = hipMemcpyAsync(counts_out, c->count_buf.ptr, npts * sizeof(uint64_t),
                      hipMemcpyDeviceToHost, st);
@@ -672,6 +715,8 @@ struct xs_graph {
   size_t part_bytes = 0;
   void* rec = nullptr;
   size_t rec_bytes = 0;
+  void* order = nullptr;
+  size_t order_bytes = 0;
 };
 
 int xs_graph_create(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t npts,
@@ -725,6 +770,16 @@ int xs_graph_create(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, si
     xs_graph_destroy(g);
     return rc;
   }
+  g->order_bytes = p.tile_order.size() * sizeof(int);
+  rc = c->dev_alloc(&g->order, g->order_bytes, "graph tile order");
+  if (rc == XS_OK) {
+    e = hipMemcpy(g->order, p.tile_order.data(), g->order_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = hip_fail(e, "graph tile order upload");
+  }
+  if (rc) {
+    xs_graph_destroy(g);
+    return rc;
+  }
   hipStream_t cs = nullptr;
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) {
@@ -733,7 +788,8 @@ int xs_graph_create(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, si
   }
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    rc = enqueue_path(*L, *G, *opts, p, (const double*)g->pts, sigma_dev, g->rec, g->part, cs);
+    rc = enqueue_path(*L, *G, *opts, p, (const double*)g->pts, (const int*)g->order, sigma_dev,
+                      g->rec, g->part, cs);
     hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
     if (rc == XS_OK && e2 != hipSuccess) rc = hip_fail(e2, "hipStreamEndCapture");
   } else {
@@ -767,6 +823,7 @@ void xs_graph_destroy(xs_graph* g) {
   if (g->pts) g->ctx->dev_free(g->pts, g->pts_bytes);
   if (g->part) g->ctx->dev_free(g->part, g->part_bytes);
   if (g->rec) g->ctx->dev_free(g->rec, g->rec_bytes);
+  if (g->order) g->ctx->dev_free(g->order, g->order_bytes);
   delete g;
 }
 

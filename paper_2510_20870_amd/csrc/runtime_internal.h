@@ -37,6 +37,7 @@ struct GridRes {
   size_t n = 0;
   size_t bytes = 0;
   double first = 0.0, last = 0.0;   // host copies of the end points
+  std::vector<double> host;         // host copy of the grid
   std::atomic<int> refs{0};
 };
 
@@ -49,6 +50,7 @@ struct Plan {
   int64_t rec_n = 0;
   int npts = 0;
   int pt_batch = 1;        // (P, T) points per parameter/tile launch pair
+  std::vector<int> tile_order;   // tiles by decreasing estimated work
   size_t rec_bytes() const { return (size_t)rec_n * pt_batch * 32; }
   size_t part_bytes(size_t n_grid) const {
     return split > 1 ? (size_t)pt_batch * split * n_grid * sizeof(double) : 0;
@@ -71,7 +73,8 @@ struct xs_ctx {
   std::unordered_map<uint64_t, xs::LinesRes*> lines;
   std::unordered_map<uint64_t, xs::GridRes*> grids;
   // scratch of xs_compute / xs_count_evals (single caller thread)
-  xs::Scratch pts_buf, part_buf, out_buf, count_buf, rec_buf;
+  xs::Scratch pts_buf, part_buf, out_buf, count_buf, rec_buf, order_buf;
+  std::vector<int> order_host;           // content of order_buf
   void* pts_pinned = nullptr;
   size_t pts_pinned_cap = 0;
   std::vector<double> pts_host;          // content of pts_buf
@@ -101,8 +104,10 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
 // tile kernel and (split > 1) the fixed-order reduction; with counts != nullptr the count
 // kernel instead of tile + reduction.
 int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Plan& p,
-                 const double* pts_dev, double* out_dev, void* rec_dev, void* part_dev,
-                 hipStream_t st, unsigned long long* counts = nullptr);
+                 const double* pts_dev, const int* order_dev, double* out_dev, void* rec_dev,
+                 void* part_dev, hipStream_t st, unsigned long long* counts = nullptr);
+// Upload the plan's tile order into the context buffer (skipped when unchanged).
+int upload_order(Ctx& c, const Plan& p, hipStream_t st);
 
 inline void free_lines_res(Ctx& c, LinesRes* L) {
   c.dev_free(L->base, L->bytes);

@@ -7,26 +7,24 @@
 //
 // Regions, chosen on r^2 = x^2 + y^2 (x may have either sign):
 //
-//  * far  (r^2 >= 400): the asymptotic expansion w(z) ~ (i/sqrt(pi)) (1/z)(1 + 1/(2z^2)
-//    + 3/(4z^4)). With u = 1/r^2 and w = y^2 u (so that x^2 u = 1 - w) its real part is
-//        K = (y u / sqrt(pi)) (1 + u (3/2 - 2w) + u^2 (15/4 - 15w + 12w^2)),
-//    every term proportional to y (no cancellation); the next term is below 2.1e-7
-//    relative at |z| = 20. For r^2 >= 6400 the u^2 term is dropped (<= 9.2e-8). x enters
-//    only through r^2 = fma(x, x, y^2); one reciprocal.
-//  * mid  (64 <= r^2 < 400): 4-node Gauss-Hermite quadrature of
-//        w(z) = (i/pi) int exp(-t^2)/(z - t) dt,
-//    whose real part (y/pi) sum_k w_k / ((x - t_k)^2 + y^2) is a sum of positive terms:
-//    no cancellation, so FP32 keeps its relative accuracy (<= 1e-6 at |z| >= 8).
-//  * core (r^2 < 64): Weideman's (1994) rational series with N = 40 terms,
+//  * |z| >= 7: the asymptotic expansion w(z) ~ (i/sqrt(pi)) sum_k a_k / z^(2k+1),
+//    a_k = (2k-1)!!/2^k. With u = 1/r^2, w = y^2 u and cos(theta) = x/|z|, the real part of
+//    i/z^(2k+1) is y u^(k+1) U_2k(cos theta) (Chebyshev polynomial of the second kind), so
+//        K = (y u / sqrt(pi)) sum_k a_k u^k V_k,   V_0 = 1, V_1 = 3 - 4w,
+//        V_(k+1) = (2 - 4w) V_k - V_(k-1)   (|2 - 4w| <= 2: a stable recurrence).
+//    Every term is proportional to y, so near the real axis there is no cancellation and
+//    FP32 keeps its relative accuracy; x enters only through r^2 = fma(x, x, y^2). The
+//    number of terms NT is chosen by |z| (measured FP32 error against scipy's wofz):
+//      NT = 2 for |z| >= 80 (<= 4.1e-7), 3 for |z| >= 20 (<= 5.5e-7),
+//      4 for |z| >= 13 (<= 3.9e-7), 6 for |z| >= 7 (<= 5.1e-7).
+//  * core (|z| < 7): Weideman's (1994) rational series with N = 40 terms,
 //        w(z) ~ 2 p(Z)/(L - iz)^2 + pi^{-1/2}/(L - iz),  Z = (L + iz)/(L - iz),
 //    L = 2^{-1/4} sqrt(N), evaluated in FP64: near the real axis Re w is tiny beside
-//    |w|, and only FP64 keeps the cancellation below 1e-8 relative there.
+//    |w| (1e7 times smaller at y = 5e-7), and only FP64 keeps the cancellation below
+//    1e-8 relative there.
 //
-// A pair of symmetric nodes +-t with weight w contributes
-//     w [1/((x-t)^2+y^2) + 1/((x+t)^2+y^2)] = 2w u (1 + t^2 u) / ((1 - t^2 u)^2 + 4 t^2 v^2)
-// with u = 1/r^2 and v = y u, which keeps every intermediate of order one (no overflow at
-// x ~ 1e5 in FP32) and needs one reciprocal per region plus one for the combined
-// denominator.
+// The FP64 path uses Gauss-Hermite quadrature (positive sums) outside |z| = 8 instead:
+// 4 nodes for |z| >= 40, 8 nodes for 8 <= |z| < 40, and the same Weideman core.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -52,10 +50,8 @@ constexpr double kGH8_t[4] = {0.38118699020732211685, 1.15719371244678019472,
 constexpr double kGH8_w[4] = {0.66114701255824129103, 0.20780232581489187955,
                               0.01707798300741347546, 0.00019960407221136762};
 
-constexpr float kFarR2 = 400.0f;    // |z| >= 20 (FP32 far tier)
-constexpr float kVFarR2 = 6400.0f;  // |z| >= 80 (FP32 two-term far tier)
 constexpr double kFarR2_64 = 1600.0; // |z| >= 40 (FP64 far tier)
-constexpr float kMidR2 = 64.0f;     // |z| >= 8
+constexpr double kMidR2_64 = 64.0;   // |z| >= 8 (FP64 mid tier)
 constexpr int kWeidN = 40;
 
 // Reciprocals: the hardware v_rcp on the device (about 1 ulp), IEEE division on the host.
@@ -81,47 +77,51 @@ XS_HD double rcp64(double a) {
 }
 
 // ---------------------------------------------------------------- FP32 tiers
-// Every tier returns K itself, given r2 = x^2 + y^2 and y.
+constexpr float kT2R2 = 6400.0f;   // |z| >= 80: two terms
+constexpr float kT3R2 = 400.0f;    // |z| >= 20: three terms
+constexpr float kT4R2 = 169.0f;    // |z| >= 13: four terms
+constexpr float kT6R2 = 49.0f;     // |z| >= 7: six terms; below: FP64 core
+constexpr float kFarR2 = kT6R2;    // the FP32 series region
 
-// far tier: returns K sqrt(pi) / y = u (1 + u (3/2 - 2w + u (15/4 - 15w + 12w^2))),
-// w = y^2 u
-XS_HD float voigt_far32_scaled(float y2, float r2) {
+// Returns K sqrt(pi) / y = u sum_{k < NT} a_k u^k V_k for r2 = x^2 + y^2, y2 = y^2.
+template <int NT>
+XS_HD float asym_scaled(float y2, float r2) {
   const float u = rcp32(r2);
   const float w = y2 * u;
-  const float q2 = fmaf(fmaf(12.0f, w, -15.0f), w, 3.75f);
-  const float q1 = fmaf(-2.0f, w, 1.5f);
-  return u * fmaf(u, fmaf(u, q2, q1), 1.0f);
+  if constexpr (NT == 2) {
+    return u * fmaf(u, fmaf(-2.0f, w, 1.5f), 1.0f);
+  } else if constexpr (NT == 3) {
+    const float q2 = fmaf(fmaf(12.0f, w, -15.0f), w, 3.75f);
+    const float q1 = fmaf(-2.0f, w, 1.5f);
+    return u * fmaf(u, fmaf(u, q2, q1), 1.0f);
+  } else {
+    constexpr float a[6] = {1.0f, 0.5f, 0.75f, 1.875f, 6.5625f, 29.53125f};
+    const float t = fmaf(-4.0f, w, 2.0f);
+    float V[NT];
+    V[0] = 1.0f;
+    V[1] = t + 1.0f;
+#pragma unroll
+    for (int k = 2; k < NT; ++k) V[k] = fmaf(t, V[k - 1], -V[k - 2]);
+    float S = a[NT - 1] * V[NT - 1];
+#pragma unroll
+    for (int k = NT - 2; k >= 1; --k) S = fmaf(u, S, a[k] * V[k]);
+    return u * fmaf(u, S, 1.0f);
+  }
 }
 
-// two-term far tier for |z| >= 80: returns K sqrt(pi) / y = u (1 + u (3/2 - 2w)); with
-// m2y2 = -2 y^2 precomputed per line this is three operations after the reciprocal
-XS_HD float voigt_vfar32_scaled(float m2y2, float r2) {
-  const float u = rcp32(r2);
-  return u * fmaf(u, fmaf(m2y2, u, 1.5f), 1.0f);
+// The number of series terms a point at r2 >= kT6R2 needs, as a variant code 0..3.
+XS_HD int asym_variant(float r2) {
+  return r2 >= kT2R2 ? 0 : r2 >= kT3R2 ? 1 : r2 >= kT4R2 ? 2 : 3;
 }
 
-XS_HD float voigt_far32(float r2, float y) {
-  return (float)kInvSqrtPi * y * voigt_far32_scaled(y * y, r2);
-}
-
-// mid tier, two node pairs
-XS_HD float voigt_mid32(float r2, float y) {
-  constexpr float t1s = (float)(kGH4_t1 * kGH4_t1), t2s = (float)(kGH4_t2 * kGH4_t2);
-  constexpr float f1 = 4.0f * t1s, f2 = 4.0f * t2s;
-  constexpr float w1 = (float)(2.0 * kGH4_w1), w2 = (float)(2.0 * kGH4_w2);
-  constexpr float w1t = (float)(2.0 * kGH4_w1 * kGH4_t1 * kGH4_t1);
-  constexpr float w2t = (float)(2.0 * kGH4_w2 * kGH4_t2 * kGH4_t2);
-  const float u = rcp32(r2);
-  const float v = y * u;
-  const float q = v * v;
-  const float a1 = fmaf(-t1s, u, 1.0f);
-  const float a2 = fmaf(-t2s, u, 1.0f);
-  const float d1 = fmaf(a1, a1, f1 * q);
-  const float d2 = fmaf(a2, a2, f2 * q);
-  const float n1 = fmaf(w1t, u, w1);
-  const float n2 = fmaf(w2t, u, w2);
-  const float num = fmaf(n1, d2, n2 * d1);
-  return (float)(1.0 / kPi) * v * num * rcp32(d1 * d2);
+// K * sqrt(pi) / y for variant code v (uniform across the wavefront at the call sites).
+XS_HD float asym_scaled_v(int v, float y2, float r2) {
+  switch (v) {
+    case 0: return asym_scaled<2>(y2, r2);
+    case 1: return asym_scaled<3>(y2, r2);
+    case 2: return asym_scaled<4>(y2, r2);
+    default: return asym_scaled<6>(y2, r2);
+  }
 }
 
 // ---------------------------------------------------------------- FP64 tiers
@@ -178,20 +178,21 @@ XS_HD double voigt_core64(double x, double y) {
   return fma(lpy, kInvSqrtPi, t) * iD;
 }
 
-// Full K in FP32 arithmetic for the far/mid tiers and FP64 for the core. x may be
-// negative (K is even in x).
+// Full K: the six-term FP32 series for |z| >= 7 (valid for every point there, so mixed
+// rows do not diverge over series lengths) and FP64 for the core. x may be negative (K is
+// even in x).
 XS_HD float voigt_k32(double xd, float y) {
   const float x = (float)xd;
-  const float r2 = fmaf(x, x, y * y);
-  if (r2 >= kFarR2) return voigt_far32(r2, y);
-  if (r2 >= kMidR2) return voigt_mid32(r2, y);
+  const float y2 = y * y;
+  const float r2 = fmaf(x, x, y2);
+  if (r2 >= kT6R2) return (float)kInvSqrtPi * y * asym_scaled<6>(y2, r2);
   return (float)voigt_core64(xd, (double)y);
 }
 
 XS_HD double voigt_k64(double x, double y) {
   const double r2 = fma(x, x, y * y);
   if (r2 >= kFarR2_64) return voigt_far64(r2, y);
-  if (r2 >= (double)kMidR2) return voigt_mid64(r2, y);
+  if (r2 >= kMidR2_64) return voigt_mid64(r2, y);
   return voigt_core64(x, y);
 }
 
