@@ -26,12 +26,57 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# per-eval algorithmic FP32 work of the far-tier evaluation (FMA = 2 FLOPs):
-# offset 1, cut test 1, x 1, r^2 2, 1/r^2 1, v 1, v^2 1, (1 - u/2) 2, 2v^2 1, d 2,
-# numerator 2, 1/d 1, three products 3, scale 1, Kahan add 4  -> 25
-FLOPS_PER_EVAL = 25.0
-PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (published)
+# Algorithmic FP32 work of one line-point evaluation in the far tier that carries almost
+# all evaluations (two-term asymptotic series; FMA = 2 FLOPs): x = off*(1/b_D) + x_row 2,
+# r^2 = x^2 + y^2 2, u = 1/r^2 1, w = y^2 u 1, 1.5 - 2w 2, 1 + u(..) 2, u*(..) 1, scale 1,
+# Kahan add 4 -> 16. Core and cut-edge evaluations do more work and count the same.
+FLOPS_PER_EVAL = 16.0
+# VALU peak without packed FP32 (the build disables packed FP32 instructions): 256 CUs x
+# 4 SIMDs x 16 lanes x 1 FMA (2 FLOPs) per clock x 2.4 GHz; the published 157.3 TFLOP/s
+# needs packed FP32.
+PEAK_ALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ("kernels.hip", "voigt.h", "physics.h", "kernel_args.h", "weideman_coef.h")
+COUNTER_PROFILE = os.path.join(ROOT, "profiles", "tile_kernel_mid_counters.md")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_20870_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """HBM bytes per tile-kernel launch from the committed counter profile, or None when
+    the kernel sources changed since it was taken."""
+    import re
+    try:
+        with open(COUNTER_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (m_hash and m_bytes) or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def copy_probe():
+    """A plain device-to-device copy of 256 MiB, three times: the calibration run for the
+    FETCH_SIZE / WRITE_SIZE counters (bytes per dispatch are known exactly)."""
+    import torch
+    n = 1 << 25
+    src = torch.arange(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8, "reads": n * 8, "writes": n * 8}), flush=True)
 
 
 def log(*a):
@@ -46,14 +91,19 @@ def main():
     ap.add_argument("--workload", default="mid")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--cpu-points", type=int, default=8192,
+    ap.add_argument("--cpu-points", type=int, default=131072,
                     help="grid points in the oracle sample (16 windows)")
     ap.add_argument("--pts-per-lane", type=int, default=0)
     ap.add_argument("--split", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
     ap.add_argument("--gen-workers", type=int, default=0,
                     help="processes generating the synthetic list (0 = one per core, max 16)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run the plain-copy calibration kernel (for HBM counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -101,24 +151,23 @@ def main():
         for _ in range(warmup):
             ctx.compute(h, g, [(P, T)], opts, out=out, stream=stream)
         torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(steps)]
+        # tile-kernel launches are bracketed by HIP events on the stream they run on
+        ctx.set_kernel_timing(True)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for a, b in evs:
-            a.record(stream)
+        for _ in range(steps):
             ctx.compute(h, g, [(P, T)], opts, out=out, stream=stream)
-            b.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
-        kms = [a.elapsed_time(b) for a, b in evs]
-        return wall, float(np.mean(kms)), float(np.min(kms))
+        kms, launches = ctx.kernel_time()
+        ctx.set_kernel_timing(False)
+        return wall, kms / max(1, launches), launches
 
-    wall32, k32, kmin32 = run(o32, args.steps, args.warmup)
+    wall32, k32, nl32 = run(o32, args.steps, args.warmup)
     sig32 = out.cpu().numpy()[0].copy()
     ms = wall32 / args.steps * 1e3
     value = evals * args.steps / wall32
-    log(f"fp32+kahan: {ms:.3f} ms/step, kernel {k32:.3f} ms (min {kmin32:.3f}), "
+    log(f"fp32+kahan: {ms:.3f} ms/step, tile kernel {k32:.3f} ms/launch ({nl32} launches), "
         f"{value:.4e} evals/s")
 
     fp64 = None
@@ -158,7 +207,10 @@ def main():
         if st["violations"]:
             log("PARITY VIOLATIONS", st)
 
-    achieved = evals * FLOPS_PER_EVAL / (k32 * 1e-3) / 1e12
+    # one tile launch covers the whole grid at the one (P, T) point: evals per launch
+    evals_per_launch = evals * args.steps / max(1, nl32)
+    achieved = evals_per_launch * FLOPS_PER_EVAL / (k32 * 1e-3) / 1e12
+    traffic = profiled_traffic()
     res = {
         "metric": "Voigt line-point evals/s at <=1e-4 rel err vs FP64",
         "value": value,
@@ -179,10 +231,15 @@ def main():
                    "evals_per_step": evals, "precision": "fp32 voigt + kahan, fp64 offsets",
                    "device": info},
         "max_rel_err": max_rel,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": None, "kernel_ms": k32,
-                     "flops_per_eval": FLOPS_PER_EVAL},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
+                     "traffic": traffic, "kernel": "xs_tile_kernel",
+                     "kernel_ms_per_launch": k32, "flops_per_eval": FLOPS_PER_EVAL,
+                     "evals_per_launch": evals_per_launch,
+                     "peak_basis": "256 CU x 64 lanes x FMA x 2.4 GHz (no packed FP32)",
+                     "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS,
+                     "hbm_frac": (traffic / (k32 * 1e-3) / 1e9 / PEAK_HBM_GBS
+                                  if traffic else None)},
         "fp64_path": fp64,
         "cpu_baseline": cpu,
     }

@@ -171,6 +171,15 @@ int xs_graph_create(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *
 int xs_graph_launch(xs_graph *g, void *stream);
 void xs_graph_destroy(xs_graph *g);
 
+/* Kernel timing (measurement of the tile kernel, the Voigt evaluation and accumulation
+ * step). With timing enabled, xs_compute and xs_count_evals record a HIP event pair on
+ * the launch stream around every tile (or count) kernel launch; xs_kernel_time waits for
+ * the recorded events, returns the summed duration in ms and the number of launches since
+ * the previous call, and starts a new period. Graph capture records no events. Enabling
+ * or disabling discards events not yet read. */
+int xs_set_kernel_timing(xs_ctx *ctx, int enable);
+int xs_kernel_time(xs_ctx *ctx, double *ms_sum, int *n_launches);
+
 /* The Voigt function K(x, y) = Re w(x + iy) as the kernels evaluate it, for n host
  * points: on the device (xs_eval_voigt) or compiled for the host (xs_eval_voigt_host).
  * precision: XS_FP32_KAHAN (FP32 tiers) or XS_FP64. */

@@ -203,6 +203,19 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
   return p;
 }
 
+int KernelTimer::record(hipStream_t st) {
+  if (used == ev.size()) {
+    hipEvent_t e = nullptr;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return hip_fail(r, "hipEventCreate");
+    ev.push_back(e);
+  }
+  hipError_t r = hipEventRecord(ev[used], st);
+  if (r != hipSuccess) return hip_fail(r, "hipEventRecord");
+  ++used;
+  return XS_OK;
+}
+
 int upload_order(Ctx& c, const Plan& p, hipStream_t st) {
   const size_t bytes = p.tile_order.size() * sizeof(int);
   if (c.order_host == p.tile_order && c.order_buf.ptr) return XS_OK;
@@ -221,7 +234,8 @@ int upload_order(Ctx& c, const Plan& p, hipStream_t st) {
 
 int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Plan& p,
                  const double* pts_dev, const int* order_dev, double* out_dev, void* rec_dev,
-                 void* part_dev, hipStream_t st, unsigned long long* counts) {
+                 void* part_dev, hipStream_t st, unsigned long long* counts,
+                 KernelTimer* tm) {
   const int* tile_order = order_dev;
   const bool f64 = o.precision == XS_FP64;
   CutDev cut;
@@ -262,15 +276,20 @@ int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Pl
     A.rec_lo = p.rec_lo;
     A.rec_n = p.rec_n;
     const int64_t phys = phys_workgroups(A.n_wg);
+    int rc = tm ? tm->record(st) : XS_OK;
+    if (rc) return rc;
     if (counts) {
       A.counts = counts;
       e = launch_count(A, p.P, st, phys);
       if (e != hipSuccess) return hip_fail(e, "count kernel launch");
-      continue;
+    } else {
+      A.out = (A.split == 1) ? out_dev : (double*)part_dev;
+      e = launch_tile(A, p.P, f64, p.W, st, phys);
+      if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
     }
-    A.out = (A.split == 1) ? out_dev : (double*)part_dev;
-    e = launch_tile(A, p.P, f64, p.W, st, phys);
-    if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
+    rc = tm ? tm->record(st) : XS_OK;
+    if (rc) return rc;
+    if (counts) continue;
     if (A.split > 1) {
       e = launch_reduce((const double*)part_dev, out_dev + (int64_t)pt0 * A.n_grid, A.n_grid,
                         nb, A.split, st);
@@ -365,7 +384,49 @@ void xs_destroy(xs_ctx* c) {
     if (s->ptr) c->dev_free(s->ptr, s->cap);
   if (c->pts_pinned) (void)hipHostFree(c->pts_pinned);
   if (c->pts_event) (void)hipEventDestroy(c->pts_event);
+  if (c->timer) {
+    for (hipEvent_t e : c->timer->ev) (void)hipEventDestroy(e);
+    delete c->timer;
+  }
   delete c;
+}
+
+int xs_set_kernel_timing(xs_ctx* c, int enable) {
+  if (!c) return fail(XS_EINVAL, "ctx is NULL");
+  if (enable && !c->timer) c->timer = new KernelTimer();
+  if (c->timer) c->timer->used = 0;
+  if (!enable && c->timer) {
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    for (hipEvent_t ev : c->timer->ev) {
+      (void)hipEventSynchronize(ev);
+      (void)hipEventDestroy(ev);
+    }
+    delete c->timer;
+    c->timer = nullptr;
+  }
+  return XS_OK;
+}
+
+int xs_kernel_time(xs_ctx* c, double* ms_sum, int* n_launches) {
+  if (!c) return fail(XS_EINVAL, "ctx is NULL");
+  if (!c->timer) return fail(XS_EINVAL, "kernel timing is not enabled");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  KernelTimer& t = *c->timer;
+  double sum = 0.0;
+  for (size_t k = 0; k + 1 < t.used; k += 2) {
+    e = hipEventSynchronize(t.ev[k + 1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, t.ev[k], t.ev[k + 1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    sum += ms;
+  }
+  if (ms_sum) *ms_sum = sum;
+  if (n_launches) *n_launches = (int)(t.used / 2);
+  t.used = 0;
+  return XS_OK;
 }
 
 int xs_device_info(xs_ctx* c, int* n_cu, size_t* lds_bytes, char* arch, size_t arch_len) {
@@ -642,7 +703,8 @@ int xs_compute(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t 
   rc = upload_order(*c, p, st);
   if (rc) return rc;
   rc = enqueue_path(*L, *G, *opts, p, (const double*)c->pts_buf.ptr,
-                    (const int*)c->order_buf.ptr, out_dev, c->rec_buf.ptr, part, st);
+                    (const int*)c->order_buf.ptr, out_dev, c->rec_buf.ptr, part, st, nullptr,
+                    c->timer);
   if (rc) return rc;
   e = hipEventRecord(c->pts_event, st);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -693,7 +755,7 @@ int xs_count_evals(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, siz
   if (rc) return rc;
   rc = enqueue_path(*L, *G, o, p, (const double*)c->pts_buf.ptr,
                     (const int*)c->order_buf.ptr, nullptr, c->rec_buf.ptr, nullptr, st,
-                    (unsigned long long*)c->count_buf.ptr);
+                    (unsigned long long*)c->count_buf.ptr, c->timer);
   if (rc) return rc;
   e = hipMemcpyAsync(counts_out, c->count_buf.ptr, npts * sizeof(uint64_t),
                      hipMemcpyDeviceToHost, st);

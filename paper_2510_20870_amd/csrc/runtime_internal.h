@@ -59,6 +59,13 @@ struct Plan {
 
 struct Server;  // serving loop (serve.hip)
 
+// HIP event pairs around tile-kernel launches (events are reused across periods).
+struct KernelTimer {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  int record(hipStream_t st);   // records the next event on st
+};
+
 }  // namespace xs
 
 struct xs_ctx {
@@ -82,6 +89,7 @@ struct xs_ctx {
   bool pts_event_valid = false;
   hipStream_t last_stream = nullptr;
   xs::Server* server = nullptr;
+  xs::KernelTimer* timer = nullptr;      // non-null while kernel timing is enabled
 
   bool reserve(size_t bytes);
   void release(size_t bytes);
@@ -105,7 +113,8 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
 // kernel instead of tile + reduction.
 int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Plan& p,
                  const double* pts_dev, const int* order_dev, double* out_dev, void* rec_dev,
-                 void* part_dev, hipStream_t st, unsigned long long* counts = nullptr);
+                 void* part_dev, hipStream_t st, unsigned long long* counts = nullptr,
+                 KernelTimer* tm = nullptr);
 // Upload the plan's tile order into the context buffer (skipped when unchanged).
 int upload_order(Ctx& c, const Plan& p, hipStream_t st);
 

@@ -89,6 +89,8 @@ _SIGS = {
                          C.POINTER(Opts), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "xs_graph_launch": ([C.c_void_p, C.c_void_p], C.c_int),
     "xs_graph_destroy": ([C.c_void_p], None),
+    "xs_set_kernel_timing": ([C.c_void_p, C.c_int], C.c_int),
+    "xs_kernel_time": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)], C.c_int),
     "xs_eval_voigt": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p],
                       C.c_int),
     "xs_eval_voigt_host": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p],
@@ -285,6 +287,17 @@ class Context:
         self._check(self._L.xs_eval_voigt(self.h, _ptr(x), _ptr(y), x.size, precision,
                                           _ptr(out)))
         return out
+
+    # ------------------------------------------------------------------ timing
+    def set_kernel_timing(self, enable: bool = True):
+        self._check(self._L.xs_set_kernel_timing(self.h, int(bool(enable))))
+
+    def kernel_time(self):
+        """(summed ms, launches) of the tile kernel since the previous call."""
+        ms = C.c_double()
+        n = C.c_int()
+        self._check(self._L.xs_kernel_time(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     # ------------------------------------------------------------------ graphs
     def graph_create(self, lines: int, grid: int, pts, opts: Opts, out) -> "Graph":
