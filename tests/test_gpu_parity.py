@@ -3,7 +3,7 @@ on seeded inputs, plus determinism, edge cases and error paths.
 
 Tolerance (the acceptance rule of the method's target): per spectrum, with m = max(ref),
 |sigma - ref|/ref <= 1e-4 where ref > 1e-8 m, |sigma - ref| <= 1e-8 m elsewhere. The
-FP32 error budget (Voigt approximation <= 1.3e-6, argument rounding, FP32 strength scale,
+FP32 error budget (Voigt approximation <= 5.5e-7, argument rounding, FP32 strength scale,
 Kahan summation) is below 1e-5, so the tests also assert that tighter bound where noted.
 """
 import numpy as np
