@@ -171,6 +171,69 @@ int xs_graph_create(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *
 int xs_graph_launch(xs_graph *g, void *stream);
 void xs_graph_destroy(xs_graph *g);
 
+/* ---------------------------------------------------------------------- serving
+ * A request loop for cross-section requests (continuous batching). A server thread owned
+ * by the context admits queued requests while an execution slot (a HIP stream) and room
+ * in the serving arena (one device allocation, sub-allocated per request) are free; the
+ * work of admitted requests runs concurrently on the device, and a finished request
+ * releases its slot and memory at once, so the next queued one starts while others are
+ * still running. Admission is in arrival order; a request whose footprint does not fit
+ * yet may be passed by later ones that fit, at most max_bypass times, after which
+ * admission waits for it. A request's result depends only on its own inputs and options
+ * (the launch shape is planned from them alone), so it is bitwise the same computed alone
+ * (xs_compute) or in any mix. Footprint = records (32 B per line that can reach the grid
+ * and per P-T point of a batch) + split partials + the output when it goes to host
+ * memory + the grid of a window request + the point table and tile order.
+ * The lines (and grid) of a request stay referenced until it is done: unloading them
+ * meanwhile fails with XS_EBUSY. */
+typedef uint64_t xs_req_t;
+typedef struct {
+  int max_inflight;   /* requests on the device at once (streams); 0 = 4                 */
+  size_t mem_bytes;   /* serving arena; 0 = min(64 GiB, half of the free budget)         */
+  int max_bypass;     /* times a waiting request may be passed; 0 = 8, < 0 = never      */
+  int start_paused;   /* nonzero: queue requests but admit none until resumed            */
+} xs_serve_opts;
+/* Start the server (once per context; xs_submit starts one with defaults otherwise).
+ * Errors: XS_EBUSY (already running), XS_ENOMEM (arena does not fit the budget). */
+int xs_serve_start(xs_ctx *ctx, const xs_serve_opts *opts);
+/* Stop or resume admissions (requests already running are not affected). */
+int xs_serve_pause(xs_ctx *ctx, int paused);
+/* Queue sigma(grid; pts) like xs_compute. sigma_out: host memory (filled when the request
+ * is done) or, with out_on_device != 0, device memory written by the server's streams
+ * (valid once the request is done). *out receives the request handle. Errors at submit:
+ * XS_EINVAL, XS_ENOTFOUND, XS_ENOMEM (the footprint exceeds the whole arena). */
+int xs_submit(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts, size_t npts,
+              const xs_opts *opts, double *sigma_out, int out_on_device, xs_req_t *out);
+/* The same for the uniform grid nu_j = nu_start + j * step, j < n_points, built on the
+ * device inside the request's arena memory (no grid handle, no allocation). */
+int xs_submit_window(xs_ctx *ctx, xs_lines_t lines, double nu_start, double step,
+                     size_t n_points, const xs_pt *pts, size_t npts, const xs_opts *opts,
+                     double *sigma_out, int out_on_device, xs_req_t *out);
+/* *done = 1 once the request has finished (successfully, failed or cancelled). */
+int xs_poll(xs_ctx *ctx, xs_req_t req, int *done);
+/* Wait for the request (timeout_s < 0: no limit). Returns the request's final status
+ * (XS_OK, XS_ECANCELLED, or the error it failed with, whose message xs_last_error then
+ * gives), or XS_ETIMEOUT if it is still pending at the timeout. */
+int xs_wait(xs_ctx *ctx, xs_req_t req, double timeout_s);
+/* Cancel a queued request (XS_OK; it finishes with XS_ECANCELLED). A request already
+ * admitted runs to completion: XS_EBUSY. A finished one: XS_OK, no effect. */
+int xs_cancel(xs_ctx *ctx, xs_req_t req);
+/* Submit, admission and completion times in seconds on a monotonic clock (a time not yet
+ * reached is returned as -1). Completion is when the output is in sigma_out. */
+int xs_request_times(xs_ctx *ctx, xs_req_t req, double *t_submit, double *t_admit,
+                     double *t_done);
+/* Forget a finished request (XS_EBUSY while it is pending). */
+int xs_release(xs_ctx *ctx, xs_req_t req);
+/* Admission rule on a simulated clock (host only, no device): n requests arriving at
+ * arrive[i] (non-decreasing) that run for duration[i] once admitted and need footprint[i]
+ * bytes of an arena of mem_bytes with max_inflight slots, admitted by the same policy and
+ * arena allocator as the server. Writes admit_out[i], done_out[i] and the peak arena bytes
+ * in use. XS_ENOMEM if a footprint exceeds the arena. */
+int xs_sched_simulate(size_t n, const double *arrive, const double *duration,
+                      const uint64_t *footprint, uint64_t mem_bytes, int max_inflight,
+                      int max_bypass, double *admit_out, double *done_out,
+                      uint64_t *peak_bytes);
+
 /* Kernel timing (measurement of the tile kernel, the Voigt evaluation and accumulation
  * step). With timing enabled, xs_compute and xs_count_evals record a HIP event pair on
  * the launch stream around every tile (or count) kernel launch; xs_kernel_time waits for

@@ -71,5 +71,7 @@ hipError_t launch_reduce(const double* part, double* out, int64_t n_grid, int n_
 hipError_t launch_eval_voigt(const double* x, const double* y, int64_t n, int f64,
                              double* out, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);
+// g[j] = a + j * h (FP64, one rounding per operation, no contraction)
+hipError_t launch_fill_uniform(double* g, int64_t n, double a, double h, hipStream_t st);
 
 }  // namespace xs

@@ -501,6 +501,11 @@ __global__ void xs_fill_u64_kernel(unsigned long long* p, int64_t n) {
   if (t < n) p[t] = 0ull;
 }
 
+__global__ void xs_fill_uniform_kernel(double* __restrict__ g, int64_t n, double a, double h) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) g[t] = __dadd_rn(a, __dmul_rn((double)t, h));
+}
+
 __global__ void xs_eval_voigt_kernel(const double* __restrict__ x, const double* __restrict__ y,
                                      int64_t n, int f64, double* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -569,6 +574,14 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(xs_fill_u64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                      p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_uniform(double* g, int64_t n, double a, double h, hipStream_t st) {
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(xs_fill_uniform_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, n, a,
+                     h);
   return hipGetLastError();
 }
 

@@ -149,7 +149,8 @@ static void line_range(const LinesRes& L, const GridRes& G, const xs_opts& o, in
   if (*hi < *lo) *hi = *lo;
 }
 
-Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const xs_opts& o) {
+Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const xs_opts& o,
+               size_t cap_bytes) {
   Plan p;
   p.P = o.pts_per_lane ? o.pts_per_lane : 2;
   p.W = o.waves_per_simd == 2 ? 0 : o.waves_per_simd;
@@ -175,9 +176,12 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
   }
   // (P, T) points per batch: the records of a batch (32 B per line and point) and its
   // partials stay under a quarter of the free budget and 16 GiB
-  const size_t used = c.used.load();
-  const size_t free_b = c.budget > used ? c.budget - used : 0;
-  const size_t cap = std::min<size_t>((size_t)16 << 30, free_b / 4);
+  size_t cap = cap_bytes;
+  if (cap == 0) {
+    const size_t used = c.used.load();
+    const size_t free_b = c.budget > used ? c.budget - used : 0;
+    cap = std::min<size_t>((size_t)16 << 30, free_b / 4);
+  }
   const size_t per_pt = std::max<size_t>(
       1, (size_t)p.rec_n * 32 + (p.split > 1 ? (size_t)p.split * G.n * 8 : 0));
   p.pt_batch = (int)std::max<size_t>(1, std::min<size_t>(npts, cap / per_pt));

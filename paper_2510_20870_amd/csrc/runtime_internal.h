@@ -89,6 +89,7 @@ struct xs_ctx {
   bool pts_event_valid = false;
   hipStream_t last_stream = nullptr;
   xs::Server* server = nullptr;
+  std::mutex serve_mu;                   // guards starting the server
   xs::KernelTimer* timer = nullptr;      // non-null while kernel timing is enabled
 
   bool reserve(size_t bytes);
@@ -103,11 +104,16 @@ struct xs_ctx {
 namespace xs {
 using Ctx = xs_ctx;
 
+extern thread_local std::string g_last_error;   // message of this thread's last failure
 int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 int validate_opts(const xs_opts* o);
 int validate_pts(const xs_pt* pts, size_t npts);
-Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const xs_opts& o);
+// Launch plan; cap_bytes bounds the records and partials of one batch of (P, T) points
+// (0: min(16 GiB, a quarter of the free budget)). The launch shape (P, split) depends only
+// on the inputs and options, never on the memory left.
+Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const xs_opts& o,
+               size_t cap_bytes = 0);
 // Enqueue the whole path on `st`: per batch of (P, T) points the parameter kernel, the
 // tile kernel and (split > 1) the fixed-order reduction; with counts != nullptr the count
 // kernel instead of tile + reduction.

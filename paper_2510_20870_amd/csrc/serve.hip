@@ -1,8 +1,622 @@
-// Serving loop (placeholder until the continuous-batching scheduler lands).
+// Serving loop: continuous batching of cross-section requests on one device.
+//
+// A server thread owns a fixed set of execution slots (non-blocking HIP streams at the
+// default priority) and one device arena. Requests wait in arrival order; whenever a slot
+// and room in the arena are free, the next admissible request gets a contiguous arena
+// block, its point table and tile order are staged through the slot's pinned buffer, and
+// its whole path (parameter, tile and reduction kernels) is enqueued on the slot's stream,
+// followed by a completion event. The thread polls the events; a finished request gives
+// back its slot and block at once, so queued work starts while other requests are still
+// running, and kernels of different requests share the device.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/xsec.h"
+#include "kernel_args.h"
 #include "runtime_internal.h"
 
 namespace xs {
 
-void serve_shutdown(Ctx*) {}
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+size_t round256(size_t b) { return (std::max<size_t>(b, 1) + 255) / 256 * 256; }
+
+// First-fit allocator over [0, size) in 256-byte units; free blocks are kept by offset and
+// merged with their neighbours on release.
+class Arena {
+ public:
+  void reset(size_t size) {
+    size_ = size / 256 * 256;
+    used_ = peak_ = 0;
+    free_.clear();
+    if (size_) free_[0] = size_;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = round256(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes, next = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[next] = rest;
+      used_ += bytes;
+      peak_ = std::max(peak_, used_);
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = round256(bytes);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t size() const { return size_; }
+  size_t peak() const { return peak_; }
+
+ private:
+  size_t size_ = 0, used_ = 0, peak_ = 0;
+  std::map<size_t, size_t> free_;
+};
+
+struct Waiting {
+  uint64_t id;
+  size_t bytes;
+  int bypassed;
+};
+
+// Admission rule. Scans the waiting requests in arrival order and admits the first whose
+// footprint fits the arena; every request it passes counts one bypass, and a request that
+// has been passed max_bypass times (any time, if max_bypass < 0) may not be passed again,
+// so the scan stops there. Returns the index admitted (its block in *off) or -1.
+int pick_admission(std::deque<Waiting>& q, Arena& a, int max_bypass, size_t* off) {
+  for (size_t i = 0; i < q.size(); ++i) {
+    if (a.alloc(q[i].bytes, off)) {
+      for (size_t j = 0; j < i; ++j) ++q[j].bypassed;
+      return (int)i;
+    }
+    if (max_bypass < 0 || q[i].bypassed >= max_bypass) return -1;
+  }
+  return -1;
+}
+
+enum { kQueued = 0, kRunning = 1, kDone = 2 };
+
+struct Request {
+  uint64_t id = 0;
+  int state = kQueued;
+  int status = XS_OK;
+  std::string err;
+  LinesRes* L = nullptr;
+  GridRes* G = nullptr;      // the context's grid, or &own for a window request
+  bool own_grid = false;
+  GridRes own;
+  double nu_start = 0.0, step = 0.0;
+  xs_opts o{};
+  std::vector<double> pt_pairs;   // (P, T) interleaved
+  double* out = nullptr;
+  bool out_dev = false;
+  Plan plan;
+  // arena block and its parts (byte offsets inside the block)
+  size_t bytes = 0, off = 0;
+  size_t o_rec = 0, o_part = 0, o_out = 0, o_grid = 0, o_pts = 0, o_order = 0;
+  int slot = -1;
+  double t_submit = -1.0, t_admit = -1.0, t_done = -1.0;
+};
+
+struct Slot {
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;
+  void* pinned = nullptr;
+  size_t pinned_cap = 0;
+  Request* req = nullptr;
+};
+
+}  // namespace
+
+struct Server {
+  Ctx* c = nullptr;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  bool stop = false, paused = false;
+  int max_inflight = 4, max_bypass = 8;
+  char* base = nullptr;
+  size_t mem = 0;
+  Arena arena;
+  std::vector<Slot> slots;
+  std::deque<Waiting> queue;
+  std::unordered_map<uint64_t, Request*> reqs;
+  uint64_t next_id = 1;
+  int running = 0;
+
+  void loop();
+  int launch(Request& r, Slot& s);
+  void finish(Request& r, int status, const std::string& err);
+};
+
+// Drop the request's references and arena block; the caller holds mu.
+void Server::finish(Request& r, int status, const std::string& err) {
+  if (r.state == kRunning) {
+    arena.release(r.off, r.bytes);
+    --running;
+    if (r.slot >= 0) slots[r.slot].req = nullptr;
+  }
+  r.L->refs.fetch_sub(1);
+  if (!r.own_grid) r.G->refs.fetch_sub(1);
+  r.status = status;
+  r.err = err;
+  r.state = kDone;
+  r.t_done = now_s();
+  cv_done.notify_all();
+}
+
+// Stage the request's inputs and enqueue its path on the slot's stream (caller holds mu).
+int Server::launch(Request& r, Slot& s) {
+  char* blk = base + r.off;
+  const size_t pts_bytes = r.pt_pairs.size() * sizeof(double);
+  const size_t ord_bytes = r.plan.tile_order.size() * sizeof(int);
+  const size_t need = round256(pts_bytes) + ord_bytes;
+  if (s.pinned_cap < need) {
+    // the slot's previous request has completed, so its staging copies are done
+    if (s.pinned) (void)hipHostFree(s.pinned);
+    s.pinned = nullptr;
+    s.pinned_cap = 0;
+    const size_t cap = std::max<size_t>(need, 64 << 10);
+    hipError_t e = hipHostMalloc(&s.pinned, cap, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipHostMalloc (serving staging)");
+    s.pinned_cap = cap;
+  }
+  memcpy(s.pinned, r.pt_pairs.data(), pts_bytes);
+  memcpy((char*)s.pinned + round256(pts_bytes), r.plan.tile_order.data(), ord_bytes);
+  hipError_t e = hipMemcpyAsync(blk + r.o_pts, s.pinned, pts_bytes, hipMemcpyHostToDevice, s.st);
+  if (e == hipSuccess && ord_bytes)
+    e = hipMemcpyAsync(blk + r.o_order, (char*)s.pinned + round256(pts_bytes), ord_bytes,
+                       hipMemcpyHostToDevice, s.st);
+  if (e != hipSuccess) return hip_fail(e, "serving upload");
+  if (r.own_grid) {
+    r.own.d = (double*)(blk + r.o_grid);
+    e = launch_fill_uniform(r.own.d, (int64_t)r.own.n, r.nu_start, r.step, s.st);
+    if (e != hipSuccess) return hip_fail(e, "grid fill launch");
+  }
+  double* out_dev = r.out_dev ? r.out : (double*)(blk + r.o_out);
+  void* part = r.plan.split > 1 ? (void*)(blk + r.o_part) : nullptr;
+  int rc = enqueue_path(*r.L, *r.G, r.o, r.plan, (const double*)(blk + r.o_pts),
+                        (const int*)(blk + r.o_order), out_dev, blk + r.o_rec, part, s.st);
+  if (rc) return rc;
+  e = hipEventRecord(s.ev, s.st);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  return XS_OK;
+}
+
+void Server::loop() {
+  (void)hipSetDevice(c->device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    // completions
+    std::vector<std::pair<Request*, hipError_t>> done;
+    for (Slot& s : slots) {
+      if (!s.req) continue;
+      const hipError_t e = hipEventQuery(s.ev);
+      if (e == hipErrorNotReady) continue;
+      done.emplace_back(s.req, e);
+    }
+    if (!done.empty()) {
+      // download host outputs without holding the lock
+      std::vector<std::pair<int, std::string>> res(done.size());
+      lk.unlock();
+      for (size_t k = 0; k < done.size(); ++k) {
+        Request& r = *done[k].first;
+        hipError_t e = done[k].second;
+        if (e == hipSuccess && !r.out_dev) {
+          const size_t ob = r.pt_pairs.size() / 2 * r.G->n * sizeof(double);
+          e = hipMemcpy(r.out, base + r.off + r.o_out, ob, hipMemcpyDeviceToHost);
+        }
+        if (e != hipSuccess) {
+          hip_fail(e, "serving request");
+          res[k] = {XS_EDEVICE, g_last_error};
+        } else {
+          res[k] = {XS_OK, std::string()};
+        }
+      }
+      lk.lock();
+      for (size_t k = 0; k < done.size(); ++k) finish(*done[k].first, res[k].first, res[k].second);
+    }
+    // admissions
+    while (!paused && !stop && running < max_inflight && !queue.empty()) {
+      size_t off = 0;
+      const int i = pick_admission(queue, arena, max_bypass, &off);
+      if (i < 0) break;
+      Request* r = reqs[queue[i].id];
+      queue.erase(queue.begin() + i);
+      int si = 0;
+      while (slots[si].req) ++si;
+      r->off = off;
+      r->slot = si;
+      r->state = kRunning;
+      r->t_admit = now_s();
+      ++running;
+      slots[si].req = r;
+      const int rc = launch(*r, slots[si]);
+      if (rc) {
+        // nothing of this request runs past the failed step, but earlier steps may have
+        // been enqueued: wait for them before the block is reused
+        (void)hipStreamSynchronize(slots[si].st);
+        finish(*r, rc, g_last_error);
+      }
+    }
+    if (stop && running == 0) break;
+    if (running == 0 && (queue.empty() || paused || stop))
+      cv_work.wait(lk);
+    else
+      cv_work.wait_for(lk, std::chrono::microseconds(20));
+  }
+}
+
+void serve_shutdown(Ctx* c) {
+  Server* s = c->server;
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    while (!s->queue.empty()) {
+      Request* r = s->reqs[s->queue.front().id];
+      s->queue.pop_front();
+      s->finish(*r, XS_ECANCELLED, "cancelled at shutdown");
+    }
+    s->cv_work.notify_all();
+  }
+  if (s->th.joinable()) s->th.join();
+  for (Slot& sl : s->slots) {
+    if (sl.st) (void)hipStreamSynchronize(sl.st);
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+    if (sl.st) (void)hipStreamDestroy(sl.st);
+    if (sl.pinned) (void)hipHostFree(sl.pinned);
+  }
+  for (auto& kv : s->reqs) delete kv.second;
+  if (s->base) c->dev_free(s->base, s->mem);
+  delete s;
+  c->server = nullptr;
+}
+
+static int serve_start_locked(Ctx* c, const xs_serve_opts* o) {
+  xs_serve_opts d{};
+  if (!o) o = &d;
+  if (o->max_inflight < 0 || o->max_inflight > 64)
+    return fail(XS_EINVAL, "max_inflight must be in [0, 64] (got %d)", o->max_inflight);
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  Server* s = new Server();
+  s->c = c;
+  s->max_inflight = o->max_inflight ? o->max_inflight : 4;
+  s->max_bypass = o->max_bypass == 0 ? 8 : o->max_bypass;
+  s->paused = o->start_paused != 0;
+  size_t mem = o->mem_bytes;
+  if (mem == 0) {
+    const size_t used = c->used.load();
+    const size_t free_b = c->budget > used ? c->budget - used : 0;
+    mem = std::min<size_t>((size_t)64 << 30, free_b / 2);
+  }
+  mem = mem / 256 * 256;
+  if (mem < 4096) {
+    delete s;
+    return fail(XS_ENOMEM, "serving arena of %zu bytes is too small", mem);
+  }
+  int rc = c->dev_alloc((void**)&s->base, mem, "serving arena");
+  if (rc) {
+    delete s;
+    return rc;
+  }
+  s->mem = mem;
+  s->arena.reset(mem);
+  s->slots.resize(s->max_inflight);
+  for (Slot& sl : s->slots) {
+    e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      c->server = s;
+      serve_shutdown(c);
+      return hip_fail(e, "serving stream/event");
+    }
+  }
+  c->server = s;
+  s->th = std::thread([s] { s->loop(); });
+  return XS_OK;
+}
+
+static int ensure_server(Ctx* c) {
+  std::lock_guard<std::mutex> lk(c->serve_mu);
+  if (c->server) return XS_OK;
+  return serve_start_locked(c, nullptr);
+}
+
+static Request* find_req(Server* s, xs_req_t id) {
+  auto it = s->reqs.find(id);
+  return it == s->reqs.end() ? nullptr : it->second;
+}
+
+// Common part of xs_submit / xs_submit_window: G == nullptr means a window request.
+static int submit(Ctx* c, xs_lines_t lh, xs_grid_t gh, bool window, double nu_start,
+                  double step, size_t n_points, const xs_pt* pts, size_t npts,
+                  const xs_opts* opts, double* sigma_out, int out_on_device, xs_req_t* out) {
+  if (!c || !out || !sigma_out) return fail(XS_EINVAL, "NULL argument");
+  int rc = validate_opts(opts);
+  if (rc) return rc;
+  rc = validate_pts(pts, npts);
+  if (rc) return rc;
+  if (window) {
+    if (n_points == 0 || n_points > ((size_t)1 << 31))
+      return fail(XS_EINVAL, "n_points must be in [1, 2^31] (got %zu)", n_points);
+    if (!isfinite(nu_start) || !(step > 0.0) || !isfinite(step) ||
+        !isfinite(nu_start + step * (double)(n_points - 1)))
+      return fail(XS_EINVAL, "window start %g / step %g invalid", nu_start, step);
+  }
+  rc = ensure_server(c);
+  if (rc) return rc;
+  Server* s = c->server;
+  Request* r = new Request();
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    r->L = c->find_lines(lh);
+    if (!window) r->G = c->find_grid(gh);
+    if (!r->L || (!window && !r->G)) {
+      delete r;
+      return fail(XS_ENOTFOUND, "unknown line list %llu or grid %llu",
+                  (unsigned long long)lh, (unsigned long long)gh);
+    }
+    r->L->refs.fetch_add(1);
+    if (!window) r->G->refs.fetch_add(1);
+  }
+  if (window) {
+    r->own_grid = true;
+    r->nu_start = nu_start;
+    r->step = step;
+    r->own.n = n_points;
+    r->own.host.resize(n_points);
+    for (size_t j = 0; j < n_points; ++j) r->own.host[j] = nu_start + (double)j * step;
+    r->own.first = r->own.host.front();
+    r->own.last = r->own.host.back();
+    r->own.bytes = n_points * sizeof(double);
+    r->G = &r->own;
+  }
+  r->o = *opts;
+  r->pt_pairs.resize(2 * npts);
+  for (size_t k = 0; k < npts; ++k) {
+    r->pt_pairs[2 * k] = pts[k].P_bar;
+    r->pt_pairs[2 * k + 1] = pts[k].T_K;
+  }
+  r->out = sigma_out;
+  r->out_dev = out_on_device != 0;
+  r->plan = make_plan(*c, *r->L, *r->G, npts, *opts, s->mem / 4);
+  const size_t n = r->G->n;
+  size_t at = 0;
+  auto part = [&](size_t bytes) {
+    const size_t o = at;
+    at += round256(bytes);
+    return o;
+  };
+  r->o_rec = part(r->plan.rec_bytes());
+  r->o_part = part(r->plan.part_bytes(n));
+  r->o_out = part(r->out_dev ? 0 : npts * n * sizeof(double));
+  r->o_grid = part(window ? n * sizeof(double) : 0);
+  r->o_pts = part(npts * 2 * sizeof(double));
+  r->o_order = part(r->plan.tile_order.size() * sizeof(int));
+  r->bytes = at;
+  if (r->bytes > s->arena.size()) {
+    const size_t b = r->bytes;
+    r->L->refs.fetch_sub(1);
+    if (!window) r->G->refs.fetch_sub(1);
+    delete r;
+    return fail(XS_ENOMEM, "request footprint %zu bytes exceeds the serving arena (%zu)", b,
+                s->arena.size());
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  r->id = s->next_id++;
+  r->t_submit = now_s();
+  s->reqs[r->id] = r;
+  s->queue.push_back({r->id, r->bytes, 0});
+  *out = r->id;
+  s->cv_work.notify_all();
+  return XS_OK;
+}
+
+// Discrete-event run of the admission rule (host only).
+static int simulate(size_t n, const double* arrive, const double* dur, const uint64_t* fp,
+                    uint64_t mem, int slots, int max_bypass, double* admit, double* done,
+                    uint64_t* peak) {
+  Arena a;
+  a.reset(mem);
+  for (size_t i = 0; i < n; ++i) {
+    if (round256(fp[i]) > a.size())
+      return fail(XS_ENOMEM, "footprint[%zu] = %llu exceeds the arena", i,
+                  (unsigned long long)fp[i]);
+    if (i && arrive[i] < arrive[i - 1]) return fail(XS_EINVAL, "arrive must be non-decreasing");
+  }
+  std::deque<Waiting> q;
+  std::vector<size_t> offs(n);
+  std::multimap<double, size_t> run;   // completion time -> request
+  size_t next = 0, finished = 0;
+  double t = n ? arrive[0] : 0.0;
+  while (finished < n) {
+    while (next < n && arrive[next] <= t) {
+      q.push_back({next, fp[next], 0});
+      ++next;
+    }
+    while ((int)run.size() < slots && !q.empty()) {
+      size_t off = 0;
+      const int i = pick_admission(q, a, max_bypass, &off);
+      if (i < 0) break;
+      const size_t id = q[i].id;
+      q.erase(q.begin() + i);
+      offs[id] = off;
+      admit[id] = t;
+      done[id] = t + dur[id];
+      run.emplace(done[id], id);
+    }
+    const double t_arr = next < n ? arrive[next] : INFINITY;
+    const double t_fin = run.empty() ? INFINITY : run.begin()->first;
+    if (t_fin <= t_arr) {
+      t = t_fin;
+      while (!run.empty() && run.begin()->first <= t) {
+        const size_t id = run.begin()->second;
+        run.erase(run.begin());
+        a.release(offs[id], fp[id]);
+        ++finished;
+      }
+    } else {
+      t = t_arr;
+    }
+  }
+  if (peak) *peak = a.peak();
+  return XS_OK;
+}
 
 }  // namespace xs
+
+using namespace xs;
+
+int xs_serve_start(xs_ctx* c, const xs_serve_opts* opts) {
+  if (!c) return fail(XS_EINVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(c->serve_mu);
+  if (c->server) return fail(XS_EBUSY, "the server is already running");
+  return serve_start_locked(c, opts);
+}
+
+int xs_serve_pause(xs_ctx* c, int paused) {
+  if (!c) return fail(XS_EINVAL, "ctx is NULL");
+  int rc = ensure_server(c);
+  if (rc) return rc;
+  Server* s = c->server;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->paused = paused != 0;
+  s->cv_work.notify_all();
+  return XS_OK;
+}
+
+int xs_submit(xs_ctx* c, xs_lines_t lines, xs_grid_t grid, const xs_pt* pts, size_t npts,
+              const xs_opts* opts, double* sigma_out, int out_on_device, xs_req_t* out) {
+  return submit(c, lines, grid, false, 0.0, 0.0, 0, pts, npts, opts, sigma_out, out_on_device,
+                out);
+}
+
+int xs_submit_window(xs_ctx* c, xs_lines_t lines, double nu_start, double step,
+                     size_t n_points, const xs_pt* pts, size_t npts, const xs_opts* opts,
+                     double* sigma_out, int out_on_device, xs_req_t* out) {
+  return submit(c, lines, 0, true, nu_start, step, n_points, pts, npts, opts, sigma_out,
+                out_on_device, out);
+}
+
+int xs_poll(xs_ctx* c, xs_req_t req, int* done) {
+  if (!c || !done) return fail(XS_EINVAL, "NULL argument");
+  Server* s = c->server;
+  if (!s) return fail(XS_ENOTFOUND, "no server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  Request* r = find_req(s, req);
+  if (!r) return fail(XS_ENOTFOUND, "unknown request %llu", (unsigned long long)req);
+  *done = r->state == kDone;
+  return XS_OK;
+}
+
+int xs_wait(xs_ctx* c, xs_req_t req, double timeout_s) {
+  if (!c) return fail(XS_EINVAL, "ctx is NULL");
+  Server* s = c->server;
+  if (!s) return fail(XS_ENOTFOUND, "no server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  Request* r = find_req(s, req);
+  if (!r) return fail(XS_ENOTFOUND, "unknown request %llu", (unsigned long long)req);
+  auto ready = [&] { return r->state == kDone; };
+  if (timeout_s < 0) {
+    s->cv_done.wait(lk, ready);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) {
+    return fail(XS_ETIMEOUT, "request %llu still pending after %g s", (unsigned long long)req,
+                timeout_s);
+  }
+  if (r->status != XS_OK) return fail(r->status, "%s", r->err.c_str());
+  return XS_OK;
+}
+
+int xs_cancel(xs_ctx* c, xs_req_t req) {
+  if (!c) return fail(XS_EINVAL, "ctx is NULL");
+  Server* s = c->server;
+  if (!s) return fail(XS_ENOTFOUND, "no server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  Request* r = find_req(s, req);
+  if (!r) return fail(XS_ENOTFOUND, "unknown request %llu", (unsigned long long)req);
+  if (r->state == kRunning) return fail(XS_EBUSY, "request %llu is running", (unsigned long long)req);
+  if (r->state == kQueued) {
+    for (auto it = s->queue.begin(); it != s->queue.end(); ++it)
+      if (it->id == req) {
+        s->queue.erase(it);
+        break;
+      }
+    s->finish(*r, XS_ECANCELLED, "cancelled");
+  }
+  return XS_OK;
+}
+
+int xs_request_times(xs_ctx* c, xs_req_t req, double* t_submit, double* t_admit,
+                     double* t_done) {
+  if (!c) return fail(XS_EINVAL, "ctx is NULL");
+  Server* s = c->server;
+  if (!s) return fail(XS_ENOTFOUND, "no server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  Request* r = find_req(s, req);
+  if (!r) return fail(XS_ENOTFOUND, "unknown request %llu", (unsigned long long)req);
+  if (t_submit) *t_submit = r->t_submit;
+  if (t_admit) *t_admit = r->t_admit;
+  if (t_done) *t_done = r->t_done;
+  return XS_OK;
+}
+
+int xs_release(xs_ctx* c, xs_req_t req) {
+  if (!c) return fail(XS_EINVAL, "ctx is NULL");
+  Server* s = c->server;
+  if (!s) return fail(XS_ENOTFOUND, "no server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  Request* r = find_req(s, req);
+  if (!r) return fail(XS_ENOTFOUND, "unknown request %llu", (unsigned long long)req);
+  if (r->state != kDone) return fail(XS_EBUSY, "request %llu is pending", (unsigned long long)req);
+  s->reqs.erase(req);
+  delete r;
+  return XS_OK;
+}
+
+int xs_sched_simulate(size_t n, const double* arrive, const double* duration,
+                      const uint64_t* footprint, uint64_t mem_bytes, int max_inflight,
+                      int max_bypass, double* admit_out, double* done_out,
+                      uint64_t* peak_bytes) {
+  if (n && (!arrive || !duration || !footprint || !admit_out || !done_out))
+    return fail(XS_EINVAL, "NULL argument");
+  if (max_inflight < 1) return fail(XS_EINVAL, "max_inflight must be >= 1");
+  for (size_t i = 0; i < n; ++i)
+    if (!isfinite(arrive[i]) || !(duration[i] >= 0.0) || !isfinite(duration[i]))
+      return fail(XS_EINVAL, "arrive/duration[%zu] invalid", i);
+  return simulate(n, arrive, duration, footprint, mem_bytes, max_inflight,
+                  max_bypass == 0 ? 8 : max_bypass, admit_out, done_out, peak_bytes);
+}

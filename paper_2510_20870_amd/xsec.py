@@ -62,6 +62,11 @@ class Opts(C.Structure):
                 ("waves_per_simd", C.c_int)]
 
 
+class ServeOpts(C.Structure):
+    _fields_ = [("max_inflight", C.c_int), ("mem_bytes", C.c_size_t), ("max_bypass", C.c_int),
+                ("start_paused", C.c_int)]
+
+
 _lib = None
 _lib_lock = threading.Lock()
 
@@ -89,6 +94,21 @@ _SIGS = {
                          C.POINTER(Opts), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "xs_graph_launch": ([C.c_void_p, C.c_void_p], C.c_int),
     "xs_graph_destroy": ([C.c_void_p], None),
+    "xs_serve_start": ([C.c_void_p, C.POINTER(ServeOpts)], C.c_int),
+    "xs_serve_pause": ([C.c_void_p, C.c_int], C.c_int),
+    "xs_submit": ([C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(Pt), C.c_size_t,
+                   C.POINTER(Opts), C.c_void_p, C.c_int, C.POINTER(C.c_uint64)], C.c_int),
+    "xs_submit_window": ([C.c_void_p, C.c_uint64, C.c_double, C.c_double, C.c_size_t,
+                          C.POINTER(Pt), C.c_size_t, C.POINTER(Opts), C.c_void_p, C.c_int,
+                          C.POINTER(C.c_uint64)], C.c_int),
+    "xs_poll": ([C.c_void_p, C.c_uint64, C.POINTER(C.c_int)], C.c_int),
+    "xs_wait": ([C.c_void_p, C.c_uint64, C.c_double], C.c_int),
+    "xs_cancel": ([C.c_void_p, C.c_uint64], C.c_int),
+    "xs_request_times": ([C.c_void_p, C.c_uint64, C.POINTER(C.c_double),
+                          C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
+    "xs_release": ([C.c_void_p, C.c_uint64], C.c_int),
+    "xs_sched_simulate": ([C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int,
+                           C.c_int, C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64)], C.c_int),
     "xs_set_kernel_timing": ([C.c_void_p, C.c_int], C.c_int),
     "xs_kernel_time": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)], C.c_int),
     "xs_eval_voigt": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p],
@@ -146,6 +166,63 @@ def _stream_handle(stream) -> Optional[int]:
     if hasattr(stream, "cuda_stream"):
         return int(stream.cuda_stream)
     return int(stream)
+
+
+def sched_simulate(arrive, duration, footprint, mem_bytes: int, max_inflight: int,
+                   max_bypass: int = 0):
+    """The server's admission rule on a simulated clock (host only): returns
+    (admit times, done times, peak arena bytes)."""
+    a = np.ascontiguousarray(arrive, np.float64)
+    d = np.ascontiguousarray(duration, np.float64)
+    f = np.ascontiguousarray(footprint, np.uint64)
+    if not (len(a) == len(d) == len(f)):
+        raise ValueError("arrive, duration and footprint differ in length")
+    ad = np.zeros(len(a))
+    dn = np.zeros(len(a))
+    peak = C.c_uint64()
+    rc = lib().xs_sched_simulate(len(a), _ptr(a), _ptr(d), _ptr(f), int(mem_bytes),
+                                 int(max_inflight), int(max_bypass), _ptr(ad), _ptr(dn),
+                                 C.byref(peak))
+    if rc:
+        raise XsError(rc, lib().xs_last_error(None).decode())
+    return ad, dn, peak.value
+
+
+class Request:
+    """A submitted cross-section request (see Context.submit)."""
+
+    def __init__(self, ctx: "Context", h: int, out, keep=()):
+        self.ctx = ctx
+        self.h = h
+        self.out = out
+        self._keep = keep   # host buffers that must outlive the request
+
+    def poll(self) -> bool:
+        d = C.c_int()
+        self.ctx._check(self.ctx._L.xs_poll(self.ctx.h, self.h, C.byref(d)))
+        return bool(d.value)
+
+    def wait(self, timeout_s: float = -1.0):
+        """Wait and return the output (raises XsError on failure or cancellation)."""
+        self.ctx._check(self.ctx._L.xs_wait(self.ctx.h, self.h, float(timeout_s)))
+        return self.out
+
+    def status(self, timeout_s: float = -1.0) -> int:
+        return self.ctx._L.xs_wait(self.ctx.h, self.h, float(timeout_s))
+
+    def cancel(self) -> int:
+        return self.ctx._L.xs_cancel(self.ctx.h, self.h)
+
+    def times(self):
+        ts, ta, td = C.c_double(), C.c_double(), C.c_double()
+        self.ctx._check(self.ctx._L.xs_request_times(self.ctx.h, self.h, C.byref(ts),
+                                                     C.byref(ta), C.byref(td)))
+        return ts.value, ta.value, td.value
+
+    def release(self):
+        if self.h:
+            self.ctx._check(self.ctx._L.xs_release(self.ctx.h, self.h))
+            self.h = None
 
 
 class Context:
@@ -287,6 +364,44 @@ class Context:
         self._check(self._L.xs_eval_voigt(self.h, _ptr(x), _ptr(y), x.size, precision,
                                           _ptr(out)))
         return out
+
+    # ------------------------------------------------------------------ serving
+    def serve_start(self, max_inflight: int = 0, mem_bytes: int = 0, max_bypass: int = 0,
+                    paused: bool = False):
+        o = ServeOpts(max_inflight, mem_bytes, max_bypass, int(bool(paused)))
+        self._check(self._L.xs_serve_start(self.h, C.byref(o)))
+
+    def serve_pause(self, paused: bool = True):
+        self._check(self._L.xs_serve_pause(self.h, int(bool(paused))))
+
+    def submit(self, lines: int, grid: int, pts, opts: Opts, out=None) -> Request:
+        """Queue sigma(grid; pts). out: None (a new host array), a host float64 array of
+        [npts, n_grid], or a device tensor (written by the server's streams)."""
+        p = self._pts(pts)
+        if out is None:
+            out = np.empty((len(p), self.grid_len(grid)), np.float64)
+        on_dev = not isinstance(out, np.ndarray)
+        if not on_dev and (out.dtype != np.float64 or not out.flags.c_contiguous):
+            raise ValueError("host out must be C-contiguous float64")
+        h = C.c_uint64()
+        self._check(self._L.xs_submit(self.h, lines, grid, p, len(p), C.byref(opts),
+                                      _dev_ptr(out) if on_dev else _ptr(out), int(on_dev),
+                                      C.byref(h)))
+        return Request(self, h.value, out, (p,))
+
+    def submit_window(self, lines: int, nu_start: float, step: float, n_points: int, pts,
+                      opts: Opts, out=None) -> Request:
+        """Queue sigma on the uniform grid nu_start + j*step, j < n_points."""
+        p = self._pts(pts)
+        if out is None:
+            out = np.empty((len(p), n_points), np.float64)
+        on_dev = not isinstance(out, np.ndarray)
+        h = C.c_uint64()
+        self._check(self._L.xs_submit_window(self.h, lines, float(nu_start), float(step),
+                                             int(n_points), p, len(p), C.byref(opts),
+                                             _dev_ptr(out) if on_dev else _ptr(out),
+                                             int(on_dev), C.byref(h)))
+        return Request(self, h.value, out, (p,))
 
     # ------------------------------------------------------------------ timing
     def set_kernel_timing(self, enable: bool = True):

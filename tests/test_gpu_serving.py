@@ -1,0 +1,176 @@
+"""GPU serving: continuous batching through the C ABI (xs_submit .. xs_release).
+
+Each request's result must be bitwise the same computed alone (xs_compute, same options)
+and served in a mix of concurrent requests of different sizes, lists, precisions and
+output kinds; a window request (grid built on the device) must match the oracle; queued
+requests can be cancelled; pending requests pin their line list; oversized requests are
+refused at submit.
+"""
+import numpy as np
+import pytest
+
+from oracle import xsec_oracle as O
+from paper_2510_20870_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _x():
+    from paper_2510_20870_amd import xsec
+    return xsec
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _opts(kind="fixed", cut=25.0, mult=100.0, f64=False):
+    X = _x()
+    return X.Context.opts(X.XS_CUT_FIXED if kind == "fixed" else X.XS_CUT_MIN_FWHM, cut, mult,
+                          X.XS_FP64 if f64 else X.XS_FP32_KAHAN)
+
+
+LISTS = ((synth.ListSpec(20_000, 500.0, 700.0, 11), 18.0),
+         (synth.ListSpec(200_000, 500.0, 700.0, 12), 28.0),
+         (synth.ListSpec(1_000_000, 500.0, 700.0, 13), 44.0))
+
+
+def test_alone_vs_mix_bitwise(torch_gpu):
+    torch = torch_gpu
+    X = _x()
+    ctx = X.Context(0)
+    hs = [ctx.load_lines(synth.make_lines(s), m) for s, m in LISTS]
+    rng = np.random.default_rng(5)
+    cases = []
+    for k in range(14):
+        li = int(rng.integers(0, len(LISTS)))
+        n = int(10 ** rng.uniform(3, 4.2))                # 1e3 .. 1.6e4 points
+        start = float(np.round(rng.uniform(505.0, 690.0 - n * 0.01), 2))
+        npts = int(rng.integers(1, 4))
+        pts = [(float(10 ** rng.uniform(-5, 2)), float(rng.uniform(300, 3000)))
+               for _ in range(npts)]
+        f64 = bool(k % 5 == 4)
+        kind = "min_fwhm" if k % 3 == 1 else "fixed"
+        cases.append(dict(li=li, n=n, start=start, pts=pts, f64=f64, kind=kind,
+                          window=bool(k % 2), device=bool(k % 4 == 3)))
+    # alone: xs_compute on a resident grid with the same values
+    alone, grids = [], []
+    for c in cases:
+        grid = c["start"] + 0.01 * np.arange(c["n"], dtype=np.float64)
+        g = ctx.set_grid(grid)
+        grids.append(g)
+        alone.append(ctx.compute(hs[c["li"]], g, c["pts"], _opts(c["kind"], f64=c["f64"])))
+    # mix: everything queued while paused, then released at once onto four slots
+    ctx.serve_start(max_inflight=4, paused=True)
+    reqs = []
+    for c, g in zip(cases, grids):
+        o = _opts(c["kind"], f64=c["f64"])
+        out = None
+        if c["device"]:
+            out = torch.full((len(c["pts"]), c["n"]), float("nan"), dtype=torch.float64,
+                             device="cuda")
+        if c["window"]:
+            reqs.append(ctx.submit_window(hs[c["li"]], c["start"], 0.01, c["n"], c["pts"], o,
+                                          out=out))
+        else:
+            reqs.append(ctx.submit(hs[c["li"]], g, c["pts"], o, out=out))
+    ctx.serve_pause(False)
+    times = []
+    for k, (c, r) in enumerate(zip(cases, reqs)):
+        res = r.wait(120.0)
+        res = res.cpu().numpy() if c["device"] else res
+        print(f"[serve] case {k} list {c['li']} n={c['n']} npts={len(c['pts'])} "
+              f"f64={c['f64']} window={c['window']} device={c['device']}", flush=True)
+        assert np.array_equal(res, alone[k]), f"case {k} differs alone vs mix"
+        times.append(r.times())
+        r.release()
+    ts = np.array(times)
+    assert np.all(ts[:, 0] <= ts[:, 1]) and np.all(ts[:, 1] <= ts[:, 2])
+    # the first four were admitted before the first of them completed
+    first_done = ts[:4, 2].min()
+    assert np.all(ts[:4, 1] <= first_done), ts[:4]
+    for g in grids:
+        ctx.free_grid(g)
+    for h in hs:
+        ctx.unload_lines(h)
+    ctx.close()
+
+
+def test_window_request_matches_oracle(torch_gpu):
+    X = _x()
+    spec, mass = LISTS[0]
+    L = synth.make_lines(spec)
+    ctx = X.Context(0)
+    h = ctx.load_lines(L, mass)
+    start, n = 600.0, 5000
+    grid = start + 0.01 * np.arange(n, dtype=np.float64)
+    pts = [(0.05, 900.0), (3.0, 2500.0)]
+    r = ctx.submit_window(h, start, 0.01, n, pts, _opts(cut=25.0))
+    sig = r.wait(60.0)
+    for k, (P, T) in enumerate(pts):
+        ref = O.sigma(L, grid, P, T, mass, cut_cm1=25.0)
+        st = O.compare(sig[k], ref, rel_tol=1e-5)
+        print(f"[serve] window P={P} T={T} max_rel={st['max_rel']:.3e}", flush=True)
+        assert st["violations"] == 0, st
+    r.release()
+    ctx.unload_lines(h)
+    ctx.close()
+
+
+def test_cancel_release_busy_and_errors(torch_gpu):
+    X = _x()
+    spec, mass = LISTS[1]
+    ctx = X.Context(0)
+    h = ctx.load_lines(synth.make_lines(spec), mass)
+    ctx.serve_start(max_inflight=1, mem_bytes=64 << 20, paused=True)
+    o = _opts()
+    rs = [ctx.submit_window(h, 550.0 + k, 0.01, 2000, [(1.0, 1000.0)], o) for k in range(3)]
+    # queued while paused
+    assert not rs[1].poll()
+    with pytest.raises(X.XsError) as e:
+        rs[1].release()
+    assert e.value.code == X.XS_EBUSY
+    with pytest.raises(X.XsError) as e:
+        ctx.unload_lines(h)
+    assert e.value.code == X.XS_EBUSY
+    assert rs[1].cancel() == X.XS_OK
+    assert rs[1].poll()
+    assert rs[1].status(1.0) == X.XS_ECANCELLED
+    ctx.serve_pause(False)
+    for k in (0, 2):
+        assert rs[k].status(60.0) == X.XS_OK
+        ts, ta, td = rs[k].times()
+        assert ts <= ta <= td
+    assert rs[0].cancel() == X.XS_OK       # finished: no effect
+    for r in rs:
+        r.release()
+    # oversized for the 64 MiB arena: 2 P-T points x 4e6 host-output points = 64 MB + more
+    with pytest.raises(X.XsError) as e:
+        ctx.submit_window(h, 500.0, 1e-5, 4_000_000, [(1.0, 1000.0), (2.0, 900.0)], o)
+    assert e.value.code == X.XS_ENOMEM
+    with pytest.raises(X.XsError) as e:
+        ctx.submit_window(12345, 500.0, 0.01, 100, [(1.0, 1000.0)], o)
+    assert e.value.code == X.XS_ENOTFOUND
+    with pytest.raises(X.XsError) as e:
+        ctx.submit_window(h, 500.0, -0.01, 100, [(1.0, 1000.0)], o)
+    assert e.value.code == X.XS_EINVAL
+    with pytest.raises(X.XsError) as e:
+        ctx.serve_start()
+    assert e.value.code == X.XS_EBUSY
+    ctx.unload_lines(h)                     # nothing pending any more
+    ctx.close()
+
+
+def test_shutdown_with_queued_requests(torch_gpu):
+    X = _x()
+    spec, mass = LISTS[0]
+    ctx = X.Context(0)
+    h = ctx.load_lines(synth.make_lines(spec), mass)
+    ctx.serve_start(max_inflight=2, paused=True)
+    rs = [ctx.submit_window(h, 520.0, 0.01, 1000, [(1.0, 1000.0)], _opts()) for _ in range(4)]
+    assert not any(r.poll() for r in rs)
+    ctx.close()     # cancels the queued requests and stops the server cleanly
