@@ -83,6 +83,92 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def serving_run(ctx, lists, reqs, opts, on_time=True):
+    """Submit `reqs` (synth.Request) at their arrival times (on_time) or all at once;
+    returns per-request (latency s, evals) and the span from first submit to last done."""
+    import threading
+    t0 = time.perf_counter()
+    handles = [None] * len(reqs)
+    done_evt = threading.Event()
+
+    def submitter():
+        for k, r in enumerate(reqs):
+            if on_time:
+                dt = r.t_arrival - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+            handles[k] = ctx.submit_window(lists[r.list_id], r.nu_min, r.step, r.n_points,
+                                           [(r.P_bar, r.T_K)], opts)
+        done_evt.set()
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    lat = np.zeros(len(reqs))
+    first, last = np.inf, -np.inf
+    for k, h in enumerate(handles):
+        h.wait()
+        ts, ta, td = h.times()
+        lat[k] = td - ts
+        first, last = min(first, ts), max(last, td)
+        h.release()
+    return lat, last - first
+
+
+def request_evals(nu0_by_list, reqs, cut):
+    """Line-point evaluations of each request (fixed cut), counted on the host from the
+    sorted centres."""
+    ev = np.zeros(len(reqs))
+    for k, r in enumerate(reqs):
+        nu0 = nu0_by_list[r.list_id]
+        g = r.nu_min + r.step * np.arange(r.n_points, dtype=np.float64)
+        ev[k] = float(np.sum(np.searchsorted(nu0, g + cut, "right") -
+                             np.searchsorted(nu0, g - cut, "left")))
+    return ev
+
+
+def serving_bench(n_requests, loads, seed=1, gen_workers=0):
+    """Serving stream over four resident lists (1e5..1e8 lines): saturation throughput
+    from a closed batch, then Poisson arrivals at the given fractions of it."""
+    from paper_2510_20870_amd import synth, xsec
+    ctx = xsec.Context(0)
+    t = time.time()
+    lists, nu0s = [], []
+    for spec, mass in synth.SERVING_LISTS:
+        L = synth.make_lines(spec, workers=gen_workers or synth.default_workers())
+        lists.append(ctx.load_lines(L, mass))
+        nu0s.append(L["nu0"])
+        del L
+    log(f"serving: loaded {len(lists)} lists in {time.time() - t:.1f} s")
+    opts = ctx.opts(xsec.XS_CUT_FIXED, 25.0)
+    ctx.serve_start()
+    # warm-up, then saturation: a closed batch submitted at once
+    warm = synth.request_stream(16, 1.0, seed=seed + 100)
+    serving_run(ctx, lists, warm, opts, on_time=False)
+    sat_reqs = synth.request_stream(max(64, n_requests // 2), 1.0, seed=seed + 200)
+    lat, span = serving_run(ctx, lists, sat_reqs, opts, on_time=False)
+    sat_rate = len(sat_reqs) / span
+    ev_sat = request_evals(nu0s, sat_reqs, 25.0)
+    log(f"serving: saturation {sat_rate:.1f} req/s, {ev_sat.sum() / span:.4e} evals/s")
+    out = {"lists": [s.n for s, _ in synth.SERVING_LISTS],
+           "saturation_req_per_s": sat_rate, "saturation_evals_per_s": ev_sat.sum() / span,
+           "loads": []}
+    for load in loads:
+        reqs = synth.request_stream(n_requests, load * sat_rate, seed=seed)
+        lat, span = serving_run(ctx, lists, reqs, opts, on_time=True)
+        ev = request_evals(nu0s, reqs, 25.0)
+        rec = {"offered_load": load, "rate_hz": load * sat_rate, "requests": n_requests,
+               "p50_ms": float(np.percentile(lat, 50) * 1e3),
+               "p99_ms": float(np.percentile(lat, 99) * 1e3),
+               "mean_ms": float(lat.mean() * 1e3),
+               "req_per_s": n_requests / span, "evals_per_s": float(ev.sum() / span)}
+        log(f"serving: load {load}: p50 {rec['p50_ms']:.2f} ms p99 {rec['p99_ms']:.2f} ms, "
+            f"{rec['req_per_s']:.1f} req/s, {rec['evals_per_s']:.4e} evals/s")
+        out["loads"].append(rec)
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +184,10 @@ def main():
     ap.add_argument("--waves-per-simd", type=int, default=0)
     ap.add_argument("--gen-workers", type=int, default=0,
                     help="processes generating the synthetic list (0 = one per core, max 16)")
+    ap.add_argument("--serving-requests", type=int, default=300,
+                    help="requests per offered load in the serving measurement (0 = skip)")
+    ap.add_argument("--serving-loads", default="0.8",
+                    help="offered loads, fractions of the measured saturation rate")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the plain-copy calibration kernel (for HBM counters)")
     args = ap.parse_args()
@@ -207,12 +297,20 @@ def main():
         if st["violations"]:
             log("PARITY VIOLATIONS", st)
 
+    serving = None
+    if args.serving_requests > 0:
+        del L
+        ctx.unload_lines(h)
+        serving = serving_bench(args.serving_requests,
+                                [float(x) for x in args.serving_loads.split(",")],
+                                gen_workers=args.gen_workers)
+
     # one tile launch covers the whole grid at the one (P, T) point: evals per launch
     evals_per_launch = evals * args.steps / max(1, nl32)
     achieved = evals_per_launch * FLOPS_PER_EVAL / (k32 * 1e-3) / 1e12
     traffic = profiled_traffic()
     res = {
-        "metric": "Voigt line-point evals/s at <=1e-4 rel err vs FP64",
+        "metric": "Voigt line-point evals/s at <=1e-4 rel err vs FP64; p50/p99 request latency",
         "value": value,
         "unit": "evals/s",
         "n_gpus": 1,
@@ -241,6 +339,7 @@ def main():
                      "hbm_frac": (traffic / (k32 * 1e-3) / 1e9 / PEAK_HBM_GBS
                                   if traffic else None)},
         "fp64_path": fp64,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

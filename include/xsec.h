@@ -172,26 +172,34 @@ int xs_graph_launch(xs_graph *g, void *stream);
 void xs_graph_destroy(xs_graph *g);
 
 /* ---------------------------------------------------------------------- serving
- * A request loop for cross-section requests (continuous batching). A server thread owned
- * by the context admits queued requests while an execution slot (a HIP stream) and room
- * in the serving arena (one device allocation, sub-allocated per request) are free; the
- * work of admitted requests runs concurrently on the device, and a finished request
- * releases its slot and memory at once, so the next queued one starts while others are
- * still running. Admission is in arrival order; a request whose footprint does not fit
- * yet may be passed by later ones that fit, at most max_bypass times, after which
- * admission waits for it. A request's result depends only on its own inputs and options
- * (the launch shape is planned from them alone), so it is bitwise the same computed alone
- * (xs_compute) or in any mix. Footprint = records (32 B per line that can reach the grid
- * and per P-T point of a batch) + split partials + the output when it goes to host
- * memory + the grid of a window request + the point table and tile order.
+ * A request loop for cross-section requests (continuous batching). Requests wait in
+ * arrival order until the serving arena (one device allocation, sub-allocated per
+ * request) has room for their footprint; a request that does not fit yet may be passed
+ * by later ones that fit, at most max_bypass times, after which admission waits for it.
+ * An admitted request holds its block until it is done. Its work is cut into steps (the
+ * parameter kernel of a batch of P-T points, tile-kernel launches over chunks of at
+ * least step_items work items, the batch's reduction); a server thread keeps
+ * max_inflight execution lanes (HIP streams) fed with steps, always taking the next step
+ * of the admitted request with the least estimated remaining work, discounted by the
+ * time it has waited (with two lanes or more, one lane only runs requests of a single
+ * step). Requests that arrive while others run are thus admitted as memory frees up,
+ * their kernels share the device with the others at step granularity, and short requests
+ * do not wait behind long ones. A served request's result depends only on its own
+ * inputs and options (the launch shape is planned from them alone), so it is bitwise the
+ * same served alone or in any mix. With an automatic split (opts.split = 0) the server
+ * plans shorter work items than xs_compute (at most 4096 lines each), so the two agree to
+ * FP32 rounding; with the same explicit split they agree bitwise. Footprint = records (32 B per line that can
+ * reach the grid and per P-T point of a batch) + split partials + the output when it
+ * goes to host memory + the grid of a window request + the point table and tile order.
  * The lines (and grid) of a request stay referenced until it is done: unloading them
  * meanwhile fails with XS_EBUSY. */
-typedef uint64_t xs_req_t;
 typedef struct {
-  int max_inflight;   /* requests on the device at once (streams); 0 = 4                 */
+  int max_inflight;   /* execution lanes (HIP streams); 0 = 4                             */
   size_t mem_bytes;   /* serving arena; 0 = min(64 GiB, half of the free budget)         */
   int max_bypass;     /* times a waiting request may be passed; 0 = 8, < 0 = never      */
   int start_paused;   /* nonzero: queue requests but admit none until resumed            */
+  int max_admitted;   /* requests admitted at once; 0 = 32                               */
+  int step_items;     /* work items per tile-kernel step; 0 = 56 per CU (two rounds)     */
 } xs_serve_opts;
 /* Start the server (once per context; xs_submit starts one with defaults otherwise).
  * Errors: XS_EBUSY (already running), XS_ENOMEM (arena does not fit the budget). */
@@ -215,8 +223,9 @@ int xs_poll(xs_ctx *ctx, xs_req_t req, int *done);
  * (XS_OK, XS_ECANCELLED, or the error it failed with, whose message xs_last_error then
  * gives), or XS_ETIMEOUT if it is still pending at the timeout. */
 int xs_wait(xs_ctx *ctx, xs_req_t req, double timeout_s);
-/* Cancel a queued request (XS_OK; it finishes with XS_ECANCELLED). A request already
- * admitted runs to completion: XS_EBUSY. A finished one: XS_OK, no effect. */
+/* Cancel a request: a queued one finishes at once, an admitted one after the steps it has
+ * in flight (its output is then incomplete); both end with XS_ECANCELLED. A finished
+ * request is not affected. Returns XS_OK. */
 int xs_cancel(xs_ctx *ctx, xs_req_t req);
 /* Submit, admission and completion times in seconds on a monotonic clock (a time not yet
  * reached is returned as -1). Completion is when the output is in sigma_out. */
@@ -225,12 +234,13 @@ int xs_request_times(xs_ctx *ctx, xs_req_t req, double *t_submit, double *t_admi
 /* Forget a finished request (XS_EBUSY while it is pending). */
 int xs_release(xs_ctx *ctx, xs_req_t req);
 /* Admission rule on a simulated clock (host only, no device): n requests arriving at
- * arrive[i] (non-decreasing) that run for duration[i] once admitted and need footprint[i]
- * bytes of an arena of mem_bytes with max_inflight slots, admitted by the same policy and
- * arena allocator as the server. Writes admit_out[i], done_out[i] and the peak arena bytes
- * in use. XS_ENOMEM if a footprint exceeds the arena. */
+ * arrive[i] (non-decreasing) that hold their arena block for duration[i] once admitted
+ * and need footprint[i] bytes of an arena of mem_bytes, with at most max_admitted admitted
+ * at once, admitted by the same policy and arena allocator as the server. Writes
+ * admit_out[i], done_out[i] and the peak arena bytes in use. XS_ENOMEM if a footprint
+ * exceeds the arena. */
 int xs_sched_simulate(size_t n, const double *arrive, const double *duration,
-                      const uint64_t *footprint, uint64_t mem_bytes, int max_inflight,
+                      const uint64_t *footprint, uint64_t mem_bytes, int max_admitted,
                       int max_bypass, double *admit_out, double *done_out,
                       uint64_t *peak_bytes);
 

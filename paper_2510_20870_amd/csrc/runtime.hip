@@ -150,7 +150,7 @@ static void line_range(const LinesRes& L, const GridRes& G, const xs_opts& o, in
 }
 
 Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const xs_opts& o,
-               size_t cap_bytes) {
+               size_t cap_bytes, int64_t max_item_lines) {
   Plan p;
   p.P = o.pts_per_lane ? o.pts_per_lane : 2;
   p.W = o.waves_per_simd == 2 ? 0 : o.waves_per_simd;
@@ -160,6 +160,19 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
   int64_t hi = 0;
   line_range(L, G, o, &p.rec_lo, &hi);
   p.rec_n = hi - p.rec_lo;
+  // line windows of the tiles (from the sampled index, within the largest cut)
+  const std::vector<double>& sm = L.sample;
+  std::vector<int64_t>& cost = p.tile_cost;
+  cost.assign(p.n_tiles, 0);
+  int64_t max_cost = 0;
+  for (int64_t t = 0; t < p.n_tiles; ++t) {
+    const int64_t j0 = t * tile, j1 = std::min<int64_t>(j0 + tile, (int64_t)G.n) - 1;
+    const double lo = G.host[j0] - o.cut_cm1, hi = G.host[j1] + o.cut_cm1;
+    cost[t] = (int64_t)(std::upper_bound(sm.begin(), sm.end(), hi) -
+                        std::lower_bound(sm.begin(), sm.end(), lo));
+    max_cost = std::max(max_cost, cost[t]);
+  }
+  const int64_t max_window = (max_cost + 1) * kSampleStride;   // lines, upper estimate
   if (o.split) {
     p.split = o.split;
   } else {
@@ -169,10 +182,13 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
     const int64_t target = (int64_t)c.n_cu * 112;
     int64_t sp = (target + base - 1) / base;
     sp = std::max<int64_t>(1, std::min<int64_t>(sp, 64));
+    // and, if asked, no item longer than max_item_lines lines, so that no wave holds its
+    // slot for long (kernels of other requests get slots quickly)
+    if (max_item_lines > 0)
+      sp = std::max<int64_t>(sp, (max_window + max_item_lines - 1) / max_item_lines);
     // no point in splits much shorter than one 64-line chunk per tile window
-    const int64_t per_tile = std::max<int64_t>(1, p.rec_n / std::max<int64_t>(1, p.n_tiles));
-    sp = std::min<int64_t>(sp, std::max<int64_t>(1, per_tile / 64));
-    p.split = (int)sp;
+    sp = std::min<int64_t>(sp, std::max<int64_t>(1, max_window / 64));
+    p.split = (int)std::min<int64_t>(sp, kMaxSplit);
   }
   // (P, T) points per batch: the records of a batch (32 B per line and point) and its
   // partials stay under a quarter of the free budget and 16 GiB
@@ -185,16 +201,8 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
   const size_t per_pt = std::max<size_t>(
       1, (size_t)p.rec_n * 32 + (p.split > 1 ? (size_t)p.split * G.n * 8 : 0));
   p.pt_batch = (int)std::max<size_t>(1, std::min<size_t>(npts, cap / per_pt));
-  // issue order: tiles by decreasing number of lines within the largest cut (from the
-  // sampled index), so the most expensive work items start first
-  std::vector<int64_t> cost(p.n_tiles);
-  const std::vector<double>& sm = L.sample;
-  for (int64_t t = 0; t < p.n_tiles; ++t) {
-    const int64_t j0 = t * tile, j1 = std::min<int64_t>(j0 + tile, (int64_t)G.n) - 1;
-    const double lo = G.host[j0] - o.cut_cm1, hi = G.host[j1] + o.cut_cm1;
-    cost[t] = (int64_t)(std::upper_bound(sm.begin(), sm.end(), hi) -
-                        std::lower_bound(sm.begin(), sm.end(), lo));
-  }
+  // issue order: tiles by decreasing number of lines within the largest cut, so the most
+  // expensive work items start first
   // coarse cost classes (ratio 2^(1/4)) keep neighbouring tiles of similar cost together,
   // so that they still share their line windows in one XCD's L2
   std::vector<int> cls(p.n_tiles);
@@ -236,18 +244,18 @@ int upload_order(Ctx& c, const Plan& p, hipStream_t st) {
   return XS_OK;
 }
 
-int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Plan& p,
+int enqueue_step(const LinesRes& L, const GridRes& G, const xs_opts& o, const Plan& p,
                  const double* pts_dev, const int* order_dev, double* out_dev, void* rec_dev,
-                 void* part_dev, hipStream_t st, unsigned long long* counts,
+                 void* part_dev, hipStream_t st, int pt0, int nb, int64_t c0, int64_t c1,
+                 bool with_params, bool with_reduce, unsigned long long* counts,
                  KernelTimer* tm) {
-  const int* tile_order = order_dev;
   const bool f64 = o.precision == XS_FP64;
   CutDev cut;
   cut.kind = o.cutoff_kind == XS_CUT_FIXED ? kCutFixed : kCutMinFwhm;
   cut.cut = o.cut_cm1;
   cut.mult = o.fwhm_mult;
-  for (int pt0 = 0; pt0 < p.npts; pt0 += p.pt_batch) {
-    const int nb = std::min(p.pt_batch, p.npts - pt0);
+  hipError_t e;
+  if (with_params) {
     ParamArgs PA;
     memset(&PA, 0, sizeof PA);
     PA.L = L.dev;
@@ -259,8 +267,10 @@ int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Pl
     PA.lo = p.rec_lo;
     PA.n = p.rec_n;
     PA.out = (LineRec*)rec_dev;
-    hipError_t e = launch_params(PA, st);
+    e = launch_params(PA, st);
     if (e != hipSuccess) return hip_fail(e, "parameter kernel launch");
+  }
+  if (c1 > c0) {
     TileArgs A;
     memset(&A, 0, sizeof A);
     A.L = L.dev;
@@ -272,10 +282,10 @@ int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Pl
     A.pt0 = pt0;
     A.n_pt = nb;
     A.split = counts ? 1 : p.split;
-    A.n_tiles = p.n_tiles;
-    A.n_items = p.n_tiles * nb * A.split;
+    A.n_tiles = c1 - c0;
+    A.n_items = A.n_tiles * nb * A.split;
     A.n_wg = (A.n_items + kWavesPerWG - 1) / kWavesPerWG;
-    A.tile_order = tile_order;
+    A.tile_order = order_dev + c0;
     A.recs = (const LineRec*)rec_dev;
     A.rec_lo = p.rec_lo;
     A.rec_n = p.rec_n;
@@ -293,12 +303,24 @@ int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Pl
     }
     rc = tm ? tm->record(st) : XS_OK;
     if (rc) return rc;
-    if (counts) continue;
-    if (A.split > 1) {
-      e = launch_reduce((const double*)part_dev, out_dev + (int64_t)pt0 * A.n_grid, A.n_grid,
-                        nb, A.split, st);
-      if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
-    }
+  }
+  if (with_reduce && !counts && p.split > 1) {
+    e = launch_reduce((const double*)part_dev, out_dev + (int64_t)pt0 * (int64_t)G.n,
+                      (int64_t)G.n, nb, p.split, st);
+    if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
+  }
+  return XS_OK;
+}
+
+int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Plan& p,
+                 const double* pts_dev, const int* order_dev, double* out_dev, void* rec_dev,
+                 void* part_dev, hipStream_t st, unsigned long long* counts,
+                 KernelTimer* tm) {
+  for (int pt0 = 0; pt0 < p.npts; pt0 += p.pt_batch) {
+    const int nb = std::min(p.pt_batch, p.npts - pt0);
+    const int rc = enqueue_step(L, G, o, p, pts_dev, order_dev, out_dev, rec_dev, part_dev, st,
+                                pt0, nb, 0, p.n_tiles, true, true, counts, tm);
+    if (rc) return rc;
   }
   return XS_OK;
 }

@@ -31,6 +31,9 @@ struct LinesRes {
 };
 
 constexpr int64_t kSampleStride = 1024;
+// Longest line range of one work item of a served request (its default split keeps items
+// at or under it, so that a new request's kernels find free wavefront slots quickly).
+constexpr int64_t kServeItemLines = 4096;
 
 struct GridRes {
   double* d = nullptr;
@@ -51,6 +54,7 @@ struct Plan {
   int npts = 0;
   int pt_batch = 1;        // (P, T) points per parameter/tile launch pair
   std::vector<int> tile_order;   // tiles by decreasing estimated work
+  std::vector<int64_t> tile_cost;  // sampled line count in each tile's window (x 1024)
   size_t rec_bytes() const { return (size_t)rec_n * pt_batch * 32; }
   size_t part_bytes(size_t n_grid) const {
     return split > 1 ? (size_t)pt_batch * split * n_grid * sizeof(double) : 0;
@@ -110,16 +114,26 @@ int hip_fail(hipError_t e, const char* what);
 int validate_opts(const xs_opts* o);
 int validate_pts(const xs_pt* pts, size_t npts);
 // Launch plan; cap_bytes bounds the records and partials of one batch of (P, T) points
-// (0: min(16 GiB, a quarter of the free budget)). The launch shape (P, split) depends only
-// on the inputs and options, never on the memory left.
+// (0: min(16 GiB, a quarter of the free budget)); max_item_lines > 0 caps the line range
+// of a work item when the split is automatic. The launch shape (P, split) depends only on
+// the inputs, the options and max_item_lines, never on the memory left.
 Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const xs_opts& o,
-               size_t cap_bytes = 0);
+               size_t cap_bytes = 0, int64_t max_item_lines = 0);
 // Enqueue the whole path on `st`: per batch of (P, T) points the parameter kernel, the
 // tile kernel and (split > 1) the fixed-order reduction; with counts != nullptr the count
 // kernel instead of tile + reduction.
 int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Plan& p,
                  const double* pts_dev, const int* order_dev, double* out_dev, void* rec_dev,
                  void* part_dev, hipStream_t st, unsigned long long* counts = nullptr,
+                 KernelTimer* tm = nullptr);
+// One step of the path for the batch of points [pt0, pt0 + nb): the parameter kernel
+// (with_params), the tile kernel over positions [c0, c1) of the tile order (order_dev is
+// required), and the fixed-order reduction of the batch (with_reduce, split > 1). The
+// steps of one batch must run in this order.
+int enqueue_step(const LinesRes& L, const GridRes& G, const xs_opts& o, const Plan& p,
+                 const double* pts_dev, const int* order_dev, double* out_dev, void* rec_dev,
+                 void* part_dev, hipStream_t st, int pt0, int nb, int64_t c0, int64_t c1,
+                 bool with_params, bool with_reduce, unsigned long long* counts = nullptr,
                  KernelTimer* tm = nullptr);
 // Upload the plan's tile order into the context buffer (skipped when unchanged).
 int upload_order(Ctx& c, const Plan& p, hipStream_t st);

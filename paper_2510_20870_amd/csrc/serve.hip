@@ -1,14 +1,20 @@
 // Serving loop: continuous batching of cross-section requests on one device.
 //
-// A server thread owns a fixed set of execution slots (non-blocking HIP streams at the
-// default priority) and one device arena. Requests wait in arrival order; whenever a slot
-// and room in the arena are free, the next admissible request gets a contiguous arena
-// block, its point table and tile order are staged through the slot's pinned buffer, and
-// its whole path (parameter, tile and reduction kernels) is enqueued on the slot's stream,
-// followed by a completion event. The thread polls the events; a finished request gives
-// back its slot and block at once, so queued work starts while other requests are still
-// running, and kernels of different requests share the device.
+// Requests wait in arrival order until room in the serving arena (one device allocation,
+// sub-allocated per request) lets them in; an admitted request holds its block until it is
+// done. Each admitted request's path is cut into steps (the parameter kernel of a batch of
+// P-T points, then the tile kernel over consecutive chunks of its tile order of at least
+// step_items work items each, then the batch's reduction), and a server thread keeps a few
+// execution lanes (non-blocking HIP streams at the default priority) fed with steps:
+// whenever a lane has room, it takes the next step of the admitted request with the least
+// estimated remaining work (weighted down by the time the request has waited, so large
+// requests are not starved); one lane is kept for requests of a single step. A request's
+// steps run in order: its next step goes to the lane of its step still in flight, or to
+// any lane once none is. Kernels of different requests therefore share the device at step
+// granularity, short requests finish while long ones are in progress, and a finished
+// request frees its block at once.
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <string.h>
 
 #include <algorithm>
@@ -108,6 +114,15 @@ int pick_admission(std::deque<Waiting>& q, Arena& a, int max_bypass, size_t* off
 
 enum { kQueued = 0, kRunning = 1, kDone = 2 };
 
+// One step of a request: the parameter kernel of batch [pt0, pt0 + nb) (params), the tile
+// kernel over tile-order positions [c0, c1), and the batch's reduction (reduce).
+struct Step {
+  int pt0, nb;
+  int64_t c0, c1;
+  bool params, reduce;
+  double est;          // estimated line-point visits
+};
+
 struct Request {
   uint64_t id = 0;
   int state = kQueued;
@@ -123,20 +138,35 @@ struct Request {
   double* out = nullptr;
   bool out_dev = false;
   Plan plan;
-  // arena block and its parts (byte offsets inside the block)
+  std::vector<Step> steps;
+  size_t next = 0;           // next step to enqueue
+  int inflight = 0;          // steps enqueued and not yet complete
+  int lane = -1;             // lane of the steps in flight
+  double remaining = 0.0;    // estimated visits of the steps not yet enqueued
+  double total = 0.0;        // estimated visits of all steps
+  bool uploaded = false;     // inputs staged to the device
+  bool cancel = false;       // stop at the next step boundary
+  int fail_rc = XS_OK;
+  std::string fail_msg;
+  // arena block and its parts (byte offsets inside the block); pinned staging block
   size_t bytes = 0, off = 0;
   size_t o_rec = 0, o_part = 0, o_out = 0, o_grid = 0, o_pts = 0, o_order = 0;
-  int slot = -1;
+  size_t pin_bytes = 0, pin_off = 0;
   double t_submit = -1.0, t_admit = -1.0, t_done = -1.0;
 };
 
-struct Slot {
-  hipStream_t st = nullptr;
-  hipEvent_t ev = nullptr;
-  void* pinned = nullptr;
-  size_t pinned_cap = 0;
-  Request* req = nullptr;
+struct InFlight {
+  Request* r;
+  hipEvent_t ev;
 };
+
+struct Lane {
+  hipStream_t st = nullptr;
+  std::deque<InFlight> q;
+};
+
+constexpr int kLaneDepth = 2;          // steps queued per lane
+constexpr double kAgeScale = 0.5;      // s: waiting this long halves a request's priority key
 
 }  // namespace
 
@@ -146,27 +176,63 @@ struct Server {
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   bool stop = false, paused = false;
-  int max_inflight = 4, max_bypass = 8;
-  char* base = nullptr;
+  int n_lanes = 4, max_bypass = 8, max_admitted = 32;
+  int64_t step_items = 0;
+  char* base = nullptr;        // device arena
   size_t mem = 0;
   Arena arena;
-  std::vector<Slot> slots;
+  char* pin_base = nullptr;    // pinned staging arena
+  size_t pin_mem = 0;
+  Arena pin_arena;
+  std::vector<Lane> lanes;
+  std::vector<hipEvent_t> events;   // free completion events
   std::deque<Waiting> queue;
+  std::vector<Request*> admitted;
   std::unordered_map<uint64_t, Request*> reqs;
   uint64_t next_id = 1;
-  int running = 0;
 
   void loop();
-  int launch(Request& r, Slot& s);
+  int enqueue_next(Request& r, Lane& ln);
   void finish(Request& r, int status, const std::string& err);
+  void build_steps(Request& r) const;
 };
 
-// Drop the request's references and arena block; the caller holds mu.
+// Cut the request's path into steps of at least step_items work items each (tiles x
+// points of the batch x split), so that every tile-kernel launch fills the device even
+// when the request runs alone; each step's estimated line-point visits (from the sampled
+// windows) rank requests.
+void Server::build_steps(Request& r) const {
+  const Plan& p = r.plan;
+  const double pts_per_tile = (double)(kWave * p.P);
+  for (int pt0 = 0; pt0 < p.npts; pt0 += p.pt_batch) {
+    const int nb = std::min(p.pt_batch, p.npts - pt0);
+    const int64_t items_per_tile = (int64_t)nb * p.split;
+    int64_t c0 = 0;
+    double acc = 0.0;
+    bool first = true;
+    for (int64_t i = 0; i < p.n_tiles; ++i) {
+      acc += (double)(p.tile_cost[p.tile_order[i]] + 1) * (double)kSampleStride *
+             pts_per_tile * nb;
+      if ((i + 1 - c0) * items_per_tile >= step_items || i + 1 == p.n_tiles) {
+        r.steps.push_back({pt0, nb, c0, i + 1, first, i + 1 == p.n_tiles, acc});
+        first = false;
+        c0 = i + 1;
+        acc = 0.0;
+      }
+    }
+  }
+  r.remaining = 0.0;
+  for (const Step& s : r.steps) r.remaining += s.est;
+  r.total = r.remaining;
+}
+
+// Drop the request's references and memory; the caller holds mu and no step of the
+// request is in flight.
 void Server::finish(Request& r, int status, const std::string& err) {
   if (r.state == kRunning) {
     arena.release(r.off, r.bytes);
-    --running;
-    if (r.slot >= 0) slots[r.slot].req = nullptr;
+    pin_arena.release(r.pin_off, r.pin_bytes);
+    admitted.erase(std::find(admitted.begin(), admitted.end(), &r));
   }
   r.L->refs.fetch_sub(1);
   if (!r.own_grid) r.G->refs.fetch_sub(1);
@@ -177,41 +243,53 @@ void Server::finish(Request& r, int status, const std::string& err) {
   cv_done.notify_all();
 }
 
-// Stage the request's inputs and enqueue its path on the slot's stream (caller holds mu).
-int Server::launch(Request& r, Slot& s) {
+// Enqueue the request's next step on the lane (staging its inputs first if this is its
+// first step) and record a completion event; the caller holds mu.
+int Server::enqueue_next(Request& r, Lane& ln) {
   char* blk = base + r.off;
-  const size_t pts_bytes = r.pt_pairs.size() * sizeof(double);
-  const size_t ord_bytes = r.plan.tile_order.size() * sizeof(int);
-  const size_t need = round256(pts_bytes) + ord_bytes;
-  if (s.pinned_cap < need) {
-    // the slot's previous request has completed, so its staging copies are done
-    if (s.pinned) (void)hipHostFree(s.pinned);
-    s.pinned = nullptr;
-    s.pinned_cap = 0;
-    const size_t cap = std::max<size_t>(need, 64 << 10);
-    hipError_t e = hipHostMalloc(&s.pinned, cap, 0);
-    if (e != hipSuccess) return hip_fail(e, "hipHostMalloc (serving staging)");
-    s.pinned_cap = cap;
+  hipError_t e;
+  if (!r.uploaded) {
+    const size_t pts_bytes = r.pt_pairs.size() * sizeof(double);
+    const size_t ord_bytes = r.plan.tile_order.size() * sizeof(int);
+    char* pin = pin_base + r.pin_off;
+    memcpy(pin, r.pt_pairs.data(), pts_bytes);
+    memcpy(pin + round256(pts_bytes), r.plan.tile_order.data(), ord_bytes);
+    e = hipMemcpyAsync(blk + r.o_pts, pin, pts_bytes, hipMemcpyHostToDevice, ln.st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(blk + r.o_order, pin + round256(pts_bytes), ord_bytes,
+                         hipMemcpyHostToDevice, ln.st);
+    if (e != hipSuccess) return hip_fail(e, "serving upload");
+    if (r.own_grid) {
+      r.own.d = (double*)(blk + r.o_grid);
+      e = launch_fill_uniform(r.own.d, (int64_t)r.own.n, r.nu_start, r.step, ln.st);
+      if (e != hipSuccess) return hip_fail(e, "grid fill launch");
+    }
+    r.uploaded = true;
   }
-  memcpy(s.pinned, r.pt_pairs.data(), pts_bytes);
-  memcpy((char*)s.pinned + round256(pts_bytes), r.plan.tile_order.data(), ord_bytes);
-  hipError_t e = hipMemcpyAsync(blk + r.o_pts, s.pinned, pts_bytes, hipMemcpyHostToDevice, s.st);
-  if (e == hipSuccess && ord_bytes)
-    e = hipMemcpyAsync(blk + r.o_order, (char*)s.pinned + round256(pts_bytes), ord_bytes,
-                       hipMemcpyHostToDevice, s.st);
-  if (e != hipSuccess) return hip_fail(e, "serving upload");
-  if (r.own_grid) {
-    r.own.d = (double*)(blk + r.o_grid);
-    e = launch_fill_uniform(r.own.d, (int64_t)r.own.n, r.nu_start, r.step, s.st);
-    if (e != hipSuccess) return hip_fail(e, "grid fill launch");
-  }
+  const Step& s = r.steps[r.next];
   double* out_dev = r.out_dev ? r.out : (double*)(blk + r.o_out);
   void* part = r.plan.split > 1 ? (void*)(blk + r.o_part) : nullptr;
-  int rc = enqueue_path(*r.L, *r.G, r.o, r.plan, (const double*)(blk + r.o_pts),
-                        (const int*)(blk + r.o_order), out_dev, blk + r.o_rec, part, s.st);
+  int rc = enqueue_step(*r.L, *r.G, r.o, r.plan, (const double*)(blk + r.o_pts),
+                        (const int*)(blk + r.o_order), out_dev, blk + r.o_rec, part, ln.st,
+                        s.pt0, s.nb, s.c0, s.c1, s.params, s.reduce);
   if (rc) return rc;
-  e = hipEventRecord(s.ev, s.st);
-  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  hipEvent_t ev;
+  if (events.empty()) {
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+  } else {
+    ev = events.back();
+    events.pop_back();
+  }
+  e = hipEventRecord(ev, ln.st);
+  if (e != hipSuccess) {
+    events.push_back(ev);
+    return hip_fail(e, "hipEventRecord");
+  }
+  ln.q.push_back({&r, ev});
+  r.remaining -= s.est;
+  ++r.next;
+  ++r.inflight;
   return XS_OK;
 }
 
@@ -219,60 +297,114 @@ void Server::loop() {
   (void)hipSetDevice(c->device);
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    // completions
-    std::vector<std::pair<Request*, hipError_t>> done;
-    for (Slot& s : slots) {
-      if (!s.req) continue;
-      const hipError_t e = hipEventQuery(s.ev);
-      if (e == hipErrorNotReady) continue;
-      done.emplace_back(s.req, e);
+    // completed steps
+    std::vector<Request*> done;
+    for (size_t li = 0; li < lanes.size(); ++li) {
+      Lane& ln = lanes[li];
+      while (!ln.q.empty()) {
+        const hipError_t e = hipEventQuery(ln.q.front().ev);
+        if (e == hipErrorNotReady) break;
+        Request& r = *ln.q.front().r;
+        events.push_back(ln.q.front().ev);
+        ln.q.pop_front();
+        --r.inflight;
+        if (e != hipSuccess && r.fail_rc == XS_OK) {
+          hip_fail(e, "serving step");
+          r.fail_rc = XS_EDEVICE;
+          r.fail_msg = g_last_error;
+        }
+        if (r.inflight == 0 && (r.next == r.steps.size() || r.cancel || r.fail_rc))
+          done.push_back(&r);
+      }
     }
     if (!done.empty()) {
       // download host outputs without holding the lock
       std::vector<std::pair<int, std::string>> res(done.size());
+      for (size_t k = 0; k < done.size(); ++k) {
+        Request& r = *done[k];
+        res[k] = r.fail_rc ? std::make_pair(r.fail_rc, r.fail_msg)
+                 : r.cancel ? std::make_pair((int)XS_ECANCELLED, std::string("cancelled"))
+                            : std::make_pair((int)XS_OK, std::string());
+      }
       lk.unlock();
       for (size_t k = 0; k < done.size(); ++k) {
-        Request& r = *done[k].first;
-        hipError_t e = done[k].second;
-        if (e == hipSuccess && !r.out_dev) {
-          const size_t ob = r.pt_pairs.size() / 2 * r.G->n * sizeof(double);
-          e = hipMemcpy(r.out, base + r.off + r.o_out, ob, hipMemcpyDeviceToHost);
-        }
+        Request& r = *done[k];
+        if (res[k].first != XS_OK || r.out_dev) continue;
+        const size_t ob = r.pt_pairs.size() / 2 * r.G->n * sizeof(double);
+        const hipError_t e = hipMemcpy(r.out, base + r.off + r.o_out, ob, hipMemcpyDeviceToHost);
         if (e != hipSuccess) {
-          hip_fail(e, "serving request");
+          hip_fail(e, "result download");
           res[k] = {XS_EDEVICE, g_last_error};
-        } else {
-          res[k] = {XS_OK, std::string()};
         }
       }
       lk.lock();
-      for (size_t k = 0; k < done.size(); ++k) finish(*done[k].first, res[k].first, res[k].second);
+      for (size_t k = 0; k < done.size(); ++k) finish(*done[k], res[k].first, res[k].second);
     }
-    // admissions
-    while (!paused && !stop && running < max_inflight && !queue.empty()) {
+    // admissions: arena room (device and pinned staging) and the admitted-set limit
+    while (!paused && !stop && (int)admitted.size() < max_admitted && !queue.empty()) {
       size_t off = 0;
       const int i = pick_admission(queue, arena, max_bypass, &off);
       if (i < 0) break;
       Request* r = reqs[queue[i].id];
+      size_t pin_off = 0;
+      if (!pin_arena.alloc(r->pin_bytes, &pin_off)) {
+        arena.release(off, r->bytes);
+        break;
+      }
       queue.erase(queue.begin() + i);
-      int si = 0;
-      while (slots[si].req) ++si;
       r->off = off;
-      r->slot = si;
+      r->pin_off = pin_off;
       r->state = kRunning;
       r->t_admit = now_s();
-      ++running;
-      slots[si].req = r;
-      const int rc = launch(*r, slots[si]);
-      if (rc) {
-        // nothing of this request runs past the failed step, but earlier steps may have
-        // been enqueued: wait for them before the block is reused
-        (void)hipStreamSynchronize(slots[si].st);
-        finish(*r, rc, g_last_error);
+      admitted.push_back(r);
+    }
+    // dispatch: fill every lane with steps of the admitted requests, least remaining work
+    // (discounted by waiting time) first. With two lanes or more, lane 0 only takes
+    // requests of at most one step's work, so a short request never queues behind a
+    // step of a long one.
+    const double t = now_s();
+    for (size_t li = 0; li < lanes.size(); ++li) {
+      Lane& ln = lanes[li];
+      const bool express = li == 0 && lanes.size() >= 2;
+      while ((int)ln.q.size() < kLaneDepth) {
+        Request* best = nullptr;
+        double best_key = 0.0;
+        for (Request* r : admitted) {
+          if (r->cancel || r->fail_rc || r->next == r->steps.size()) continue;
+          if (r->inflight > 0 && r->lane != (int)li) continue;
+          if (express && r->steps.size() > 1) continue;
+          const double key = r->remaining / (1.0 + (t - r->t_submit) / kAgeScale);
+          if (!best || key < best_key) {
+            best = r;
+            best_key = key;
+          }
+        }
+        if (!best) break;
+        const int rc = enqueue_next(*best, ln);
+        if (rc) {
+          best->fail_rc = rc;
+          best->fail_msg = g_last_error;
+          if (best->inflight == 0) {
+            // earlier parts of the failed step may be queued: let them drain first
+            (void)hipStreamSynchronize(ln.st);
+            finish(*best, rc, best->fail_msg);
+          }
+          continue;
+        }
+        best->lane = (int)li;
       }
     }
-    if (stop && running == 0) break;
-    if (running == 0 && (queue.empty() || paused || stop))
+    // requests cancelled with nothing in flight
+    for (size_t k = 0; k < admitted.size();) {
+      Request* r = admitted[k];
+      if (r->cancel && r->inflight == 0) {
+        finish(*r, XS_ECANCELLED, "cancelled");
+        continue;
+      }
+      ++k;
+    }
+    if (stop && admitted.empty()) break;
+    if (admitted.empty() && (queue.empty() || paused || stop))
       cv_work.wait(lk);
     else
       cv_work.wait_for(lk, std::chrono::microseconds(20));
@@ -290,16 +422,17 @@ void serve_shutdown(Ctx* c) {
       s->queue.pop_front();
       s->finish(*r, XS_ECANCELLED, "cancelled at shutdown");
     }
+    for (Request* r : s->admitted) r->cancel = true;
     s->cv_work.notify_all();
   }
   if (s->th.joinable()) s->th.join();
-  for (Slot& sl : s->slots) {
-    if (sl.st) (void)hipStreamSynchronize(sl.st);
-    if (sl.ev) (void)hipEventDestroy(sl.ev);
-    if (sl.st) (void)hipStreamDestroy(sl.st);
-    if (sl.pinned) (void)hipHostFree(sl.pinned);
+  for (Lane& ln : s->lanes) {
+    if (ln.st) (void)hipStreamSynchronize(ln.st);
+    if (ln.st) (void)hipStreamDestroy(ln.st);
   }
+  for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
   for (auto& kv : s->reqs) delete kv.second;
+  if (s->pin_base) (void)hipHostFree(s->pin_base);
   if (s->base) c->dev_free(s->base, s->mem);
   delete s;
   c->server = nullptr;
@@ -310,12 +443,18 @@ static int serve_start_locked(Ctx* c, const xs_serve_opts* o) {
   if (!o) o = &d;
   if (o->max_inflight < 0 || o->max_inflight > 64)
     return fail(XS_EINVAL, "max_inflight must be in [0, 64] (got %d)", o->max_inflight);
+  if (o->max_admitted < 0 || o->max_admitted > 4096)
+    return fail(XS_EINVAL, "max_admitted must be in [0, 4096] (got %d)", o->max_admitted);
+  if (o->step_items < 0) return fail(XS_EINVAL, "step_items must be >= 0");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   Server* s = new Server();
   s->c = c;
-  s->max_inflight = o->max_inflight ? o->max_inflight : 4;
+  s->n_lanes = o->max_inflight ? o->max_inflight : 4;
   s->max_bypass = o->max_bypass == 0 ? 8 : o->max_bypass;
+  s->max_admitted = o->max_admitted ? o->max_admitted : 32;
+  // default: two rounds of wavefront slots of the device (4 SIMDs x 7 waves per CU)
+  s->step_items = o->step_items > 0 ? o->step_items : (int64_t)c->n_cu * 56;
   s->paused = o->start_paused != 0;
   size_t mem = o->mem_bytes;
   if (mem == 0) {
@@ -335,17 +474,24 @@ static int serve_start_locked(Ctx* c, const xs_serve_opts* o) {
   }
   s->mem = mem;
   s->arena.reset(mem);
-  s->slots.resize(s->max_inflight);
-  for (Slot& sl : s->slots) {
-    e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+  c->server = s;
+  s->pin_mem = (size_t)32 << 20;
+  e = hipHostMalloc((void**)&s->pin_base, s->pin_mem, 0);
+  if (e != hipSuccess) {
+    s->pin_base = nullptr;
+    serve_shutdown(c);
+    return hip_fail(e, "hipHostMalloc (serving staging)");
+  }
+  s->pin_arena.reset(s->pin_mem);
+  s->lanes.resize(s->n_lanes);
+  for (Lane& ln : s->lanes) {
+    e = hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking);
     if (e != hipSuccess) {
-      c->server = s;
+      ln.st = nullptr;
       serve_shutdown(c);
-      return hip_fail(e, "serving stream/event");
+      return hip_fail(e, "serving stream");
     }
   }
-  c->server = s;
   s->th = std::thread([s] { s->loop(); });
   return XS_OK;
 }
@@ -413,7 +559,7 @@ static int submit(Ctx* c, xs_lines_t lh, xs_grid_t gh, bool window, double nu_st
   }
   r->out = sigma_out;
   r->out_dev = out_on_device != 0;
-  r->plan = make_plan(*c, *r->L, *r->G, npts, *opts, s->mem / 4);
+  r->plan = make_plan(*c, *r->L, *r->G, npts, *opts, s->mem / 4, kServeItemLines);
   const size_t n = r->G->n;
   size_t at = 0;
   auto part = [&](size_t bytes) {
@@ -428,7 +574,9 @@ static int submit(Ctx* c, xs_lines_t lh, xs_grid_t gh, bool window, double nu_st
   r->o_pts = part(npts * 2 * sizeof(double));
   r->o_order = part(r->plan.tile_order.size() * sizeof(int));
   r->bytes = at;
-  if (r->bytes > s->arena.size()) {
+  r->pin_bytes = round256(npts * 2 * sizeof(double)) + r->plan.tile_order.size() * sizeof(int);
+  s->build_steps(*r);
+  if (r->bytes > s->arena.size() || round256(r->pin_bytes) > s->pin_arena.size()) {
     const size_t b = r->bytes;
     r->L->refs.fetch_sub(1);
     if (!window) r->G->refs.fetch_sub(1);
@@ -568,7 +716,12 @@ int xs_cancel(xs_ctx* c, xs_req_t req) {
   std::lock_guard<std::mutex> lk(s->mu);
   Request* r = find_req(s, req);
   if (!r) return fail(XS_ENOTFOUND, "unknown request %llu", (unsigned long long)req);
-  if (r->state == kRunning) return fail(XS_EBUSY, "request %llu is running", (unsigned long long)req);
+  if (r->state == kRunning) {
+    // stops at its next step boundary (the server thread finishes it)
+    r->cancel = true;
+    s->cv_work.notify_all();
+    return XS_OK;
+  }
   if (r->state == kQueued) {
     for (auto it = s->queue.begin(); it != s->queue.end(); ++it)
       if (it->id == req) {
@@ -608,15 +761,15 @@ int xs_release(xs_ctx* c, xs_req_t req) {
 }
 
 int xs_sched_simulate(size_t n, const double* arrive, const double* duration,
-                      const uint64_t* footprint, uint64_t mem_bytes, int max_inflight,
+                      const uint64_t* footprint, uint64_t mem_bytes, int max_admitted,
                       int max_bypass, double* admit_out, double* done_out,
                       uint64_t* peak_bytes) {
   if (n && (!arrive || !duration || !footprint || !admit_out || !done_out))
     return fail(XS_EINVAL, "NULL argument");
-  if (max_inflight < 1) return fail(XS_EINVAL, "max_inflight must be >= 1");
+  if (max_admitted < 1) return fail(XS_EINVAL, "max_admitted must be >= 1");
   for (size_t i = 0; i < n; ++i)
     if (!isfinite(arrive[i]) || !(duration[i] >= 0.0) || !isfinite(duration[i]))
       return fail(XS_EINVAL, "arrive/duration[%zu] invalid", i);
-  return simulate(n, arrive, duration, footprint, mem_bytes, max_inflight,
+  return simulate(n, arrive, duration, footprint, mem_bytes, max_admitted,
                   max_bypass == 0 ? 8 : max_bypass, admit_out, done_out, peak_bytes);
 }

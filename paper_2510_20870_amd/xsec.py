@@ -64,7 +64,8 @@ class Opts(C.Structure):
 
 class ServeOpts(C.Structure):
     _fields_ = [("max_inflight", C.c_int), ("mem_bytes", C.c_size_t), ("max_bypass", C.c_int),
-                ("start_paused", C.c_int)]
+                ("start_paused", C.c_int), ("max_admitted", C.c_int),
+                ("step_items", C.c_int)]
 
 
 _lib = None
@@ -168,7 +169,7 @@ def _stream_handle(stream) -> Optional[int]:
     return int(stream)
 
 
-def sched_simulate(arrive, duration, footprint, mem_bytes: int, max_inflight: int,
+def sched_simulate(arrive, duration, footprint, mem_bytes: int, max_admitted: int,
                    max_bypass: int = 0):
     """The server's admission rule on a simulated clock (host only): returns
     (admit times, done times, peak arena bytes)."""
@@ -181,7 +182,7 @@ def sched_simulate(arrive, duration, footprint, mem_bytes: int, max_inflight: in
     dn = np.zeros(len(a))
     peak = C.c_uint64()
     rc = lib().xs_sched_simulate(len(a), _ptr(a), _ptr(d), _ptr(f), int(mem_bytes),
-                                 int(max_inflight), int(max_bypass), _ptr(ad), _ptr(dn),
+                                 int(max_admitted), int(max_bypass), _ptr(ad), _ptr(dn),
                                  C.byref(peak))
     if rc:
         raise XsError(rc, lib().xs_last_error(None).decode())
@@ -367,8 +368,9 @@ class Context:
 
     # ------------------------------------------------------------------ serving
     def serve_start(self, max_inflight: int = 0, mem_bytes: int = 0, max_bypass: int = 0,
-                    paused: bool = False):
-        o = ServeOpts(max_inflight, mem_bytes, max_bypass, int(bool(paused)))
+                    paused: bool = False, max_admitted: int = 0, step_items: int = 0):
+        o = ServeOpts(max_inflight, mem_bytes, max_bypass, int(bool(paused)), max_admitted,
+                      int(step_items))
         self._check(self._L.xs_serve_start(self.h, C.byref(o)))
 
     def serve_pause(self, paused: bool = True):

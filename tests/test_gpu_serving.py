@@ -28,10 +28,10 @@ def torch_gpu():
     return torch
 
 
-def _opts(kind="fixed", cut=25.0, mult=100.0, f64=False):
+def _opts(kind="fixed", cut=25.0, mult=100.0, f64=False, split=0):
     X = _x()
     return X.Context.opts(X.XS_CUT_FIXED if kind == "fixed" else X.XS_CUT_MIN_FWHM, cut, mult,
-                          X.XS_FP64 if f64 else X.XS_FP32_KAHAN)
+                          X.XS_FP64 if f64 else X.XS_FP32_KAHAN, 0, split)
 
 
 LISTS = ((synth.ListSpec(20_000, 500.0, 700.0, 11), 18.0),
@@ -53,46 +53,62 @@ def test_alone_vs_mix_bitwise(torch_gpu):
         npts = int(rng.integers(1, 4))
         pts = [(float(10 ** rng.uniform(-5, 2)), float(rng.uniform(300, 3000)))
                for _ in range(npts)]
-        f64 = bool(k % 5 == 4)
-        kind = "min_fwhm" if k % 3 == 1 else "fixed"
-        cases.append(dict(li=li, n=n, start=start, pts=pts, f64=f64, kind=kind,
+        cases.append(dict(li=li, n=n, start=start, pts=pts, f64=bool(k % 5 == 4),
+                          kind="min_fwhm" if k % 3 == 1 else "fixed",
+                          split=3 if k % 4 == 2 else 0,
                           window=bool(k % 2), device=bool(k % 4 == 3)))
-    # alone: xs_compute on a resident grid with the same values
-    alone, grids = [], []
-    for c in cases:
-        grid = c["start"] + 0.01 * np.arange(c["n"], dtype=np.float64)
-        g = ctx.set_grid(grid)
-        grids.append(g)
-        alone.append(ctx.compute(hs[c["li"]], g, c["pts"], _opts(c["kind"], f64=c["f64"])))
-    # mix: everything queued while paused, then released at once onto four slots
-    ctx.serve_start(max_inflight=4, paused=True)
-    reqs = []
-    for c, g in zip(cases, grids):
-        o = _opts(c["kind"], f64=c["f64"])
+    grids = [ctx.set_grid(c["start"] + 0.01 * np.arange(c["n"], dtype=np.float64))
+             for c in cases]
+    # small steps, so that most requests run as many interleaved tile-kernel launches
+    ctx.serve_start(max_inflight=4, paused=True, step_items=64)
+
+    def submit(c, g):
+        o = _opts(c["kind"], f64=c["f64"], split=c["split"])
         out = None
         if c["device"]:
             out = torch.full((len(c["pts"]), c["n"]), float("nan"), dtype=torch.float64,
                              device="cuda")
         if c["window"]:
-            reqs.append(ctx.submit_window(hs[c["li"]], c["start"], 0.01, c["n"], c["pts"], o,
-                                          out=out))
-        else:
-            reqs.append(ctx.submit(hs[c["li"]], g, c["pts"], o, out=out))
+            return ctx.submit_window(hs[c["li"]], c["start"], 0.01, c["n"], c["pts"], o,
+                                     out=out)
+        return ctx.submit(hs[c["li"]], g, c["pts"], o, out=out)
+
+    def result(c, r):
+        res = r.wait(120.0)
+        return res.cpu().numpy() if c["device"] else res.copy()
+
+    # alone: one request at a time on the idle server
+    ctx.serve_pause(False)
+    alone = []
+    for c, g in zip(cases, grids):
+        r = submit(c, g)
+        alone.append(result(c, r))
+        r.release()
+    # mix: everything queued while paused, then released at once
+    ctx.serve_pause(True)
+    reqs = [submit(c, g) for c, g in zip(cases, grids)]
     ctx.serve_pause(False)
     times = []
-    for k, (c, r) in enumerate(zip(cases, reqs)):
-        res = r.wait(120.0)
-        res = res.cpu().numpy() if c["device"] else res
+    for k, (c, r, g) in enumerate(zip(cases, reqs, grids)):
+        res = result(c, r)
         print(f"[serve] case {k} list {c['li']} n={c['n']} npts={len(c['pts'])} "
-              f"f64={c['f64']} window={c['window']} device={c['device']}", flush=True)
+              f"f64={c['f64']} split={c['split']} window={c['window']} device={c['device']}",
+              flush=True)
         assert np.array_equal(res, alone[k]), f"case {k} differs alone vs mix"
+        # xs_compute: bitwise with the same explicit split, FP32 rounding otherwise
+        direct = ctx.compute(hs[c["li"]], g, c["pts"], _opts(c["kind"], f64=c["f64"],
+                                                              split=c["split"]))
+        if c["split"]:
+            assert np.array_equal(res, direct), f"case {k} differs served vs xs_compute"
+        for row, drow in zip(res, direct):
+            st = O.compare(row, drow, rel_tol=1e-5)
+            assert st["violations"] == 0, (k, st)
         times.append(r.times())
         r.release()
     ts = np.array(times)
     assert np.all(ts[:, 0] <= ts[:, 1]) and np.all(ts[:, 1] <= ts[:, 2])
-    # the first four were admitted before the first of them completed
-    first_done = ts[:4, 2].min()
-    assert np.all(ts[:4, 1] <= first_done), ts[:4]
+    # all were admitted (memory allows) before the first completed: they ran as a mix
+    assert np.all(ts[:, 1] <= ts[:, 2].min()), ts
     for g in grids:
         ctx.free_grid(g)
     for h in hs:
@@ -162,6 +178,27 @@ def test_cancel_release_busy_and_errors(torch_gpu):
         ctx.serve_start()
     assert e.value.code == X.XS_EBUSY
     ctx.unload_lines(h)                     # nothing pending any more
+    ctx.close()
+
+
+def test_cancel_running_request(torch_gpu):
+    X = _x()
+    spec, mass = LISTS[2]
+    ctx = X.Context(0)
+    h = ctx.load_lines(synth.make_lines(spec), mass)
+    # tiny steps: the request needs thousands of step launches
+    ctx.serve_start(max_inflight=1, step_items=1)
+    big = ctx.submit_window(h, 520.0, 0.01, 15000, [(1.0, 1000.0)], _opts())
+    while big.times()[1] < 0:
+        pass
+    assert big.cancel() == X.XS_OK
+    assert big.status(60.0) == X.XS_ECANCELLED
+    # the server keeps serving afterwards, and the lines are free again once it is done
+    small = ctx.submit_window(h, 600.0, 0.01, 1000, [(1.0, 1000.0)], _opts())
+    assert small.status(60.0) == X.XS_OK
+    big.release()
+    small.release()
+    ctx.unload_lines(h)
     ctx.close()
 
 
