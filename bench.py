@@ -182,6 +182,8 @@ def main():
     ap.add_argument("--pts-per-lane", type=int, default=0)
     ap.add_argument("--split", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the default launch shape instead of tuning it first")
     ap.add_argument("--gen-workers", type=int, default=0,
                     help="processes generating the synthetic list (0 = one per core, max 16)")
     ap.add_argument("--serving-requests", type=int, default=300,
@@ -223,6 +225,14 @@ def main():
     o64 = ctx.opts(kind, W.cut_cm1, W.fwhm_mult, xsec.XS_FP64, args.pts_per_lane, args.split,
                    args.waves_per_simd)
 
+    tuned = None
+    if not args.no_autotune and not (args.pts_per_lane or args.split or args.waves_per_simd):
+        # launch shapes for this workload class (FP32 and FP64 paths), outside the timing
+        t = time.time()
+        tuned = {"fp32": ctx.autotune(h, g, [(P, T)], o32)}
+        if not args.no_fp64:
+            tuned["fp64"] = ctx.autotune(h, g, [(P, T)], o64)
+        log(f"autotuned in {time.time() - t:.1f} s: {tuned}")
     evals = int(ctx.count_evals(h, g, [(P, T)], o32)[0])
     if W.cut_kind == "fixed":
         # independent count from the sorted centres (searchsorted), the harness's rule
@@ -327,6 +337,7 @@ def main():
                                f"P={P} bar T={T} K, cut {W.cut_cm1} cm^-1",
                    "lines": W.lines.n, "grid_points": len(grid), "pt_points": 1,
                    "evals_per_step": evals, "precision": "fp32 voigt + kahan, fp64 offsets",
+                   "launch_shape": tuned["fp32"] if tuned else "default",
                    "device": info},
         "max_rel_err": max_rel,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS,

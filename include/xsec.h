@@ -244,6 +244,45 @@ int xs_sched_simulate(size_t n, const double *arrive, const double *duration,
                       int max_bypass, double *admit_out, double *done_out,
                       uint64_t *peak_bytes);
 
+/* ---------------------------------------------------------------------- autotuning
+ * The launch shape has three parameters: points per lane (the tile of one wavefront is
+ * 64 * pts_per_lane grid points), the work items per resident wavefront slot that the
+ * automatic split aims at (which sets the line range of one item, i.e. how many 64-line
+ * LDS chunks a wavefront walks per item), and the occupancy the tile kernel is compiled
+ * for (waves_per_simd). xs_autotune times candidate shapes on probe blocks of the given
+ * workload (up to three grid blocks, up to three of its P-T points, every line that
+ * reaches them) and stores the fastest in a process-wide cache under the workload's
+ * class: device arch and CU count, precision, cutoff kind, the line density around the
+ * grid middle (power of two of the lines within the cut) and the number of P-T points
+ * (1, 2..16, more). Every later call with pts_per_lane, split and waves_per_simd all 0
+ * uses the cached shape of its class (results then follow that shape, so they agree with
+ * untuned runs to FP32 rounding, and bitwise among runs with the same cache). */
+typedef struct {
+  int pts_per_lane, split, waves_per_simd;  /* the tuned shape for this workload        */
+  int items_per_slot;                       /* the cached class parameter               */
+  double probe_ms;                          /* probe time of the tuned shape            */
+  double default_probe_ms;                  /* probe time of the untuned default        */
+  int candidates;                           /* shapes timed                             */
+  char key[192];                            /* the workload class                       */
+} xs_tune_result;
+int xs_autotune(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts,
+                size_t npts, const xs_opts *opts, xs_tune_result *out);
+/* The class key of a workload (as xs_autotune stores it). */
+int xs_tune_key(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, size_t npts,
+                const xs_opts *opts, char *key_out, size_t key_len);
+/* The process-wide cache (host only): read/write one entry, clear, and JSON persistence.
+ * xs_tune_cache_load merges the file's entries (XS_ENOTFOUND: no such file, XS_EINVAL:
+ * malformed); xs_tune_cache_save writes every entry. xs_tune_cache_get returns
+ * XS_ENOTFOUND for a key not cached. */
+int xs_tune_cache_put(const char *key, int pts_per_lane, int waves_per_simd,
+                      int items_per_slot, double probe_ms);
+int xs_tune_cache_get(const char *key, int *pts_per_lane, int *waves_per_simd,
+                      int *items_per_slot, double *probe_ms);
+int xs_tune_cache_clear(void);
+int xs_tune_cache_size(size_t *n);
+int xs_tune_cache_load(const char *path);
+int xs_tune_cache_save(const char *path);
+
 /* Kernel timing (measurement of the tile kernel, the Voigt evaluation and accumulation
  * step). With timing enabled, xs_compute and xs_count_evals record a HIP event pair on
  * the launch stream around every tile (or count) kernel launch; xs_kernel_time waits for

@@ -134,12 +134,12 @@ int validate_pts(const xs_pt* pts, size_t npts) {
 // Lines that can reach the grid: nu0 within the largest possible cut of its ends. The
 // host index holds every kSampleStride-th centre, so the range is found to within a block
 // and errs on the inclusive side.
-static void line_range(const LinesRes& L, const GridRes& G, const xs_opts& o, int64_t* lo,
-                       int64_t* hi) {
+void line_range_nu(const LinesRes& L, double first, double last, double cut, int64_t* lo,
+                   int64_t* hi) {
   const int64_t n = (int64_t)L.n;
-  const double reach = o.cut_cm1 * (1.0 + 1e-9);
-  const double klo = G.first - reach - fabs(G.first) * 1e-12;
-  const double khi = G.last + reach + fabs(G.last) * 1e-12;
+  const double reach = cut * (1.0 + 1e-9);
+  const double klo = first - reach - fabs(first) * 1e-12;
+  const double khi = last + reach + fabs(last) * 1e-12;
   const std::vector<double>& sm = L.sample;
   // largest sample index k with sm[k] < klo: lines before k * stride are all < klo
   int64_t k0 = (int64_t)(std::lower_bound(sm.begin(), sm.end(), klo) - sm.begin()) - 1;
@@ -149,11 +149,27 @@ static void line_range(const LinesRes& L, const GridRes& G, const xs_opts& o, in
   if (*hi < *lo) *hi = *lo;
 }
 
+static void line_range(const LinesRes& L, const GridRes& G, const xs_opts& o, int64_t* lo,
+                       int64_t* hi) {
+  line_range_nu(L, G.first, G.last, o.cut_cm1, lo, hi);
+}
+
 Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const xs_opts& o,
-               size_t cap_bytes, int64_t max_item_lines) {
+               size_t cap_bytes, int64_t max_item_lines, int items_per_slot) {
   Plan p;
   p.P = o.pts_per_lane ? o.pts_per_lane : 2;
   p.W = o.waves_per_simd == 2 ? 0 : o.waves_per_simd;
+  int ips = items_per_slot > 0 ? items_per_slot : 4;
+  if (o.pts_per_lane == 0 && o.split == 0 && o.waves_per_simd == 0) {
+    // fully automatic launch shape: the tuned one of this workload class, if any
+    TuneVal tv;
+    if (tune_get(tune_key(c, L, G, npts, o), &tv)) {
+      p.P = tv.P;
+      p.W = tv.W;
+      ips = tv.ips;
+      p.tuned = true;
+    }
+  }
   const int64_t tile = (int64_t)kWave * p.P;
   p.n_tiles = ((int64_t)G.n + tile - 1) / tile;
   p.npts = (int)npts;
@@ -176,10 +192,10 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
   if (o.split) {
     p.split = o.split;
   } else {
-    // about four work items per resident wavefront slot (4 SIMDs x 7 waves per CU), so
-    // the last round of waves is short
+    // a few work items per resident wavefront slot (4 SIMDs x 7 waves per CU; 4 by
+    // default, or the tuned count), so the last round of waves is short
     const int64_t base = p.n_tiles * (int64_t)npts;
-    const int64_t target = (int64_t)c.n_cu * 112;
+    const int64_t target = (int64_t)c.n_cu * 28 * ips;
     int64_t sp = (target + base - 1) / base;
     sp = std::max<int64_t>(1, std::min<int64_t>(sp, 64));
     // and, if asked, no item longer than max_item_lines lines, so that no wave holds its

@@ -55,6 +55,7 @@ struct Plan {
   int pt_batch = 1;        // (P, T) points per parameter/tile launch pair
   std::vector<int> tile_order;   // tiles by decreasing estimated work
   std::vector<int64_t> tile_cost;  // sampled line count in each tile's window (x 1024)
+  bool tuned = false;              // launch shape from the tuning cache
   size_t rec_bytes() const { return (size_t)rec_n * pt_batch * 32; }
   size_t part_bytes(size_t n_grid) const {
     return split > 1 ? (size_t)pt_batch * split * n_grid * sizeof(double) : 0;
@@ -117,8 +118,27 @@ int validate_pts(const xs_pt* pts, size_t npts);
 // (0: min(16 GiB, a quarter of the free budget)); max_item_lines > 0 caps the line range
 // of a work item when the split is automatic. The launch shape (P, split) depends only on
 // the inputs, the options and max_item_lines, never on the memory left.
+// items_per_slot > 0 sets the work items per resident wavefront slot of the automatic
+// split (default 4). With pts_per_lane, split and waves_per_simd all 0 the shape comes
+// from the tuning cache when it holds the workload's class.
 Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const xs_opts& o,
-               size_t cap_bytes = 0, int64_t max_item_lines = 0);
+               size_t cap_bytes = 0, int64_t max_item_lines = 0, int items_per_slot = 0);
+
+// Lines [lo, hi) that can reach [first, last] within cut (from the sampled index; the
+// range errs on the inclusive side).
+void line_range_nu(const LinesRes& L, double first, double last, double cut, int64_t* lo,
+                   int64_t* hi);
+int upload_pts(Ctx& c, const xs_pt* pts, size_t npts, hipStream_t st);
+
+// Tuning cache (tune.hip): launch shapes per workload class, process-wide.
+struct TuneVal {
+  int P = 2, W = 0, ips = 4;
+  double probe_ms = 0.0;
+};
+std::string tune_key(const Ctx& c, const LinesRes& L, const GridRes& G, size_t npts,
+                     const xs_opts& o);
+bool tune_get(const std::string& key, TuneVal* v);
+void tune_put(const std::string& key, const TuneVal& v);
 // Enqueue the whole path on `st`: per batch of (P, T) points the parameter kernel, the
 // tile kernel and (split > 1) the fixed-order reduction; with counts != nullptr the count
 // kernel instead of tile + reduction.

@@ -1,0 +1,497 @@
+// Autotuner: launch shapes (points per lane = tile width, work items per wavefront slot =
+// line range of one item, occupancy target) timed on probe blocks of the real workload,
+// kept in a process-wide cache per workload class and persisted as JSON.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cctype>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/xsec.h"
+#include "kernel_args.h"
+#include "runtime_internal.h"
+
+namespace xs {
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneVal> g_tune;
+
+bool valid_val(const TuneVal& v) {
+  return (v.P == 1 || v.P == 2 || v.P == 4 || v.P == 8) && (v.W == 0 || v.W == 3 || v.W == 4) &&
+         v.ips >= 1 && v.ips <= 64;
+}
+
+// ------------------------------------------------------------------ minimal JSON reader
+// Enough for the cache file: objects, strings (with \" and \\ escapes), numbers, and
+// nested values that are skipped.
+struct Json {
+  const char* p;
+  const char* e;
+  bool ok = true;
+
+  void ws() {
+    while (p < e && isspace((unsigned char)*p)) ++p;
+  }
+  bool eat(char c) {
+    ws();
+    if (p < e && *p == c) {
+      ++p;
+      return true;
+    }
+    return false;
+  }
+  bool str(std::string* out) {
+    ws();
+    if (p >= e || *p != '"') return ok = false;
+    ++p;
+    std::string s;
+    while (p < e && *p != '"') {
+      if (*p == '\\') {
+        ++p;
+        if (p >= e) return ok = false;
+      }
+      s.push_back(*p++);
+    }
+    if (p >= e) return ok = false;
+    ++p;
+    if (out) *out = s;
+    return true;
+  }
+  bool num(double* out) {
+    ws();
+    char* end = nullptr;
+    const double v = strtod(p, &end);
+    if (end == p || end > e) return ok = false;
+    p = end;
+    if (out) *out = v;
+    return true;
+  }
+  bool skip() {   // any value
+    ws();
+    if (p >= e) return ok = false;
+    if (*p == '"') return str(nullptr);
+    if (*p == '{' || *p == '[') {
+      const char close = *p == '{' ? '}' : ']';
+      const bool obj = *p == '{';
+      ++p;
+      if (eat(close)) return true;
+      do {
+        if (obj && !(str(nullptr) && eat(':'))) return ok = false;
+        if (!skip()) return false;
+      } while (eat(','));
+      return eat(close) || (ok = false);
+    }
+    if (!strncmp(p, "true", 4) || !strncmp(p, "null", 4)) {
+      p += 4;
+      return true;
+    }
+    if (!strncmp(p, "false", 5)) {
+      p += 5;
+      return true;
+    }
+    return num(nullptr);
+  }
+};
+
+// Reads {"version": 1, "entries": {key: {"P": .., "W": .., "items_per_slot": ..,
+// "probe_ms": ..}, ...}} into *out.
+bool parse_cache(const std::string& text, std::map<std::string, TuneVal>* out) {
+  Json j{text.data(), text.data() + text.size()};
+  if (!j.eat('{')) return false;
+  if (j.eat('}')) return true;
+  do {
+    std::string k;
+    if (!j.str(&k) || !j.eat(':')) return false;
+    if (k != "entries") {
+      if (!j.skip()) return false;
+      continue;
+    }
+    if (!j.eat('{')) return false;
+    if (j.eat('}')) continue;
+    do {
+      std::string key;
+      if (!j.str(&key) || !j.eat(':') || !j.eat('{')) return false;
+      TuneVal v;
+      bool hasP = false, hasW = false, hasI = false;
+      if (!j.eat('}')) {
+        do {
+          std::string f;
+          if (!j.str(&f) || !j.eat(':')) return false;
+          double x = 0.0;
+          if (f == "P" || f == "W" || f == "items_per_slot" || f == "probe_ms") {
+            if (!j.num(&x)) return false;
+            if (f == "P") v.P = (int)x, hasP = true;
+            if (f == "W") v.W = (int)x, hasW = true;
+            if (f == "items_per_slot") v.ips = (int)x, hasI = true;
+            if (f == "probe_ms") v.probe_ms = x;
+          } else if (!j.skip()) {
+            return false;
+          }
+        } while (j.eat(','));
+        if (!j.eat('}')) return false;
+      }
+      if (!hasP || !hasW || !hasI || !valid_val(v)) return false;
+      (*out)[key] = v;
+    } while (j.eat(','));
+    if (!j.eat('}')) return false;
+  } while (j.eat(','));
+  if (!j.eat('}')) return false;
+  j.ws();
+  return j.ok && j.p == j.e;
+}
+
+std::string escape(const std::string& s) {
+  std::string o;
+  for (char ch : s) {
+    if (ch == '"' || ch == '\\') o.push_back('\\');
+    o.push_back(ch);
+  }
+  return o;
+}
+
+}  // namespace
+
+std::string tune_key(const Ctx& c, const LinesRes& L, const GridRes& G, size_t npts,
+                     const xs_opts& o) {
+  // line density: lines within the largest cut of the grid's middle point
+  const double mid = G.host[G.n / 2];
+  const std::vector<double>& sm = L.sample;
+  const int64_t k = (int64_t)(std::upper_bound(sm.begin(), sm.end(), mid + o.cut_cm1) -
+                              std::lower_bound(sm.begin(), sm.end(), mid - o.cut_cm1));
+  const int dens = (int)lround(log2(((double)k + 0.5) * (double)kSampleStride));
+  const char* pc = npts == 1 ? "p1" : npts <= 16 ? "p16" : "pmany";
+  char buf[192];
+  snprintf(buf, sizeof buf, "%s|cu%d|%s|%s|d%d|%s", c.arch.c_str(), c.n_cu,
+           o.precision == XS_FP64 ? "fp64" : "fp32",
+           o.cutoff_kind == XS_CUT_FIXED ? "fixed" : "fwhm", dens, pc);
+  return buf;
+}
+
+bool tune_get(const std::string& key, TuneVal* v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  *v = it->second;
+  return true;
+}
+
+void tune_put(const std::string& key, const TuneVal& v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = v;
+}
+
+namespace {
+
+struct Block {
+  int64_t j0, j1;          // grid points [j0, j1), multiples of 512 except at the end
+  int64_t rec_lo, rec_n;   // lines that can reach them
+};
+
+// Time one candidate shape over the probe blocks: per block the parameter kernel (not
+// timed) and the tile kernel (timed with events on the launch stream; one warm-up run,
+// then one timed run). A block too small to fill the device with the plan's split gets a
+// larger one (at least one round of wavefront slots), so that every candidate is timed
+// at full occupancy.
+int time_candidate(Ctx& c, const LinesRes& L, const GridRes& G, const xs_opts& o,
+                   const std::vector<Block>& blocks, int nprobe, const Plan& full,
+                   KernelTimer& tm, double* ms_out) {
+  const int64_t tile = (int64_t)kWave * full.P;
+  const int64_t round_items = (int64_t)c.n_cu * 28;
+  double total = 0.0;
+  for (const Block& b : blocks) {
+    Plan p = full;
+    p.rec_lo = b.rec_lo;
+    p.rec_n = b.rec_n;
+    p.npts = nprobe;
+    p.pt_batch = nprobe;
+    const int64_t t0 = b.j0 / tile, t1 = (b.j1 + tile - 1) / tile;
+    const int64_t nt = t1 - t0;
+    int64_t sp = std::max<int64_t>(p.split, (round_items + nt * nprobe - 1) / (nt * nprobe));
+    const int64_t part_cap = std::max<int64_t>(
+        1, (int64_t)((size_t)2 << 30) / ((int64_t)nprobe * (int64_t)G.n * 8));
+    sp = std::min<int64_t>(sp, std::min<int64_t>(kMaxSplit, part_cap));
+    p.split = (int)std::max<int64_t>(sp, 1);
+    std::vector<int> order((size_t)nt);
+    for (int64_t t = t0; t < t1; ++t) order[(size_t)(t - t0)] = (int)t;
+    int rc = c.scratch(c.rec_buf, p.rec_bytes(), "tuning records");
+    if (rc) return rc;
+    void* part = nullptr;
+    if (p.split > 1) {
+      rc = c.scratch(c.part_buf, p.part_bytes(G.n), "tuning partials");
+      if (rc) return rc;
+      part = c.part_buf.ptr;
+    }
+    rc = c.scratch(c.out_buf, (size_t)nprobe * G.n * sizeof(double), "tuning output");
+    if (rc) return rc;
+    rc = c.scratch(c.order_buf, order.size() * sizeof(int), "tuning tile order");
+    if (rc) return rc;
+    c.order_host.clear();   // the buffer no longer holds a plan's order
+    hipError_t e = hipMemcpy(c.order_buf.ptr, order.data(), order.size() * sizeof(int),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "tuning order upload");
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2; ++rep) {
+      tm.used = 0;
+      rc = enqueue_step(L, G, o, p, (const double*)c.pts_buf.ptr, (const int*)c.order_buf.ptr,
+                        (double*)c.out_buf.ptr, c.rec_buf.ptr, part, nullptr, 0, nprobe, 0, nt,
+                        true, false, nullptr, &tm);
+      if (rc) return rc;
+      e = hipEventSynchronize(tm.ev[1]);
+      if (e != hipSuccess) return hip_fail(e, "tuning run");
+      e = hipEventElapsedTime(&ms, tm.ev[0], tm.ev[1]);
+      if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    }
+    total += ms;
+  }
+  *ms_out = total;
+  return XS_OK;
+}
+
+}  // namespace
+
+}  // namespace xs
+
+using namespace xs;
+
+int xs_tune_key(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, size_t npts, const xs_opts* opts,
+                char* key_out, size_t key_len) {
+  if (!c || !key_out || key_len == 0) return fail(XS_EINVAL, "NULL argument");
+  int rc = validate_opts(opts);
+  if (rc) return rc;
+  if (npts == 0) return fail(XS_EINVAL, "npts must be >= 1");
+  LinesRes* L;
+  GridRes* G;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    L = c->find_lines(lh);
+    G = c->find_grid(gh);
+  }
+  if (!L || !G) return fail(XS_ENOTFOUND, "unknown line list or grid");
+  const std::string k = tune_key(*c, *L, *G, npts, *opts);
+  if (k.size() + 1 > key_len) return fail(XS_EINVAL, "key buffer too small (%zu)", key_len);
+  memcpy(key_out, k.c_str(), k.size() + 1);
+  return XS_OK;
+}
+
+int xs_autotune(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t npts,
+                const xs_opts* opts, xs_tune_result* out) {
+  if (!c || !out) return fail(XS_EINVAL, "NULL argument");
+  int rc = validate_opts(opts);
+  if (rc) return rc;
+  rc = validate_pts(pts, npts);
+  if (rc) return rc;
+  LinesRes* L;
+  GridRes* G;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    L = c->find_lines(lh);
+    G = c->find_grid(gh);
+  }
+  if (!L || !G) return fail(XS_ENOTFOUND, "unknown line list or grid");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if (c->pts_event_valid) {
+    e = hipEventSynchronize(c->pts_event);   // scratch buffers are reused below
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  }
+  const std::string key = tune_key(*c, *L, *G, npts, *opts);
+
+  // probe points: the first, middle and last P-T points
+  std::vector<xs_pt> pp{pts[0]};
+  if (npts > 2) pp.push_back(pts[npts / 2]);
+  if (npts > 1) pp.push_back(pts[npts - 1]);
+  const int nprobe = (int)pp.size();
+  rc = upload_pts(*c, pp.data(), pp.size(), nullptr);
+  if (rc) return rc;
+
+  // probe blocks: about 4e10 line-point visits in total (a few tens of ms), in up to
+  // three blocks of whole 512-point units at 1/6, 1/2 and 5/6 of the grid
+  const double mid = G->host[G->n / 2];
+  const std::vector<double>& sm = L->sample;
+  const double dens =
+      ((double)(std::upper_bound(sm.begin(), sm.end(), mid + opts->cut_cm1) -
+                std::lower_bound(sm.begin(), sm.end(), mid - opts->cut_cm1)) +
+       0.5) *
+      (double)kSampleStride;
+  const int64_t n = (int64_t)G->n;
+  int64_t want = (int64_t)std::min(4e10 / (dens * nprobe), 9e15);
+  want = std::max<int64_t>(want, 3 * 512);
+  std::vector<Block> blocks;
+  if (2 * want >= n) {
+    blocks.push_back({0, n, 0, 0});
+  } else {
+    const int64_t bl = (want / 3 + 511) / 512 * 512;
+    for (double f : {1.0 / 6.0, 0.5, 5.0 / 6.0}) {
+      int64_t j0 = ((int64_t)(f * (double)n) - bl / 2) / 512 * 512;
+      j0 = std::max<int64_t>(0, std::min<int64_t>(j0, (n - bl) / 512 * 512));
+      const int64_t j1 = std::min<int64_t>(n, j0 + bl);
+      if (!blocks.empty() && j0 < blocks.back().j1) j0 = blocks.back().j1;
+      if (j0 < j1) blocks.push_back({j0, j1, 0, 0});
+    }
+  }
+  for (Block& b : blocks) {
+    int64_t hi = 0;
+    line_range_nu(*L, G->host[b.j0], G->host[b.j1 - 1], opts->cut_cm1, &b.rec_lo, &hi);
+    b.rec_n = hi - b.rec_lo;
+  }
+
+  KernelTimer tm;
+  auto cleanup = [&]() {
+    for (hipEvent_t ev : tm.ev) (void)hipEventDestroy(ev);
+  };
+  struct Cand {
+    int P, ips, W;
+    double ms;
+  };
+  auto run = [&](int P, int ips, int W, double* ms) -> int {
+    xs_opts o = *opts;
+    o.pts_per_lane = P;
+    o.split = 0;
+    o.waves_per_simd = W;
+    const Plan full = make_plan(*c, *L, *G, npts, o, 0, 0, ips);
+    return time_candidate(*c, *L, *G, o, blocks, nprobe, full, tm, ms);
+  };
+  std::vector<Cand> tried;
+  double def_ms = 0.0;
+  rc = run(2, 4, 0, &def_ms);   // the untuned default
+  if (rc) {
+    cleanup();
+    return rc;
+  }
+  tried.push_back({2, 4, 0, def_ms});
+  for (int P : {1, 2, 4})
+    for (int ips : {1, 2, 4, 8, 16}) {
+      if (P == 2 && ips == 4) continue;
+      double ms = 0.0;
+      rc = run(P, ips, 0, &ms);
+      if (rc) {
+        cleanup();
+        return rc;
+      }
+      tried.push_back({P, ips, 0, ms});
+    }
+  Cand best = *std::min_element(tried.begin(), tried.end(),
+                                [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+  for (int W : {3, 4}) {
+    double ms = 0.0;
+    rc = run(best.P, best.ips, W, &ms);
+    if (rc) {
+      cleanup();
+      return rc;
+    }
+    tried.push_back({best.P, best.ips, W, ms});
+    if (ms < best.ms) best = tried.back();
+  }
+  // keep the default unless a shape is clearly faster (probe timings vary by ~2 %)
+  if (best.ms > 0.97 * def_ms) best = tried.front();
+  cleanup();
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "tuning");
+  TuneVal v;
+  v.P = best.P;
+  v.W = best.W;
+  v.ips = best.ips;
+  v.probe_ms = best.ms;
+  tune_put(key, v);
+  // the shape this workload now gets
+  xs_opts o = *opts;
+  o.pts_per_lane = 0;
+  o.split = 0;
+  o.waves_per_simd = 0;
+  const Plan p = make_plan(*c, *L, *G, npts, o);
+  memset(out, 0, sizeof *out);
+  out->pts_per_lane = p.P;
+  out->split = p.split;
+  out->waves_per_simd = p.W;
+  out->items_per_slot = v.ips;
+  out->probe_ms = best.ms;
+  out->default_probe_ms = def_ms;
+  out->candidates = (int)tried.size();
+  snprintf(out->key, sizeof out->key, "%s", key.c_str());
+  return XS_OK;
+}
+
+int xs_tune_cache_put(const char* key, int P, int W, int ips, double probe_ms) {
+  if (!key || !*key) return fail(XS_EINVAL, "empty key");
+  TuneVal v;
+  v.P = P;
+  v.W = W;
+  v.ips = ips;
+  v.probe_ms = probe_ms;
+  if (!valid_val(v))
+    return fail(XS_EINVAL, "invalid shape P=%d W=%d items_per_slot=%d", P, W, ips);
+  tune_put(key, v);
+  return XS_OK;
+}
+
+int xs_tune_cache_get(const char* key, int* P, int* W, int* ips, double* probe_ms) {
+  if (!key) return fail(XS_EINVAL, "NULL key");
+  TuneVal v;
+  if (!tune_get(key, &v)) return fail(XS_ENOTFOUND, "no tuned shape for '%s'", key);
+  if (P) *P = v.P;
+  if (W) *W = v.W;
+  if (ips) *ips = v.ips;
+  if (probe_ms) *probe_ms = v.probe_ms;
+  return XS_OK;
+}
+
+int xs_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  return XS_OK;
+}
+
+int xs_tune_cache_size(size_t* n) {
+  if (!n) return fail(XS_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  *n = g_tune.size();
+  return XS_OK;
+}
+
+int xs_tune_cache_load(const char* path) {
+  if (!path) return fail(XS_EINVAL, "NULL path");
+  FILE* f = fopen(path, "rb");
+  if (!f) return fail(XS_ENOTFOUND, "cannot open %s", path);
+  std::string text;
+  char buf[4096];
+  size_t r;
+  while ((r = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, r);
+  fclose(f);
+  std::map<std::string, TuneVal> m;
+  if (!parse_cache(text, &m)) return fail(XS_EINVAL, "%s is not a valid tuning cache", path);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& kv : m) g_tune[kv.first] = kv.second;
+  return XS_OK;
+}
+
+int xs_tune_cache_save(const char* path) {
+  if (!path) return fail(XS_EINVAL, "NULL path");
+  std::string o = "{\n  \"version\": 1,\n  \"entries\": {";
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    bool first = true;
+    for (auto& kv : g_tune) {
+      char val[160];
+      snprintf(val, sizeof val,
+               "{\"P\": %d, \"W\": %d, \"items_per_slot\": %d, \"probe_ms\": %.6g}",
+               kv.second.P, kv.second.W, kv.second.ips, kv.second.probe_ms);
+      o += first ? "\n    \"" : ",\n    \"";
+      o += escape(kv.first) + "\": " + val;
+      first = false;
+    }
+  }
+  o += "\n  }\n}\n";
+  FILE* f = fopen(path, "wb");
+  if (!f) return fail(XS_EINVAL, "cannot write %s", path);
+  const bool ok = fwrite(o.data(), 1, o.size(), f) == o.size();
+  if (fclose(f) != 0 || !ok) return fail(XS_EINVAL, "write to %s failed", path);
+  return XS_OK;
+}

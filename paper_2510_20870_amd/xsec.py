@@ -68,6 +68,13 @@ class ServeOpts(C.Structure):
                 ("step_items", C.c_int)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("pts_per_lane", C.c_int), ("split", C.c_int), ("waves_per_simd", C.c_int),
+                ("items_per_slot", C.c_int), ("probe_ms", C.c_double),
+                ("default_probe_ms", C.c_double), ("candidates", C.c_int),
+                ("key", C.c_char * 192)]
+
+
 _lib = None
 _lib_lock = threading.Lock()
 
@@ -110,6 +117,17 @@ _SIGS = {
     "xs_release": ([C.c_void_p, C.c_uint64], C.c_int),
     "xs_sched_simulate": ([C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int,
                            C.c_int, C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64)], C.c_int),
+    "xs_autotune": ([C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(Pt), C.c_size_t,
+                     C.POINTER(Opts), C.POINTER(TuneResult)], C.c_int),
+    "xs_tune_key": ([C.c_void_p, C.c_uint64, C.c_uint64, C.c_size_t, C.POINTER(Opts),
+                     C.c_char_p, C.c_size_t], C.c_int),
+    "xs_tune_cache_put": ([C.c_char_p, C.c_int, C.c_int, C.c_int, C.c_double], C.c_int),
+    "xs_tune_cache_get": ([C.c_char_p, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                           C.POINTER(C.c_int), C.POINTER(C.c_double)], C.c_int),
+    "xs_tune_cache_clear": ([], C.c_int),
+    "xs_tune_cache_size": ([C.POINTER(C.c_size_t)], C.c_int),
+    "xs_tune_cache_load": ([C.c_char_p], C.c_int),
+    "xs_tune_cache_save": ([C.c_char_p], C.c_int),
     "xs_set_kernel_timing": ([C.c_void_p, C.c_int], C.c_int),
     "xs_kernel_time": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)], C.c_int),
     "xs_eval_voigt": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p],
@@ -187,6 +205,45 @@ def sched_simulate(arrive, duration, footprint, mem_bytes: int, max_admitted: in
     if rc:
         raise XsError(rc, lib().xs_last_error(None).decode())
     return ad, dn, peak.value
+
+
+def _lib_check(rc: int):
+    if rc != XS_OK:
+        raise XsError(rc, lib().xs_last_error(None).decode())
+
+
+def tune_cache_put(key: str, pts_per_lane: int, waves_per_simd: int, items_per_slot: int,
+                   probe_ms: float = 0.0):
+    _lib_check(lib().xs_tune_cache_put(key.encode(), pts_per_lane, waves_per_simd,
+                                       items_per_slot, probe_ms))
+
+
+def tune_cache_get(key: str):
+    """(pts_per_lane, waves_per_simd, items_per_slot, probe_ms) or None."""
+    P, W, I, ms = C.c_int(), C.c_int(), C.c_int(), C.c_double()
+    rc = lib().xs_tune_cache_get(key.encode(), C.byref(P), C.byref(W), C.byref(I), C.byref(ms))
+    if rc == XS_ENOTFOUND:
+        return None
+    _lib_check(rc)
+    return P.value, W.value, I.value, ms.value
+
+
+def tune_cache_clear():
+    _lib_check(lib().xs_tune_cache_clear())
+
+
+def tune_cache_size() -> int:
+    n = C.c_size_t()
+    _lib_check(lib().xs_tune_cache_size(C.byref(n)))
+    return n.value
+
+
+def tune_cache_load(path: str):
+    _lib_check(lib().xs_tune_cache_load(os.fsencode(path)))
+
+
+def tune_cache_save(path: str):
+    _lib_check(lib().xs_tune_cache_save(os.fsencode(path)))
 
 
 class Request:
@@ -404,6 +461,24 @@ class Context:
                                              _dev_ptr(out) if on_dev else _ptr(out),
                                              int(on_dev), C.byref(h)))
         return Request(self, h.value, out, (p,))
+
+    # ------------------------------------------------------------------ tuning
+    def autotune(self, lines: int, grid: int, pts, opts: Opts) -> Dict[str, object]:
+        """Time launch shapes on probes of this workload and cache the fastest for its
+        class; returns the shape this workload now gets."""
+        p = self._pts(pts)
+        r = TuneResult()
+        self._check(self._L.xs_autotune(self.h, lines, grid, p, len(p), C.byref(opts),
+                                        C.byref(r)))
+        return {"pts_per_lane": r.pts_per_lane, "split": r.split,
+                "waves_per_simd": r.waves_per_simd, "items_per_slot": r.items_per_slot,
+                "probe_ms": r.probe_ms, "default_probe_ms": r.default_probe_ms,
+                "candidates": r.candidates, "key": r.key.decode()}
+
+    def tune_key(self, lines: int, grid: int, npts: int, opts: Opts) -> str:
+        buf = C.create_string_buffer(192)
+        self._check(self._L.xs_tune_key(self.h, lines, grid, npts, C.byref(opts), buf, 192))
+        return buf.value.decode()
 
     # ------------------------------------------------------------------ timing
     def set_kernel_timing(self, enable: bool = True):
