@@ -49,7 +49,7 @@
 namespace xs {
 
 constexpr int kScaleTarget = 96;   // exponent of the strongest FP32 contribution scale
-enum { kSkip = 0, kRows = 1, kLeft = 2, kRight = 6 };   // kLeft/kRight + variant 0..3
+enum { kSkip = 0, kRows = 1, kLeft = 2, kRight = 6, kModes = 10 };   // kLeft/kRight + variant 0..3
 constexpr int kNoScale = -(1 << 28);
 
 // ------------------------------------------------------------------ parameter kernel
@@ -87,6 +87,7 @@ template <int P> struct alignas(16) Rec<false, P> {
   double nu0, cut, ib;
   float y, y2, sc, scy;   // scy = sc * y / sqrt(pi): scale of the series blocks
   float ib32;
+  float m2y2;             // -2 y^2 (two-term series)
   int cls;
   int mode;
   float xr[P];
@@ -282,6 +283,7 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
   } else {
     r.y = y;
     r.y2 = y * y;
+    r.m2y2 = -2.0f * r.y2;
     r.ib32 = (float)lr.ib;
     r.sc = 0.0f;
     r.scy = 0.0f;
@@ -304,9 +306,19 @@ __device__ __forceinline__ void series_values(const Rec<false, P>& q, const floa
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const float x = fmaf(off[p], q.ib32, q.xr[p]);
-    v[p] = q.scy * asym_scaled<NT>(q.y2, fmaf(x, x, q.y2));
+    const float r2 = fmaf(x, x, q.y2);
+    v[p] = q.scy * (NT == 2 ? asym2_m(q.m2y2, r2) : asym_scaled<NT>(q.y2, r2));
   }
 }
+
+// K sqrt(pi) / y of a series row with variant code `var` (wave-uniform).
+__device__ __forceinline__ float series_row(int var, float y2, float m2y2, float r2) {
+  return var == 0 ? asym2_m(m2y2, r2) : asym_scaled_v(var, y2, r2);
+}
+
+// Lines per plain FP32 partial sum before it enters the Kahan-compensated sum: the
+// partial of at most kChunk positive terms carries a relative error below kChunk u32.
+constexpr int kChunk = 16;
 
 // W > 0 asks the compiler for at least W waves per SIMD (capping VGPRs at 512/W).
 template <int P, bool F64, int W>
@@ -368,14 +380,28 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       r.sc = (float)scd;
       r.scy = (float)(scd * (double)r.y * (double)kInvSqrtPi);
     }
-    recs[wv][lane] = r;
+    // Group the chunk's lines by mode (stable inside each mode) so that the walk below
+    // runs every mode's lines in a loop of its own with no per-line dispatch; lines with
+    // no point inside the cut are dropped. The order is fixed by the data alone.
+    int gstart[kModes + 1];
+    {
+      const uint64_t lt = (1ull << lane) - 1ull;
+      int pos = -1, acc = 0;
+      gstart[0] = 0;
+#pragma unroll
+      for (int m = 1; m < kModes; ++m) {
+        const uint64_t mk = __ballot(r.mode == m);
+        if (r.mode == m) pos = acc + __popcll(mk & lt);
+        gstart[m] = acc;
+        acc += __popcll(mk);
+      }
+      gstart[kModes] = acc;
+      if (pos >= 0) recs[wv][pos] = r;
+    }
     wave_sync();
-    const int nk = (int)min((int64_t)kWave, it.e - base);
-    for (int kk = 0; kk < nk; ++kk) {
-      const Rec<F64, P>& q = recs[wv][kk];
-      const int mode = __builtin_amdgcn_readfirstlane(q.mode);
-      if (mode == kSkip) continue;
-      if constexpr (F64) {
+    if constexpr (F64) {
+      for (int kk = gstart[kRows]; kk < gstart[kRows + 1]; ++kk) {
+        const Rec<F64, P>& q = recs[wv][kk];
         const int cls = __builtin_amdgcn_readfirstlane(q.cls);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
@@ -383,47 +409,66 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
           const double d = nu[p] - q.nu0;
           if (fabs(d) <= q.cut) s[p] += q.sc * voigt_k64(d * q.ib, q.y);
         }
-      } else {
-        // Every path only produces the P contributions of this line; one shared Kahan
-        // update follows, so the sums live in fixed registers.
-        float v[P];
-        if (mode >= kLeft) {
-          // The line lies left (or right) of the whole tile and every point is inside the
-          // cut and in the series region: one branch-free block over the P rows.
-          switch (mode) {
-            case kLeft + 0: series_values<P, 2>(q, da32, v); break;
-            case kLeft + 1: series_values<P, 3>(q, da32, v); break;
-            case kLeft + 2: series_values<P, 4>(q, da32, v); break;
-            case kLeft + 3: series_values<P, 6>(q, da32, v); break;
-            case kRight + 0: series_values<P, 2>(q, db32, v); break;
-            case kRight + 1: series_values<P, 3>(q, db32, v); break;
-            case kRight + 2: series_values<P, 4>(q, db32, v); break;
-            default: series_values<P, 6>(q, db32, v); break;
-          }
-        } else {
-          const int cls = __builtin_amdgcn_readfirstlane(q.cls);
+      }
+    } else {
+      // Each group: blocks of kChunk lines summed in plain FP32, each block then added to
+      // the Kahan-compensated sums.
+      auto run = [&](int g0, int g1, auto&& values) {
+        for (int b0 = g0; b0 < g1; b0 += kChunk) {
+          const int b1 = min(b0 + kChunk, g1);
+          float t[P];
 #pragma unroll
-          for (int p = 0; p < P; ++p) {
-            const int cp = (cls >> (2 * p)) & 3;
-            v[p] = 0.0f;
-            if (cp == 1) {
-              // general: FP64 offset and cut test, series or core per point
-              const double d = nu[p] - q.nu0;
-              if (fabs(d) <= q.cut) v[p] = q.sc * voigt_k32(d * q.ib, q.y);
-            } else if (cp >= 2) {
-              // whole row in the series region; the lanes inside the cut are one side of bnd
-              const int info = __builtin_amdgcn_readfirstlane((int)q.rinfo[p]);
-              const float x = fmaf(cp == 2 ? da32[p] : db32[p], q.ib32, q.xr[p]);
-              const float f = q.scy * asym_scaled_v(info >> 6, q.y2, fmaf(x, x, q.y2));
-              const int bnd = info & 63;
-              const bool in = cp == 2 ? (lane <= bnd) : (lane >= bnd);
-              v[p] = in ? f : 0.0f;
-            }
+          for (int p = 0; p < P; ++p) t[p] = 0.0f;
+          for (int kk = b0; kk < b1; ++kk) {
+            float v[P];
+            values(recs[wv][kk], v);
+#pragma unroll
+            for (int p = 0; p < P; ++p) t[p] += v[p];
+          }
+#pragma unroll
+          for (int p = 0; p < P; ++p) kahan_add(s[p], c[p], t[p]);
+        }
+      };
+      // general rows: per-row classes
+      run(gstart[kRows], gstart[kRows + 1], [&](const Rec<false, P>& q, float (&v)[P]) {
+        const int cls = __builtin_amdgcn_readfirstlane(q.cls);
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          const int cp = (cls >> (2 * p)) & 3;
+          v[p] = 0.0f;
+          if (cp == 1) {
+            // general: FP64 offset and cut test, series or core per point
+            const double d = nu[p] - q.nu0;
+            if (fabs(d) <= q.cut) v[p] = q.sc * voigt_k32(d * q.ib, q.y);
+          } else if (cp >= 2) {
+            // whole row in the series region; the lanes inside the cut are one side of bnd
+            const int info = __builtin_amdgcn_readfirstlane((int)q.rinfo[p]);
+            const float x = fmaf(cp == 2 ? da32[p] : db32[p], q.ib32, q.xr[p]);
+            const float f = q.scy * series_row(info >> 6, q.y2, q.m2y2, fmaf(x, x, q.y2));
+            const int bnd = info & 63;
+            const bool in = cp == 2 ? (lane <= bnd) : (lane >= bnd);
+            v[p] = in ? f : 0.0f;
           }
         }
-#pragma unroll
-        for (int p = 0; p < P; ++p) kahan_add(s[p], c[p], v[p]);
-      }
+      });
+      // whole-tile series blocks: the line lies left (right) of the tile, every point is
+      // inside the cut and in the series region
+      run(gstart[kLeft + 0], gstart[kLeft + 1],
+          [&](const Rec<false, P>& q, float (&v)[P]) { series_values<P, 2>(q, da32, v); });
+      run(gstart[kLeft + 1], gstart[kLeft + 2],
+          [&](const Rec<false, P>& q, float (&v)[P]) { series_values<P, 3>(q, da32, v); });
+      run(gstart[kLeft + 2], gstart[kLeft + 3],
+          [&](const Rec<false, P>& q, float (&v)[P]) { series_values<P, 4>(q, da32, v); });
+      run(gstart[kLeft + 3], gstart[kLeft + 4],
+          [&](const Rec<false, P>& q, float (&v)[P]) { series_values<P, 6>(q, da32, v); });
+      run(gstart[kRight + 0], gstart[kRight + 1],
+          [&](const Rec<false, P>& q, float (&v)[P]) { series_values<P, 2>(q, db32, v); });
+      run(gstart[kRight + 1], gstart[kRight + 2],
+          [&](const Rec<false, P>& q, float (&v)[P]) { series_values<P, 3>(q, db32, v); });
+      run(gstart[kRight + 2], gstart[kRight + 3],
+          [&](const Rec<false, P>& q, float (&v)[P]) { series_values<P, 4>(q, db32, v); });
+      run(gstart[kRight + 3], gstart[kRight + 4],
+          [&](const Rec<false, P>& q, float (&v)[P]) { series_values<P, 6>(q, db32, v); });
     }
     wave_sync();
   }

@@ -109,6 +109,13 @@ XS_HD float asym_scaled(float y2, float r2) {
   }
 }
 
+// The two-term case with the line constant m2y2 = -2 y^2 folded in:
+// u (1 + u (1.5 - 2 y^2 u)) for r2 >= kT2R2.
+XS_HD float asym2_m(float m2y2, float r2) {
+  const float u = rcp32(r2);
+  return u * fmaf(u, fmaf(m2y2, u, 1.5f), 1.0f);
+}
+
 // The number of series terms a point at r2 >= kT6R2 needs, as a variant code 0..3.
 XS_HD int asym_variant(float r2) {
   return r2 >= kT2R2 ? 0 : r2 >= kT3R2 ? 1 : r2 >= kT4R2 ? 2 : 3;
