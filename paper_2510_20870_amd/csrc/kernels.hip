@@ -82,21 +82,25 @@ __global__ __launch_bounds__(256) void xs_params_kernel(ParamArgs A) {
 // mode selects the hot-loop path of the line: kSkip (no row inside the cut), kRows
 // (per-row classes), or one whole-tile series block when every row is of class 2
 // (kLeft + variant) or of class 3 (kRight + variant) with every point inside the cut.
+// For a general row (class 1) of the FP32 path, ginfo[p] holds the lanes inside the cut,
+// [lo, hi), and the lanes of the FP64 core region (r^2 < 49), [a, a + n), found exactly at
+// staging time with the same FP64 difference and FP32 r^2 as the per-point evaluation;
+// the core points of all lines are evaluated packed across lines, one point per lane.
+// xr[p] is x at the row's first point for general rows.
 template <bool F64, int P> struct Rec;
 template <int P> struct alignas(16) Rec<false, P> {
-  double nu0, cut, ib;
+  double nu0, ib;
   float y, y2, sc, scy;   // scy = sc * y / sqrt(pi): scale of the series blocks
   float ib32;
   float m2y2;             // -2 y^2 (two-term series)
   int cls;
-  int mode;
   float xr[P];
+  unsigned int ginfo[P];  // general rows: lo | hi << 7 | a << 14 | n << 21
   unsigned char rinfo[P];
 };
 template <int P> struct alignas(16) Rec<true, P> {
   double nu0, cut, ib, y, sc;
   int cls;
-  int mode;
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -196,20 +200,35 @@ struct Rows {
   int last[P];          // lane of the last valid point of the row
 };
 
+// First j in [lo, hi) with pred(j), for pred false then true over [lo, hi); hi if none.
+template <class F>
+__device__ __forceinline__ int first_true(int lo, int hi, F pred) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (pred(mid)) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
+
 // Stages line i: the record (except the FP32 scales, set once the chunk's scale is known)
-// with the row classes; returns the FP64 profile scale in *sc64.
+// with the row classes; returns the FP64 profile scale in *sc64, the line's mode in
+// *mode_out and its number of core points (FP32 path) in *npairs_out.
 template <bool F64, int P>
 __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, const Rows<P>& rows,
                                                   const double* rowv, int64_t i,
-                                                  double* sc64) {
+                                                  double* sc64, int* mode_out,
+                                                  int* npairs_out) {
   const double nu0 = A.L.nu0[i];
   const LineRec lr = A.recs[(int64_t)k * A.rec_n + (i - A.rec_lo)];
   Rec<F64, P> r;
   r.nu0 = nu0;
-  r.cut = lr.cut;
+  if constexpr (F64) r.cut = lr.cut;
   r.ib = lr.ib;
   *sc64 = lr.sc;
   const float y = (float)lr.y;
+  int npairs = 0;
   // Classify each row with the same FP64 difference and test the per-point path uses;
   // the difference is monotone in nu_j, so the row's two ends decide for every point, and
   // a binary search over the row's grid values (rowv, LDS) finds the cut boundary.
@@ -219,6 +238,7 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
     int c = 0;
     float xr = 0.0f;
     int bnd = 0, var = 0;
+    unsigned int ginfo = 0;
     if (rows.valid[p]) {
       const double da = rows.ra[p] - nu0, db = rows.rb[p] - nu0;
       const bool none = (da > lr.cut) || (db < -lr.cut);
@@ -254,14 +274,37 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
             }
           }
         }
+        if (!F64 && c == 1) {
+          // general row: the lanes inside the cut and the core segment among them
+          const double* rv = rowv + kWave * p;
+          const int n = rows.last[p] + 1;
+          const double cut = lr.cut;
+          const float y2 = y * y;
+          const int lo = first_true(0, n, [&](int j) { return rv[j] - nu0 >= -cut; });
+          const int hi = first_true(lo, n, [&](int j) { return rv[j] - nu0 > cut; });
+          const int js = first_true(lo, hi, [&](int j) { return rv[j] - nu0 >= 0.0; });
+          auto core = [&](int j) {
+            const float x = (float)((rv[j] - nu0) * lr.ib);
+            return fmaf(x, x, y2) < kT6R2;
+          };
+          const int a = first_true(lo, js, core);
+          const int b = first_true(js, hi, [&](int j) { return !core(j); });
+          const int nc = b - a;
+          npairs += nc;
+          ginfo = (unsigned)lo | ((unsigned)hi << 7) | ((unsigned)a << 14) |
+                  ((unsigned)nc << 21);
+          xr = (float)((rows.ra[p] - nu0) * lr.ib);
+        }
       }
     }
     cls |= c << (2 * p);
     if constexpr (!F64) {
       r.xr[p] = xr;
       r.rinfo[p] = (unsigned char)(bnd | (var << 6));
+      r.ginfo[p] = ginfo;
     }
   }
+  *npairs_out = npairs;
   int mode = cls == 0 ? kSkip : kRows;
   if constexpr (!F64) {
     // whole-tile series blocks: every row on one side with every point inside the cut;
@@ -276,7 +319,7 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
     else if (cls == kAllRight && full) mode = kRight + (r.rinfo[P - 1] >> 6);
   }
   r.cls = cls;
-  r.mode = mode;
+  *mode_out = mode;
   if constexpr (F64) {
     r.y = lr.y;
     r.sc = lr.sc;
@@ -325,6 +368,11 @@ template <int P, bool F64, int W>
 __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileArgs A) {
   __shared__ Rec<F64, P> recs[kWavesPerWG][kWave];
   __shared__ double rowvals[kWavesPerWG][kWave * P];
+  __shared__ int incl[kWavesPerWG][kWave];           // packed core points, inclusive prefix
+  // packed core contributions: a pass holds the core points of whole lines, at most
+  // kCoreQ (one line brings at most 64 P)
+  constexpr int kCoreQ = kWave * P;
+  __shared__ float cval[kWavesPerWG][F64 ? 1 : kCoreQ];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x >> 6;
   ItemInfo it;
@@ -358,11 +406,11 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     const int64_t i = base + lane;
     Rec<F64, P> r;
     double sc64 = 0.0;
+    int mode = kSkip, npairs = 0;
     if (i < it.e) {
-      r = stage_line<F64, P>(A, it.k, rows, rowvals[wv], i, &sc64);
+      r = stage_line<F64, P>(A, it.k, rows, rowvals[wv], i, &sc64, &mode, &npairs);
     } else {
       r.cls = 0;
-      r.mode = kSkip;
     }
     if constexpr (!F64) {
       const int ex = wave_max(sc64 > 0.0 ? ilogb(sc64) : kNoScale);
@@ -390,13 +438,24 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       gstart[0] = 0;
 #pragma unroll
       for (int m = 1; m < kModes; ++m) {
-        const uint64_t mk = __ballot(r.mode == m);
-        if (r.mode == m) pos = acc + __popcll(mk & lt);
+        const uint64_t mk = __ballot(mode == m);
+        if (mode == m) pos = acc + __popcll(mk & lt);
         gstart[m] = acc;
         acc += __popcll(mk);
       }
       gstart[kModes] = acc;
       if (pos >= 0) recs[wv][pos] = r;
+      if constexpr (!F64) {
+        // inclusive prefix of the packed core points over the general group (lane order
+        // is group order)
+        int w = mode == kRows ? npairs : 0;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+          const int u = __shfl_up(w, o, kWave);
+          if (lane >= o) w += u;
+        }
+        if (mode == kRows) incl[wv][pos] = w;
+      }
     }
     wave_sync();
     if constexpr (F64) {
@@ -429,28 +488,81 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
           for (int p = 0; p < P; ++p) kahan_add(s[p], c[p], t[p]);
         }
       };
-      // general rows: per-row classes
-      run(gstart[kRows], gstart[kRows + 1], [&](const Rec<false, P>& q, float (&v)[P]) {
-        const int cls = __builtin_amdgcn_readfirstlane(q.cls);
+      // General rows, in sub-batches of lines whose core segments hold at most kCoreQ
+      // points: first every core point of the sub-batch is evaluated, one point per lane
+      // (FP64 core), into cval; then the lines are walked in order, each general row
+      // taking the series for its in-cut lanes outside the core and the core values from
+      // cval.
+      {
+        const int g1 = gstart[kRows + 1];
+        int k = gstart[kRows];
+        int base = 0;   // packed points of the lines before k
+        while (k < g1) {
+          const int ke =
+              first_true(k + 1, g1, [&](int kk) { return incl[wv][kk] - base > kCoreQ; });
+          const int npk = incl[wv][ke - 1] - base;
+          for (int r0 = 0; r0 < npk; r0 += kWave) {
+            const int g = r0 + lane;
+            if (g < npk) {
+              const int kk = first_true(k, ke, [&](int m) { return incl[wv][m] - base > g; });
+              const int local = g - (kk > k ? incl[wv][kk - 1] - base : 0);
+              const Rec<false, P>& q = recs[wv][kk];
+              // the row holding point `local` of this line (rows in order)
+              int row = 0, j = 0;
+              int acc = 0;
+              bool found = false;
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-          const int cp = (cls >> (2 * p)) & 3;
-          v[p] = 0.0f;
-          if (cp == 1) {
-            // general: FP64 offset and cut test, series or core per point
-            const double d = nu[p] - q.nu0;
-            if (fabs(d) <= q.cut) v[p] = q.sc * voigt_k32(d * q.ib, q.y);
-          } else if (cp >= 2) {
-            // whole row in the series region; the lanes inside the cut are one side of bnd
-            const int info = __builtin_amdgcn_readfirstlane((int)q.rinfo[p]);
-            const float x = fmaf(cp == 2 ? da32[p] : db32[p], q.ib32, q.xr[p]);
-            const float f = q.scy * series_row(info >> 6, q.y2, q.m2y2, fmaf(x, x, q.y2));
-            const int bnd = info & 63;
-            const bool in = cp == 2 ? (lane <= bnd) : (lane >= bnd);
-            v[p] = in ? f : 0.0f;
+              for (int p = 0; p < P; ++p) {
+                const unsigned gi = q.ginfo[p];
+                const int n = (((q.cls >> (2 * p)) & 3) == 1) ? (int)((gi >> 21) & 127u) : 0;
+                if (!found && local < acc + n) {
+                  row = p;
+                  j = (int)((gi >> 14) & 127u) + (local - acc);
+                  found = true;
+                }
+                acc += n;
+              }
+              const double d = rowvals[wv][kWave * row + j] - q.nu0;
+              cval[wv][g] = q.sc * (float)voigt_core64(d * q.ib, (double)q.y);
+            }
           }
+          wave_sync();
+          int off = 0;   // packed points of the sub-batch's lines walked so far
+          run(k, ke, [&](const Rec<false, P>& q, float (&v)[P]) {
+            const int cls = __builtin_amdgcn_readfirstlane(q.cls);
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+              const int cp = (cls >> (2 * p)) & 3;
+              v[p] = 0.0f;
+              if (cp == 1) {
+                const unsigned gi = (unsigned)__builtin_amdgcn_readfirstlane((int)q.ginfo[p]);
+                const int lo = (int)(gi & 127u), hi = (int)((gi >> 7) & 127u);
+                const int a = (int)((gi >> 14) & 127u), n = (int)((gi >> 21) & 127u);
+                const float x = fmaf(da32[p], q.ib32, q.xr[p]);
+                const float f = q.scy * asym_scaled<6>(q.y2, fmaf(x, x, q.y2));
+                const bool in_cut = lane >= lo && lane < hi;
+                const bool in_core = lane >= a && lane < a + n;
+                const float cv = cval[wv][min(max(off + lane - a, 0), kCoreQ - 1)];
+                off += n;
+                v[p] = in_cut ? (in_core ? cv : f) : 0.0f;
+              } else if (cp >= 2) {
+                // whole row in the series region; the lanes inside the cut are one side of
+                // bnd
+                const int info = __builtin_amdgcn_readfirstlane((int)q.rinfo[p]);
+                const float x = fmaf(cp == 2 ? da32[p] : db32[p], q.ib32, q.xr[p]);
+                const float f =
+                    q.scy * series_row(info >> 6, q.y2, q.m2y2, fmaf(x, x, q.y2));
+                const int bnd = info & 63;
+                const bool in = cp == 2 ? (lane <= bnd) : (lane >= bnd);
+                v[p] = in ? f : 0.0f;
+              }
+            }
+          });
+          wave_sync();   // cval is refilled by the next sub-batch
+          base = incl[wv][ke - 1];
+          k = ke;
         }
-      });
+      }
       // whole-tile series blocks: the line lies left (right) of the tile, every point is
       // inside the cut and in the series region
       run(gstart[kLeft + 0], gstart[kLeft + 1],
