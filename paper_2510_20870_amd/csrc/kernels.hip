@@ -33,7 +33,7 @@
 // sign along the row), with the shortest series the row's nearest point allows and the cut
 // applied as a lane bound found at staging time. FP32 contributions carry a power-of-two scale chosen per wavefront:
 // whenever a staged chunk holds a line stronger than any before, the scale is lowered so
-// the strongest contribution is about 2^97 and the running sums are rescaled exactly, so
+// the strongest line's scale is about 2^48 and the running sums are rescaled exactly, so
 // any absolute magnitude of sigma stays inside FP32 range; the scale is removed exactly
 // when the FP64 result is stored.
 #include <hip/hip_runtime.h>
@@ -48,8 +48,9 @@
 
 namespace xs {
 
-constexpr int kScaleTarget = 96;   // exponent of the strongest FP32 contribution scale
-enum { kSkip = 0, kRows = 1, kLeft = 2, kRight = 6, kModes = 10 };   // kLeft/kRight + variant 0..3
+// exponent of the strongest line's FP32 scale: leaves 2^80 of headroom for sums and keeps
+// the expanded two-term coefficient 2 y^2 c1 finite for y up to 8e7
+constexpr int kScaleTarget = 48;
 constexpr int kNoScale = -(1 << 28);
 
 // ------------------------------------------------------------------ parameter kernel
@@ -76,27 +77,38 @@ __global__ __launch_bounds__(256) void xs_params_kernel(ParamArgs A) {
 // Record of one staged line in LDS. cls holds 2 bits per row p of the wave's tile:
 // 0 = no point of the row is inside the cut, 1 = general path, 2 / 3 = every point of the
 // row is in the FP32 series region (|z| >= 7), the line lying left / right of the row; xr[p]
-// is then x at the row's nearest end (first / last point), rinfo[p] & 63 = bnd: the points
-// inside the cut are the lanes <= bnd (class 2) or >= bnd (class 3), found exactly at
-// staging time, and rinfo[p] >> 6 is the series variant the row's nearest point needs.
-// mode selects the hot-loop path of the line: kSkip (no row inside the cut), kRows
-// (per-row classes), or one whole-tile series block when every row is of class 2
-// (kLeft + variant) or of class 3 (kRight + variant) with every point inside the cut.
-// For a general row (class 1) of the FP32 path, ginfo[p] holds the lanes inside the cut,
-// [lo, hi), and the lanes of the FP64 core region (r^2 < 49), [a, a + n), found exactly at
-// staging time with the same FP64 difference and FP32 r^2 as the per-point evaluation;
-// the core points of all lines are evaluated packed across lines, one point per lane.
-// xr[p] is x at the row's first point for general rows.
+// is then x at the row's nearest end (first / last point) and info[p] = bnd | var << 8:
+// the points inside the cut are the lanes < bnd (class 2) or >= bnd (class 3), found
+// exactly at staging time, and var is the series variant the row's nearest point needs.
+// For a general row (class 1) of the FP32 path, info[p] = lo | hi << 7 | a << 14 | n << 21
+// holds the lanes inside the cut, [lo, hi), and the lanes of the FP64 core region
+// (r^2 < 49), [a, a + n), found exactly at staging time with the same FP64 difference and
+// FP32 r^2 as the per-point evaluation. The core points of all lines are evaluated packed
+// across lines, one point per lane.
+// The line's mode (kept outside the record: lines are grouped by mode) selects its
+// hot-loop path: kSkip (no row inside the cut), kRows (per-row classes), or a series mode
+// when the line lies on one side of the whole tile with every row of class 2 (or 3) or 0:
+// then all rows take the series with the variant of the tile's nearest point, masked by
+// the rows' lane bounds unless every point is inside the cut.
+enum {
+  kSkip = 0,
+  kRows = 1,
+  kSeries = 2,   // + side * 8 + masked * 4 + variant
+  kModes = 18
+};
+__host__ __device__ constexpr int series_mode(int side, int masked, int var) {
+  return kSeries + side * 8 + masked * 4 + var;
+}
+
 template <bool F64, int P> struct Rec;
 template <int P> struct alignas(16) Rec<false, P> {
   double nu0, ib;
-  float y, y2, sc, scy;   // scy = sc * y / sqrt(pi): scale of the series blocks
+  float y, y2, sc;
+  float c1, c2, c3;   // c1 = sc y / sqrt(pi); two-term series = u (c1 + u (c2 + u c3))
   float ib32;
-  float m2y2;             // -2 y^2 (two-term series)
   int cls;
   float xr[P];
-  unsigned int ginfo[P];  // general rows: lo | hi << 7 | a << 14 | n << 21
-  unsigned char rinfo[P];
+  unsigned int info[P];
 };
 template <int P> struct alignas(16) Rec<true, P> {
   double nu0, cut, ib, y, sc;
@@ -196,6 +208,7 @@ __device__ __forceinline__ bool decode_item(const TileArgs& A, int lane, ItemInf
 template <int P>
 struct Rows {
   double ra[P], rb[P];
+  double lanes_per_nu[P];   // last / (rb - ra): linear estimate of a lane from nu
   bool valid[P];
   int last[P];          // lane of the last valid point of the row
 };
@@ -209,6 +222,29 @@ __device__ __forceinline__ int first_true(int lo, int hi, F pred) {
     else lo = mid + 1;
   }
   return lo;
+}
+
+// The same answer, starting from a guess: two probes around est settle it when the guess
+// is within one lane (grids that are close to uniform over a row), else a binary search
+// over the side the probes leave.
+template <class F>
+__device__ __forceinline__ int first_true_near(int lo, int hi, int est, F pred) {
+  if (lo >= hi) return lo;
+  est = min(max(est, lo), hi - 1);
+  if (pred(est)) {
+    if (est == lo || !pred(est - 1)) return est;
+    return first_true(lo, est - 1, pred);   // pred(est - 1) holds
+  }
+  if (est + 1 == hi || pred(est + 1)) return est + 1;
+  return first_true(est + 2, hi, pred);     // pred(est + 1) fails
+}
+
+// Lane guess for the first point with nu >= v in a row (linear in nu, clamped to a small
+// range so that the conversion is always defined).
+template <int P>
+__device__ __forceinline__ int lane_guess(const Rows<P>& rows, int p, double v) {
+  const double g = (v - rows.ra[p]) * rows.lanes_per_nu[p];
+  return (int)ceil(fmin(fmax(g, -1.0), (double)kWave));
 }
 
 
@@ -228,108 +264,117 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
   r.ib = lr.ib;
   *sc64 = lr.sc;
   const float y = (float)lr.y;
+  const float y2 = y * y;
+  const double cut = lr.cut;
   int npairs = 0;
   // Classify each row with the same FP64 difference and test the per-point path uses;
   // the difference is monotone in nu_j, so the row's two ends decide for every point, and
-  // a binary search over the row's grid values (rowv, LDS) finds the cut boundary.
+  // searches over the row's grid values (rowv, LDS) find the cut and core boundaries.
   int cls = 0;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     int c = 0;
     float xr = 0.0f;
-    int bnd = 0, var = 0;
-    unsigned int ginfo = 0;
+    unsigned int info = 0;
     if (rows.valid[p]) {
       const double da = rows.ra[p] - nu0, db = rows.rb[p] - nu0;
-      const bool none = (da > lr.cut) || (db < -lr.cut);
+      const bool none = (da > cut) || (db < -cut);
       if (!none) {
         c = 1;
+        const double* rv = rowv + kWave * p;
+        const int n = rows.last[p] + 1;
         if (!F64 && (da > 0.0 || db < 0.0)) {
           const bool left = da > 0.0;   // the line lies left of the row
           const float x = (float)((left ? da : db) * lr.ib);
-          const float r2n = fmaf(x, x, y * y);
+          const float r2n = fmaf(x, x, y2);
           if (r2n >= kFarR2) {
             c = left ? 2 : 3;
             xr = x;
-            var = asym_variant(r2n);
-            const double* rv = rowv + kWave * p;
+            int bnd;
             if (left) {
-              // last lane with nu - nu0 <= cut (lane 0 qualifies: da <= cut)
-              int lo = 0, hi = rows.last[p] + 1;
-              if (db <= lr.cut) lo = rows.last[p];
-              while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (rv[mid] - nu0 <= lr.cut) lo = mid; else hi = mid;
-              }
-              bnd = lo == rows.last[p] ? kWave - 1 : lo;
+              // lanes before the first one with nu - nu0 > cut (lane 0 is inside: da <= cut)
+              bnd = db <= cut ? kWave
+                    : first_true_near(1, n, lane_guess(rows, p, nu0 + cut),
+                                      [&](int j) { return rv[j] - nu0 > cut; });
             } else {
-              // first lane with nu - nu0 >= -cut (the last lane qualifies: db >= -cut)
-              int lo = -1, hi = rows.last[p];
-              if (da >= -lr.cut) hi = 0;
-              while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (rv[mid] - nu0 >= -lr.cut) hi = mid; else lo = mid;
-              }
-              bnd = hi;
+              // the first lane with nu - nu0 >= -cut (the last lane is inside: db >= -cut)
+              bnd = da >= -cut ? 0
+                    : first_true_near(0, n - 1, lane_guess(rows, p, nu0 - cut),
+                                      [&](int j) { return rv[j] - nu0 >= -cut; });
             }
+            info = (unsigned)bnd | ((unsigned)asym_variant(r2n) << 8);
           }
         }
         if (!F64 && c == 1) {
-          // general row: the lanes inside the cut and the core segment among them
-          const double* rv = rowv + kWave * p;
-          const int n = rows.last[p] + 1;
-          const double cut = lr.cut;
-          const float y2 = y * y;
-          const int lo = first_true(0, n, [&](int j) { return rv[j] - nu0 >= -cut; });
-          const int hi = first_true(lo, n, [&](int j) { return rv[j] - nu0 > cut; });
-          const int js = first_true(lo, hi, [&](int j) { return rv[j] - nu0 >= 0.0; });
+          // general row: the lanes inside the cut and the core segment among them, from
+          // linear guesses checked with the exact predicates
+          const int lo = da >= -cut ? 0
+                         : first_true_near(0, n, lane_guess(rows, p, nu0 - cut),
+                                           [&](int j) { return rv[j] - nu0 >= -cut; });
+          const int hi = db <= cut ? n
+                         : first_true_near(lo, n, lane_guess(rows, p, nu0 + cut),
+                                           [&](int j) { return rv[j] - nu0 > cut; });
+          const int js = first_true_near(lo, hi, lane_guess(rows, p, nu0),
+                                         [&](int j) { return rv[j] - nu0 >= 0.0; });
           auto core = [&](int j) {
             const float x = (float)((rv[j] - nu0) * lr.ib);
             return fmaf(x, x, y2) < kT6R2;
           };
-          const int a = first_true(lo, js, core);
-          const int b = first_true(js, hi, [&](int j) { return !core(j); });
-          const int nc = b - a;
-          npairs += nc;
-          ginfo = (unsigned)lo | ((unsigned)hi << 7) | ((unsigned)a << 14) |
-                  ((unsigned)nc << 21);
-          xr = (float)((rows.ra[p] - nu0) * lr.ib);
+          // the core reaches |x| = sqrt(49 - y^2), i.e. nu0 -+ b_D times that
+          const double xc =
+              (double)(sqrtf(fmaxf(49.0f - y2, 0.0f)) * rcp32((float)lr.ib));
+          const int a = first_true_near(lo, js, lane_guess(rows, p, nu0 - xc), core);
+          const int b = first_true_near(js, hi, lane_guess(rows, p, nu0 + xc),
+                                        [&](int j) { return !core(j); });
+          npairs += b - a;
+          info = (unsigned)lo | ((unsigned)hi << 7) | ((unsigned)a << 14) |
+                 ((unsigned)(b - a) << 21);
         }
       }
     }
     cls |= c << (2 * p);
     if constexpr (!F64) {
       r.xr[p] = xr;
-      r.rinfo[p] = (unsigned char)(bnd | (var << 6));
-      r.ginfo[p] = ginfo;
+      r.info[p] = info;
     }
   }
-  *npairs_out = npairs;
   int mode = cls == 0 ? kSkip : kRows;
   if constexpr (!F64) {
-    // whole-tile series blocks: every row on one side with every point inside the cut;
+    // series modes: the line on one side of the whole tile, every row of that side's
+    // series class or out of the cut (the rows out of the cut get an empty lane range);
     // the variant is that of the tile's point nearest to the line
-    constexpr int kAllLeft = (int)(0xAAAAAAAAu & ((1u << (2 * P)) - 1u));
-    constexpr int kAllRight = (int)(0xFFFFFFFFu & ((1u << (2 * P)) - 1u));
-    bool full = true;
+    constexpr unsigned kOnes = (unsigned)(0x55555555u & ((1u << (2 * P)) - 1u));
+    const unsigned uc = (unsigned)cls;
+    // per row: class in {0, 2} (left) or {0, 3} (right)
+    const bool left_ok = cls != 0 && ((uc & kOnes) == 0u);
+    const bool right_ok = cls != 0 && ((uc & (uc >> 1) & kOnes) == ((uc | (uc >> 1)) & kOnes));
+    if (left_ok || right_ok) {
+      const int side = left_ok ? 0 : 1;
+      bool full = true;
+      int var = 0;   // the nearest row needs the most terms
 #pragma unroll
-    for (int p = 0; p < P; ++p)
-      full = full && ((r.rinfo[p] & 63) == (cls == kAllLeft ? kWave - 1 : 0));
-    if (cls == kAllLeft && full) mode = kLeft + (r.rinfo[0] >> 6);
-    else if (cls == kAllRight && full) mode = kRight + (r.rinfo[P - 1] >> 6);
+      for (int p = 0; p < P; ++p) {
+        const int cp = (cls >> (2 * p)) & 3;
+        if (cp == 0) r.info[p] = side ? (unsigned)kWave : 0u;
+        else var = max(var, (int)(r.info[p] >> 8));
+        const int bnd = (int)(r.info[p] & 255u);
+        full = full && cp != 0 && bnd == (side ? 0 : kWave);
+      }
+      mode = series_mode(side, full ? 0 : 1, var);
+    }
   }
   r.cls = cls;
   *mode_out = mode;
+  *npairs_out = npairs;
   if constexpr (F64) {
     r.y = lr.y;
     r.sc = lr.sc;
   } else {
     r.y = y;
-    r.y2 = y * y;
-    r.m2y2 = -2.0f * r.y2;
+    r.y2 = y2;
     r.ib32 = (float)lr.ib;
     r.sc = 0.0f;
-    r.scy = 0.0f;
+    r.c1 = r.c2 = r.c3 = 0.0f;
   }
   return r;
 }
@@ -341,8 +386,15 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
   s = t;
 }
 
-// Contributions of one line to all P rows when every row is in the series region with
-// NT terms, x from the row end.
+// The two-term series of a line, scaled: u (c1 + u (c2 + u c3)), u = 1/r^2.
+template <int P>
+__device__ __forceinline__ float two_term(const Rec<false, P>& q, float r2) {
+  const float u = rcp32(r2);
+  return u * fmaf(u, fmaf(u, q.c3, q.c2), q.c1);
+}
+
+// Scaled contributions of one line to all P rows in the series region with NT terms, x
+// from the row's nearer end (off = the lane's offsets from that end).
 template <int P, int NT>
 __device__ __forceinline__ void series_values(const Rec<false, P>& q, const float (&off)[P],
                                               float (&v)[P]) {
@@ -350,13 +402,25 @@ __device__ __forceinline__ void series_values(const Rec<false, P>& q, const floa
   for (int p = 0; p < P; ++p) {
     const float x = fmaf(off[p], q.ib32, q.xr[p]);
     const float r2 = fmaf(x, x, q.y2);
-    v[p] = q.scy * (NT == 2 ? asym2_m(q.m2y2, r2) : asym_scaled<NT>(q.y2, r2));
+    v[p] = NT == 2 ? two_term(q, r2) : q.c1 * asym_scaled<NT>(q.y2, r2);
   }
 }
 
-// K sqrt(pi) / y of a series row with variant code `var` (wave-uniform).
-__device__ __forceinline__ float series_row(int var, float y2, float m2y2, float r2) {
-  return var == 0 ? asym2_m(m2y2, r2) : asym_scaled_v(var, y2, r2);
+// Keeps the lanes of each row inside the cut: lanes < bnd (SIDE 0) or >= bnd (SIDE 1).
+template <int P, int SIDE>
+__device__ __forceinline__ void series_mask(const Rec<false, P>& q, int lane, float (&v)[P]) {
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int bnd = __builtin_amdgcn_readfirstlane((int)q.info[p]) & 255;
+    const bool in = SIDE == 0 ? lane < bnd : lane >= bnd;
+    v[p] = in ? v[p] : 0.0f;
+  }
+}
+
+// Scaled series value of one row with variant code `var` (wave-uniform).
+template <int P>
+__device__ __forceinline__ float series_row(int var, const Rec<false, P>& q, float r2) {
+  return var == 0 ? two_term(q, r2) : q.c1 * asym_scaled_v(var, q.y2, r2);
 }
 
 // Lines per plain FP32 partial sum before it enters the Kahan-compensated sum: the
@@ -389,6 +453,8 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     rows.ra[p] = rows.valid[p] ? A.grid[ja] : 0.0;
     rows.rb[p] = rows.valid[p] ? A.grid[jb] : 0.0;
     rows.last[p] = rows.valid[p] ? (int)(jb - ja) : 0;
+    rows.lanes_per_nu[p] =
+        rows.last[p] > 0 ? (double)rows.last[p] / (rows.rb[p] - rows.ra[p]) : 0.0;
     const int64_t j = ja + lane;
     nu[p] = (j < A.n_grid) ? A.grid[j] : __builtin_nan("");
     da32[p] = (float)(nu[p] - rows.ra[p]);
@@ -426,7 +492,9 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       }
       const double scd = ldexp(sc64, kScaleTarget - e_ref);
       r.sc = (float)scd;
-      r.scy = (float)(scd * (double)r.y * (double)kInvSqrtPi);
+      r.c1 = (float)(scd * (double)r.y * (double)kInvSqrtPi);
+      r.c2 = 1.5f * r.c1;
+      r.c3 = -2.0f * r.y2 * r.c1;
     }
     // Group the chunk's lines by mode (stable inside each mode) so that the walk below
     // runs every mode's lines in a loop of its own with no per-line dispatch; lines with
@@ -437,13 +505,14 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       int pos = -1, acc = 0;
       gstart[0] = 0;
 #pragma unroll
-      for (int m = 1; m < kModes; ++m) {
+      for (int m = 1; m < (F64 ? 2 : kModes); ++m) {
         const uint64_t mk = __ballot(mode == m);
         if (mode == m) pos = acc + __popcll(mk & lt);
         gstart[m] = acc;
         acc += __popcll(mk);
       }
-      gstart[kModes] = acc;
+#pragma unroll
+      for (int m = F64 ? 2 : kModes; m <= kModes; ++m) gstart[m] = acc;
       if (pos >= 0) recs[wv][pos] = r;
       if constexpr (!F64) {
         // inclusive prefix of the packed core points over the general group (lane order
@@ -478,6 +547,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
           float t[P];
 #pragma unroll
           for (int p = 0; p < P; ++p) t[p] = 0.0f;
+#pragma unroll 2
           for (int kk = b0; kk < b1; ++kk) {
             float v[P];
             values(recs[wv][kk], v);
@@ -513,7 +583,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
               bool found = false;
 #pragma unroll
               for (int p = 0; p < P; ++p) {
-                const unsigned gi = q.ginfo[p];
+                const unsigned gi = q.info[p];
                 const int n = (((q.cls >> (2 * p)) & 3) == 1) ? (int)((gi >> 21) & 127u) : 0;
                 if (!found && local < acc + n) {
                   row = p;
@@ -534,26 +604,26 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
             for (int p = 0; p < P; ++p) {
               const int cp = (cls >> (2 * p)) & 3;
               v[p] = 0.0f;
+              const unsigned info = (unsigned)__builtin_amdgcn_readfirstlane((int)q.info[p]);
               if (cp == 1) {
-                const unsigned gi = (unsigned)__builtin_amdgcn_readfirstlane((int)q.ginfo[p]);
-                const int lo = (int)(gi & 127u), hi = (int)((gi >> 7) & 127u);
-                const int a = (int)((gi >> 14) & 127u), n = (int)((gi >> 21) & 127u);
-                const float x = fmaf(da32[p], q.ib32, q.xr[p]);
-                const float f = q.scy * asym_scaled<6>(q.y2, fmaf(x, x, q.y2));
+                const int lo = (int)(info & 127u), hi = (int)((info >> 7) & 127u);
+                const int a = (int)((info >> 14) & 127u), n = (int)((info >> 21) & 127u);
+                // x from the FP64 difference: x changes sign along a general row, so the
+                // offset form would cancel
+                const float x = (float)((nu[p] - q.nu0) * q.ib);
+                const float f = q.c1 * asym_scaled<6>(q.y2, fmaf(x, x, q.y2));
                 const bool in_cut = lane >= lo && lane < hi;
                 const bool in_core = lane >= a && lane < a + n;
                 const float cv = cval[wv][min(max(off + lane - a, 0), kCoreQ - 1)];
                 off += n;
                 v[p] = in_cut ? (in_core ? cv : f) : 0.0f;
               } else if (cp >= 2) {
-                // whole row in the series region; the lanes inside the cut are one side of
-                // bnd
-                const int info = __builtin_amdgcn_readfirstlane((int)q.rinfo[p]);
+                // whole row in the series region; the lanes inside the cut are one side
+                // of bnd
                 const float x = fmaf(cp == 2 ? da32[p] : db32[p], q.ib32, q.xr[p]);
-                const float f =
-                    q.scy * series_row(info >> 6, q.y2, q.m2y2, fmaf(x, x, q.y2));
-                const int bnd = info & 63;
-                const bool in = cp == 2 ? (lane <= bnd) : (lane >= bnd);
+                const float f = series_row((int)(info >> 8), q, fmaf(x, x, q.y2));
+                const int bnd = (int)(info & 255u);
+                const bool in = cp == 2 ? (lane < bnd) : (lane >= bnd);
                 v[p] = in ? f : 0.0f;
               }
             }
@@ -563,24 +633,32 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
           k = ke;
         }
       }
-      // whole-tile series blocks: the line lies left (right) of the tile, every point is
-      // inside the cut and in the series region
-      run(gstart[kLeft + 0], gstart[kLeft + 1],
-          [&](const Rec<false, P>& q, float (&v)[P]) { series_values<P, 2>(q, da32, v); });
-      run(gstart[kLeft + 1], gstart[kLeft + 2],
-          [&](const Rec<false, P>& q, float (&v)[P]) { series_values<P, 3>(q, da32, v); });
-      run(gstart[kLeft + 2], gstart[kLeft + 3],
-          [&](const Rec<false, P>& q, float (&v)[P]) { series_values<P, 4>(q, da32, v); });
-      run(gstart[kLeft + 3], gstart[kLeft + 4],
-          [&](const Rec<false, P>& q, float (&v)[P]) { series_values<P, 6>(q, da32, v); });
-      run(gstart[kRight + 0], gstart[kRight + 1],
-          [&](const Rec<false, P>& q, float (&v)[P]) { series_values<P, 2>(q, db32, v); });
-      run(gstart[kRight + 1], gstart[kRight + 2],
-          [&](const Rec<false, P>& q, float (&v)[P]) { series_values<P, 3>(q, db32, v); });
-      run(gstart[kRight + 2], gstart[kRight + 3],
-          [&](const Rec<false, P>& q, float (&v)[P]) { series_values<P, 4>(q, db32, v); });
-      run(gstart[kRight + 3], gstart[kRight + 4],
-          [&](const Rec<false, P>& q, float (&v)[P]) { series_values<P, 6>(q, db32, v); });
+      // series modes: the line lies left (right) of the tile; all rows take the series
+      // of the mode's variant, masked by the rows' lane bounds unless every point is
+      // inside the cut
+#define XS_SERIES_GROUP(SIDE, MASKED, VAR, NT)                                        \
+  run(gstart[series_mode(SIDE, MASKED, VAR)], gstart[series_mode(SIDE, MASKED, VAR) + 1], \
+      [&](const Rec<false, P>& q, float (&v)[P]) {                                    \
+        series_values<P, NT>(q, SIDE ? db32 : da32, v);                               \
+        if (MASKED) series_mask<P, SIDE>(q, lane, v);                                 \
+      })
+      XS_SERIES_GROUP(0, 0, 0, 2);
+      XS_SERIES_GROUP(0, 0, 1, 3);
+      XS_SERIES_GROUP(0, 0, 2, 4);
+      XS_SERIES_GROUP(0, 0, 3, 6);
+      XS_SERIES_GROUP(0, 1, 0, 2);
+      XS_SERIES_GROUP(0, 1, 1, 3);
+      XS_SERIES_GROUP(0, 1, 2, 4);
+      XS_SERIES_GROUP(0, 1, 3, 6);
+      XS_SERIES_GROUP(1, 0, 0, 2);
+      XS_SERIES_GROUP(1, 0, 1, 3);
+      XS_SERIES_GROUP(1, 0, 2, 4);
+      XS_SERIES_GROUP(1, 0, 3, 6);
+      XS_SERIES_GROUP(1, 1, 0, 2);
+      XS_SERIES_GROUP(1, 1, 1, 3);
+      XS_SERIES_GROUP(1, 1, 2, 4);
+      XS_SERIES_GROUP(1, 1, 3, 6);
+#undef XS_SERIES_GROUP
     }
     wave_sync();
   }
