@@ -183,7 +183,13 @@ def main():
     ap.add_argument("--split", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true",
-                    help="use the default launch shape instead of tuning it first")
+                    help="use the default launch shape (no tuning cache, no tuning)")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2510_20870_amd",
+                                                         "tune_cache.json"),
+                    help="tuning cache to load (JSON written by --save-tune)")
+    ap.add_argument("--retune", action="store_true",
+                    help="tune the launch shapes even when the cache holds them")
+    ap.add_argument("--save-tune", default="", help="write the tuning cache here")
     ap.add_argument("--gen-workers", type=int, default=0,
                     help="processes generating the synthetic list (0 = one per core, max 16)")
     ap.add_argument("--serving-requests", type=int, default=300,
@@ -225,14 +231,27 @@ def main():
     o64 = ctx.opts(kind, W.cut_cm1, W.fwhm_mult, xsec.XS_FP64, args.pts_per_lane, args.split,
                    args.waves_per_simd)
 
+    # launch shapes for this workload class: from the tuning cache when it holds the class,
+    # else tuned now (outside the timing); --retune forces tuning
     tuned = None
     if not args.no_autotune and not (args.pts_per_lane or args.split or args.waves_per_simd):
-        # launch shapes for this workload class (FP32 and FP64 paths), outside the timing
-        t = time.time()
-        tuned = {"fp32": ctx.autotune(h, g, [(P, T)], o32)}
-        if not args.no_fp64:
-            tuned["fp64"] = ctx.autotune(h, g, [(P, T)], o64)
-        log(f"autotuned in {time.time() - t:.1f} s: {tuned}")
+        if args.tune_cache and os.path.exists(args.tune_cache):
+            xsec.tune_cache_load(args.tune_cache)
+        tuned = {}
+        paths = [("fp32", o32)] + ([] if args.no_fp64 else [("fp64", o64)])
+        for name, o in paths:
+            key = ctx.tune_key(h, g, 1, o)
+            hit = xsec.tune_cache_get(key)
+            if hit is not None and not args.retune:
+                tuned[name] = {"pts_per_lane": hit[0], "waves_per_simd": hit[1],
+                               "items_per_slot": hit[2], "key": key, "source": "cache"}
+            else:
+                t = time.time()
+                tuned[name] = dict(ctx.autotune(h, g, [(P, T)], o), source="tuned")
+                log(f"autotuned {name} in {time.time() - t:.1f} s")
+        log(f"launch shapes: {tuned}")
+        if args.save_tune:
+            xsec.tune_cache_save(args.save_tune)
     evals = int(ctx.count_evals(h, g, [(P, T)], o32)[0])
     if W.cut_kind == "fixed":
         # independent count from the sorted centres (searchsorted), the harness's rule
