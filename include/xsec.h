@@ -134,7 +134,7 @@ typedef struct { double P_bar, T_K; } xs_pt;
  * min(cap, fwhm_mult * f_V) (XS_CUT_MIN_FWHM). Launch shape (each 0 = autotuned):
  * pts_per_lane (1, 2, 4 or 8) sets the grid tile of one wavefront to 64 * pts_per_lane
  * points; split (1..256) divides each tile's line window into that many independent work
- * items whose partial sums are added in a fixed order; waves_per_simd (2, 3 or 4) is the
+ * items whose partial sums are added in a fixed order; waves_per_simd (2..6) is the
  * occupancy the tile kernel is compiled for. The result does not depend on the launch
  * shape beyond FP32 rounding (bitwise for a fixed shape). */
 typedef struct {

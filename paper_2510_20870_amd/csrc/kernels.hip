@@ -250,12 +250,13 @@ __device__ __forceinline__ int lane_guess(const Rows<P>& rows, int p, double v) 
 
 // Stages line i: the record (except the FP32 scales, set once the chunk's scale is known)
 // with the row classes; returns the FP64 profile scale in *sc64, the line's mode in
-// *mode_out and its number of core points (FP32 path) in *npairs_out.
+// *mode_out and its number of core points (FP32 path) in *npairs_out. The lane ranges of
+// general rows are found only when `general` is set (their lines are staged again later).
 template <bool F64, int P>
 __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, const Rows<P>& rows,
                                                   const double* rowv, int64_t i,
                                                   double* sc64, int* mode_out,
-                                                  int* npairs_out) {
+                                                  int* npairs_out, bool general) {
   const double nu0 = A.L.nu0[i];
   const LineRec lr = A.recs[(int64_t)k * A.rec_n + (i - A.rec_lo)];
   Rec<F64, P> r;
@@ -305,7 +306,7 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
             info = (unsigned)bnd | ((unsigned)asym_variant(r2n) << 8);
           }
         }
-        if (!F64 && c == 1) {
+        if (!F64 && c == 1 && general) {
           // general row: the lanes inside the cut and the core segment among them, from
           // linear guesses checked with the exact predicates
           const int lo = da >= -cut ? 0
@@ -393,27 +394,30 @@ __device__ __forceinline__ float two_term(const Rec<false, P>& q, float r2) {
   return u * fmaf(u, fmaf(u, q.c3, q.c2), q.c1);
 }
 
-// Scaled contributions of one line to all P rows in the series region with NT terms, x
-// from the row's nearer end (off = the lane's offsets from that end).
-template <int P, int NT>
-__device__ __forceinline__ void series_values(const Rec<false, P>& q, const float (&off)[P],
-                                              float (&v)[P]) {
+// Adds the scaled contributions of one line to all P rows in the series region with NT
+// terms (x from the row's nearer end, off = the lane's offsets from that end); with MASKED
+// only the lanes inside the cut add: lanes < bnd (SIDE 0) or >= bnd (SIDE 1).
+template <int P, int NT, int SIDE, bool MASKED>
+__device__ __forceinline__ void series_add(const Rec<false, P>& q, const float (&off)[P],
+                                           int lane, float (&t)[P]) {
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const float x = fmaf(off[p], q.ib32, q.xr[p]);
     const float r2 = fmaf(x, x, q.y2);
-    v[p] = NT == 2 ? two_term(q, r2) : q.c1 * asym_scaled<NT>(q.y2, r2);
-  }
-}
-
-// Keeps the lanes of each row inside the cut: lanes < bnd (SIDE 0) or >= bnd (SIDE 1).
-template <int P, int SIDE>
-__device__ __forceinline__ void series_mask(const Rec<false, P>& q, int lane, float (&v)[P]) {
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    const int bnd = __builtin_amdgcn_readfirstlane((int)q.info[p]) & 255;
-    const bool in = SIDE == 0 ? lane < bnd : lane >= bnd;
-    v[p] = in ? v[p] : 0.0f;
+    float tn;
+    if constexpr (NT == 2) {
+      const float u = rcp32(r2);
+      tn = fmaf(u, fmaf(u, fmaf(u, q.c3, q.c2), q.c1), t[p]);
+    } else {
+      tn = fmaf(q.c1, asym_scaled<NT>(q.y2, r2), t[p]);
+    }
+    if constexpr (MASKED) {
+      const int bnd = __builtin_amdgcn_readfirstlane((int)q.info[p]) & 255;
+      const bool in = SIDE == 0 ? lane < bnd : lane >= bnd;
+      t[p] = in ? tn : t[p];
+    } else {
+      t[p] = tn;
+    }
   }
 }
 
@@ -433,6 +437,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   __shared__ Rec<F64, P> recs[kWavesPerWG][kWave];
   __shared__ double rowvals[kWavesPerWG][kWave * P];
   __shared__ int incl[kWavesPerWG][kWave];           // packed core points, inclusive prefix
+  __shared__ int dlist[kWavesPerWG][F64 ? 1 : 2 * kWave];   // lines put aside (FP32 path)
   // packed core contributions: a pass holds the core points of whole lines, at most
   // kCoreQ (one line brings at most 64 P)
   constexpr int kCoreQ = kWave * P;
@@ -468,20 +473,12 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   for (int p = 0; p < P; ++p) { s[p] = 0; c[p] = 0; }
   int e_ref = kNoScale;   // FP32 path: contributions are scaled by 2^(kScaleTarget - e_ref)
 
-  for (int64_t base = it.b; base < it.e; base += kWave) {
-    const int64_t i = base + lane;
-    Rec<F64, P> r;
-    double sc64 = 0.0;
-    int mode = kSkip, npairs = 0;
-    if (i < it.e) {
-      r = stage_line<F64, P>(A, it.k, rows, rowvals[wv], i, &sc64, &mode, &npairs);
-    } else {
-      r.cls = 0;
-    }
+  // FP32 path: the power-of-two scale of a staged chunk (every lane's line): a stronger
+  // line than any before lowers the scale, and the running sums are rescaled exactly
+  auto set_scale = [&](Rec<F64, P>& r, double sc64) {
     if constexpr (!F64) {
       const int ex = wave_max(sc64 > 0.0 ? ilogb(sc64) : kNoScale);
       if (ex > e_ref) {
-        // a stronger line: lower the scale and rescale the sums exactly
         const int d = max(e_ref - ex, -1000);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
@@ -496,6 +493,143 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       r.c2 = 1.5f * r.c1;
       r.c3 = -2.0f * r.y2 * r.c1;
     }
+  };
+  // Blocks of kChunk lines summed in plain FP32, each block then added to the
+  // Kahan-compensated sums.
+  auto run = [&](int g0, int g1, auto&& add) {
+    for (int b0 = g0; b0 < g1; b0 += kChunk) {
+      const int b1 = min(b0 + kChunk, g1);
+      float t[P];
+#pragma unroll
+      for (int p = 0; p < P; ++p) t[p] = 0.0f;
+#pragma unroll 2
+      for (int kk = b0; kk < b1; ++kk) add(recs[wv][kk], t);
+      if constexpr (!F64) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) kahan_add(s[p], c[p], t[p]);
+      }
+    }
+  };
+  // FP32 general rows of the lines in LDS slots [g0, g1), in sub-batches of lines whose
+  // core segments hold at most kCoreQ points: first every core point of the sub-batch is
+  // evaluated, one point per lane (FP64 core), into cval; then the lines are walked in
+  // order, each general row taking the series for its in-cut lanes outside the core and
+  // the core values from cval (incl holds the inclusive prefix of core points).
+  auto rows_group = [&](int g0, int g1) {
+    if constexpr (!F64) {
+      int k = g0;
+      int base = 0;   // packed points of the lines before k
+      while (k < g1) {
+        const int ke =
+            first_true(k + 1, g1, [&](int kk) { return incl[wv][kk] - base > kCoreQ; });
+        const int npk = incl[wv][ke - 1] - base;
+        for (int r0 = 0; r0 < npk; r0 += kWave) {
+          const int g = r0 + lane;
+          if (g < npk) {
+            const int kk = first_true(k, ke, [&](int m) { return incl[wv][m] - base > g; });
+            const int local = g - (kk > k ? incl[wv][kk - 1] - base : 0);
+            const Rec<false, P>& q = recs[wv][kk];
+            // the row holding point `local` of this line (rows in order)
+            int row = 0, j = 0;
+            int acc = 0;
+            bool found = false;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+              const unsigned gi = q.info[p];
+              const int n = (((q.cls >> (2 * p)) & 3) == 1) ? (int)((gi >> 21) & 127u) : 0;
+              if (!found && local < acc + n) {
+                row = p;
+                j = (int)((gi >> 14) & 127u) + (local - acc);
+                found = true;
+              }
+              acc += n;
+            }
+            const double d = rowvals[wv][kWave * row + j] - q.nu0;
+            cval[wv][g] = q.sc * (float)voigt_core64(d * q.ib, (double)q.y);
+          }
+        }
+        wave_sync();
+        int off = 0;   // packed points of the sub-batch's lines walked so far
+        run(k, ke, [&](const Rec<false, P>& q, float (&t)[P]) {
+          const int cls = __builtin_amdgcn_readfirstlane(q.cls);
+          float v[P];
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            const int cp = (cls >> (2 * p)) & 3;
+            v[p] = 0.0f;
+            const unsigned info = (unsigned)__builtin_amdgcn_readfirstlane((int)q.info[p]);
+            if (cp == 1) {
+              const int lo = (int)(info & 127u), hi = (int)((info >> 7) & 127u);
+              const int a = (int)((info >> 14) & 127u), n = (int)((info >> 21) & 127u);
+              // x from the FP64 difference: x changes sign along a general row, so the
+              // offset form would cancel
+              const float x = (float)((nu[p] - q.nu0) * q.ib);
+              const float f = q.c1 * asym_scaled<6>(q.y2, fmaf(x, x, q.y2));
+              const bool in_cut = lane >= lo && lane < hi;
+              const bool in_core = lane >= a && lane < a + n;
+              const float cv = cval[wv][min(max(off + lane - a, 0), kCoreQ - 1)];
+              off += n;
+              v[p] = in_cut ? (in_core ? cv : f) : 0.0f;
+            } else if (cp >= 2) {
+              // whole row in the series region; the lanes inside the cut are one side of
+              // bnd
+              const float x = fmaf(cp == 2 ? da32[p] : db32[p], q.ib32, q.xr[p]);
+              const float f = series_row((int)(info >> 8), q, fmaf(x, x, q.y2));
+              const int bnd = (int)(info & 255u);
+              const bool in = cp == 2 ? (lane < bnd) : (lane >= bnd);
+              v[p] = in ? f : 0.0f;
+            }
+          }
+#pragma unroll
+          for (int p = 0; p < P; ++p) t[p] += v[p];
+        });
+        wave_sync();   // cval is refilled by the next sub-batch
+        base = incl[wv][ke - 1];
+        k = ke;
+      }
+    }
+  };
+  // FP32 path: lines needing per-row classes (general rows) are put aside in dlist (line
+  // offsets from it.b, in order) and staged again, with their lane ranges, 64 at a time,
+  // so that the search code runs with full wavefronts instead of in almost every chunk.
+  auto deferred_pass = [&](int nd) {
+    if constexpr (!F64) {
+      Rec<F64, P> r;
+      double sc64 = 0.0;
+      int mode = kSkip, npairs = 0;
+      if (lane < nd) {
+        r = stage_line<F64, P>(A, it.k, rows, rowvals[wv], it.b + dlist[wv][lane], &sc64,
+                               &mode, &npairs, true);
+      }
+      set_scale(r, sc64);
+      int w = lane < nd ? npairs : 0;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int u = __shfl_up(w, o, kWave);
+        if (lane >= o) w += u;
+      }
+      if (lane < nd) {
+        recs[wv][lane] = r;
+        incl[wv][lane] = w;
+      }
+      wave_sync();
+      rows_group(0, nd);
+      wave_sync();
+    }
+  };
+  int ndef = 0;   // lines waiting in dlist
+
+  for (int64_t base = it.b; base < it.e; base += kWave) {
+    const int64_t i = base + lane;
+    Rec<F64, P> r;
+    double sc64 = 0.0;
+    int mode = kSkip, npairs = 0;
+    if (i < it.e) {
+      r = stage_line<F64, P>(A, it.k, rows, rowvals[wv], i, &sc64, &mode, &npairs, false);
+    } else {
+      r.cls = 0;
+    }
+    set_scale(r, sc64);
     // Group the chunk's lines by mode (stable inside each mode) so that the walk below
     // runs every mode's lines in a loop of its own with no per-line dispatch; lines with
     // no point inside the cut are dropped. The order is fixed by the data alone.
@@ -513,17 +647,16 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       }
 #pragma unroll
       for (int m = F64 ? 2 : kModes; m <= kModes; ++m) gstart[m] = acc;
-      if (pos >= 0) recs[wv][pos] = r;
-      if constexpr (!F64) {
-        // inclusive prefix of the packed core points over the general group (lane order
-        // is group order)
-        int w = mode == kRows ? npairs : 0;
+      if constexpr (F64) {
+        if (pos >= 0) recs[wv][pos] = r;
+      } else {
+        // general lines wait in dlist; the series groups start at slot 0
+        const int nrows = gstart[kRows + 1];
+        if (mode == kRows) dlist[wv][ndef + pos] = (int)(i - it.b);
+        else if (pos >= 0) recs[wv][pos - nrows] = r;
 #pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-          const int u = __shfl_up(w, o, kWave);
-          if (lane >= o) w += u;
-        }
-        if (mode == kRows) incl[wv][pos] = w;
+        for (int m = kRows + 1; m <= kModes; ++m) gstart[m] -= nrows;
+        ndef += nrows;
       }
     }
     wave_sync();
@@ -539,108 +672,13 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
         }
       }
     } else {
-      // Each group: blocks of kChunk lines summed in plain FP32, each block then added to
-      // the Kahan-compensated sums.
-      auto run = [&](int g0, int g1, auto&& values) {
-        for (int b0 = g0; b0 < g1; b0 += kChunk) {
-          const int b1 = min(b0 + kChunk, g1);
-          float t[P];
-#pragma unroll
-          for (int p = 0; p < P; ++p) t[p] = 0.0f;
-#pragma unroll 2
-          for (int kk = b0; kk < b1; ++kk) {
-            float v[P];
-            values(recs[wv][kk], v);
-#pragma unroll
-            for (int p = 0; p < P; ++p) t[p] += v[p];
-          }
-#pragma unroll
-          for (int p = 0; p < P; ++p) kahan_add(s[p], c[p], t[p]);
-        }
-      };
-      // General rows, in sub-batches of lines whose core segments hold at most kCoreQ
-      // points: first every core point of the sub-batch is evaluated, one point per lane
-      // (FP64 core), into cval; then the lines are walked in order, each general row
-      // taking the series for its in-cut lanes outside the core and the core values from
-      // cval.
-      {
-        const int g1 = gstart[kRows + 1];
-        int k = gstart[kRows];
-        int base = 0;   // packed points of the lines before k
-        while (k < g1) {
-          const int ke =
-              first_true(k + 1, g1, [&](int kk) { return incl[wv][kk] - base > kCoreQ; });
-          const int npk = incl[wv][ke - 1] - base;
-          for (int r0 = 0; r0 < npk; r0 += kWave) {
-            const int g = r0 + lane;
-            if (g < npk) {
-              const int kk = first_true(k, ke, [&](int m) { return incl[wv][m] - base > g; });
-              const int local = g - (kk > k ? incl[wv][kk - 1] - base : 0);
-              const Rec<false, P>& q = recs[wv][kk];
-              // the row holding point `local` of this line (rows in order)
-              int row = 0, j = 0;
-              int acc = 0;
-              bool found = false;
-#pragma unroll
-              for (int p = 0; p < P; ++p) {
-                const unsigned gi = q.info[p];
-                const int n = (((q.cls >> (2 * p)) & 3) == 1) ? (int)((gi >> 21) & 127u) : 0;
-                if (!found && local < acc + n) {
-                  row = p;
-                  j = (int)((gi >> 14) & 127u) + (local - acc);
-                  found = true;
-                }
-                acc += n;
-              }
-              const double d = rowvals[wv][kWave * row + j] - q.nu0;
-              cval[wv][g] = q.sc * (float)voigt_core64(d * q.ib, (double)q.y);
-            }
-          }
-          wave_sync();
-          int off = 0;   // packed points of the sub-batch's lines walked so far
-          run(k, ke, [&](const Rec<false, P>& q, float (&v)[P]) {
-            const int cls = __builtin_amdgcn_readfirstlane(q.cls);
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-              const int cp = (cls >> (2 * p)) & 3;
-              v[p] = 0.0f;
-              const unsigned info = (unsigned)__builtin_amdgcn_readfirstlane((int)q.info[p]);
-              if (cp == 1) {
-                const int lo = (int)(info & 127u), hi = (int)((info >> 7) & 127u);
-                const int a = (int)((info >> 14) & 127u), n = (int)((info >> 21) & 127u);
-                // x from the FP64 difference: x changes sign along a general row, so the
-                // offset form would cancel
-                const float x = (float)((nu[p] - q.nu0) * q.ib);
-                const float f = q.c1 * asym_scaled<6>(q.y2, fmaf(x, x, q.y2));
-                const bool in_cut = lane >= lo && lane < hi;
-                const bool in_core = lane >= a && lane < a + n;
-                const float cv = cval[wv][min(max(off + lane - a, 0), kCoreQ - 1)];
-                off += n;
-                v[p] = in_cut ? (in_core ? cv : f) : 0.0f;
-              } else if (cp >= 2) {
-                // whole row in the series region; the lanes inside the cut are one side
-                // of bnd
-                const float x = fmaf(cp == 2 ? da32[p] : db32[p], q.ib32, q.xr[p]);
-                const float f = series_row((int)(info >> 8), q, fmaf(x, x, q.y2));
-                const int bnd = (int)(info & 255u);
-                const bool in = cp == 2 ? (lane < bnd) : (lane >= bnd);
-                v[p] = in ? f : 0.0f;
-              }
-            }
-          });
-          wave_sync();   // cval is refilled by the next sub-batch
-          base = incl[wv][ke - 1];
-          k = ke;
-        }
-      }
       // series modes: the line lies left (right) of the tile; all rows take the series
       // of the mode's variant, masked by the rows' lane bounds unless every point is
       // inside the cut
 #define XS_SERIES_GROUP(SIDE, MASKED, VAR, NT)                                        \
   run(gstart[series_mode(SIDE, MASKED, VAR)], gstart[series_mode(SIDE, MASKED, VAR) + 1], \
-      [&](const Rec<false, P>& q, float (&v)[P]) {                                    \
-        series_values<P, NT>(q, SIDE ? db32 : da32, v);                               \
-        if (MASKED) series_mask<P, SIDE>(q, lane, v);                                 \
+      [&](const Rec<false, P>& q, float (&t)[P]) {                                    \
+        series_add<P, NT, SIDE, MASKED>(q, SIDE ? db32 : da32, lane, t);              \
       })
       XS_SERIES_GROUP(0, 0, 0, 2);
       XS_SERIES_GROUP(0, 0, 1, 3);
@@ -661,7 +699,18 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
 #undef XS_SERIES_GROUP
     }
     wave_sync();
+    if (!F64 && ndef >= kWave) {
+      deferred_pass(kWave);
+      // the lines still waiting move to the front
+      const int left = ndef - kWave;
+      const int keep = lane < left ? dlist[wv][kWave + lane] : 0;
+      wave_sync();
+      if (lane < left) dlist[wv][lane] = keep;
+      wave_sync();
+      ndef = left;
+    }
   }
+  if (!F64 && ndef > 0) deferred_pass(ndef);
 
   const int64_t row = (A.split == 1) ? (int64_t)(A.pt0 + it.k)
                                      : ((int64_t)it.k * A.split + it.s);
@@ -765,6 +814,8 @@ static hipError_t launch_tile_w(const TileArgs& A, int W, hipStream_t st, dim3 g
     case 0: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 0>), grid, block, 0, st, A); break;
     case 3: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 3>), grid, block, 0, st, A); break;
     case 4: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 4>), grid, block, 0, st, A); break;
+    case 5: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 5>), grid, block, 0, st, A); break;
+    case 6: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 6>), grid, block, 0, st, A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -112,9 +112,8 @@ int validate_opts(const xs_opts* o) {
     return fail(XS_EINVAL, "pts_per_lane must be 0, 1, 2, 4 or 8 (got %d)", P);
   if (o->split < 0 || o->split > kMaxSplit)
     return fail(XS_EINVAL, "split must be in [0, %d] (got %d)", kMaxSplit, o->split);
-  if (o->waves_per_simd != 0 && o->waves_per_simd != 2 && o->waves_per_simd != 3 &&
-      o->waves_per_simd != 4)
-    return fail(XS_EINVAL, "waves_per_simd must be 0, 2, 3 or 4 (got %d)", o->waves_per_simd);
+  if (o->waves_per_simd != 0 && (o->waves_per_simd < 2 || o->waves_per_simd > 6))
+    return fail(XS_EINVAL, "waves_per_simd must be 0 or 2..6 (got %d)", o->waves_per_simd);
   return XS_OK;
 }
 

@@ -25,7 +25,7 @@ std::mutex g_tune_mu;
 std::map<std::string, TuneVal> g_tune;
 
 bool valid_val(const TuneVal& v) {
-  return (v.P == 1 || v.P == 2 || v.P == 4 || v.P == 8) && (v.W == 0 || v.W == 3 || v.W == 4) &&
+  return (v.P == 1 || v.P == 2 || v.P == 4 || v.P == 8) && (v.W == 0 || (v.W >= 3 && v.W <= 6)) &&
          v.ips >= 1 && v.ips <= 64;
 }
 
@@ -380,7 +380,7 @@ int xs_autotune(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t
     }
   Cand best = *std::min_element(tried.begin(), tried.end(),
                                 [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
-  for (int W : {3, 4}) {
+  for (int W : {3, 4, 5, 6}) {
     double ms = 0.0;
     rc = run(best.P, best.ips, W, &ms);
     if (rc) {
