@@ -197,7 +197,7 @@ struct Block {
 
 // Time one candidate shape over the probe blocks: per block the parameter kernel (not
 // timed) and the tile kernel (timed with events on the launch stream; one warm-up run,
-// then one timed run). A block too small to fill the device with the plan's split gets a
+// then the fastest of three). A block too small to fill the device with the plan's split gets a
 // larger one (at least one round of wavefront slots), so that every candidate is timed
 // at full occupancy.
 int time_candidate(Ctx& c, const LinesRes& L, const GridRes& G, const xs_opts& o,
@@ -237,8 +237,8 @@ int time_candidate(Ctx& c, const LinesRes& L, const GridRes& G, const xs_opts& o
     hipError_t e = hipMemcpy(c.order_buf.ptr, order.data(), order.size() * sizeof(int),
                              hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "tuning order upload");
-    float ms = 0.0f;
-    for (int rep = 0; rep < 2; ++rep) {
+    float best = 0.0f;
+    for (int rep = 0; rep < 4; ++rep) {
       tm.used = 0;
       rc = enqueue_step(L, G, o, p, (const double*)c.pts_buf.ptr, (const int*)c.order_buf.ptr,
                         (double*)c.out_buf.ptr, c.rec_buf.ptr, part, nullptr, 0, nprobe, 0, nt,
@@ -246,10 +246,12 @@ int time_candidate(Ctx& c, const LinesRes& L, const GridRes& G, const xs_opts& o
       if (rc) return rc;
       e = hipEventSynchronize(tm.ev[1]);
       if (e != hipSuccess) return hip_fail(e, "tuning run");
+      float ms = 0.0f;
       e = hipEventElapsedTime(&ms, tm.ev[0], tm.ev[1]);
       if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+      if (rep == 1 || (rep > 1 && ms < best)) best = ms;   // run 0 warms up
     }
-    total += ms;
+    total += best;
   }
   *ms_out = total;
   return XS_OK;
@@ -378,18 +380,22 @@ int xs_autotune(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t
       }
       tried.push_back({P, ips, 0, ms});
     }
-  Cand best = *std::min_element(tried.begin(), tried.end(),
-                                [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
-  for (int W : {3, 4, 5, 6}) {
-    double ms = 0.0;
-    rc = run(best.P, best.ips, W, &ms);
-    if (rc) {
-      cleanup();
-      return rc;
+  // occupancy targets for the two fastest (P, items per slot)
+  std::vector<Cand> top = tried;
+  std::sort(top.begin(), top.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+  top.resize(std::min<size_t>(2, top.size()));
+  Cand best = top.front();
+  for (const Cand& t : top)
+    for (int W : {3, 4, 5, 6}) {
+      double ms = 0.0;
+      rc = run(t.P, t.ips, W, &ms);
+      if (rc) {
+        cleanup();
+        return rc;
+      }
+      tried.push_back({t.P, t.ips, W, ms});
+      if (ms < best.ms) best = tried.back();
     }
-    tried.push_back({best.P, best.ips, W, ms});
-    if (ms < best.ms) best = tried.back();
-  }
   // keep the default unless a shape is clearly faster (probe timings vary by ~2 %)
   if (best.ms > 0.97 * def_ms) best = tried.front();
   cleanup();
