@@ -523,30 +523,49 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
         const int ke =
             first_true(k + 1, g1, [&](int kk) { return incl[wv][kk] - base > kCoreQ; });
         const int npk = incl[wv][ke - 1] - base;
-        for (int r0 = 0; r0 < npk; r0 += kWave) {
-          const int g = r0 + lane;
-          if (g < npk) {
-            const int kk = first_true(k, ke, [&](int m) { return incl[wv][m] - base > g; });
-            const int local = g - (kk > k ? incl[wv][kk - 1] - base : 0);
-            const Rec<false, P>& q = recs[wv][kk];
-            // the row holding point `local` of this line (rows in order)
-            int row = 0, j = 0;
-            int acc = 0;
-            bool found = false;
+        // one term count for the sub-batch: the largest its lines need (a loop of its own
+        // per count, so the pass keeps one evaluation path)
+        const int tier = __builtin_amdgcn_readfirstlane(
+            wave_max(lane < ke - k ? core_tier((double)recs[wv][k + lane].y) : 0));
+        auto packed = [&](auto nterms) {
+          constexpr int N = decltype(nterms)::value;
+          const double* wa = N == 16 ? kWeidA16 : N == 24 ? kWeidA24 : N == 32 ? kWeidA32
+                                                                               : kWeidA;
+          const double wl = N == 16 ? kWeidL16 : N == 24 ? kWeidL24 : N == 32 ? kWeidL32
+                                                                            : kWeidL;
+          for (int r0 = 0; r0 < npk; r0 += kWave) {
+            const int g = r0 + lane;
+            if (g < npk) {
+              const int kk =
+                  first_true(k, ke, [&](int m) { return incl[wv][m] - base > g; });
+              const int local = g - (kk > k ? incl[wv][kk - 1] - base : 0);
+              const Rec<false, P>& q = recs[wv][kk];
+              // the row holding point `local` of this line (rows in order)
+              int row = 0, j = 0;
+              int acc = 0;
+              bool found = false;
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-              const unsigned gi = q.info[p];
-              const int n = (((q.cls >> (2 * p)) & 3) == 1) ? (int)((gi >> 21) & 127u) : 0;
-              if (!found && local < acc + n) {
-                row = p;
-                j = (int)((gi >> 14) & 127u) + (local - acc);
-                found = true;
+              for (int p = 0; p < P; ++p) {
+                const unsigned gi = q.info[p];
+                const int n =
+                    (((q.cls >> (2 * p)) & 3) == 1) ? (int)((gi >> 21) & 127u) : 0;
+                if (!found && local < acc + n) {
+                  row = p;
+                  j = (int)((gi >> 14) & 127u) + (local - acc);
+                  found = true;
+                }
+                acc += n;
               }
-              acc += n;
+              const double d = rowvals[wv][kWave * row + j] - q.nu0;
+              cval[wv][g] = q.sc * (float)voigt_core64_n<N>(wa, wl, d * q.ib, (double)q.y);
             }
-            const double d = rowvals[wv][kWave * row + j] - q.nu0;
-            cval[wv][g] = q.sc * (float)voigt_core64(d * q.ib, (double)q.y);
           }
+        };
+        switch (tier) {
+          case 0: packed(std::integral_constant<int, 16>{}); break;
+          case 1: packed(std::integral_constant<int, 24>{}); break;
+          case 2: packed(std::integral_constant<int, 32>{}); break;
+          default: packed(std::integral_constant<int, 40>{}); break;
         }
         wave_sync();
         int off = 0;   // packed points of the sub-batch's lines walked so far

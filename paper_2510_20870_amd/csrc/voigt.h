@@ -163,18 +163,17 @@ XS_HD double voigt_mid64(double r2, double y) {
   return (1.0 / kPi) * v * fma(n01, d23, n23 * d01) * rcp64(d01 * d23);
 }
 
-// core: Weideman N = 40 in FP64 (kWeidA[n-1] multiplies Z^(n-1)).
-XS_HD double voigt_core64(double x, double y) {
-  const double* a = kWeidA;
-  const double L = kWeidL;
+// core: Weideman's rational series with N terms in FP64 (a[n-1] multiplies Z^(n-1)).
+template <int N>
+XS_HD double voigt_core64_n(const double* a, double L, double x, double y) {
   const double lpy = L + y;
   const double D = fma(lpy, lpy, x * x);
   const double iD = rcp64(D);
   const double zr = (L * L - y * y - x * x) * iD;
   const double zi = 2.0 * L * x * iD;
-  double pr = a[kWeidN - 1], pi = 0.0;
+  double pr = a[N - 1], pi = 0.0;
 #pragma unroll
-  for (int n = kWeidN - 2; n >= 0; --n) {
+  for (int n = N - 2; n >= 0; --n) {
     const double tr = fma(pr, zr, fma(-pi, zi, a[n]));
     pi = fma(pr, zi, pi * zr);
     pr = tr;
@@ -185,15 +184,31 @@ XS_HD double voigt_core64(double x, double y) {
   return fma(lpy, kInvSqrtPi, t) * iD;
 }
 
-// Full K: the six-term FP32 series for |z| >= 7 (valid for every point there, so mixed
-// rows do not diverge over series lengths) and FP64 for the core. x may be negative (K is
-// even in x).
+XS_HD double voigt_core64(double x, double y) {
+  return voigt_core64_n<kWeidN>(kWeidA, kWeidL, x, y);
+}
+
+// Core tiers of the FP32 path: the truncation error of Weideman's series inside |z| < 7
+// grows as y falls, so the term count follows y. Measured worst relative error of Re w
+// over x^2 + y^2 < 49 against the reference Faddeeva routine: N = 16 for y >= 1 (2e-7),
+// 24 for y >= 0.01 (2e-7), 32 for y >= 1e-5 (2e-7), 40 below (8e-9 down to y = 5e-7).
+XS_HD int core_tier(double y) { return y >= 1.0 ? 0 : y >= 0.01 ? 1 : y >= 1e-5 ? 2 : 3; }
+
+XS_HD double voigt_core64_tier(int tier, double x, double y) {
+  switch (tier) {
+    case 0: return voigt_core64_n<16>(kWeidA16, kWeidL16, x, y);
+    case 1: return voigt_core64_n<24>(kWeidA24, kWeidL24, x, y);
+    case 2: return voigt_core64_n<32>(kWeidA32, kWeidL32, x, y);
+    default: return voigt_core64(x, y);
+  }
+}
+
 XS_HD float voigt_k32(double xd, float y) {
   const float x = (float)xd;
   const float y2 = y * y;
   const float r2 = fmaf(x, x, y2);
   if (r2 >= kT6R2) return (float)kInvSqrtPi * y * asym_scaled<6>(y2, r2);
-  return (float)voigt_core64(xd, (double)y);
+  return (float)voigt_core64_tier(core_tier((double)y), xd, (double)y);
 }
 
 XS_HD double voigt_k64(double x, double y) {

@@ -72,6 +72,27 @@ def test_voigt_fp32_error_map():
     assert np.array_equal(Kn, K[:1000])
 
 
+def test_voigt_fp32_core_tiers():
+    # inside |z| < 7 the FP32 path's FP64 core picks its term count from y; every tier,
+    # including both sides of each switch point, stays within the FP32 budget
+    rng = np.random.default_rng(7)
+    edges = [5e-7, 1e-5, 0.01, 1.0, 7.0]
+    ys, xs_ = [], []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        ys.append(10 ** rng.uniform(np.log10(lo), np.log10(hi), 40_000))
+        xs_.append(rng.uniform(0.0, 7.0, 40_000))
+    for e in edges[1:-1]:   # right at the switch points
+        ys.append(np.full(5000, e) * (1 + rng.uniform(-1e-12, 1e-12, 5000)))
+        xs_.append(rng.uniform(0.0, 7.0, 5000))
+    x, y = np.concatenate(xs_), np.concatenate(ys)
+    m = x * x + y * y < 49.0
+    x, y = x[m], y[m]
+    ref = wofz(x + 1j * y).real
+    K = xsec.eval_voigt_host(x, y, xsec.XS_FP32_KAHAN)
+    rel = np.abs(K - ref) / ref
+    assert rel.max() < 4e-7, (rel.max(), x[rel.argmax()], y[rel.argmax()])
+
+
 def test_voigt_fp64_error_map():
     x, y = _domain(200_000, 2)
     ref = wofz(x + 1j * y).real
