@@ -37,7 +37,7 @@ FLOPS_PER_EVAL = 16.0
 PEAK_ALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ("kernels.hip", "voigt.h", "physics.h", "kernel_args.h", "weideman_coef.h")
+KERNEL_SOURCES = ("tile_kernel.h", "voigt.h", "physics.h", "kernel_args.h", "weideman_coef.h")
 COUNTER_PROFILE = os.path.join(ROOT, "profiles", "tile_kernel_mid_counters.md")
 
 

@@ -66,6 +66,11 @@ hipError_t launch_params(const ParamArgs& A, hipStream_t st);
 hipError_t launch_tile(const TileArgs& A, int P, bool f64, int W, hipStream_t st,
                        int64_t phys_wg);
 hipError_t launch_count(const TileArgs& A, int P, hipStream_t st, int64_t phys_wg);
+// per points-per-lane instantiations of the tile kernel (tile_p*.hip)
+hipError_t launch_tile_p1(const TileArgs& A, bool f64, int W, hipStream_t st, dim3 grid);
+hipError_t launch_tile_p2(const TileArgs& A, bool f64, int W, hipStream_t st, dim3 grid);
+hipError_t launch_tile_p4(const TileArgs& A, bool f64, int W, hipStream_t st, dim3 grid);
+hipError_t launch_tile_p8(const TileArgs& A, bool f64, int W, hipStream_t st, dim3 grid);
 hipError_t launch_reduce(const double* part, double* out, int64_t n_grid, int n_pts, int split,
                          hipStream_t st);
 hipError_t launch_eval_voigt(const double* x, const double* y, int64_t n, int f64,

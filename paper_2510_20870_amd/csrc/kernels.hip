@@ -36,22 +36,12 @@
 // the strongest line's scale is about 2^48 and the running sums are rescaled exactly, so
 // any absolute magnitude of sigma stays inside FP32 range; the scale is removed exactly
 // when the FP64 result is stored.
-#include <hip/hip_runtime.h>
-#include <math.h>
-#include <stdint.h>
 
-#include <type_traits>
 
-#include "kernel_args.h"
-#include "physics.h"
-#include "voigt.h"
+
+#include "tile_kernel.h"
 
 namespace xs {
-
-// exponent of the strongest line's FP32 scale: leaves 2^80 of headroom for sums and keeps
-// the expanded two-term coefficient 2 y^2 c1 finite for y up to 8e7
-constexpr int kScaleTarget = 48;
-constexpr int kNoScale = -(1 << 28);
 
 // ------------------------------------------------------------------ parameter kernel
 __global__ __launch_bounds__(256) void xs_params_kernel(ParamArgs A) {
@@ -70,678 +60,6 @@ __global__ __launch_bounds__(256) void xs_params_kernel(ParamArgs A) {
     r.sc = lp.S * r.ib * (1.0 / kSqrtPiD);
     r.y = lp.gL * r.ib;
     out[t] = r;
-  }
-}
-
-// ------------------------------------------------------------------ tile kernel
-// Record of one staged line in LDS. cls holds 2 bits per row p of the wave's tile:
-// 0 = no point of the row is inside the cut, 1 = general path, 2 / 3 = every point of the
-// row is in the FP32 series region (|z| >= 7), the line lying left / right of the row; xr[p]
-// is then x at the row's nearest end (first / last point) and info[p] = bnd | var << 8:
-// the points inside the cut are the lanes < bnd (class 2) or >= bnd (class 3), found
-// exactly at staging time, and var is the series variant the row's nearest point needs.
-// For a general row (class 1) of the FP32 path, info[p] = lo | hi << 7 | a << 14 | n << 21
-// holds the lanes inside the cut, [lo, hi), and the lanes of the FP64 core region
-// (r^2 < 49), [a, a + n), found exactly at staging time with the same FP64 difference and
-// FP32 r^2 as the per-point evaluation. The core points of all lines are evaluated packed
-// across lines, one point per lane.
-// The line's mode (kept outside the record: lines are grouped by mode) selects its
-// hot-loop path: kSkip (no row inside the cut), kRows (per-row classes), or a series mode
-// when the line lies on one side of the whole tile with every row of class 2 (or 3) or 0:
-// then all rows take the series with the variant of the tile's nearest point, masked by
-// the rows' lane bounds unless every point is inside the cut.
-enum {
-  kSkip = 0,
-  kRows = 1,
-  kSeries = 2,   // + side * 8 + masked * 4 + variant
-  kModes = 18
-};
-__host__ __device__ constexpr int series_mode(int side, int masked, int var) {
-  return kSeries + side * 8 + masked * 4 + var;
-}
-
-template <bool F64, int P> struct Rec;
-template <int P> struct alignas(16) Rec<false, P> {
-  double nu0, ib;
-  float y, y2, sc;
-  float c1, c2, c3;   // c1 = sc y / sqrt(pi); two-term series = u (c1 + u (c2 + u c3))
-  float ib32;
-  int cls;
-  float xr[P];
-  unsigned int info[P];
-};
-template <int P> struct alignas(16) Rec<true, P> {
-  double nu0, cut, ib, y, sc;
-  int cls;
-};
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
-  return v;
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs. Logical workgroups are grouped in
-// blocks of kXcdBlock consecutive ones (neighbouring tiles, which share most of their line
-// windows, so they reuse one XCD's L2), and the blocks are dealt round-robin to the XCDs,
-// so every XCD gets a share of cheap and expensive tiles.
-constexpr int64_t kXcdBlock = 16;
-__device__ __forceinline__ int64_t xcd_logical_wg(int64_t phys) {
-  const int64_t xcd = phys & 7, slot = phys >> 3;
-  return (slot / kXcdBlock) * (8 * kXcdBlock) + xcd * kXcdBlock + (slot % kXcdBlock);
-}
-
-// First index i in [0, n) with a[i] >= key (n if none); LE selects a[i] > key instead.
-// 64-ary search: every lane probes one position per level.
-template <bool LE>
-__device__ int64_t wave_search(const double* __restrict__ a, int64_t n, double key, int lane) {
-  int64_t lo = 0, hi = n;   // the answer lies in [lo, hi]
-  while (hi - lo > kWave) {
-    const int64_t span = hi - lo;
-    const int64_t idx = lo + span * (lane + 1) / (kWave + 1);
-    const double v = a[idx];
-    const bool before = LE ? (v <= key) : (v < key);
-    const uint64_t mask = __ballot(before);
-    const int c = __popcll(mask);
-    const int64_t nlo = (c > 0) ? lo + span * c / (kWave + 1) + 1 : lo;
-    const int64_t nhi = (c < kWave) ? lo + span * (c + 1) / (kWave + 1) : hi;
-    lo = nlo;
-    hi = nhi;
-  }
-  const int64_t idx = lo + lane;
-  bool before = false;
-  if (idx < hi) {
-    const double v = a[idx];
-    before = LE ? (v <= key) : (v < key);
-  }
-  return lo + __popcll(__ballot(before));
-}
-
-struct ItemInfo {
-  int64_t j0;        // first grid index of the tile
-  int k;             // (P, T) index within the batch
-  int s;             // split index
-  int64_t b, e;      // line range of this item (global line indices)
-};
-
-template <int P>
-__device__ __forceinline__ bool decode_item(const TileArgs& A, int lane, ItemInfo& it) {
-  const int64_t phys = blockIdx.x;
-  const int64_t wg = xcd_logical_wg(phys);
-  // the wave index is wave-uniform; say so, so that everything derived from it is scalar
-  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t item = wg * kWavesPerWG + wave;
-  if (wg >= A.n_wg || item >= A.n_items) return false;
-  it.s = (int)(item % A.split);
-  const int64_t r = item / A.split;
-  it.k = (int)(r % A.n_pt);
-  // tiles are issued in the order the host chose (most expensive first)
-  const int64_t tile = A.tile_order ? (int64_t)A.tile_order[r / A.n_pt] : r / A.n_pt;
-  it.j0 = tile * (int64_t)(kWave * P);
-  const int64_t jl = min(it.j0 + (int64_t)(kWave * P), A.n_grid) - 1;
-  const int pt = A.pt0 + it.k;
-  const PtConst pc = make_pt(A.sp, A.pts[2 * pt], A.pts[2 * pt + 1]);
-  const double nu_first = A.grid[it.j0];
-  const double nu_last = A.grid[jl];
-  const double cb = cut_bound(A.sp, pc, A.cut, nu_last);
-  // widen the keys by a few ulps of nu so that rounding of nu -+ cb never drops a line
-  const double lk = nu_first - cb - fabs(nu_first) * 0x1p-48;
-  const double hk = nu_last + cb + fabs(nu_last) * 0x1p-48;
-  // search inside the record range only (the host sized it to cover every tile)
-  const double* base = A.L.nu0 + A.rec_lo;
-  const int64_t lo = A.rec_lo + wave_search<false>(base, A.rec_n, lk, lane);
-  const int64_t hi = A.rec_lo + wave_search<true>(base, A.rec_n, hk, lane);
-  const int64_t cnt = hi > lo ? hi - lo : 0;
-  it.b = lo + cnt * it.s / A.split;
-  it.e = lo + cnt * (it.s + 1) / A.split;
-  return true;
-}
-
-// Row bounds of a wave's tile: row p holds points j0 + 64p + lane; ra/rb are its first and
-// last valid grid values (wave-uniform).
-template <int P>
-struct Rows {
-  double ra[P], rb[P];
-  double lanes_per_nu[P];   // last / (rb - ra): linear estimate of a lane from nu
-  bool valid[P];
-  int last[P];          // lane of the last valid point of the row
-};
-
-// First j in [lo, hi) with pred(j), for pred false then true over [lo, hi); hi if none.
-template <class F>
-__device__ __forceinline__ int first_true(int lo, int hi, F pred) {
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (pred(mid)) hi = mid;
-    else lo = mid + 1;
-  }
-  return lo;
-}
-
-// The same answer, starting from a guess: two probes around est settle it when the guess
-// is within one lane (grids that are close to uniform over a row), else a binary search
-// over the side the probes leave.
-template <class F>
-__device__ __forceinline__ int first_true_near(int lo, int hi, int est, F pred) {
-  if (lo >= hi) return lo;
-  est = min(max(est, lo), hi - 1);
-  if (pred(est)) {
-    if (est == lo || !pred(est - 1)) return est;
-    return first_true(lo, est - 1, pred);   // pred(est - 1) holds
-  }
-  if (est + 1 == hi || pred(est + 1)) return est + 1;
-  return first_true(est + 2, hi, pred);     // pred(est + 1) fails
-}
-
-// Lane guess for the first point with nu >= v in a row (linear in nu, clamped to a small
-// range so that the conversion is always defined).
-template <int P>
-__device__ __forceinline__ int lane_guess(const Rows<P>& rows, int p, double v) {
-  const double g = (v - rows.ra[p]) * rows.lanes_per_nu[p];
-  return (int)ceil(fmin(fmax(g, -1.0), (double)kWave));
-}
-
-
-// Stages line i: the record (except the FP32 scales, set once the chunk's scale is known)
-// with the row classes; returns the FP64 profile scale in *sc64, the line's mode in
-// *mode_out and its number of core points (FP32 path) in *npairs_out. The lane ranges of
-// general rows are found only when `general` is set (their lines are staged again later).
-template <bool F64, int P>
-__device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, const Rows<P>& rows,
-                                                  const double* rowv, int64_t i,
-                                                  double* sc64, int* mode_out,
-                                                  int* npairs_out, bool general) {
-  const double nu0 = A.L.nu0[i];
-  const LineRec lr = A.recs[(int64_t)k * A.rec_n + (i - A.rec_lo)];
-  Rec<F64, P> r;
-  r.nu0 = nu0;
-  if constexpr (F64) r.cut = lr.cut;
-  r.ib = lr.ib;
-  *sc64 = lr.sc;
-  const float y = (float)lr.y;
-  const float y2 = y * y;
-  const double cut = lr.cut;
-  int npairs = 0;
-  // Classify each row with the same FP64 difference and test the per-point path uses;
-  // the difference is monotone in nu_j, so the row's two ends decide for every point, and
-  // searches over the row's grid values (rowv, LDS) find the cut and core boundaries.
-  int cls = 0;
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    int c = 0;
-    float xr = 0.0f;
-    unsigned int info = 0;
-    if (rows.valid[p]) {
-      const double da = rows.ra[p] - nu0, db = rows.rb[p] - nu0;
-      const bool none = (da > cut) || (db < -cut);
-      if (!none) {
-        c = 1;
-        const double* rv = rowv + kWave * p;
-        const int n = rows.last[p] + 1;
-        if (!F64 && (da > 0.0 || db < 0.0)) {
-          const bool left = da > 0.0;   // the line lies left of the row
-          const float x = (float)((left ? da : db) * lr.ib);
-          const float r2n = fmaf(x, x, y2);
-          if (r2n >= kFarR2) {
-            c = left ? 2 : 3;
-            xr = x;
-            int bnd;
-            if (left) {
-              // lanes before the first one with nu - nu0 > cut (lane 0 is inside: da <= cut)
-              bnd = db <= cut ? kWave
-                    : first_true_near(1, n, lane_guess(rows, p, nu0 + cut),
-                                      [&](int j) { return rv[j] - nu0 > cut; });
-            } else {
-              // the first lane with nu - nu0 >= -cut (the last lane is inside: db >= -cut)
-              bnd = da >= -cut ? 0
-                    : first_true_near(0, n - 1, lane_guess(rows, p, nu0 - cut),
-                                      [&](int j) { return rv[j] - nu0 >= -cut; });
-            }
-            info = (unsigned)bnd | ((unsigned)asym_variant(r2n) << 8);
-          }
-        }
-        if (!F64 && c == 1 && general) {
-          // general row: the lanes inside the cut and the core segment among them, from
-          // linear guesses checked with the exact predicates
-          const int lo = da >= -cut ? 0
-                         : first_true_near(0, n, lane_guess(rows, p, nu0 - cut),
-                                           [&](int j) { return rv[j] - nu0 >= -cut; });
-          const int hi = db <= cut ? n
-                         : first_true_near(lo, n, lane_guess(rows, p, nu0 + cut),
-                                           [&](int j) { return rv[j] - nu0 > cut; });
-          const int js = first_true_near(lo, hi, lane_guess(rows, p, nu0),
-                                         [&](int j) { return rv[j] - nu0 >= 0.0; });
-          auto core = [&](int j) {
-            const float x = (float)((rv[j] - nu0) * lr.ib);
-            return fmaf(x, x, y2) < kT6R2;
-          };
-          // the core reaches |x| = sqrt(49 - y^2), i.e. nu0 -+ b_D times that
-          const double xc =
-              (double)(sqrtf(fmaxf(49.0f - y2, 0.0f)) * rcp32((float)lr.ib));
-          const int a = first_true_near(lo, js, lane_guess(rows, p, nu0 - xc), core);
-          const int b = first_true_near(js, hi, lane_guess(rows, p, nu0 + xc),
-                                        [&](int j) { return !core(j); });
-          npairs += b - a;
-          info = (unsigned)lo | ((unsigned)hi << 7) | ((unsigned)a << 14) |
-                 ((unsigned)(b - a) << 21);
-        }
-      }
-    }
-    cls |= c << (2 * p);
-    if constexpr (!F64) {
-      r.xr[p] = xr;
-      r.info[p] = info;
-    }
-  }
-  int mode = cls == 0 ? kSkip : kRows;
-  if constexpr (!F64) {
-    // series modes: the line on one side of the whole tile, every row of that side's
-    // series class or out of the cut (the rows out of the cut get an empty lane range);
-    // the variant is that of the tile's point nearest to the line
-    constexpr unsigned kOnes = (unsigned)(0x55555555u & ((1u << (2 * P)) - 1u));
-    const unsigned uc = (unsigned)cls;
-    // per row: class in {0, 2} (left) or {0, 3} (right)
-    const bool left_ok = cls != 0 && ((uc & kOnes) == 0u);
-    const bool right_ok = cls != 0 && ((uc & (uc >> 1) & kOnes) == ((uc | (uc >> 1)) & kOnes));
-    if (left_ok || right_ok) {
-      const int side = left_ok ? 0 : 1;
-      bool full = true;
-      int var = 0;   // the nearest row needs the most terms
-#pragma unroll
-      for (int p = 0; p < P; ++p) {
-        const int cp = (cls >> (2 * p)) & 3;
-        if (cp == 0) r.info[p] = side ? (unsigned)kWave : 0u;
-        else var = max(var, (int)(r.info[p] >> 8));
-        const int bnd = (int)(r.info[p] & 255u);
-        full = full && cp != 0 && bnd == (side ? 0 : kWave);
-      }
-      mode = series_mode(side, full ? 0 : 1, var);
-    }
-  }
-  r.cls = cls;
-  *mode_out = mode;
-  *npairs_out = npairs;
-  if constexpr (F64) {
-    r.y = lr.y;
-    r.sc = lr.sc;
-  } else {
-    r.y = y;
-    r.y2 = y2;
-    r.ib32 = (float)lr.ib;
-    r.sc = 0.0f;
-    r.c1 = r.c2 = r.c3 = 0.0f;
-  }
-  return r;
-}
-
-__device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
-  const float yk = v - c;
-  const float t = s + yk;
-  c = (t - s) - yk;
-  s = t;
-}
-
-// The two-term series of a line, scaled: u (c1 + u (c2 + u c3)), u = 1/r^2.
-template <int P>
-__device__ __forceinline__ float two_term(const Rec<false, P>& q, float r2) {
-  const float u = rcp32(r2);
-  return u * fmaf(u, fmaf(u, q.c3, q.c2), q.c1);
-}
-
-// Adds the scaled contributions of one line to all P rows in the series region with NT
-// terms (x from the row's nearer end, off = the lane's offsets from that end); with MASKED
-// only the lanes inside the cut add: lanes < bnd (SIDE 0) or >= bnd (SIDE 1).
-template <int P, int NT, int SIDE, bool MASKED>
-__device__ __forceinline__ void series_add(const Rec<false, P>& q, const float (&off)[P],
-                                           int lane, float (&t)[P]) {
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    const float x = fmaf(off[p], q.ib32, q.xr[p]);
-    const float r2 = fmaf(x, x, q.y2);
-    float tn;
-    if constexpr (NT == 2) {
-      const float u = rcp32(r2);
-      tn = fmaf(u, fmaf(u, fmaf(u, q.c3, q.c2), q.c1), t[p]);
-    } else {
-      tn = fmaf(q.c1, asym_scaled<NT>(q.y2, r2), t[p]);
-    }
-    if constexpr (MASKED) {
-      const int bnd = __builtin_amdgcn_readfirstlane((int)q.info[p]) & 255;
-      const bool in = SIDE == 0 ? lane < bnd : lane >= bnd;
-      t[p] = in ? tn : t[p];
-    } else {
-      t[p] = tn;
-    }
-  }
-}
-
-// Scaled series value of one row with variant code `var` (wave-uniform).
-template <int P>
-__device__ __forceinline__ float series_row(int var, const Rec<false, P>& q, float r2) {
-  return var == 0 ? two_term(q, r2) : q.c1 * asym_scaled_v(var, q.y2, r2);
-}
-
-// Lines per plain FP32 partial sum before it enters the Kahan-compensated sum: the
-// partial of at most kChunk positive terms carries a relative error below kChunk u32.
-constexpr int kChunk = 16;
-
-// W > 0 asks the compiler for at least W waves per SIMD (capping VGPRs at 512/W).
-template <int P, bool F64, int W>
-__global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileArgs A) {
-  __shared__ Rec<F64, P> recs[kWavesPerWG][kWave];
-  __shared__ double rowvals[kWavesPerWG][kWave * P];
-  __shared__ int incl[kWavesPerWG][kWave];           // packed core points, inclusive prefix
-  __shared__ int dlist[kWavesPerWG][F64 ? 1 : 2 * kWave];   // lines put aside (FP32 path)
-  // packed core contributions: a pass holds the core points of whole lines, at most
-  // kCoreQ (one line brings at most 64 P)
-  constexpr int kCoreQ = kWave * P;
-  __shared__ float cval[kWavesPerWG][F64 ? 1 : kCoreQ];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x >> 6;
-  ItemInfo it;
-  if (!decode_item<P>(A, lane, it)) return;
-
-  Rows<P> rows;
-  double nu[P];
-  float da32[P], db32[P];   // offsets of this lane's points from the row ends
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    const int64_t ja = it.j0 + kWave * p;
-    rows.valid[p] = ja < A.n_grid;
-    const int64_t jb = min(ja + kWave - 1, A.n_grid - 1);
-    rows.ra[p] = rows.valid[p] ? A.grid[ja] : 0.0;
-    rows.rb[p] = rows.valid[p] ? A.grid[jb] : 0.0;
-    rows.last[p] = rows.valid[p] ? (int)(jb - ja) : 0;
-    rows.lanes_per_nu[p] =
-        rows.last[p] > 0 ? (double)rows.last[p] / (rows.rb[p] - rows.ra[p]) : 0.0;
-    const int64_t j = ja + lane;
-    nu[p] = (j < A.n_grid) ? A.grid[j] : __builtin_nan("");
-    da32[p] = (float)(nu[p] - rows.ra[p]);
-    db32[p] = (float)(nu[p] - rows.rb[p]);
-    rowvals[wv][kWave * p + lane] = nu[p];
-  }
-  wave_sync();
-  using acc_t = typename std::conditional<F64, double, float>::type;
-  acc_t s[P], c[P];
-#pragma unroll
-  for (int p = 0; p < P; ++p) { s[p] = 0; c[p] = 0; }
-  int e_ref = kNoScale;   // FP32 path: contributions are scaled by 2^(kScaleTarget - e_ref)
-
-  // FP32 path: the power-of-two scale of a staged chunk (every lane's line): a stronger
-  // line than any before lowers the scale, and the running sums are rescaled exactly
-  auto set_scale = [&](Rec<F64, P>& r, double sc64) {
-    if constexpr (!F64) {
-      const int ex = wave_max(sc64 > 0.0 ? ilogb(sc64) : kNoScale);
-      if (ex > e_ref) {
-        const int d = max(e_ref - ex, -1000);
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-          s[p] = ldexpf(s[p], d);
-          c[p] = ldexpf(c[p], d);
-        }
-        e_ref = ex;
-      }
-      const double scd = ldexp(sc64, kScaleTarget - e_ref);
-      r.sc = (float)scd;
-      r.c1 = (float)(scd * (double)r.y * (double)kInvSqrtPi);
-      r.c2 = 1.5f * r.c1;
-      r.c3 = -2.0f * r.y2 * r.c1;
-    }
-  };
-  // Blocks of kChunk lines summed in plain FP32, each block then added to the
-  // Kahan-compensated sums.
-  auto run = [&](int g0, int g1, auto&& add) {
-    for (int b0 = g0; b0 < g1; b0 += kChunk) {
-      const int b1 = min(b0 + kChunk, g1);
-      float t[P];
-#pragma unroll
-      for (int p = 0; p < P; ++p) t[p] = 0.0f;
-#pragma unroll 2
-      for (int kk = b0; kk < b1; ++kk) add(recs[wv][kk], t);
-      if constexpr (!F64) {
-#pragma unroll
-        for (int p = 0; p < P; ++p) kahan_add(s[p], c[p], t[p]);
-      }
-    }
-  };
-  // FP32 general rows of the lines in LDS slots [g0, g1), in sub-batches of lines whose
-  // core segments hold at most kCoreQ points: first every core point of the sub-batch is
-  // evaluated, one point per lane (FP64 core), into cval; then the lines are walked in
-  // order, each general row taking the series for its in-cut lanes outside the core and
-  // the core values from cval (incl holds the inclusive prefix of core points).
-  auto rows_group = [&](int g0, int g1) {
-    if constexpr (!F64) {
-      int k = g0;
-      int base = 0;   // packed points of the lines before k
-      while (k < g1) {
-        const int ke =
-            first_true(k + 1, g1, [&](int kk) { return incl[wv][kk] - base > kCoreQ; });
-        const int npk = incl[wv][ke - 1] - base;
-        // one term count for the sub-batch: the largest its lines need (a loop of its own
-        // per count, so the pass keeps one evaluation path)
-        const int tier = __builtin_amdgcn_readfirstlane(
-            wave_max(lane < ke - k ? core_tier((double)recs[wv][k + lane].y) : 0));
-        auto packed = [&](auto nterms) {
-          constexpr int N = decltype(nterms)::value;
-          const double* wa = N == 16 ? kWeidA16 : N == 24 ? kWeidA24 : N == 32 ? kWeidA32
-                                                                               : kWeidA;
-          const double wl = N == 16 ? kWeidL16 : N == 24 ? kWeidL24 : N == 32 ? kWeidL32
-                                                                            : kWeidL;
-          for (int r0 = 0; r0 < npk; r0 += kWave) {
-            const int g = r0 + lane;
-            if (g < npk) {
-              const int kk =
-                  first_true(k, ke, [&](int m) { return incl[wv][m] - base > g; });
-              const int local = g - (kk > k ? incl[wv][kk - 1] - base : 0);
-              const Rec<false, P>& q = recs[wv][kk];
-              // the row holding point `local` of this line (rows in order)
-              int row = 0, j = 0;
-              int acc = 0;
-              bool found = false;
-#pragma unroll
-              for (int p = 0; p < P; ++p) {
-                const unsigned gi = q.info[p];
-                const int n =
-                    (((q.cls >> (2 * p)) & 3) == 1) ? (int)((gi >> 21) & 127u) : 0;
-                if (!found && local < acc + n) {
-                  row = p;
-                  j = (int)((gi >> 14) & 127u) + (local - acc);
-                  found = true;
-                }
-                acc += n;
-              }
-              const double d = rowvals[wv][kWave * row + j] - q.nu0;
-              cval[wv][g] = q.sc * (float)voigt_core64_n<N>(wa, wl, d * q.ib, (double)q.y);
-            }
-          }
-        };
-        switch (tier) {
-          case 0: packed(std::integral_constant<int, 16>{}); break;
-          case 1: packed(std::integral_constant<int, 24>{}); break;
-          case 2: packed(std::integral_constant<int, 32>{}); break;
-          default: packed(std::integral_constant<int, 40>{}); break;
-        }
-        wave_sync();
-        int off = 0;   // packed points of the sub-batch's lines walked so far
-        run(k, ke, [&](const Rec<false, P>& q, float (&t)[P]) {
-          const int cls = __builtin_amdgcn_readfirstlane(q.cls);
-          float v[P];
-#pragma unroll
-          for (int p = 0; p < P; ++p) {
-            const int cp = (cls >> (2 * p)) & 3;
-            v[p] = 0.0f;
-            const unsigned info = (unsigned)__builtin_amdgcn_readfirstlane((int)q.info[p]);
-            if (cp == 1) {
-              const int lo = (int)(info & 127u), hi = (int)((info >> 7) & 127u);
-              const int a = (int)((info >> 14) & 127u), n = (int)((info >> 21) & 127u);
-              // x from the FP64 difference: x changes sign along a general row, so the
-              // offset form would cancel
-              const float x = (float)((nu[p] - q.nu0) * q.ib);
-              const float f = q.c1 * asym_scaled<6>(q.y2, fmaf(x, x, q.y2));
-              const bool in_cut = lane >= lo && lane < hi;
-              const bool in_core = lane >= a && lane < a + n;
-              const float cv = cval[wv][min(max(off + lane - a, 0), kCoreQ - 1)];
-              off += n;
-              v[p] = in_cut ? (in_core ? cv : f) : 0.0f;
-            } else if (cp >= 2) {
-              // whole row in the series region; the lanes inside the cut are one side of
-              // bnd
-              const float x = fmaf(cp == 2 ? da32[p] : db32[p], q.ib32, q.xr[p]);
-              const float f = series_row((int)(info >> 8), q, fmaf(x, x, q.y2));
-              const int bnd = (int)(info & 255u);
-              const bool in = cp == 2 ? (lane < bnd) : (lane >= bnd);
-              v[p] = in ? f : 0.0f;
-            }
-          }
-#pragma unroll
-          for (int p = 0; p < P; ++p) t[p] += v[p];
-        });
-        wave_sync();   // cval is refilled by the next sub-batch
-        base = incl[wv][ke - 1];
-        k = ke;
-      }
-    }
-  };
-  // FP32 path: lines needing per-row classes (general rows) are put aside in dlist (line
-  // offsets from it.b, in order) and staged again, with their lane ranges, 64 at a time,
-  // so that the search code runs with full wavefronts instead of in almost every chunk.
-  auto deferred_pass = [&](int nd) {
-    if constexpr (!F64) {
-      Rec<F64, P> r;
-      double sc64 = 0.0;
-      int mode = kSkip, npairs = 0;
-      if (lane < nd) {
-        r = stage_line<F64, P>(A, it.k, rows, rowvals[wv], it.b + dlist[wv][lane], &sc64,
-                               &mode, &npairs, true);
-      }
-      set_scale(r, sc64);
-      int w = lane < nd ? npairs : 0;
-#pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const int u = __shfl_up(w, o, kWave);
-        if (lane >= o) w += u;
-      }
-      if (lane < nd) {
-        recs[wv][lane] = r;
-        incl[wv][lane] = w;
-      }
-      wave_sync();
-      rows_group(0, nd);
-      wave_sync();
-    }
-  };
-  int ndef = 0;   // lines waiting in dlist
-
-  for (int64_t base = it.b; base < it.e; base += kWave) {
-    const int64_t i = base + lane;
-    Rec<F64, P> r;
-    double sc64 = 0.0;
-    int mode = kSkip, npairs = 0;
-    if (i < it.e) {
-      r = stage_line<F64, P>(A, it.k, rows, rowvals[wv], i, &sc64, &mode, &npairs, false);
-    } else {
-      r.cls = 0;
-    }
-    set_scale(r, sc64);
-    // Group the chunk's lines by mode (stable inside each mode) so that the walk below
-    // runs every mode's lines in a loop of its own with no per-line dispatch; lines with
-    // no point inside the cut are dropped. The order is fixed by the data alone.
-    int gstart[kModes + 1];
-    {
-      const uint64_t lt = (1ull << lane) - 1ull;
-      int pos = -1, acc = 0;
-      gstart[0] = 0;
-#pragma unroll
-      for (int m = 1; m < (F64 ? 2 : kModes); ++m) {
-        const uint64_t mk = __ballot(mode == m);
-        if (mode == m) pos = acc + __popcll(mk & lt);
-        gstart[m] = acc;
-        acc += __popcll(mk);
-      }
-#pragma unroll
-      for (int m = F64 ? 2 : kModes; m <= kModes; ++m) gstart[m] = acc;
-      if constexpr (F64) {
-        if (pos >= 0) recs[wv][pos] = r;
-      } else {
-        // general lines wait in dlist; the series groups start at slot 0
-        const int nrows = gstart[kRows + 1];
-        if (mode == kRows) dlist[wv][ndef + pos] = (int)(i - it.b);
-        else if (pos >= 0) recs[wv][pos - nrows] = r;
-#pragma unroll
-        for (int m = kRows + 1; m <= kModes; ++m) gstart[m] -= nrows;
-        ndef += nrows;
-      }
-    }
-    wave_sync();
-    if constexpr (F64) {
-      for (int kk = gstart[kRows]; kk < gstart[kRows + 1]; ++kk) {
-        const Rec<F64, P>& q = recs[wv][kk];
-        const int cls = __builtin_amdgcn_readfirstlane(q.cls);
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-          if (((cls >> (2 * p)) & 3) == 0) continue;
-          const double d = nu[p] - q.nu0;
-          if (fabs(d) <= q.cut) s[p] += q.sc * voigt_k64(d * q.ib, q.y);
-        }
-      }
-    } else {
-      // series modes: the line lies left (right) of the tile; all rows take the series
-      // of the mode's variant, masked by the rows' lane bounds unless every point is
-      // inside the cut
-#define XS_SERIES_GROUP(SIDE, MASKED, VAR, NT)                                        \
-  run(gstart[series_mode(SIDE, MASKED, VAR)], gstart[series_mode(SIDE, MASKED, VAR) + 1], \
-      [&](const Rec<false, P>& q, float (&t)[P]) {                                    \
-        series_add<P, NT, SIDE, MASKED>(q, SIDE ? db32 : da32, lane, t);              \
-      })
-      XS_SERIES_GROUP(0, 0, 0, 2);
-      XS_SERIES_GROUP(0, 0, 1, 3);
-      XS_SERIES_GROUP(0, 0, 2, 4);
-      XS_SERIES_GROUP(0, 0, 3, 6);
-      XS_SERIES_GROUP(0, 1, 0, 2);
-      XS_SERIES_GROUP(0, 1, 1, 3);
-      XS_SERIES_GROUP(0, 1, 2, 4);
-      XS_SERIES_GROUP(0, 1, 3, 6);
-      XS_SERIES_GROUP(1, 0, 0, 2);
-      XS_SERIES_GROUP(1, 0, 1, 3);
-      XS_SERIES_GROUP(1, 0, 2, 4);
-      XS_SERIES_GROUP(1, 0, 3, 6);
-      XS_SERIES_GROUP(1, 1, 0, 2);
-      XS_SERIES_GROUP(1, 1, 1, 3);
-      XS_SERIES_GROUP(1, 1, 2, 4);
-      XS_SERIES_GROUP(1, 1, 3, 6);
-#undef XS_SERIES_GROUP
-    }
-    wave_sync();
-    if (!F64 && ndef >= kWave) {
-      deferred_pass(kWave);
-      // the lines still waiting move to the front
-      const int left = ndef - kWave;
-      const int keep = lane < left ? dlist[wv][kWave + lane] : 0;
-      wave_sync();
-      if (lane < left) dlist[wv][lane] = keep;
-      wave_sync();
-      ndef = left;
-    }
-  }
-  if (!F64 && ndef > 0) deferred_pass(ndef);
-
-  const int64_t row = (A.split == 1) ? (int64_t)(A.pt0 + it.k)
-                                     : ((int64_t)it.k * A.split + it.s);
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    const int64_t j = it.j0 + kWave * p + lane;
-    if (j < A.n_grid) {
-      double v;
-      if constexpr (F64) v = s[p];
-      else v = ldexp((double)s[p] - (double)c[p], e_ref - kScaleTarget);
-      A.out[row * A.n_grid + j] = v;
-    }
   }
 }
 
@@ -826,28 +144,14 @@ hipError_t launch_params(const ParamArgs& A, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int P, bool F64>
-static hipError_t launch_tile_w(const TileArgs& A, int W, hipStream_t st, dim3 grid) {
-  const dim3 block(kBlock);
-  switch (W) {
-    case 0: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 0>), grid, block, 0, st, A); break;
-    case 3: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 3>), grid, block, 0, st, A); break;
-    case 4: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 4>), grid, block, 0, st, A); break;
-    case 5: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 5>), grid, block, 0, st, A); break;
-    case 6: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 6>), grid, block, 0, st, A); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
 hipError_t launch_tile(const TileArgs& A, int P, bool f64, int W, hipStream_t st,
                        int64_t phys_wg) {
   const dim3 grid((unsigned)phys_wg);
   switch (P) {
-    case 1: return f64 ? launch_tile_w<1, true>(A, W, st, grid) : launch_tile_w<1, false>(A, W, st, grid);
-    case 2: return f64 ? launch_tile_w<2, true>(A, W, st, grid) : launch_tile_w<2, false>(A, W, st, grid);
-    case 4: return f64 ? launch_tile_w<4, true>(A, W, st, grid) : launch_tile_w<4, false>(A, W, st, grid);
-    case 8: return f64 ? launch_tile_w<8, true>(A, W, st, grid) : launch_tile_w<8, false>(A, W, st, grid);
+    case 1: return launch_tile_p1(A, f64, W, st, grid);
+    case 2: return launch_tile_p2(A, f64, W, st, grid);
+    case 4: return launch_tile_p4(A, f64, W, st, grid);
+    case 8: return launch_tile_p8(A, f64, W, st, grid);
     default: return hipErrorInvalidValue;
   }
 }
