@@ -300,6 +300,18 @@ int xs_eval_voigt(xs_ctx *ctx, const double *x, const double *y, size_t n, int p
 int xs_eval_voigt_host(const double *x, const double *y, size_t n, int precision,
                        double *K_out);
 
+/* The far-region (x^2 + y^2 >= 49) FP32 forms of the tile kernel, compiled for the host,
+ * for mapping their error (Voigt profile as Re w, section "Functionality of pyROX"): a line
+ * lying outside a row of grid points is evaluated at every point of the row with the
+ * variant its nearest point needs.
+ *   variant 0: shifted Lorentzian (y / sqrt(pi)) / (x^2 + y^2 - 3/2);
+ *   variant 1, 2, 3, 4: the asymptotic series of w with 2, 3, 4, 6 terms;
+ *   variant -1: per point, the variant the kernel picks for a nearest point there.
+ * x, y, K_out: n host values; variant_out (NULL or n ints) receives the variant used.
+ * Points with x^2 + y^2 < 49 or y <= 0 give XS_EINVAL. */
+int xs_eval_series_host(const double *x, const double *y, size_t n, int variant,
+                        double *K_out, int *variant_out);
+
 #ifdef __cplusplus
 }
 #endif

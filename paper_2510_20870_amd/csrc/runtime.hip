@@ -964,4 +964,21 @@ int xs_eval_voigt_host(const double* x, const double* y, size_t n, int precision
   return XS_OK;
 }
 
+int xs_eval_series_host(const double* x, const double* y, size_t n, int variant,
+                        double* K_out, int* variant_out) {
+  if (n && (!x || !y || !K_out)) return fail(XS_EINVAL, "NULL argument");
+  if (variant < -1 || variant >= kNVar) return fail(XS_EINVAL, "unknown variant %d", variant);
+  for (size_t i = 0; i < n; ++i) {
+    const float xf = (float)x[i], yf = (float)y[i];
+    const float y2 = yf * yf;
+    const float r2 = fmaf(xf, xf, y2);
+    if (!(yf > 0.0f) || !(r2 >= kT6R2))
+      return fail(XS_EINVAL, "point %zu (x %g, y %g) outside the series region", i, x[i], y[i]);
+    const int v = variant < 0 ? asym_variant(y2, r2) : variant;
+    K_out[i] = (double)((float)kInvSqrtPi * yf * asym_scaled_v(v, y2, r2));
+    if (variant_out) variant_out[i] = v;
+  }
+  return XS_OK;
+}
+
 }  // extern "C"

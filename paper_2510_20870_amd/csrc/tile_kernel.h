@@ -28,6 +28,8 @@ constexpr int kNoScale = -(1 << 28);
 // is then x at the row's nearest end (first / last point) and info[p] = bnd | var << 8:
 // the points inside the cut are the lanes < bnd (class 2) or >= bnd (class 3), found
 // exactly at staging time, and var is the series variant the row's nearest point needs.
+// y2 is y^2, except for lines of a shifted-Lorentzian series mode, where it is
+// y^2 - 3/2 (their only use of it is the shifted r^2).
 // For a general row (class 1) of the FP32 path, info[p] = lo | hi << 7 | a << 14 | n << 21
 // holds the lanes inside the cut, [lo, hi), and the lanes of the FP64 core region
 // (r^2 < 49), [a, a + n), found exactly at staging time with the same FP64 difference and
@@ -41,11 +43,11 @@ constexpr int kNoScale = -(1 << 28);
 enum {
   kSkip = 0,
   kRows = 1,
-  kSeries = 2,   // + side * 8 + masked * 4 + variant
-  kModes = 18
+  kSeries = 2,   // + side * 2 kNVar + masked * kNVar + variant
+  kModes = kSeries + 4 * kNVar
 };
 __host__ __device__ constexpr int series_mode(int side, int masked, int var) {
-  return kSeries + side * 8 + masked * 4 + var;
+  return kSeries + side * 2 * kNVar + masked * kNVar + var;
 }
 
 template <bool F64, int P> struct Rec;
@@ -251,7 +253,7 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
                     : first_true_near(0, n - 1, lane_guess(rows, p, nu0 - cut),
                                       [&](int j) { return rv[j] - nu0 >= -cut; });
             }
-            info = (unsigned)bnd | ((unsigned)asym_variant(r2n) << 8);
+            info = (unsigned)bnd | ((unsigned)asym_variant(y2, r2n) << 8);
           }
         }
         if (!F64 && c == 1 && general) {
@@ -288,6 +290,7 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
     }
   }
   int mode = cls == 0 ? kSkip : kRows;
+  bool shifted = false;
   if constexpr (!F64) {
     // series modes: the line on one side of the whole tile, every row of that side's
     // series class or out of the cut (the rows out of the cut get an empty lane range);
@@ -310,6 +313,7 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
         full = full && cp != 0 && bnd == (side ? 0 : kWave);
       }
       mode = series_mode(side, full ? 0 : 1, var);
+      shifted = var == 0;
     }
   }
   r.cls = cls;
@@ -320,7 +324,7 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, cons
     r.sc = lr.sc;
   } else {
     r.y = y;
-    r.y2 = y2;
+    r.y2 = shifted ? y2 - 1.5f : y2;
     r.ib32 = (float)lr.ib;
     r.sc = 0.0f;
     r.c1 = r.c2 = r.c3 = 0.0f;
@@ -343,8 +347,9 @@ __device__ __forceinline__ float two_term(const Rec<false, P>& q, float r2) {
 }
 
 // Adds the scaled contributions of one line to all P rows in the series region with NT
-// terms (x from the row's nearer end, off = the lane's offsets from that end); with MASKED
-// only the lanes inside the cut add: lanes < bnd (SIDE 0) or >= bnd (SIDE 1).
+// terms, NT = 1 being the shifted Lorentzian (x from the row's nearer end, off = the lane's
+// offsets from that end); with MASKED only the lanes inside the cut add: lanes < bnd
+// (SIDE 0) or >= bnd (SIDE 1).
 template <int P, int NT, int SIDE, bool MASKED>
 __device__ __forceinline__ void series_add(const Rec<false, P>& q, const float (&off)[P],
                                            int lane, float (&t)[P]) {
@@ -353,7 +358,9 @@ __device__ __forceinline__ void series_add(const Rec<false, P>& q, const float (
     const float x = fmaf(off[p], q.ib32, q.xr[p]);
     const float r2 = fmaf(x, x, q.y2);
     float tn;
-    if constexpr (NT == 2) {
+    if constexpr (NT == 1) {
+      tn = fmaf(q.c1, rcp32(r2), t[p]);   // r2 holds x^2 + y^2 - 3/2 here
+    } else if constexpr (NT == 2) {
       const float u = rcp32(r2);
       tn = fmaf(u, fmaf(u, fmaf(u, q.c3, q.c2), q.c1), t[p]);
     } else {
@@ -369,10 +376,11 @@ __device__ __forceinline__ void series_add(const Rec<false, P>& q, const float (
   }
 }
 
-// Scaled series value of one row with variant code `var` (wave-uniform).
+// Scaled series value of one row with variant code `var` (wave-uniform) in a line of the
+// general mode (y2 unshifted).
 template <int P>
 __device__ __forceinline__ float series_row(int var, const Rec<false, P>& q, float r2) {
-  return var == 0 ? two_term(q, r2) : q.c1 * asym_scaled_v(var, q.y2, r2);
+  return var == 1 ? two_term(q, r2) : q.c1 * asym_scaled_v(var, q.y2, r2);
 }
 
 // Lines per plain FP32 partial sum before it enters the Kahan-compensated sum: the
@@ -647,22 +655,26 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       [&](const Rec<false, P>& q, float (&t)[P]) {                                    \
         series_add<P, NT, SIDE, MASKED>(q, SIDE ? db32 : da32, lane, t);              \
       })
-      XS_SERIES_GROUP(0, 0, 0, 2);
-      XS_SERIES_GROUP(0, 0, 1, 3);
-      XS_SERIES_GROUP(0, 0, 2, 4);
-      XS_SERIES_GROUP(0, 0, 3, 6);
-      XS_SERIES_GROUP(0, 1, 0, 2);
-      XS_SERIES_GROUP(0, 1, 1, 3);
-      XS_SERIES_GROUP(0, 1, 2, 4);
-      XS_SERIES_GROUP(0, 1, 3, 6);
-      XS_SERIES_GROUP(1, 0, 0, 2);
-      XS_SERIES_GROUP(1, 0, 1, 3);
-      XS_SERIES_GROUP(1, 0, 2, 4);
-      XS_SERIES_GROUP(1, 0, 3, 6);
-      XS_SERIES_GROUP(1, 1, 0, 2);
-      XS_SERIES_GROUP(1, 1, 1, 3);
-      XS_SERIES_GROUP(1, 1, 2, 4);
-      XS_SERIES_GROUP(1, 1, 3, 6);
+      XS_SERIES_GROUP(0, 0, 0, 1);
+      XS_SERIES_GROUP(0, 0, 1, 2);
+      XS_SERIES_GROUP(0, 0, 2, 3);
+      XS_SERIES_GROUP(0, 0, 3, 4);
+      XS_SERIES_GROUP(0, 0, 4, 6);
+      XS_SERIES_GROUP(0, 1, 0, 1);
+      XS_SERIES_GROUP(0, 1, 1, 2);
+      XS_SERIES_GROUP(0, 1, 2, 3);
+      XS_SERIES_GROUP(0, 1, 3, 4);
+      XS_SERIES_GROUP(0, 1, 4, 6);
+      XS_SERIES_GROUP(1, 0, 0, 1);
+      XS_SERIES_GROUP(1, 0, 1, 2);
+      XS_SERIES_GROUP(1, 0, 2, 3);
+      XS_SERIES_GROUP(1, 0, 3, 4);
+      XS_SERIES_GROUP(1, 0, 4, 6);
+      XS_SERIES_GROUP(1, 1, 0, 1);
+      XS_SERIES_GROUP(1, 1, 1, 2);
+      XS_SERIES_GROUP(1, 1, 2, 3);
+      XS_SERIES_GROUP(1, 1, 3, 4);
+      XS_SERIES_GROUP(1, 1, 4, 6);
 #undef XS_SERIES_GROUP
     }
     wave_sync();

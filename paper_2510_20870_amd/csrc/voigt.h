@@ -17,6 +17,12 @@
 //    number of terms NT is chosen by |z| (measured FP32 error against scipy's wofz):
 //      NT = 2 for |z| >= 80 (<= 4.1e-7), 3 for |z| >= 20 (<= 5.5e-7),
 //      4 for |z| >= 13 (<= 3.9e-7), 6 for |z| >= 7 (<= 5.1e-7).
+//    Farther out one reciprocal suffices: 1/(r^2 - 3/2) = u (1 + 3u/2 + 9u^2/4 + ...)
+//    matches the series through the u^2 term for every y, and the first neglected terms
+//    are (3/2 - 2 y^2) u^3 against u, so the shifted Lorentzian
+//        K = (y / sqrt(pi)) / (x^2 + y^2 - 3/2)
+//    is within (3/2 + 2 y^2) u^2 relative of K; it is used where that bound is at most
+//    2e-7 (r^4 >= 5e6 (3/2 + 2 y^2)), which for y < 1.7 starts before |z| = 80.
 //  * core (|z| < 7): Weideman's (1994) rational series with N = 40 terms,
 //        w(z) ~ 2 p(Z)/(L - iz)^2 + pi^{-1/2}/(L - iz),  Z = (L + iz)/(L - iz),
 //    L = 2^{-1/4} sqrt(N), evaluated in FP64: near the real axis Re w is tiny beside
@@ -116,17 +122,30 @@ XS_HD float asym2_m(float m2y2, float r2) {
   return u * fmaf(u, fmaf(m2y2, u, 1.5f), 1.0f);
 }
 
-// The number of series terms a point at r2 >= kT6R2 needs, as a variant code 0..3.
-XS_HD int asym_variant(float r2) {
-  return r2 >= kT2R2 ? 0 : r2 >= kT3R2 ? 1 : r2 >= kT4R2 ? 2 : 3;
+// Shifted-Lorentzian region: (3/2 + 2 y^2) / r^4 <= kL1Eps.
+constexpr float kL1Eps = 2e-7f;
+XS_HD bool shifted_lorentz_ok(float y2, float r2) {
+  return r2 * r2 * kL1Eps >= fmaf(2.0f, y2, 1.5f);
+}
+
+// Series variants of the far region, cheapest first: 0 = shifted Lorentzian, 1..4 =
+// NT = 2, 3, 4, 6 terms. For a fixed y the variant a point needs does not increase with
+// r^2, so a variant chosen at the point nearest to a line serves every farther point.
+constexpr int kNVar = 5;
+
+// The variant a point at r2 >= kT6R2 needs.
+XS_HD int asym_variant(float y2, float r2) {
+  if (shifted_lorentz_ok(y2, r2)) return 0;
+  return r2 >= kT2R2 ? 1 : r2 >= kT3R2 ? 2 : r2 >= kT4R2 ? 3 : 4;
 }
 
 // K * sqrt(pi) / y for variant code v (uniform across the wavefront at the call sites).
 XS_HD float asym_scaled_v(int v, float y2, float r2) {
   switch (v) {
-    case 0: return asym_scaled<2>(y2, r2);
-    case 1: return asym_scaled<3>(y2, r2);
-    case 2: return asym_scaled<4>(y2, r2);
+    case 0: return rcp32(r2 - 1.5f);
+    case 1: return asym_scaled<2>(y2, r2);
+    case 2: return asym_scaled<3>(y2, r2);
+    case 3: return asym_scaled<4>(y2, r2);
     default: return asym_scaled<6>(y2, r2);
   }
 }

@@ -134,6 +134,8 @@ _SIGS = {
                       C.c_int),
     "xs_eval_voigt_host": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p],
                            C.c_int),
+    "xs_eval_series_host": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p,
+                             C.c_void_p], C.c_int),
 }
 
 
@@ -171,6 +173,21 @@ def eval_voigt_host(x, y, precision: int = XS_FP32_KAHAN) -> np.ndarray:
     if rc:
         raise XsError(rc, lib().xs_last_error(None).decode())
     return out
+
+
+def eval_series_host(x, y, variant: int = -1):
+    """The tile kernel's FP32 far-region forms on the host: (K, variant used per point).
+    variant 0 = shifted Lorentzian, 1..4 = asymptotic series with 2, 3, 4, 6 terms, -1 =
+    the variant the kernel picks for a nearest point at (x, y)."""
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    out = np.empty_like(x)
+    var = np.empty(x.shape, np.int32)
+    rc = lib().xs_eval_series_host(_ptr(x), _ptr(y), x.size, int(variant), _ptr(out),
+                                   _ptr(var))
+    if rc:
+        raise XsError(rc, lib().xs_last_error(None).decode())
+    return out, var
 
 
 def _dev_ptr(t) -> int:

@@ -93,6 +93,61 @@ def test_voigt_fp32_core_tiers():
     assert rel.max() < 4e-7, (rel.max(), x[rel.argmax()], y[rel.argmax()])
 
 
+def _far_points(n, seed):
+    # |z| log-uniform from 7 to 2e5 and y log-uniform over the workloads' range, x >= 0
+    rng = np.random.default_rng(seed)
+    y = 10 ** rng.uniform(np.log10(5e-7), np.log10(3.5e4), n)
+    r = np.maximum(7.0, y) * 10 ** rng.uniform(0.0, 4.5, n)
+    x = np.sqrt(np.maximum(r * r - y * y, 0.0))
+    # the kernel works on FP32 x and y: compare against w at exactly those values
+    x, y = x.astype(np.float32).astype(np.float64), y.astype(np.float32).astype(np.float64)
+    m = (x * x + y * y >= 49.0 * (1 + 1e-6)) & (y > 0)
+    return x[m], y[m]
+
+
+def test_series_variants_error_map():
+    # The far region's FP32 forms: the variant the kernel picks for a nearest point keeps
+    # the error budget there and at every farther point (a line's whole row takes it).
+    x, y = _far_points(300_000, 11)
+    ref = wofz(x + 1j * y).real
+    K, v = xsec.eval_series_host(x, y, -1)
+    rel = np.abs(K - ref) / ref
+    assert rel.max() < 6e-7, (rel.max(), x[rel.argmax()], y[rel.argmax()], v[rel.argmax()])
+    assert set(np.unique(v)) == {0, 1, 2, 3, 4}
+    # the shifted Lorentzian carries the bulk of the far wing
+    assert np.mean(v == 0) > 0.5
+    # the kernel's use: the variant picked at a row's nearest point, evaluated at farther
+    # points of the same line (same y, larger |x|)
+    rng = np.random.default_rng(12)
+    xf = (x + 10 ** rng.uniform(-2, 4, x.size)).astype(np.float32).astype(np.float64)
+    reff = wofz(xf + 1j * y).real
+    for var in range(5):
+        m = v == var
+        Kv, used = xsec.eval_series_host(xf[m], y[m], var)
+        assert np.all(used == var)
+        rv = np.abs(Kv - reff[m]) / reff[m]
+        assert rv.max() < 6e-7, (var, rv.max(), xf[m][rv.argmax()], y[m][rv.argmax()])
+    # a farther point never needs a costlier variant (same y)
+    _, v2 = xsec.eval_series_host(xf, y, -1)
+    assert np.all(v2 <= v)
+    # the shifted Lorentzian's switch point: (3/2 + 2 y^2) / r^4 = 2e-7
+    for yy in (1e-6, 0.1, 1.0, 10.0, 300.0):
+        r4 = (1.5 + 2 * yy * yy) / 2e-7
+        r2 = np.sqrt(r4)
+        xs_ = np.sqrt(r2 * np.array([1.001, 0.999]) - yy * yy)
+        _, vv = xsec.eval_series_host(xs_, np.full(2, yy), -1)
+        assert vv[0] == 0 and vv[1] != 0, (yy, vv)
+
+
+def test_series_variant_errors():
+    with pytest.raises(xsec.XsError):
+        xsec.eval_series_host([1.0], [1.0], 0)        # |z| < 7
+    with pytest.raises(xsec.XsError):
+        xsec.eval_series_host([100.0], [1.0], 5)      # no such variant
+    with pytest.raises(xsec.XsError):
+        xsec.eval_series_host([100.0], [0.0], 0)      # y must be positive
+
+
 def test_voigt_fp64_error_map():
     x, y = _domain(200_000, 2)
     ref = wofz(x + 1j * y).real
