@@ -26,11 +26,20 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP32 work of one line-point evaluation in the far tier that carries almost
-# all evaluations (two-term asymptotic series; FMA = 2 FLOPs): x = off*(1/b_D) + x_row 2,
-# r^2 = x^2 + y^2 2, u = 1/r^2 1, w = y^2 u 1, 1.5 - 2w 2, 1 + u(..) 2, u*(..) 1, scale 1,
-# Kahan add 4 -> 16. Core and cut-edge evaluations do more work and count the same.
-FLOPS_PER_EVAL = 16.0
+# Algorithmic work of one line-point evaluation by the tier the point needs (FMA = 2 FLOPs,
+# reciprocal = 1; FP32 in the far region, FP64 in the core; counted per point by
+# xs_count_evals_by_tier):
+#   shifted Lorentzian: x = off/b_D + x_row 2, r^2 - 3/2 2, 1/r^2 1, += c1 u 2         -> 7
+#   two-term series:    x 2, r^2 2, u 1, u(c1 + u(c2 + u c3)) + t 6                    -> 11
+#   3 / 4 / 6 terms:    x 2, r^2 2, u 1, w 1, the V_k recurrence and the sum, += c1 K  -> 19/25/35
+#   FP64 core (N terms): offset and x 2, setup (D, 1/D by two Newton steps, Z) 19,
+#                        N - 1 complex Horner steps 7 each, Re of the result 12, scale
+#                        and add 2                                                      -> 35 + 7(N-1)
+# plus the Kahan-compensated fold of each 16-line partial (4 FLOPs per point per 16
+# lines).
+FLOPS_BY_TIER = (7.0, 11.0, 19.0, 25.0, 35.0, 35.0 + 7 * 15, 35.0 + 7 * 23, 35.0 + 7 * 31,
+                 35.0 + 7 * 39)
+KAHAN_FLOPS_PER_EVAL = 4.0 / 16.0
 # VALU peak without packed FP32 (the build disables packed FP32 instructions): 256 CUs x
 # 4 SIMDs x 16 lanes x 1 FMA (2 FLOPs) per clock x 2.4 GHz; the published 157.3 TFLOP/s
 # needs packed FP32.
@@ -252,7 +261,13 @@ def main():
         log(f"launch shapes: {tuned}")
         if args.save_tune:
             xsec.tune_cache_save(args.save_tune)
+    tiers = ctx.count_evals_by_tier(h, g, [(P, T)], o32)[0].astype(np.float64)
     evals = int(ctx.count_evals(h, g, [(P, T)], o32)[0])
+    if int(tiers.sum()) != evals:
+        raise SystemExit(f"tier counts {tiers.sum()} do not add up to {evals}")
+    flops_per_eval = float(tiers @ np.array(FLOPS_BY_TIER)) / evals + KAHAN_FLOPS_PER_EVAL
+    eval_mix = {n: float(c / evals) for n, c in zip(xsec.EVAL_TIERS, tiers)}
+    log(f"evaluation tiers: {eval_mix}; {flops_per_eval:.3f} algorithmic FLOPs per eval")
     if W.cut_kind == "fixed":
         # independent count from the sorted centres (searchsorted), the harness's rule
         nu0 = L["nu0"]
@@ -336,7 +351,7 @@ def main():
 
     # one tile launch covers the whole grid at the one (P, T) point: evals per launch
     evals_per_launch = evals * args.steps / max(1, nl32)
-    achieved = evals_per_launch * FLOPS_PER_EVAL / (k32 * 1e-3) / 1e12
+    achieved = evals_per_launch * flops_per_eval / (k32 * 1e-3) / 1e12
     traffic = profiled_traffic()
     res = {
         "metric": "Voigt line-point evals/s at <=1e-4 rel err vs FP64; p50/p99 request latency",
@@ -362,7 +377,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
                      "traffic": traffic, "kernel": "xs_tile_kernel",
-                     "kernel_ms_per_launch": k32, "flops_per_eval": FLOPS_PER_EVAL,
+                     "kernel_ms_per_launch": k32, "flops_per_eval": flops_per_eval,
+                     "eval_mix": eval_mix,
                      "evals_per_launch": evals_per_launch,
                      "peak_basis": "256 CU x 64 lanes x FMA x 2.4 GHz (no packed FP32)",
                      "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS,

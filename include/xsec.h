@@ -163,6 +163,16 @@ int xs_compute(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts, 
 int xs_count_evals(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts,
                    size_t npts, const xs_opts *opts, uint64_t *counts_out);
 
+/* The same pairs split by the evaluation tier each point needs on the FP32 path (its own
+ * x^2 + y^2 and y, the tiers of the Voigt approximation described with
+ * xs_eval_series_host): tiers 0..4 are the far-region variants (shifted Lorentzian, then
+ * the asymptotic series with 2, 3, 4, 6 terms), tiers 5..8 the FP64 core with 16, 24, 32,
+ * 40 terms. counts_out: npts * XS_N_EVAL_TIERS host values, [k][tier]. Accounting only
+ * (the algorithmic work of a launch); the sum over tiers is xs_count_evals. */
+#define XS_N_EVAL_TIERS 9
+int xs_count_evals_by_tier(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts,
+                           size_t npts, const xs_opts *opts, uint64_t *counts_out);
+
 /* Batched computation captured once in a hipGraph (its point table and scratch are owned
  * by the graph) and replayed by xs_graph_launch on any stream; sigma_dev is device memory
  * of npts * n_grid float64. */

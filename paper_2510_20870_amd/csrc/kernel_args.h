@@ -56,7 +56,7 @@ struct TileArgs {
   int64_t rec_lo, rec_n;
   double* out;            // split == 1: sigma rows [n_pts][n_grid] (row pt0 + k);
                           // else partials [n_pt][split][n_grid] of this batch
-  unsigned long long* counts;  // count kernel only: [n_pts]
+  unsigned long long* counts;  // count kernel only: [n_pts][kNEvalTiers]
 };
 
 // Launchers (kernels.hip). phys_wg = number of workgroups launched: n_wg rounded up to a

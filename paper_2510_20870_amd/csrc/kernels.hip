@@ -78,11 +78,15 @@ __global__ __launch_bounds__(256) void xs_reduce_kernel(const double* __restrict
   }
 }
 
-// Count of (line, point) pairs inside the cutoff, per (P, T) point; same traversal and
-// the same FP64 test as the tile kernel.
+// Count of (line, point) pairs inside the cutoff, per (P, T) point and evaluation tier;
+// same traversal and the same FP64 cut test as the tile kernel. The tier is the one the
+// point itself needs (its own FP32 r^2 and y): the far-region variants 0..kNVar-1, then
+// the FP64 core with its y-dependent term count (kNVar + core_tier). counts is
+// [n_pt][kNEvalTiers].
 template <int P>
 __global__ __launch_bounds__(kBlock) void xs_count_kernel(TileArgs A) {
   __shared__ double cen[kWavesPerWG][kWave], cut[kWavesPerWG][kWave];
+  __shared__ double ibs[kWavesPerWG][kWave], ys[kWavesPerWG][kWave];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x >> 6;
   ItemInfo it;
@@ -93,28 +97,51 @@ __global__ __launch_bounds__(kBlock) void xs_count_kernel(TileArgs A) {
     const int64_t j = it.j0 + kWave * p + lane;
     nu[p] = (j < A.n_grid) ? A.grid[j] : __builtin_nan("");
   }
-  unsigned long long cnt = 0;
+  unsigned long long cnt[kNEvalTiers];
+#pragma unroll
+  for (int t = 0; t < kNEvalTiers; ++t) cnt[t] = 0;
   for (int64_t base = it.b; base < it.e; base += kWave) {
     const int64_t i = base + lane;
-    double c0 = 0.0, ct = -1.0;
+    double c0 = 0.0, ct = -1.0, ib = 0.0, yv = 0.0;
     if (i < it.e) {
+      const LineRec lr = A.recs[(int64_t)it.k * A.rec_n + (i - A.rec_lo)];
       c0 = A.L.nu0[i];
-      ct = A.recs[(int64_t)it.k * A.rec_n + (i - A.rec_lo)].cut;
+      ct = lr.cut;
+      ib = lr.ib;
+      yv = lr.y;
     }
     cen[wv][lane] = c0;
     cut[wv][lane] = ct;
+    ibs[wv][lane] = ib;
+    ys[wv][lane] = yv;
     wave_sync();
     const int nk = (int)min((int64_t)kWave, it.e - base);
     for (int kk = 0; kk < nk; ++kk) {
       const double q0 = cen[wv][kk], qc = cut[wv][kk];
+      const float y = (float)ys[wv][kk];
+      const float y2 = y * y;
+      const int core = kNVar + core_tier(ys[wv][kk]);
 #pragma unroll
-      for (int p = 0; p < P; ++p) cnt += (fabs(nu[p] - q0) <= qc) ? 1ull : 0ull;
+      for (int p = 0; p < P; ++p) {
+        const double d = nu[p] - q0;
+        if (fabs(d) <= qc) {
+          const float x = (float)(d * ibs[wv][kk]);
+          const float r2 = fmaf(x, x, y2);
+          const int tier = r2 >= kT6R2 ? asym_variant(y2, r2) : core;
+#pragma unroll
+          for (int t = 0; t < kNEvalTiers; ++t) cnt[t] += (tier == t) ? 1ull : 0ull;
+        }
+      }
     }
     wave_sync();
   }
-  // wave reduction, then one 64-bit integer atomic per wave (exact, order-free)
-  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
-  if (lane == 0) atomicAdd(A.counts + A.pt0 + it.k, cnt);
+  // wave reductions, then one 64-bit integer atomic per tier and wave (exact, order-free)
+#pragma unroll
+  for (int t = 0; t < kNEvalTiers; ++t) {
+    unsigned long long v = cnt[t];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0 && v) atomicAdd(A.counts + (int64_t)(A.pt0 + it.k) * kNEvalTiers + t, v);
+  }
 }
 
 __global__ void xs_fill_u64_kernel(unsigned long long* p, int64_t n) {

@@ -759,8 +759,24 @@ int xs_compute(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t 
   return XS_OK;
 }
 
+static_assert(XS_N_EVAL_TIERS == kNEvalTiers, "evaluation tiers of the ABI and the kernels");
+
 int xs_count_evals(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t npts,
                    const xs_opts* opts, uint64_t* counts_out) {
+  if (!counts_out) return fail(XS_EINVAL, "NULL argument");
+  std::vector<uint64_t> t(npts * kNEvalTiers);
+  const int rc = xs_count_evals_by_tier(c, lh, gh, pts, npts, opts, t.data());
+  if (rc) return rc;
+  for (size_t k = 0; k < npts; ++k) {
+    uint64_t sum = 0;
+    for (int j = 0; j < kNEvalTiers; ++j) sum += t[k * kNEvalTiers + j];
+    counts_out[k] = sum;
+  }
+  return XS_OK;
+}
+
+int xs_count_evals_by_tier(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts,
+                           size_t npts, const xs_opts* opts, uint64_t* counts_out) {
   if (!c || !counts_out) return fail(XS_EINVAL, "NULL argument");
   int rc = validate_opts(opts);
   if (rc) return rc;
@@ -786,11 +802,12 @@ int xs_count_evals(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, siz
   const Plan p = make_plan(*c, *L, *G, npts, o);
   rc = upload_pts(*c, pts, npts, st);
   if (rc) return rc;
-  rc = c->scratch(c->count_buf, npts * sizeof(uint64_t), "counters");
+  const size_t ncnt = npts * kNEvalTiers;
+  rc = c->scratch(c->count_buf, ncnt * sizeof(uint64_t), "counters");
   if (rc) return rc;
   rc = c->scratch(c->rec_buf, p.rec_bytes(), "line records");
   if (rc) return rc;
-  e = launch_fill_u64((unsigned long long*)c->count_buf.ptr, (int64_t)npts, st);
+  e = launch_fill_u64((unsigned long long*)c->count_buf.ptr, (int64_t)ncnt, st);
   if (e != hipSuccess) return hip_fail(e, "counter clear");
   rc = upload_order(*c, p, st);
   if (rc) return rc;
@@ -798,7 +815,7 @@ int xs_count_evals(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, siz
                     (const int*)c->order_buf.ptr, nullptr, c->rec_buf.ptr, nullptr, st,
                     (unsigned long long*)c->count_buf.ptr, c->timer);
   if (rc) return rc;
-  e = hipMemcpyAsync(counts_out, c->count_buf.ptr, npts * sizeof(uint64_t),
+  e = hipMemcpyAsync(counts_out, c->count_buf.ptr, ncnt * sizeof(uint64_t),
                      hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "count download");

@@ -616,9 +616,11 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
 #pragma unroll
       for (int m = 1; m < (F64 ? 2 : kModes); ++m) {
         const uint64_t mk = __ballot(mode == m);
-        if (mode == m) pos = acc + __popcll(mk & lt);
         gstart[m] = acc;
-        acc += __popcll(mk);
+        if (mk) {   // wave-uniform: most chunks hold only a few of the modes
+          if (mode == m) pos = acc + __popcll(mk & lt);
+          acc += __popcll(mk);
+        }
       }
 #pragma unroll
       for (int m = F64 ? 2 : kModes; m <= kModes; ++m) gstart[m] = acc;

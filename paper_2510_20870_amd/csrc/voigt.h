@@ -132,6 +132,9 @@ XS_HD bool shifted_lorentz_ok(float y2, float r2) {
 // NT = 2, 3, 4, 6 terms. For a fixed y the variant a point needs does not increase with
 // r^2, so a variant chosen at the point nearest to a line serves every farther point.
 constexpr int kNVar = 5;
+// Evaluation tiers of a point (accounting): the kNVar far-region variants, then the four
+// term counts of the FP64 core (core_tier).
+constexpr int kNEvalTiers = kNVar + 4;
 
 // The variant a point at r2 >= kT6R2 needs.
 XS_HD int asym_variant(float y2, float r2) {

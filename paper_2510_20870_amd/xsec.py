@@ -23,6 +23,10 @@ XS_EINSTEIN_A, XS_REF_STRENGTH = 0, 1
 XS_Q_POWER, XS_Q_TABLE = 0, 1
 XS_CUT_FIXED, XS_CUT_MIN_FWHM = 0, 1
 XS_FP32_KAHAN, XS_FP64 = 0, 1
+XS_N_EVAL_TIERS = 9
+# names of the evaluation tiers counted by Context.count_evals_by_tier
+EVAL_TIERS = ("lorentz_shifted", "series2", "series3", "series4", "series6",
+              "core16", "core24", "core32", "core40")
 
 _STATUS = {0: "XS_OK", -1: "XS_EINVAL", -2: "XS_ENOMEM", -3: "XS_EDEVICE",
            -4: "XS_ENOTFOUND", -5: "XS_EUNSORTED", -6: "XS_EBUSY", -7: "XS_ECANCELLED",
@@ -98,6 +102,8 @@ _SIGS = {
                     C.POINTER(Opts), C.c_void_p, C.c_int, C.c_void_p], C.c_int),
     "xs_count_evals": ([C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(Pt), C.c_size_t,
                         C.POINTER(Opts), C.c_void_p], C.c_int),
+    "xs_count_evals_by_tier": ([C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(Pt),
+                                C.c_size_t, C.POINTER(Opts), C.c_void_p], C.c_int),
     "xs_graph_create": ([C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(Pt), C.c_size_t,
                          C.POINTER(Opts), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "xs_graph_launch": ([C.c_void_p, C.c_void_p], C.c_int),
@@ -425,6 +431,14 @@ class Context:
         out = np.zeros(len(p), np.uint64)
         self._check(self._L.xs_count_evals(self.h, lines, grid, p, len(p), C.byref(opts),
                                            _ptr(out)))
+        return out
+
+    def count_evals_by_tier(self, lines: int, grid: int, pts, opts: Opts) -> np.ndarray:
+        """[npts, XS_N_EVAL_TIERS] counts of in-cut pairs by the tier each point needs."""
+        p = self._pts(pts)
+        out = np.zeros((len(p), XS_N_EVAL_TIERS), np.uint64)
+        self._check(self._L.xs_count_evals_by_tier(self.h, lines, grid, p, len(p),
+                                                   C.byref(opts), _ptr(out)))
         return out
 
     def grid_len(self, grid: int) -> int:

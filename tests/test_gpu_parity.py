@@ -136,6 +136,50 @@ def test_count_evals_fixed(ctx):
     ctx.free_grid(g)
 
 
+def _tiers_fp64(L, grid, P, T, mass, cut):
+    """Evaluation tier of every in-cut pair, classified in FP64 from the oracle's line
+    parameters with the documented thresholds: far region x^2 + y^2 >= 49 split into the
+    shifted Lorentzian ((3/2 + 2 y^2) / r^4 <= 2e-7) and the asymptotic series with 2, 3,
+    4, 6 terms (r^2 >= 6400, 400, 169, 49); the core by y (>= 1, 0.01, 1e-5, below)."""
+    par = O.line_parameters(L, P, T, mass, cut_cm1=cut)
+    nu0 = np.asarray(L["nu0"], np.float64)
+    y = par["gamma_L"] / par["b_D"]
+    counts = np.zeros(9, np.int64)
+    for j0 in range(0, len(grid), 512):
+        d = grid[j0:j0 + 512, None] - nu0[None, :]
+        m = np.abs(d) <= cut
+        x = d / par["b_D"][None, :]
+        yy = np.broadcast_to(y[None, :], x.shape)
+        r2 = x * x + yy * yy
+        far = np.where((1.5 + 2 * yy * yy) / (r2 * r2) <= 2e-7, 0,
+                       np.where(r2 >= 6400, 1, np.where(r2 >= 400, 2,
+                                np.where(r2 >= 169, 3, 4))))
+        core = np.where(yy >= 1.0, 5, np.where(yy >= 0.01, 6, np.where(yy >= 1e-5, 7, 8)))
+        t = np.where(r2 >= 49.0, far, core)
+        counts += np.bincount(t[m], minlength=9)
+    return counts
+
+
+def test_count_evals_by_tier(ctx):
+    W, L, grid = _tiny()
+    grid = grid[:3000]
+    h = ctx.load_lines(L, W.mass_amu)
+    g = ctx.set_grid(grid)
+    pts = [(1e-4, 300.0), (1.0, 1000.0), (60.0, 2500.0)]
+    tiers = ctx.count_evals_by_tier(h, g, pts, _opts(cut=10.0))
+    tot = ctx.count_evals(h, g, pts, _opts(cut=10.0))
+    for k, (P, T) in enumerate(pts):
+        assert int(tiers[k].sum()) == int(tot[k])
+        ref = _tiers_fp64(L, grid, P, T, W.mass_amu, 10.0)
+        assert int(ref.sum()) == int(tot[k])
+        # the kernel classifies with FP32 r^2: only pairs right at a threshold may differ
+        diff = np.abs(tiers[k].astype(np.int64) - ref)
+        print(f"[tiers] P={P} T={T} {tiers[k].tolist()} ref {ref.tolist()}", flush=True)
+        assert np.all(diff <= 2 + 1e-5 * ref.sum()), (P, T, tiers[k], ref)
+    ctx.unload_lines(h)
+    ctx.free_grid(g)
+
+
 def _small_list(n, lo, hi, seed):
     return synth.make_lines(synth.ListSpec(n, lo, hi, seed))
 
