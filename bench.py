@@ -261,10 +261,9 @@ def main():
         log(f"launch shapes: {tuned}")
         if args.save_tune:
             xsec.tune_cache_save(args.save_tune)
-    tiers = ctx.count_evals_by_tier(h, g, [(P, T)], o32)[0].astype(np.float64)
-    evals = int(ctx.count_evals(h, g, [(P, T)], o32)[0])
-    if int(tiers.sum()) != evals:
-        raise SystemExit(f"tier counts {tiers.sum()} do not add up to {evals}")
+    tiers = ctx.count_evals_by_tier(h, g, [(P, T)], o32)[0]
+    evals = int(tiers.sum())
+    tiers = tiers.astype(np.float64)
     flops_per_eval = float(tiers @ np.array(FLOPS_BY_TIER)) / evals + KAHAN_FLOPS_PER_EVAL
     eval_mix = {n: float(c / evals) for n, c in zip(xsec.EVAL_TIERS, tiers)}
     log(f"evaluation tiers: {eval_mix}; {flops_per_eval:.3f} algorithmic FLOPs per eval")
