@@ -134,8 +134,10 @@ typedef struct { double P_bar, T_K; } xs_pt;
  * min(cap, fwhm_mult * f_V) (XS_CUT_MIN_FWHM). Launch shape (each 0 = autotuned):
  * pts_per_lane (1, 2, 4 or 8) sets the grid tile of one wavefront to 64 * pts_per_lane
  * points; split (1..256) divides each tile's line window into that many independent work
- * items whose partial sums are added in a fixed order; waves_per_simd (2..6) is the
- * occupancy the tile kernel is compiled for. The result does not depend on the launch
+ * items whose partial sums are added in a fixed order; waves_per_simd is the
+ * occupancy the tile kernel is compiled for: 3..6 waves per SIMD, 2 the compiler's own
+ * choice, 0 automatic (the tuned value, else 6 on the FP32 path with 1 or 2 points per
+ * lane and the compiler's choice otherwise). The result does not depend on the launch
  * shape beyond FP32 rounding (bitwise for a fixed shape). */
 typedef struct {
   int cutoff_kind;
@@ -268,7 +270,7 @@ int xs_sched_simulate(size_t n, const double *arrive, const double *duration,
  * uses the cached shape of its class (results then follow that shape, so they agree with
  * untuned runs to FP32 rounding, and bitwise among runs with the same cache). */
 typedef struct {
-  int pts_per_lane, split, waves_per_simd;  /* the tuned shape for this workload        */
+  int pts_per_lane, split, waves_per_simd;  /* the tuned shape (waves_per_simd 2..6)    */
   int items_per_slot;                       /* the cached class parameter               */
   double probe_ms;                          /* probe time of the tuned shape            */
   double default_probe_ms;                  /* probe time of the untuned default        */
@@ -280,7 +282,8 @@ int xs_autotune(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts,
 /* The class key of a workload (as xs_autotune stores it). */
 int xs_tune_key(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, size_t npts,
                 const xs_opts *opts, char *key_out, size_t key_len);
-/* The process-wide cache (host only): read/write one entry, clear, and JSON persistence.
+/* The process-wide cache (host only): read/write one entry (waves_per_simd 2..6, as in
+ * xs_opts), clear, and JSON persistence.
  * xs_tune_cache_load merges the file's entries (XS_ENOTFOUND: no such file, XS_EINVAL:
  * malformed); xs_tune_cache_save writes every entry. xs_tune_cache_get returns
  * XS_ENOTFOUND for a key not cached. */

@@ -157,14 +157,15 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
                size_t cap_bytes, int64_t max_item_lines, int items_per_slot) {
   Plan p;
   p.P = o.pts_per_lane ? o.pts_per_lane : 2;
-  p.W = o.waves_per_simd == 2 ? 0 : o.waves_per_simd;
+  const bool f64 = o.precision == XS_FP64;
+  p.W = waves_target(o.waves_per_simd, p.P, f64);
   int ips = items_per_slot > 0 ? items_per_slot : 4;
   if (o.pts_per_lane == 0 && o.split == 0 && o.waves_per_simd == 0) {
     // fully automatic launch shape: the tuned one of this workload class, if any
     TuneVal tv;
     if (tune_get(tune_key(c, L, G, npts, o), &tv)) {
       p.P = tv.P;
-      p.W = tv.W;
+      p.W = waves_target(tv.W, tv.P, f64);
       ips = tv.ips;
       p.tuned = true;
     }

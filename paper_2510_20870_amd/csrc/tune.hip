@@ -25,7 +25,7 @@ std::mutex g_tune_mu;
 std::map<std::string, TuneVal> g_tune;
 
 bool valid_val(const TuneVal& v) {
-  return (v.P == 1 || v.P == 2 || v.P == 4 || v.P == 8) && (v.W == 0 || (v.W >= 3 && v.W <= 6)) &&
+  return (v.P == 1 || v.P == 2 || v.P == 4 || v.P == 8) && v.W >= 2 && v.W <= 6 &&
          v.ips >= 1 && v.ips <= 64;
 }
 
@@ -129,7 +129,8 @@ bool parse_cache(const std::string& text, std::map<std::string, TuneVal>* out) {
           if (f == "P" || f == "W" || f == "items_per_slot" || f == "probe_ms") {
             if (!j.num(&x)) return false;
             if (f == "P") v.P = (int)x, hasP = true;
-            if (f == "W") v.W = (int)x, hasW = true;
+            // (0 in files of an earlier version: no occupancy target, the option 2)
+            if (f == "W") v.W = (int)x == 0 ? 2 : (int)x, hasW = true;
             if (f == "items_per_slot") v.ips = (int)x, hasI = true;
             if (f == "probe_ms") v.probe_ms = x;
           } else if (!j.skip()) {
@@ -315,7 +316,11 @@ int xs_autotune(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t
   if (rc) return rc;
 
   // probe blocks: about 4e10 line-point visits in total (a few tens of ms), in up to
-  // three blocks of whole 512-point units at 1/6, 1/2 and 5/6 of the grid
+  // three blocks of whole 512-point units at 1/6, 1/2 and 5/6 of the grid; each block
+  // (timed by a launch of its own) at least large enough that the widest tiles (4 x 64
+  // points) fill one round of wavefront slots with a split of at most 16, so that no
+  // candidate is timed on a starved device or with a split far from the one the whole
+  // workload gets
   const double mid = G->host[G->n / 2];
   const std::vector<double>& sm = L->sample;
   const double dens =
@@ -325,7 +330,8 @@ int xs_autotune(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t
       (double)kSampleStride;
   const int64_t n = (int64_t)G->n;
   int64_t want = (int64_t)std::min(4e10 / (dens * nprobe), 9e15);
-  want = std::max<int64_t>(want, 3 * 512);
+  const int64_t min_tiles = ((int64_t)c->n_cu * 28 + 16 * nprobe - 1) / (16 * nprobe);
+  want = std::max<int64_t>(want, 3 * std::max<int64_t>(min_tiles * 4 * kWave, 512));
   std::vector<Block> blocks;
   if (2 * want >= n) {
     blocks.push_back({0, n, 0, 0});
@@ -350,52 +356,53 @@ int xs_autotune(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t
     for (hipEvent_t ev : tm.ev) (void)hipEventDestroy(ev);
   };
   struct Cand {
-    int P, ips, W;
+    int P, ips, W;   // W: option value (2..6)
     double ms;
   };
-  auto run = [&](int P, int ips, int W, double* ms) -> int {
+  // times (P, ips) with occupancy option W (0: the automatic one) and records it
+  std::vector<Cand> tried;
+  auto run = [&](int P, int ips, int W) -> int {
     xs_opts o = *opts;
     o.pts_per_lane = P;
     o.split = 0;
     o.waves_per_simd = W;
     const Plan full = make_plan(*c, *L, *G, npts, o, 0, 0, ips);
-    return time_candidate(*c, *L, *G, o, blocks, nprobe, full, tm, ms);
+    double ms = 0.0;
+    const int r = time_candidate(*c, *L, *G, o, blocks, nprobe, full, tm, &ms);
+    if (r == XS_OK) tried.push_back({P, ips, waves_option(full.W), ms});
+    return r;
   };
-  std::vector<Cand> tried;
-  double def_ms = 0.0;
-  rc = run(2, 4, 0, &def_ms);   // the untuned default
+  rc = run(2, 4, 0);   // the untuned default
   if (rc) {
     cleanup();
     return rc;
   }
-  tried.push_back({2, 4, 0, def_ms});
+  const double def_ms = tried.front().ms;
   for (int P : {1, 2, 4})
     for (int ips : {1, 2, 4, 8, 16}) {
       if (P == 2 && ips == 4) continue;
-      double ms = 0.0;
-      rc = run(P, ips, 0, &ms);
+      rc = run(P, ips, 0);
       if (rc) {
         cleanup();
         return rc;
       }
-      tried.push_back({P, ips, 0, ms});
     }
-  // occupancy targets for the two fastest (P, items per slot)
+  // the other occupancy options for the two fastest (P, items per slot)
   std::vector<Cand> top = tried;
   std::sort(top.begin(), top.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
   top.resize(std::min<size_t>(2, top.size()));
-  Cand best = top.front();
   for (const Cand& t : top)
-    for (int W : {3, 4, 5, 6}) {
-      double ms = 0.0;
-      rc = run(t.P, t.ips, W, &ms);
+    for (int W : {2, 3, 4, 5, 6}) {
+      if (W == t.W) continue;
+      rc = run(t.P, t.ips, W);
       if (rc) {
         cleanup();
         return rc;
       }
-      tried.push_back({t.P, t.ips, W, ms});
-      if (ms < best.ms) best = tried.back();
     }
+  Cand best = tried.front();
+  for (const Cand& t : tried)
+    if (t.ms < best.ms) best = t;
   // keep the default unless a shape is clearly faster (probe timings vary by ~2 %)
   if (best.ms > 0.97 * def_ms) best = tried.front();
   cleanup();
@@ -416,7 +423,7 @@ int xs_autotune(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t
   memset(out, 0, sizeof *out);
   out->pts_per_lane = p.P;
   out->split = p.split;
-  out->waves_per_simd = p.W;
+  out->waves_per_simd = waves_option(p.W);
   out->items_per_slot = v.ips;
   out->probe_ms = best.ms;
   out->default_probe_ms = def_ms;

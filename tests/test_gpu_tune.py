@@ -40,7 +40,7 @@ def test_autotune_mid_sized_and_reuse(ctx, tmp_path):
     res = ctx.autotune(h, g, pts, auto)
     print("[tune]", res, flush=True)
     assert res["pts_per_lane"] in (1, 2, 4, 8)
-    assert res["waves_per_simd"] in (0, 3, 4, 5, 6)
+    assert res["waves_per_simd"] in (2, 3, 4, 5, 6)
     assert 1 <= res["split"] <= 256
     assert res["candidates"] >= 16
     assert res["probe_ms"] <= res["default_probe_ms"]

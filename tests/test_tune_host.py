@@ -20,20 +20,21 @@ def test_put_get_and_validation():
     assert xsec.tune_cache_get("k") is None
     xsec.tune_cache_put("k", 4, 3, 8, 1.5)
     assert xsec.tune_cache_get("k") == (4, 3, 8, 1.5)
-    xsec.tune_cache_put("k", 1, 0, 1)
-    assert xsec.tune_cache_get("k")[:3] == (1, 0, 1)
+    xsec.tune_cache_put("k", 1, 2, 1)
+    assert xsec.tune_cache_get("k")[:3] == (1, 2, 1)
     assert xsec.tune_cache_size() == 1
-    for bad in ((3, 0, 4), (2, 2, 4), (2, 0, 0), (2, 0, 65), (16, 0, 4)):
+    # occupancy options 2..6 (0, automatic, is not a shape)
+    for bad in ((3, 2, 4), (2, 0, 4), (2, 7, 4), (2, 2, 0), (2, 2, 65), (16, 2, 4)):
         with pytest.raises(xsec.XsError) as e:
             xsec.tune_cache_put("x", *bad)
         assert e.value.code == xsec.XS_EINVAL
     with pytest.raises(xsec.XsError):
-        xsec.tune_cache_put("", 2, 0, 4)
+        xsec.tune_cache_put("", 2, 2, 4)
     assert xsec.tune_cache_size() == 1
 
 
 def test_save_load_roundtrip(tmp_path):
-    keys = {'gfx950:sramecc+:xnack-|cu256|fp32|fixed|d16|p1': (2, 0, 4, 12.5),
+    keys = {'gfx950:sramecc+:xnack-|cu256|fp32|fixed|d16|p1': (2, 6, 4, 12.5),
             'gfx950|cu256|fp64|fwhm|d20|pmany': (8, 4, 16, 0.25),
             'odd "quoted" \\ key': (1, 3, 2, 3.0)}
     for k, v in keys.items():
@@ -49,8 +50,8 @@ def test_save_load_roundtrip(tmp_path):
     for k, v in keys.items():
         assert xsec.tune_cache_get(k) == v
     # loading merges: existing entries not in the file stay, file entries win
-    xsec.tune_cache_put("extra", 2, 0, 4)
-    xsec.tune_cache_put('gfx950|cu256|fp64|fwhm|d20|pmany', 1, 0, 1)
+    xsec.tune_cache_put("extra", 2, 2, 4)
+    xsec.tune_cache_put('gfx950|cu256|fp64|fwhm|d20|pmany', 1, 2, 1)
     xsec.tune_cache_load(str(f))
     assert xsec.tune_cache_get("extra") is not None
     assert xsec.tune_cache_get('gfx950|cu256|fp64|fwhm|d20|pmany') == (8, 4, 16, 0.25)
@@ -62,7 +63,8 @@ def test_load_accepts_extra_fields(tmp_path):
                              "entries": {"k": {"P": 4, "W": 0, "items_per_slot": 2,
                                                "probe_ms": 1.0, "comment": "x"}}}))
     xsec.tune_cache_load(str(f))
-    assert xsec.tune_cache_get("k") == (4, 0, 2, 1.0)
+    # W 0 (no occupancy target, as files of an earlier version wrote it) is the option 2
+    assert xsec.tune_cache_get("k") == (4, 2, 2, 1.0)
 
 
 @pytest.mark.parametrize("text", [
