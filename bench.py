@@ -205,6 +205,9 @@ def main():
                     help="requests per offered load in the serving measurement (0 = skip)")
     ap.add_argument("--serving-loads", default="0.8",
                     help="offered loads, fractions of the measured saturation rate")
+    ap.add_argument("--select-eps", default="1e-4,1e-5",
+                    help="main-contributor selection tolerances timed beside the full sum "
+                         "(comma-separated; empty: none)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the plain-copy calibration kernel (for HBM counters)")
     args = ap.parse_args()
@@ -312,6 +315,25 @@ def main():
                 "kernel_ms": k64, "steps": steps64, "fp32_speedup": value / v64}
         log(f"fp64 path: {wall64 / steps64 * 1e3:.3f} ms/step, {v64:.4e} evals/s")
 
+    # main-contributor selection: the same workload with lines dropped within eps (not the
+    # headline: fewer evaluations are done); drop against the full FP32 sum, kept share
+    selection = []
+    for eps in [float(v) for v in args.select_eps.split(",") if v.strip()]:
+        o_sel = ctx.opts(kind, W.cut_cm1, W.fwhm_mult, xsec.XS_FP32_KAHAN, args.pts_per_lane,
+                         args.split, args.waves_per_simd, eps)
+        wall_s, k_s, _ = run(o_sel, args.steps, args.warmup)
+        sig_s = out.cpu().numpy()[0].copy()
+        kept = int(ctx.count_evals(h, g, [(P, T)], o_sel)[0])
+        ms_s = wall_s / args.steps * 1e3
+        drop = (sig32 - sig_s) / sig32
+        selection.append({"eps": eps, "ms_per_step": ms_s, "tile_kernel_ms": k_s,
+                          "speedup_vs_full": ms / ms_s, "kept_evals_frac": kept / evals,
+                          "equivalent_evals_per_s": evals / (ms_s * 1e-3),
+                          "max_drop_vs_full": float(drop.max()),
+                          "min_drop_vs_full": float(drop.min()), "_sig": sig_s})
+        log(f"selection eps {eps:g}: {ms_s:.3f} ms/step ({ms / ms_s:.2f}x), kept "
+            f"{kept / evals:.3f} of the evaluations, max drop {drop.max():.3e}")
+
     # oracle on a bounded sample: 16 windows of contiguous points
     cpu = None
     max_rel = None
@@ -339,6 +361,13 @@ def main():
             f"parity max_rel {st['max_rel']:.3e} violations {st['violations']}")
         if st["violations"]:
             log("PARITY VIOLATIONS", st)
+        for sel in selection:
+            ss = O.compare(sel["_sig"][idx], ref, rel_tol=sel["eps"] + 1e-5,
+                           ref_max=float(sig32.max()))
+            sel["max_rel_vs_oracle"] = ss["max_rel"]
+            sel["oracle_violations"] = ss["violations"]
+    for sel in selection:
+        del sel["_sig"]
 
     serving = None
     if args.serving_requests > 0:
@@ -384,6 +413,7 @@ def main():
                      "hbm_frac": (traffic / (k32 * 1e-3) / 1e9 / PEAK_HBM_GBS
                                   if traffic else None)},
         "fp64_path": fp64,
+        "selection": selection,
         "serving": serving,
         "cpu_baseline": cpu,
     }

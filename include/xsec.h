@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define XS_ABI_VERSION 1
+#define XS_ABI_VERSION 2
 
 typedef enum {
   XS_OK = 0,
@@ -138,7 +138,13 @@ typedef struct { double P_bar, T_K; } xs_pt;
  * occupancy the tile kernel is compiled for: 3..6 waves per SIMD, 2 the compiler's own
  * choice, 0 automatic (the tuned value, else 6 on the FP32 path with 1 or 2 points per
  * lane and the compiler's choice otherwise). The result does not depend on the launch
- * shape beyond FP32 rounding (bitwise for a fixed shape). */
+ * shape beyond FP32 rounding (bitwise for a fixed shape).
+ * select_eps > 0 turns on main-contributor selection (named in "Functionality of pyROX"
+ * as a way to speed up the profile computation; the paper does not define it): per tile of
+ * the grid and (P, T) point, lines are dropped when the sum of their contributions' upper
+ * bounds over the tile stays within select_eps times a lower bound of sigma over the tile,
+ * so that sigma changes by at most select_eps * sigma at every point (plus the FP32
+ * rounding of the kept lines); 0 computes every line. Must be in [0, 1). */
 typedef struct {
   int cutoff_kind;
   double cut_cm1;
@@ -147,6 +153,7 @@ typedef struct {
   int pts_per_lane;
   int split;
   int waves_per_simd;
+  double select_eps;
 } xs_opts;
 
 /* sigma(nu_j; P_k, T_k) for k < npts on every point of `grid`, written to
@@ -324,6 +331,13 @@ int xs_eval_voigt_host(const double *x, const double *y, size_t n, int precision
  * Points with x^2 + y^2 < 49 or y <= 0 give XS_EINVAL. */
 int xs_eval_series_host(const double *x, const double *y, size_t n, int variant,
                         double *K_out, int *variant_out);
+
+/* The bounds of K(x, y) that main-contributor selection uses (FP64, compiled for the
+ * host): K_lo = erf(2) (y / sqrt(pi)) / ((|x| + 2)^2 + y^2) <= K, and K <= K_hi = 1, or
+ * for x^2 + y^2 >= 49 the shifted Lorentzian widened by twice its error bound. Either
+ * output may be NULL; y must be > 0 (XS_EINVAL otherwise). */
+int xs_eval_bounds_host(const double *x, const double *y, size_t n, double *K_lo,
+                        double *K_hi);
 
 #ifdef __cplusplus
 }

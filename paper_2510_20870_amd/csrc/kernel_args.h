@@ -57,6 +57,11 @@ struct TileArgs {
   double* out;            // split == 1: sigma rows [n_pts][n_grid] (row pt0 + k);
                           // else partials [n_pt][split][n_grid] of this batch
   unsigned long long* counts;  // count kernel only: [n_pts][kNEvalTiers]
+  // main-contributor selection (nullptr: off): per (P, T) point of the batch and tile,
+  // the contribution bound below which a line is dropped, [n_pt][tau_stride]
+  double* tau;
+  int64_t tau_stride;     // tiles of the whole grid
+  double select_eps;      // select kernel: the allowed relative error
 };
 
 // Launchers (kernels.hip). phys_wg = number of workgroups launched: n_wg rounded up to a
@@ -66,6 +71,8 @@ hipError_t launch_params(const ParamArgs& A, hipStream_t st);
 hipError_t launch_tile(const TileArgs& A, int P, bool f64, int W, hipStream_t st,
                        int64_t phys_wg);
 hipError_t launch_count(const TileArgs& A, int P, hipStream_t st, int64_t phys_wg);
+// one wavefront per (tile position, P-T point) of A: writes A.tau
+hipError_t launch_select(const TileArgs& A, int P, hipStream_t st);
 // per points-per-lane instantiations of the tile kernel (tile_p*.hip)
 hipError_t launch_tile_p1(const TileArgs& A, bool f64, int W, hipStream_t st, dim3 grid);
 hipError_t launch_tile_p2(const TileArgs& A, bool f64, int W, hipStream_t st, dim3 grid);

@@ -97,6 +97,9 @@ __global__ __launch_bounds__(kBlock) void xs_count_kernel(TileArgs A) {
     const int64_t j = it.j0 + kWave * p + lane;
     nu[p] = (j < A.n_grid) ? A.grid[j] : __builtin_nan("");
   }
+  // with main-contributor selection, only the kept lines count
+  const double tau = A.tau ? A.tau[(int64_t)it.k * A.tau_stride + it.tile] : 0.0;
+  const double t_first = A.grid[it.j0], t_last = it.nu_last;
   unsigned long long cnt[kNEvalTiers];
 #pragma unroll
   for (int t = 0; t < kNEvalTiers; ++t) cnt[t] = 0;
@@ -106,7 +109,7 @@ __global__ __launch_bounds__(kBlock) void xs_count_kernel(TileArgs A) {
     if (i < it.e) {
       const LineRec lr = A.recs[(int64_t)it.k * A.rec_n + (i - A.rec_lo)];
       c0 = A.L.nu0[i];
-      ct = lr.cut;
+      ct = (tau > 0.0 && contrib_upper(c0, lr, t_first, t_last) < tau) ? -1.0 : lr.cut;
       ib = lr.ib;
       yv = lr.y;
     }
@@ -142,6 +145,70 @@ __global__ __launch_bounds__(kBlock) void xs_count_kernel(TileArgs A) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     if (lane == 0 && v) atomicAdd(A.counts + (int64_t)(A.pt0 + it.k) * kNEvalTiers + t, v);
   }
+}
+
+// Main-contributor selection (the paper names it as a way to speed up the line-profile
+// computation, "Functionality of pyROX", without defining it). For one tile and (P, T)
+// point: a lower bound of sigma at every point of the tile, L = sum of the lines' lower
+// bounds (contrib_lower), and the largest power-of-two threshold tau such that the upper
+// bounds (contrib_upper) of all lines below tau add up to at most eps L. Dropping those
+// lines changes sigma by at most eps sigma at every point of the tile. The bounds are
+// binned by binary exponent into an exact integer histogram (fixed point, rounded up), so
+// tau does not depend on the order of the additions.
+template <int P>
+__global__ __launch_bounds__(kBlock) void xs_select_kernel(TileArgs A) {
+  __shared__ unsigned long long hist[kWavesPerWG][kWave];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(wv);
+  const int64_t item = (int64_t)blockIdx.x * kWavesPerWG + wave;
+  if (item >= A.n_tiles * A.n_pt) return;
+  const int k = (int)(item % A.n_pt);
+  const int64_t pos = item / A.n_pt;
+  const int64_t tile = A.tile_order ? (int64_t)A.tile_order[pos] : pos;
+  const int64_t j0 = tile * (int64_t)(kWave * P);
+  const int64_t jl = min(j0 + (int64_t)(kWave * P), A.n_grid) - 1;
+  const double t_first = A.grid[j0], t_last = A.grid[jl];
+  int64_t lo, hi;
+  line_window(A, k, t_first, t_last, lane, &lo, &hi);
+  const LineRec* rec = A.recs + (int64_t)k * A.rec_n - A.rec_lo;
+  double acc = 0.0;
+  for (int64_t i = lo + lane; i < hi; i += kWave)
+    acc += contrib_lower(A.L.nu0[i], rec[i], t_first, t_last);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  double tau = 0.0;
+  if (acc > 0.0) {
+    // bins: 0 for bounds below 2^elo, 1 + ilogb - elo for [2^elo, 2^eL), eL = ilogb(eps L)
+    const double budget = A.select_eps * acc;
+    const int eL = ilogb(budget);
+    const int elo = eL - 62;
+    const double top = ldexp(1.0, eL), low = ldexp(1.0, elo);
+    const double unit = ldexp(1.0, 40) / budget;   // histogram units per unit of sigma
+    hist[wv][lane] = 0ull;
+    wave_sync();
+    for (int64_t i = lo + lane; i < hi; i += kWave) {
+      const double c = contrib_upper(A.L.nu0[i], rec[i], t_first, t_last);
+      if (c < top) {
+        const int bin = c < low ? 0 : ilogb(c) - elo + 1;
+        atomicAdd(&hist[wv][bin], (unsigned long long)(c * unit) + 1ull);
+      }
+    }
+    wave_sync();
+    // the bins below b stay within the budget (2^40 units) for b = 0 .. b*: an exclusive
+    // prefix sum over the bins, one bin per lane
+    const unsigned long long h = hist[wv][lane];
+    unsigned long long incl = h;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const unsigned long long u = __shfl_up(incl, o, kWave);
+      if (lane >= o) incl += u;
+    }
+    const bool ok = incl - h <= (1ull << 40);
+    const int bstar = __popcll(__ballot(ok)) - 1;
+    tau = bstar == 0 ? 0.0 : ldexp(1.0, elo + bstar - 1);
+  }
+  if (lane == 0) A.tau[(int64_t)k * A.tau_stride + tile] = tau;
 }
 
 __global__ void xs_fill_u64_kernel(unsigned long long* p, int64_t n) {
@@ -190,6 +257,20 @@ hipError_t launch_count(const TileArgs& A, int P, hipStream_t st, int64_t phys_w
     case 2: hipLaunchKernelGGL((xs_count_kernel<2>), grid, block, 0, st, A); break;
     case 4: hipLaunchKernelGGL((xs_count_kernel<4>), grid, block, 0, st, A); break;
     case 8: hipLaunchKernelGGL((xs_count_kernel<8>), grid, block, 0, st, A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const TileArgs& A, int P, hipStream_t st) {
+  const int64_t waves = A.n_tiles * A.n_pt;
+  if (waves <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((waves + kWavesPerWG - 1) / kWavesPerWG)), block(kBlock);
+  switch (P) {
+    case 1: hipLaunchKernelGGL((xs_select_kernel<1>), grid, block, 0, st, A); break;
+    case 2: hipLaunchKernelGGL((xs_select_kernel<2>), grid, block, 0, st, A); break;
+    case 4: hipLaunchKernelGGL((xs_select_kernel<4>), grid, block, 0, st, A); break;
+    case 8: hipLaunchKernelGGL((xs_select_kernel<8>), grid, block, 0, st, A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

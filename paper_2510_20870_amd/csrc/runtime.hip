@@ -114,6 +114,8 @@ int validate_opts(const xs_opts* o) {
     return fail(XS_EINVAL, "split must be in [0, %d] (got %d)", kMaxSplit, o->split);
   if (o->waves_per_simd != 0 && (o->waves_per_simd < 2 || o->waves_per_simd > 6))
     return fail(XS_EINVAL, "waves_per_simd must be 0 or 2..6 (got %d)", o->waves_per_simd);
+  if (!(o->select_eps >= 0.0 && o->select_eps < 1.0))
+    return fail(XS_EINVAL, "select_eps must be in [0, 1) (got %g)", o->select_eps);
   return XS_OK;
 }
 
@@ -157,6 +159,7 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
                size_t cap_bytes, int64_t max_item_lines, int items_per_slot) {
   Plan p;
   p.P = o.pts_per_lane ? o.pts_per_lane : 2;
+  p.select_eps = o.select_eps;
   const bool f64 = o.precision == XS_FP64;
   p.W = waves_target(o.waves_per_simd, p.P, f64);
   int ips = items_per_slot > 0 ? items_per_slot : 4;
@@ -215,7 +218,8 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
     cap = std::min<size_t>((size_t)16 << 30, free_b / 4);
   }
   const size_t per_pt = std::max<size_t>(
-      1, (size_t)p.rec_n * 32 + (p.split > 1 ? (size_t)p.split * G.n * 8 : 0));
+      1, (size_t)p.rec_n * 32 + (p.split > 1 ? (size_t)p.split * G.n * 8 : 0) +
+             (p.select_eps > 0.0 ? (size_t)p.n_tiles * 8 : 0));
   p.pt_batch = (int)std::max<size_t>(1, std::min<size_t>(npts, cap / per_pt));
   // issue order: tiles by decreasing number of lines within the largest cut, so the most
   // expensive work items start first
@@ -305,6 +309,15 @@ int enqueue_step(const LinesRes& L, const GridRes& G, const xs_opts& o, const Pl
     A.recs = (const LineRec*)rec_dev;
     A.rec_lo = p.rec_lo;
     A.rec_n = p.rec_n;
+    if (p.select_eps > 0.0) {
+      // main-contributor selection: the thresholds of these tiles, then the kernels drop
+      // the lines below them
+      A.tau = (double*)((char*)rec_dev + p.tau_offset());
+      A.tau_stride = p.n_tiles;
+      A.select_eps = p.select_eps;
+      e = launch_select(A, p.P, st);
+      if (e != hipSuccess) return hip_fail(e, "select kernel launch");
+    }
     const int64_t phys = phys_workgroups(A.n_wg);
     int rc = tm ? tm->record(st) : XS_OK;
     if (rc) return rc;
@@ -979,6 +992,17 @@ int xs_eval_voigt_host(const double* x, const double* y, size_t n, int precision
   for (size_t i = 0; i < n; ++i)
     K_out[i] = precision == XS_FP64 ? voigt_k64(x[i], y[i])
                                     : (double)voigt_k32(x[i], (float)y[i]);
+  return XS_OK;
+}
+
+int xs_eval_bounds_host(const double* x, const double* y, size_t n, double* K_lo,
+                        double* K_hi) {
+  if (n && (!x || !y)) return fail(XS_EINVAL, "NULL argument");
+  for (size_t i = 0; i < n; ++i) {
+    if (!(y[i] > 0.0)) return fail(XS_EINVAL, "point %zu: y must be > 0 (got %g)", i, y[i]);
+    if (K_lo) K_lo[i] = voigt_lower(x[i], y[i]);
+    if (K_hi) K_hi[i] = voigt_upper(x[i], y[i]);
+  }
   return XS_OK;
 }
 

@@ -56,7 +56,13 @@ struct Plan {
   std::vector<int> tile_order;   // tiles by decreasing estimated work
   std::vector<int64_t> tile_cost;  // sampled line count in each tile's window (x 1024)
   bool tuned = false;              // launch shape from the tuning cache
-  size_t rec_bytes() const { return (size_t)rec_n * pt_batch * 32; }
+  double select_eps = 0.0;         // main-contributor selection (0: off)
+  // line records [pt_batch][rec_n] (32 B), then with selection the tiles' thresholds
+  // [pt_batch][n_tiles] (8 B)
+  size_t tau_offset() const { return (size_t)rec_n * pt_batch * 32; }
+  size_t rec_bytes() const {
+    return tau_offset() + (select_eps > 0.0 ? (size_t)pt_batch * n_tiles * 8 : 0);
+  }
   size_t part_bytes(size_t n_grid) const {
     return split > 1 ? (size_t)pt_batch * split * n_grid * sizeof(double) : 0;
   }

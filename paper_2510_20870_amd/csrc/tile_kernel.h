@@ -115,10 +115,46 @@ __device__ int64_t wave_search(const double* __restrict__ a, int64_t n, double k
 
 struct ItemInfo {
   int64_t j0;        // first grid index of the tile
+  int64_t tile;      // the tile
+  double nu_last;    // the tile's last grid value
   int k;             // (P, T) index within the batch
   int s;             // split index
   int64_t b, e;      // line range of this item (global line indices)
 };
+
+// Lines [lo, hi) whose cut can reach the grid range [nu_first, nu_last] at (P, T) point k
+// of the batch: two 64-ary wave searches with the range's widest possible cut.
+__device__ __forceinline__ void line_window(const TileArgs& A, int k, double nu_first,
+                                           double nu_last, int lane, int64_t* lo,
+                                           int64_t* hi) {
+  const int pt = A.pt0 + k;
+  const PtConst pc = make_pt(A.sp, A.pts[2 * pt], A.pts[2 * pt + 1]);
+  const double cb = cut_bound(A.sp, pc, A.cut, nu_last);
+  // widen the keys by a few ulps of nu so that rounding of nu -+ cb never drops a line
+  const double lk = nu_first - cb - fabs(nu_first) * 0x1p-48;
+  const double hk = nu_last + cb + fabs(nu_last) * 0x1p-48;
+  // search inside the record range only (the host sized it to cover every tile)
+  const double* base = A.L.nu0 + A.rec_lo;
+  *lo = A.rec_lo + wave_search<false>(base, A.rec_n, lk, lane);
+  *hi = A.rec_lo + wave_search<true>(base, A.rec_n, hk, lane);
+}
+
+// Main-contributor selection: bounds of line i's contribution over the tile
+// [t_first, t_last] (FP64). Upper: at the tile's point nearest to the line (zero when that
+// point is outside the cut). Lower: at the farthest point, zero unless every point of the
+// tile is inside the cut (K falls with |x|, so the nearest and farthest points bound it).
+__device__ __forceinline__ double contrib_upper(double nu0, const LineRec& lr,
+                                                double t_first, double t_last) {
+  const double d = nu0 < t_first ? t_first - nu0 : nu0 > t_last ? nu0 - t_last : 0.0;
+  if (d > lr.cut) return 0.0;
+  return lr.sc * voigt_upper(d * lr.ib, lr.y);
+}
+__device__ __forceinline__ double contrib_lower(double nu0, const LineRec& lr,
+                                                double t_first, double t_last) {
+  const double d = fmax(fabs(t_first - nu0), fabs(t_last - nu0));
+  if (d > lr.cut) return 0.0;
+  return lr.sc * voigt_lower(d * lr.ib, lr.y);
+}
 
 template <int P>
 __device__ __forceinline__ bool decode_item(const TileArgs& A, int lane, ItemInfo& it) {
@@ -135,18 +171,10 @@ __device__ __forceinline__ bool decode_item(const TileArgs& A, int lane, ItemInf
   const int64_t tile = A.tile_order ? (int64_t)A.tile_order[r / A.n_pt] : r / A.n_pt;
   it.j0 = tile * (int64_t)(kWave * P);
   const int64_t jl = min(it.j0 + (int64_t)(kWave * P), A.n_grid) - 1;
-  const int pt = A.pt0 + it.k;
-  const PtConst pc = make_pt(A.sp, A.pts[2 * pt], A.pts[2 * pt + 1]);
-  const double nu_first = A.grid[it.j0];
-  const double nu_last = A.grid[jl];
-  const double cb = cut_bound(A.sp, pc, A.cut, nu_last);
-  // widen the keys by a few ulps of nu so that rounding of nu -+ cb never drops a line
-  const double lk = nu_first - cb - fabs(nu_first) * 0x1p-48;
-  const double hk = nu_last + cb + fabs(nu_last) * 0x1p-48;
-  // search inside the record range only (the host sized it to cover every tile)
-  const double* base = A.L.nu0 + A.rec_lo;
-  const int64_t lo = A.rec_lo + wave_search<false>(base, A.rec_n, lk, lane);
-  const int64_t hi = A.rec_lo + wave_search<true>(base, A.rec_n, hk, lane);
+  it.tile = tile;
+  it.nu_last = A.grid[jl];
+  int64_t lo, hi;
+  line_window(A, it.k, A.grid[it.j0], it.nu_last, lane, &lo, &hi);
   const int64_t cnt = hi > lo ? hi - lo : 0;
   it.b = lo + cnt * it.s / A.split;
   it.e = lo + cnt * (it.s + 1) / A.split;
@@ -402,6 +430,9 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   const int wv = threadIdx.x >> 6;
   ItemInfo it;
   if (!decode_item<P>(A, lane, it)) return;
+  // main-contributor selection: the tile's drop threshold (0: every line is kept)
+  const double tau = A.tau ? A.tau[(int64_t)it.k * A.tau_stride + it.tile] : 0.0;
+  const double t_first = A.grid[it.j0], t_last = it.nu_last;
 
   Rows<P> rows;
   double nu[P];
@@ -599,7 +630,13 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     Rec<F64, P> r;
     double sc64 = 0.0;
     int mode = kSkip, npairs = 0;
-    if (i < it.e) {
+    // main-contributor selection: a line whose bound over the tile is below tau is dropped
+    bool keep = i < it.e;
+    if (tau > 0.0 && keep) {
+      const LineRec lr = A.recs[(int64_t)it.k * A.rec_n + (i - A.rec_lo)];
+      keep = contrib_upper(A.L.nu0[i], lr, t_first, t_last) >= tau;
+    }
+    if (keep) {
       r = stage_line<F64, P>(A, it.k, rows, rowvals[wv], i, &sc64, &mode, &npairs, false);
     } else {
       r.cls = 0;

@@ -170,9 +170,10 @@ std::string tune_key(const Ctx& c, const LinesRes& L, const GridRes& G, size_t n
   const int dens = (int)lround(log2(((double)k + 0.5) * (double)kSampleStride));
   const char* pc = npts == 1 ? "p1" : npts <= 16 ? "p16" : "pmany";
   char buf[192];
-  snprintf(buf, sizeof buf, "%s|cu%d|%s|%s|d%d|%s", c.arch.c_str(), c.n_cu,
+  snprintf(buf, sizeof buf, "%s|cu%d|%s|%s|d%d|%s%s", c.arch.c_str(), c.n_cu,
            o.precision == XS_FP64 ? "fp64" : "fp32",
-           o.cutoff_kind == XS_CUT_FIXED ? "fixed" : "fwhm", dens, pc);
+           o.cutoff_kind == XS_CUT_FIXED ? "fixed" : "fwhm", dens, pc,
+           o.select_eps > 0.0 ? "|sel" : "");
   return buf;
 }
 

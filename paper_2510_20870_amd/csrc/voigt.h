@@ -233,6 +233,24 @@ XS_HD float voigt_k32(double xd, float y) {
   return (float)voigt_core64_tier(core_tier((double)y), xd, (double)y);
 }
 
+// Bounds of K for main-contributor selection (FP64, any x, y > 0):
+//  lower: the part |t| <= 2 of the convolution integral K = (y/pi) int e^{-t^2} /
+//    ((x - t)^2 + y^2) dt alone gives K >= erf(2) (y/sqrt(pi)) / ((|x| + 2)^2 + y^2);
+//  upper: K <= K(0, y) = erfcx(y) <= 1, and for r^2 >= 49 the shifted Lorentzian widened
+//    by twice its error bound (3/2 + 2 y^2) / r^4 (plus 1e-6).
+constexpr double kErf2 = 0.99532226501895273416;
+XS_HD double voigt_lower(double x, double y) {
+  const double a = fabs(x) + 2.0;
+  return kErf2 * kInvSqrtPi * y * rcp64(fma(a, a, y * y));
+}
+XS_HD double voigt_upper(double x, double y) {
+  const double r2 = fma(x, x, y * y);
+  if (!(r2 >= 49.0)) return 1.0;
+  const double u = rcp64(r2);
+  const double e = fma(2.0 * y, y, 1.5) * u * u;
+  return fmin(1.0, kInvSqrtPi * y * rcp64(r2 - 1.5) * fma(2.0, e, 1.0 + 1e-6));
+}
+
 XS_HD double voigt_k64(double x, double y) {
   const double r2 = fma(x, x, y * y);
   if (r2 >= kFarR2_64) return voigt_far64(r2, y);

@@ -63,7 +63,7 @@ class Pt(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("cutoff_kind", C.c_int), ("cut_cm1", C.c_double), ("fwhm_mult", C.c_double),
                 ("precision", C.c_int), ("pts_per_lane", C.c_int), ("split", C.c_int),
-                ("waves_per_simd", C.c_int)]
+                ("waves_per_simd", C.c_int), ("select_eps", C.c_double)]
 
 
 class ServeOpts(C.Structure):
@@ -142,6 +142,8 @@ _SIGS = {
                            C.c_int),
     "xs_eval_series_host": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p,
                              C.c_void_p], C.c_int),
+    "xs_eval_bounds_host": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p],
+                            C.c_int),
 }
 
 
@@ -194,6 +196,18 @@ def eval_series_host(x, y, variant: int = -1):
     if rc:
         raise XsError(rc, lib().xs_last_error(None).decode())
     return out, var
+
+
+def eval_bounds_host(x, y):
+    """(K_lo, K_hi): the bounds of K(x, y) used by main-contributor selection."""
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    lo = np.empty_like(x)
+    hi = np.empty_like(x)
+    rc = lib().xs_eval_bounds_host(_ptr(x), _ptr(y), x.size, _ptr(lo), _ptr(hi))
+    if rc:
+        raise XsError(rc, lib().xs_last_error(None).decode())
+    return lo, hi
 
 
 def _dev_ptr(t) -> int:
@@ -400,9 +414,9 @@ class Context:
     @staticmethod
     def opts(cutoff_kind: int = XS_CUT_FIXED, cut_cm1: float = 25.0, fwhm_mult: float = 100.0,
              precision: int = XS_FP32_KAHAN, pts_per_lane: int = 0, split: int = 0,
-             waves_per_simd: int = 0) -> Opts:
+             waves_per_simd: int = 0, select_eps: float = 0.0) -> Opts:
         return Opts(cutoff_kind, cut_cm1, fwhm_mult, precision, pts_per_lane, split,
-                    waves_per_simd)
+                    waves_per_simd, float(select_eps))
 
     @staticmethod
     def _pts(pts) -> C.Array:

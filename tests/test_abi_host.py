@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
     # the binding covers every declared entry point
     assert set(decl) <= set(xsec.exported_symbols())
-    assert L.xs_abi_version() == 1
+    assert L.xs_abi_version() == 2
 
 
 def test_no_compute_without_device_is_a_clean_error():
@@ -137,6 +137,32 @@ def test_series_variants_error_map():
         xs_ = np.sqrt(r2 * np.array([1.001, 0.999]) - yy * yy)
         _, vv = xsec.eval_series_host(xs_, np.full(2, yy), -1)
         assert vv[0] == 0 and vv[1] != 0, (yy, vv)
+
+
+def test_selection_bounds_enclose_k():
+    # main-contributor selection rests on K_lo <= K <= K_hi at every (x, y)
+    x, y = _domain(200_000, 21)
+    xf, yf = _far_points(200_000, 22)
+    x, y = np.concatenate([x, xf, [0.0, 7.0, 0.0]]), np.concatenate([y, yf, [1e-6, 1e-6, 7.0]])
+    K = wofz(x + 1j * y).real
+    lo, hi = xsec.eval_bounds_host(x, y)
+    assert np.all(lo <= K * (1 + 1e-12)), (x[np.argmax(lo / K)], y[np.argmax(lo / K)])
+    assert np.all(hi >= K * (1 - 1e-12)), (x[np.argmin(hi / K)], y[np.argmin(hi / K)])
+    assert np.all(hi <= 1.0) and np.all(lo > 0.0)
+    # tight where it matters: outside |z| = 7 the upper bound exceeds K by at most about
+    # four times the shifted Lorentzian's error bound, and the lower bound is within
+    # (1 + 2/|x|)^2 (the |t| <= 2 part of the integral) far from the line
+    r2 = x * x + y * y
+    m = r2 >= 49.0
+    e = (1.5 + 2 * y[m] ** 2) / r2[m] ** 2
+    assert np.all(hi[m] / K[m] - 1 <= 4 * e + 2e-6)
+    big = x > 100
+    assert np.min(lo[big] / K[big] * (1 + 2 / x[big]) ** 2) > 0.99
+    # negative x mirrors; y <= 0 is refused
+    lo2, hi2 = xsec.eval_bounds_host(-x[:100], y[:100])
+    assert np.array_equal(lo2, lo[:100]) and np.array_equal(hi2, hi[:100])
+    with pytest.raises(xsec.XsError):
+        xsec.eval_bounds_host([1.0], [0.0])
 
 
 def test_series_variant_errors():
