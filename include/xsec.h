@@ -332,10 +332,11 @@ int xs_eval_voigt_host(const double *x, const double *y, size_t n, int precision
 int xs_eval_series_host(const double *x, const double *y, size_t n, int variant,
                         double *K_out, int *variant_out);
 
-/* The bounds of K(x, y) that main-contributor selection uses (FP64, compiled for the
- * host): K_lo = erf(2) (y / sqrt(pi)) / ((|x| + 2)^2 + y^2) <= K, and K <= K_hi = 1, or
- * for x^2 + y^2 >= 49 the shifted Lorentzian widened by twice its error bound. Either
- * output may be NULL; y must be > 0 (XS_EINVAL otherwise). */
+/* The bounds of K(x, y) that main-contributor selection uses (FP32 arithmetic with
+ * 1e-5 margins, compiled for the host, at x and y rounded to FP32):
+ * K_lo = erf(2) (y / sqrt(pi)) / ((|x| + 2)^2 + y^2) <= K, and K <= K_hi = 1, or for
+ * x^2 + y^2 >= 49 the shifted Lorentzian widened by twice its error bound. Either output
+ * may be NULL; y must be > 0 (XS_EINVAL otherwise). */
 int xs_eval_bounds_host(const double *x, const double *y, size_t n, double *K_lo,
                         double *K_hi);
 

@@ -12,6 +12,7 @@ constexpr int kWave = 64;
 constexpr int kWavesPerWG = 4;
 constexpr int kBlock = kWave * kWavesPerWG;
 constexpr int kMaxSplit = 256;
+constexpr int kSelGroup = 4;   // tiles per main-contributor selection group
 
 struct LinesDev {
   const double* nu0;
@@ -57,10 +58,11 @@ struct TileArgs {
   double* out;            // split == 1: sigma rows [n_pts][n_grid] (row pt0 + k);
                           // else partials [n_pt][split][n_grid] of this batch
   unsigned long long* counts;  // count kernel only: [n_pts][kNEvalTiers]
-  // main-contributor selection (nullptr: off): per (P, T) point of the batch and tile,
-  // the contribution bound below which a line is dropped, [n_pt][tau_stride]
+  // main-contributor selection (nullptr: off): per (P, T) point of the batch and group of
+  // kSelGroup neighbouring tiles (tile / kSelGroup), the contribution bound below which a
+  // line is dropped, [n_pt][tau_stride]
   double* tau;
-  int64_t tau_stride;     // tiles of the whole grid
+  int64_t tau_stride;     // groups of the whole grid
   double select_eps;      // select kernel: the allowed relative error
 };
 
@@ -71,7 +73,7 @@ hipError_t launch_params(const ParamArgs& A, hipStream_t st);
 hipError_t launch_tile(const TileArgs& A, int P, bool f64, int W, hipStream_t st,
                        int64_t phys_wg);
 hipError_t launch_count(const TileArgs& A, int P, hipStream_t st, int64_t phys_wg);
-// one wavefront per (tile position, P-T point) of A: writes A.tau
+// one wavefront per (group of 4 tiles, P-T point), A.n_tiles groups: writes A.tau
 hipError_t launch_select(const TileArgs& A, int P, hipStream_t st);
 // per points-per-lane instantiations of the tile kernel (tile_p*.hip)
 hipError_t launch_tile_p1(const TileArgs& A, bool f64, int W, hipStream_t st, dim3 grid);

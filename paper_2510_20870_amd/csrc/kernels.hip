@@ -98,8 +98,9 @@ __global__ __launch_bounds__(kBlock) void xs_count_kernel(TileArgs A) {
     nu[p] = (j < A.n_grid) ? A.grid[j] : __builtin_nan("");
   }
   // with main-contributor selection, only the kept lines count
-  const double tau = A.tau ? A.tau[(int64_t)it.k * A.tau_stride + it.tile] : 0.0;
-  const double t_first = A.grid[it.j0], t_last = it.nu_last;
+  const double tau = A.tau ? A.tau[(int64_t)it.k * A.tau_stride + it.tile / kSelGroup] : 0.0;
+  double g_first = 0.0, g_last = 0.0;
+  if (tau > 0.0) sel_span<P>(A, it.tile, &g_first, &g_last);
   unsigned long long cnt[kNEvalTiers];
 #pragma unroll
   for (int t = 0; t < kNEvalTiers; ++t) cnt[t] = 0;
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void xs_count_kernel(TileArgs A) {
     if (i < it.e) {
       const LineRec lr = A.recs[(int64_t)it.k * A.rec_n + (i - A.rec_lo)];
       c0 = A.L.nu0[i];
-      ct = (tau > 0.0 && contrib_upper(c0, lr, t_first, t_last) < tau) ? -1.0 : lr.cut;
+      ct = (tau > 0.0 && contrib_upper(c0, lr, g_first, g_last) < tau) ? -1.0 : lr.cut;
       ib = lr.ib;
       yv = lr.y;
     }
@@ -148,13 +149,14 @@ __global__ __launch_bounds__(kBlock) void xs_count_kernel(TileArgs A) {
 }
 
 // Main-contributor selection (the paper names it as a way to speed up the line-profile
-// computation, "Functionality of pyROX", without defining it). For one tile and (P, T)
-// point: a lower bound of sigma at every point of the tile, L = sum of the lines' lower
-// bounds (contrib_lower), and the largest power-of-two threshold tau such that the upper
-// bounds (contrib_upper) of all lines below tau add up to at most eps L. Dropping those
-// lines changes sigma by at most eps sigma at every point of the tile. The bounds are
-// binned by binary exponent into an exact integer histogram (fixed point, rounded up), so
-// tau does not depend on the order of the additions.
+// computation, "Functionality of pyROX", without defining it). For one group of kSelGroup
+// neighbouring tiles and one (P, T) point: a lower bound of sigma at every point of the
+// group, L = sum of the lines' lower bounds (contrib_lower), and the largest power-of-two
+// threshold tau such that the upper bounds (contrib_upper) of all lines below tau add up
+// to at most eps L. Dropping those lines changes sigma by at most eps sigma at every point
+// of the group. The bounds are binned by binary exponent into an exact integer histogram
+// (fixed point, rounded up), so tau does not depend on the order of the additions.
+// One wavefront per (group, point): A.n_tiles counts groups here.
 template <int P>
 __global__ __launch_bounds__(kBlock) void xs_select_kernel(TileArgs A) {
   __shared__ unsigned long long hist[kWavesPerWG][kWave];
@@ -164,11 +166,9 @@ __global__ __launch_bounds__(kBlock) void xs_select_kernel(TileArgs A) {
   const int64_t item = (int64_t)blockIdx.x * kWavesPerWG + wave;
   if (item >= A.n_tiles * A.n_pt) return;
   const int k = (int)(item % A.n_pt);
-  const int64_t pos = item / A.n_pt;
-  const int64_t tile = A.tile_order ? (int64_t)A.tile_order[pos] : pos;
-  const int64_t j0 = tile * (int64_t)(kWave * P);
-  const int64_t jl = min(j0 + (int64_t)(kWave * P), A.n_grid) - 1;
-  const double t_first = A.grid[j0], t_last = A.grid[jl];
+  const int64_t group = item / A.n_pt;
+  double t_first, t_last;
+  sel_span<P>(A, group * kSelGroup, &t_first, &t_last);
   int64_t lo, hi;
   line_window(A, k, t_first, t_last, lane, &lo, &hi);
   const LineRec* rec = A.recs + (int64_t)k * A.rec_n - A.rec_lo;
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void xs_select_kernel(TileArgs A) {
     const int bstar = __popcll(__ballot(ok)) - 1;
     tau = bstar == 0 ? 0.0 : ldexp(1.0, elo + bstar - 1);
   }
-  if (lane == 0) A.tau[(int64_t)k * A.tau_stride + tile] = tau;
+  if (lane == 0) A.tau[(int64_t)k * A.tau_stride + group] = tau;
 }
 
 __global__ void xs_fill_u64_kernel(unsigned long long* p, int64_t n) {

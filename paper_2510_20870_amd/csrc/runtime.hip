@@ -219,7 +219,7 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
   }
   const size_t per_pt = std::max<size_t>(
       1, (size_t)p.rec_n * 32 + (p.split > 1 ? (size_t)p.split * G.n * 8 : 0) +
-             (p.select_eps > 0.0 ? (size_t)p.n_tiles * 8 : 0));
+             (p.select_eps > 0.0 ? (size_t)p.n_groups() * 8 : 0));
   p.pt_batch = (int)std::max<size_t>(1, std::min<size_t>(npts, cap / per_pt));
   // issue order: tiles by decreasing number of lines within the largest cut, so the most
   // expensive work items start first
@@ -289,6 +289,29 @@ int enqueue_step(const LinesRes& L, const GridRes& G, const xs_opts& o, const Pl
     PA.out = (LineRec*)rec_dev;
     e = launch_params(PA, st);
     if (e != hipSuccess) return hip_fail(e, "parameter kernel launch");
+    if (p.select_eps > 0.0) {
+      // main-contributor selection: the thresholds of every tile group of the grid
+      // (the tile launches of the batch, whatever their tile range, read them)
+      TileArgs S;
+      memset(&S, 0, sizeof S);
+      S.L = L.dev;
+      S.sp = L.sp;
+      S.cut = cut;
+      S.grid = G.d;
+      S.n_grid = (int64_t)G.n;
+      S.pts = pts_dev;
+      S.pt0 = pt0;
+      S.n_pt = nb;
+      S.n_tiles = p.n_groups();
+      S.recs = (const LineRec*)rec_dev;
+      S.rec_lo = p.rec_lo;
+      S.rec_n = p.rec_n;
+      S.tau = (double*)((char*)rec_dev + p.tau_offset());
+      S.tau_stride = p.n_groups();
+      S.select_eps = p.select_eps;
+      e = launch_select(S, p.P, st);
+      if (e != hipSuccess) return hip_fail(e, "select kernel launch");
+    }
   }
   if (c1 > c0) {
     TileArgs A;
@@ -310,13 +333,10 @@ int enqueue_step(const LinesRes& L, const GridRes& G, const xs_opts& o, const Pl
     A.rec_lo = p.rec_lo;
     A.rec_n = p.rec_n;
     if (p.select_eps > 0.0) {
-      // main-contributor selection: the thresholds of these tiles, then the kernels drop
-      // the lines below them
+      // main-contributor selection: the kernels drop the lines below their group's
+      // threshold
       A.tau = (double*)((char*)rec_dev + p.tau_offset());
-      A.tau_stride = p.n_tiles;
-      A.select_eps = p.select_eps;
-      e = launch_select(A, p.P, st);
-      if (e != hipSuccess) return hip_fail(e, "select kernel launch");
+      A.tau_stride = p.n_groups();
     }
     const int64_t phys = phys_workgroups(A.n_wg);
     int rc = tm ? tm->record(st) : XS_OK;
@@ -1000,8 +1020,8 @@ int xs_eval_bounds_host(const double* x, const double* y, size_t n, double* K_lo
   if (n && (!x || !y)) return fail(XS_EINVAL, "NULL argument");
   for (size_t i = 0; i < n; ++i) {
     if (!(y[i] > 0.0)) return fail(XS_EINVAL, "point %zu: y must be > 0 (got %g)", i, y[i]);
-    if (K_lo) K_lo[i] = voigt_lower(x[i], y[i]);
-    if (K_hi) K_hi[i] = voigt_upper(x[i], y[i]);
+    if (K_lo) K_lo[i] = (double)voigt_lower((float)x[i], (float)y[i]);
+    if (K_hi) K_hi[i] = (double)voigt_upper((float)x[i], (float)y[i]);
   }
   return XS_OK;
 }

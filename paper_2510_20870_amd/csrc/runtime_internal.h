@@ -57,11 +57,12 @@ struct Plan {
   std::vector<int64_t> tile_cost;  // sampled line count in each tile's window (x 1024)
   bool tuned = false;              // launch shape from the tuning cache
   double select_eps = 0.0;         // main-contributor selection (0: off)
-  // line records [pt_batch][rec_n] (32 B), then with selection the tiles' thresholds
-  // [pt_batch][n_tiles] (8 B)
+  // line records [pt_batch][rec_n] (32 B), then with selection the thresholds of the
+  // groups of kSelGroup tiles [pt_batch][n_groups()] (8 B)
+  int64_t n_groups() const { return (n_tiles + kSelGroup - 1) / kSelGroup; }
   size_t tau_offset() const { return (size_t)rec_n * pt_batch * 32; }
   size_t rec_bytes() const {
-    return tau_offset() + (select_eps > 0.0 ? (size_t)pt_batch * n_tiles * 8 : 0);
+    return tau_offset() + (select_eps > 0.0 ? (size_t)pt_batch * n_groups() * 8 : 0);
   }
   size_t part_bytes(size_t n_grid) const {
     return split > 1 ? (size_t)pt_batch * split * n_grid * sizeof(double) : 0;

@@ -139,21 +139,32 @@ __device__ __forceinline__ void line_window(const TileArgs& A, int k, double nu_
   *hi = A.rec_lo + wave_search<true>(base, A.rec_n, hk, lane);
 }
 
-// Main-contributor selection: bounds of line i's contribution over the tile
-// [t_first, t_last] (FP64). Upper: at the tile's point nearest to the line (zero when that
-// point is outside the cut). Lower: at the farthest point, zero unless every point of the
-// tile is inside the cut (K falls with |x|, so the nearest and farthest points bound it).
+// Main-contributor selection works on groups of kSelGroup neighbouring tiles (one
+// threshold per group and (P, T) point): bounds of line i's contribution over the group's
+// grid span [g_first, g_last]. Upper: at the span's point nearest to the line (zero when
+// that point is outside the cut). Lower: at the farthest point, zero unless every point of
+// the span is inside the cut (K falls with |x|, so these points bound it). The offsets and
+// the cut tests are FP64, the bounds of K FP32 with margins, the scale FP64.
 __device__ __forceinline__ double contrib_upper(double nu0, const LineRec& lr,
-                                                double t_first, double t_last) {
-  const double d = nu0 < t_first ? t_first - nu0 : nu0 > t_last ? nu0 - t_last : 0.0;
+                                                double g_first, double g_last) {
+  const double d = nu0 < g_first ? g_first - nu0 : nu0 > g_last ? nu0 - g_last : 0.0;
   if (d > lr.cut) return 0.0;
-  return lr.sc * voigt_upper(d * lr.ib, lr.y);
+  return lr.sc * (double)voigt_upper((float)(d * lr.ib), (float)lr.y);
 }
 __device__ __forceinline__ double contrib_lower(double nu0, const LineRec& lr,
-                                                double t_first, double t_last) {
-  const double d = fmax(fabs(t_first - nu0), fabs(t_last - nu0));
+                                                double g_first, double g_last) {
+  const double d = fmax(fabs(g_first - nu0), fabs(g_last - nu0));
   if (d > lr.cut) return 0.0;
-  return lr.sc * voigt_lower(d * lr.ib, lr.y);
+  return lr.sc * (double)voigt_lower((float)(d * lr.ib), (float)lr.y);
+}
+// The grid span of the selection group of tile t (tiles of 64 P points).
+template <int P>
+__device__ __forceinline__ void sel_span(const TileArgs& A, int64_t t, double* g_first,
+                                         double* g_last) {
+  constexpr int64_t kSpan = (int64_t)kWave * P * kSelGroup;
+  const int64_t j0 = (t / kSelGroup) * kSpan;
+  *g_first = A.grid[j0];
+  *g_last = A.grid[min(j0 + kSpan, A.n_grid) - 1];
 }
 
 template <int P>
@@ -430,9 +441,11 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   const int wv = threadIdx.x >> 6;
   ItemInfo it;
   if (!decode_item<P>(A, lane, it)) return;
-  // main-contributor selection: the tile's drop threshold (0: every line is kept)
-  const double tau = A.tau ? A.tau[(int64_t)it.k * A.tau_stride + it.tile] : 0.0;
-  const double t_first = A.grid[it.j0], t_last = it.nu_last;
+  // main-contributor selection: the drop threshold of the tile's group (0: every line is
+  // kept)
+  const double tau = A.tau ? A.tau[(int64_t)it.k * A.tau_stride + it.tile / kSelGroup] : 0.0;
+  double g_first = 0.0, g_last = 0.0;
+  if (tau > 0.0) sel_span<P>(A, it.tile, &g_first, &g_last);
 
   Rows<P> rows;
   double nu[P];
@@ -625,18 +638,49 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   };
   int ndef = 0;   // lines waiting in dlist
 
-  for (int64_t base = it.b; base < it.e; base += kWave) {
-    const int64_t i = base + lane;
+  // Main-contributor selection: the lines whose bound over the tile's group reaches tau
+  // are gathered into a queue of line offsets from it.b (q0: the next 64, q1: the
+  // overflow; compacted through incl, which is free at this point of a pass), so that only
+  // kept lines are staged, 64 at a time. Without selection the chunks are consecutive.
+  const uint64_t lt = (1ull << lane) - 1ull;
+  int q0 = 0, q1 = 0, nq = 0;
+  int64_t base = it.b;
+  for (;;) {
+    int64_t i = -1;   // this lane's line in the chunk (-1: none)
+    if (tau > 0.0) {
+      while (nq < kWave && base < it.e) {
+        const int64_t j = base + lane;
+        bool keep = false;
+        if (j < it.e) {
+          const LineRec lr = A.recs[(int64_t)it.k * A.rec_n + (j - A.rec_lo)];
+          keep = contrib_upper(A.L.nu0[j], lr, g_first, g_last) >= tau;
+        }
+        const uint64_t km = __ballot(keep);
+        const int cnt = __popcll(km);
+        if (keep) incl[wv][__popcll(km & lt)] = (int)(j - it.b);
+        wave_sync();
+        // queue position nq + r of the r-th kept line: lane (nq + r) mod 64 of q0 or q1
+        const int src = (lane - nq) & (kWave - 1);
+        const int q = src < cnt ? incl[wv][src] : 0;
+        if (lane >= nq && lane - nq < cnt) q0 = q;
+        if (lane < nq && lane + kWave - nq < cnt) q1 = q;
+        wave_sync();
+        nq += cnt;
+        base += kWave;
+      }
+      if (nq == 0) break;
+      if (lane < nq) i = it.b + q0;
+      q0 = q1;
+      nq = max(nq - kWave, 0);
+    } else {
+      if (base >= it.e) break;
+      if (base + lane < it.e) i = base + lane;
+      base += kWave;
+    }
     Rec<F64, P> r;
     double sc64 = 0.0;
     int mode = kSkip, npairs = 0;
-    // main-contributor selection: a line whose bound over the tile is below tau is dropped
-    bool keep = i < it.e;
-    if (tau > 0.0 && keep) {
-      const LineRec lr = A.recs[(int64_t)it.k * A.rec_n + (i - A.rec_lo)];
-      keep = contrib_upper(A.L.nu0[i], lr, t_first, t_last) >= tau;
-    }
-    if (keep) {
+    if (i >= 0) {
       r = stage_line<F64, P>(A, it.k, rows, rowvals[wv], i, &sc64, &mode, &npairs, false);
     } else {
       r.cls = 0;
@@ -647,7 +691,6 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     // no point inside the cut are dropped. The order is fixed by the data alone.
     int gstart[kModes + 1];
     {
-      const uint64_t lt = (1ull << lane) - 1ull;
       int pos = -1, acc = 0;
       gstart[0] = 0;
 #pragma unroll

@@ -233,22 +233,24 @@ XS_HD float voigt_k32(double xd, float y) {
   return (float)voigt_core64_tier(core_tier((double)y), xd, (double)y);
 }
 
-// Bounds of K for main-contributor selection (FP64, any x, y > 0):
+// Bounds of K for main-contributor selection (FP32 arithmetic, any x, y > 0; the factors
+// 1 -+ 1e-5 cover the FP32 rounding of x, y and of the reciprocals):
 //  lower: the part |t| <= 2 of the convolution integral K = (y/pi) int e^{-t^2} /
 //    ((x - t)^2 + y^2) dt alone gives K >= erf(2) (y/sqrt(pi)) / ((|x| + 2)^2 + y^2);
 //  upper: K <= K(0, y) = erfcx(y) <= 1, and for r^2 >= 49 the shifted Lorentzian widened
-//    by twice its error bound (3/2 + 2 y^2) / r^4 (plus 1e-6).
-constexpr double kErf2 = 0.99532226501895273416;
-XS_HD double voigt_lower(double x, double y) {
-  const double a = fabs(x) + 2.0;
-  return kErf2 * kInvSqrtPi * y * rcp64(fma(a, a, y * y));
+//    by twice its error bound (3/2 + 2 y^2) / r^4.
+constexpr float kErf2 = 0.99532226501895273416f;
+XS_HD float voigt_lower(float x, float y) {
+  const float a = fabsf(x) + 2.0f;
+  return (kErf2 * (float)kInvSqrtPi * (1.0f - 1e-5f)) * y * rcp32(fmaf(a, a, y * y));
 }
-XS_HD double voigt_upper(double x, double y) {
-  const double r2 = fma(x, x, y * y);
-  if (!(r2 >= 49.0)) return 1.0;
-  const double u = rcp64(r2);
-  const double e = fma(2.0 * y, y, 1.5) * u * u;
-  return fmin(1.0, kInvSqrtPi * y * rcp64(r2 - 1.5) * fma(2.0, e, 1.0 + 1e-6));
+XS_HD float voigt_upper(float x, float y) {
+  const float r2 = fmaf(x, x, y * y);
+  if (!(r2 >= 49.0f)) return 1.0f;
+  const float u = rcp32(r2);
+  const float e = fmaf(2.0f * y, y, 1.5f) * u * u;
+  return fminf(1.0f, ((float)kInvSqrtPi * (1.0f + 1e-5f)) * y * rcp32(r2 - 1.5f) *
+                         fmaf(2.0f, e, 1.0f));
 }
 
 XS_HD double voigt_k64(double x, double y) {
