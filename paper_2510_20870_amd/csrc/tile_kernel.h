@@ -427,7 +427,9 @@ __device__ __forceinline__ float series_row(int var, const Rec<false, P>& q, flo
 constexpr int kChunk = 16;
 
 // W > 0 asks the compiler for at least W waves per SIMD (capping VGPRs at 512/W).
-template <int P, bool F64, int W>
+// SEL: main-contributor selection (a variant of its own, so that the kernel without it
+// keeps its register allocation).
+template <int P, bool F64, int W, bool SEL>
 __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileArgs A) {
   __shared__ Rec<F64, P> recs[kWavesPerWG][kWave];
   __shared__ double rowvals[kWavesPerWG][kWave * P];
@@ -443,9 +445,11 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   if (!decode_item<P>(A, lane, it)) return;
   // main-contributor selection: the drop threshold of the tile's group (0: every line is
   // kept)
-  const double tau = A.tau ? A.tau[(int64_t)it.k * A.tau_stride + it.tile / kSelGroup] : 0.0;
-  double g_first = 0.0, g_last = 0.0;
-  if (tau > 0.0) sel_span<P>(A, it.tile, &g_first, &g_last);
+  double tau = 0.0, g_first = 0.0, g_last = 0.0;
+  if constexpr (SEL) {
+    tau = A.tau[(int64_t)it.k * A.tau_stride + it.tile / kSelGroup];
+    sel_span<P>(A, it.tile, &g_first, &g_last);
+  }
 
   Rows<P> rows;
   double nu[P];
@@ -638,16 +642,15 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   };
   int ndef = 0;   // lines waiting in dlist
 
-  // Main-contributor selection: the lines whose bound over the tile's group reaches tau
-  // are gathered into a queue of line offsets from it.b (q0: the next 64, q1: the
-  // overflow; compacted through incl, which is free at this point of a pass), so that only
-  // kept lines are staged, 64 at a time. Without selection the chunks are consecutive.
-  const uint64_t lt = (1ull << lane) - 1ull;
-  int q0 = 0, q1 = 0, nq = 0;
-  int64_t base = it.b;
-  for (;;) {
-    int64_t i = -1;   // this lane's line in the chunk (-1: none)
-    if (tau > 0.0) {
+  // Main-contributor selection (SEL): the lines whose bound over the tile's group reaches
+  // tau are gathered into a queue of line offsets from it.b (q0: the next 64, q1: the
+  // overflow; compacted through incl, which is free between passes), so that only kept
+  // lines are staged, 64 at a time. Without selection the chunks are consecutive lines.
+  [[maybe_unused]] int q0 = 0, q1 = 0, nq = 0;
+  for (int64_t base = it.b; SEL || base < it.e; base += SEL ? 0 : kWave) {
+    int64_t i = base + lane;   // this lane's line in the chunk (it.e or later: none)
+    if constexpr (SEL) {
+      const uint64_t lt = (1ull << lane) - 1ull;
       while (nq < kWave && base < it.e) {
         const int64_t j = base + lane;
         bool keep = false;
@@ -669,18 +672,14 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
         base += kWave;
       }
       if (nq == 0) break;
-      if (lane < nq) i = it.b + q0;
+      i = lane < nq ? it.b + q0 : it.e;
       q0 = q1;
       nq = max(nq - kWave, 0);
-    } else {
-      if (base >= it.e) break;
-      if (base + lane < it.e) i = base + lane;
-      base += kWave;
     }
     Rec<F64, P> r;
     double sc64 = 0.0;
     int mode = kSkip, npairs = 0;
-    if (i >= 0) {
+    if (i < it.e) {
       r = stage_line<F64, P>(A, it.k, rows, rowvals[wv], i, &sc64, &mode, &npairs, false);
     } else {
       r.cls = 0;
@@ -691,6 +690,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     // no point inside the cut are dropped. The order is fixed by the data alone.
     int gstart[kModes + 1];
     {
+      const uint64_t lt = (1ull << lane) - 1ull;
       int pos = -1, acc = 0;
       gstart[0] = 0;
 #pragma unroll
@@ -787,18 +787,26 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   }
 }
 
-template <int P, bool F64>
-static hipError_t launch_tile_w(const TileArgs& A, int W, hipStream_t st, dim3 grid) {
+template <int P, bool F64, bool SEL>
+static hipError_t launch_tile_ws(const TileArgs& A, int W, hipStream_t st, dim3 grid) {
   const dim3 block(kBlock);
   switch (W) {
-    case 0: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 0>), grid, block, 0, st, A); break;
-    case 3: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 3>), grid, block, 0, st, A); break;
-    case 4: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 4>), grid, block, 0, st, A); break;
-    case 5: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 5>), grid, block, 0, st, A); break;
-    case 6: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 6>), grid, block, 0, st, A); break;
+    case 0: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 0, SEL>), grid, block, 0, st, A); break;
+    case 3: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 3, SEL>), grid, block, 0, st, A); break;
+    case 4: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 4, SEL>), grid, block, 0, st, A); break;
+    case 5: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 5, SEL>), grid, block, 0, st, A); break;
+    case 6: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 6, SEL>), grid, block, 0, st, A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// The tile kernel for occupancy target W, with main-contributor selection when A.tau is
+// set.
+template <int P, bool F64>
+static hipError_t launch_tile_w(const TileArgs& A, int W, hipStream_t st, dim3 grid) {
+  return A.tau ? launch_tile_ws<P, F64, true>(A, W, st, grid)
+               : launch_tile_ws<P, F64, false>(A, W, st, grid);
 }
 
 }  // namespace xs
