@@ -122,8 +122,23 @@ int xs_unload_lines(xs_ctx *ctx, xs_lines_t lines);
 int xs_lines_info(xs_ctx *ctx, xs_lines_t lines, size_t *n, size_t *bytes);
 
 /* Copy a wavenumber grid of n points into HBM. It must be finite and strictly increasing
- * (else XS_EUNSORTED); n >= 1. A wavelength grid is converted by the caller. */
+ * (else XS_EUNSORTED); n >= 1. A wavelength grid is converted by the caller (or built
+ * by xs_set_grid_wavelength for a fixed resolving power). */
 int xs_set_grid(xs_ctx *ctx, const double *nu_cm1, size_t n, xs_grid_t *out);
+
+/* Fixed resolving power ("Similar tools": any user grid, which lets the user fix
+ * R = lambda / delta lambda): the wavelengths lambda_k = lambda_min (1 + 1/R)^k, k = 0, 1,
+ * ... while lambda_k <= lambda_max (micrometres), as wavenumbers nu = 1e4 / lambda in
+ * increasing order (so point j of a result is the wavelength lambda_(n-1-j)); a
+ * cross-section per molecule is the same at a wavelength and at its wavenumber.
+ * xs_wavelength_grid_host writes the n points into nu_out (host, capacity cap; with
+ * nu_out NULL or cap too small only *n_out is set, XS_OK and XS_EINVAL respectively);
+ * xs_set_grid_wavelength makes it a resident grid. XS_EINVAL for lambda_min <= 0,
+ * lambda_max < lambda_min, R <= 0, non-finite values or more than 2^31 points. */
+int xs_wavelength_grid_host(double lambda_min_um, double lambda_max_um, double R,
+                            double *nu_out, size_t cap, size_t *n_out);
+int xs_set_grid_wavelength(xs_ctx *ctx, double lambda_min_um, double lambda_max_um,
+                           double R, xs_grid_t *out, size_t *n_out);
 int xs_free_grid(xs_ctx *ctx, xs_grid_t grid);
 /* Number of points of a resident grid. */
 int xs_grid_info(xs_ctx *ctx, xs_grid_t grid, size_t *n);

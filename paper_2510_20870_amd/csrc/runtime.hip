@@ -709,6 +709,41 @@ int xs_set_grid(xs_ctx* c, const double* nu, size_t n, xs_grid_t* out) {
   return XS_OK;
 }
 
+int xs_wavelength_grid_host(double lmin, double lmax, double R, double* nu_out, size_t cap,
+                            size_t* n_out) {
+  if (!n_out) return fail(XS_EINVAL, "NULL argument");
+  if (!(lmin > 0.0) || !(lmax >= lmin) || !(R > 0.0) || !isfinite(lmax) || !isfinite(R))
+    return fail(XS_EINVAL, "need 0 < lambda_min <= lambda_max and R > 0 (got %g, %g, %g)",
+                lmin, lmax, R);
+  // lambda_k = lambda_min exp(k log(1 + 1/R)): the last k with lambda_k <= lambda_max
+  const double step = log1p(1.0 / R);
+  const double kmax = floor(log(lmax / lmin) / step);
+  if (!(kmax < 2147483647.0)) return fail(XS_EINVAL, "more than 2^31 grid points");
+  size_t n = (size_t)kmax + 1;
+  // rounding of the logarithms: keep exactly the points with lambda_k <= lambda_max
+  while (n > 1 && lmin * exp((double)(n - 1) * step) > lmax) --n;
+  while (lmin * exp((double)n * step) <= lmax) ++n;
+  *n_out = n;
+  if (!nu_out) return XS_OK;
+  if (cap < n) return fail(XS_EINVAL, "nu_out holds %zu points, the grid has %zu", cap, n);
+  for (size_t k = 0; k < n; ++k) nu_out[n - 1 - k] = 1e4 / (lmin * exp((double)k * step));
+  return XS_OK;
+}
+
+int xs_set_grid_wavelength(xs_ctx* c, double lmin, double lmax, double R, xs_grid_t* out,
+                           size_t* n_out) {
+  if (!c || !out || !n_out) return fail(XS_EINVAL, "NULL argument");
+  size_t n = 0;
+  int rc = xs_wavelength_grid_host(lmin, lmax, R, nullptr, 0, &n);
+  if (rc) return rc;
+  std::vector<double> nu(n);
+  rc = xs_wavelength_grid_host(lmin, lmax, R, nu.data(), n, &n);
+  if (rc) return rc;
+  rc = xs_set_grid(c, nu.data(), n, out);
+  if (rc == XS_OK) *n_out = n;
+  return rc;
+}
+
 int xs_free_grid(xs_ctx* c, xs_grid_t h) {
   if (!c) return fail(XS_EINVAL, "ctx is NULL");
   std::lock_guard<std::mutex> lk(c->mu);

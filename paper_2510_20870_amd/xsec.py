@@ -144,6 +144,10 @@ _SIGS = {
                              C.c_void_p], C.c_int),
     "xs_eval_bounds_host": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p],
                             C.c_int),
+    "xs_wavelength_grid_host": ([C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_size_t,
+                                 C.POINTER(C.c_size_t)], C.c_int),
+    "xs_set_grid_wavelength": ([C.c_void_p, C.c_double, C.c_double, C.c_double,
+                                C.POINTER(C.c_uint64), C.POINTER(C.c_size_t)], C.c_int),
 }
 
 
@@ -196,6 +200,18 @@ def eval_series_host(x, y, variant: int = -1):
     if rc:
         raise XsError(rc, lib().xs_last_error(None).decode())
     return out, var
+
+
+def wavelength_grid(lambda_min_um: float, lambda_max_um: float, R: float) -> np.ndarray:
+    """Wavenumbers (increasing) of the fixed-resolving-power wavelength grid, as the
+    library builds it (xs_wavelength_grid_host)."""
+    n = C.c_size_t()
+    _lib_check(lib().xs_wavelength_grid_host(float(lambda_min_um), float(lambda_max_um),
+                                             float(R), None, 0, C.byref(n)))
+    out = np.empty(n.value, np.float64)
+    _lib_check(lib().xs_wavelength_grid_host(float(lambda_min_um), float(lambda_max_um),
+                                             float(R), _ptr(out), out.size, C.byref(n)))
+    return out
 
 
 def eval_bounds_host(x, y):
@@ -406,6 +422,17 @@ class Context:
         h = C.c_uint64()
         self._check(self._L.xs_set_grid(self.h, _ptr(nu), nu.size, C.byref(h)))
         return h.value
+
+    def set_grid_wavelength(self, lambda_min_um: float, lambda_max_um: float, R: float):
+        """Resident grid of fixed resolving power R over [lambda_min, lambda_max] (um):
+        (handle, wavenumbers in increasing order). Point j of a result is at wavelength
+        1e4 / nu[j]; reverse a row for increasing wavelength."""
+        h = C.c_uint64()
+        n = C.c_size_t()
+        self._check(self._L.xs_set_grid_wavelength(self.h, float(lambda_min_um),
+                                                   float(lambda_max_um), float(R),
+                                                   C.byref(h), C.byref(n)))
+        return h.value, wavelength_grid(lambda_min_um, lambda_max_um, R)
 
     def free_grid(self, h: int):
         self._check(self._L.xs_free_grid(self.h, h))

@@ -207,3 +207,24 @@ def test_tier_boundaries_are_continuous():
             ref = wofz(x + 1j * y).real
             K = xsec.eval_voigt_host(x, y, xsec.XS_FP32_KAHAN)
             assert np.max(np.abs(K / ref - 1)) < 2e-6
+
+
+def test_fixed_resolving_power_grid():
+    # lambda_k = lambda_min (1 + 1/R)^k up to lambda_max, as increasing wavenumbers
+    lmin, lmax, R = 1.0, 20.0, 1e5
+    nu = xsec.wavelength_grid(lmin, lmax, R)
+    lam = 1e4 / nu[::-1]
+    assert np.all(np.diff(nu) > 0)
+    assert lam[0] == pytest.approx(lmin, rel=1e-15)
+    assert lam[-1] <= lmax * (1 + 1e-15) and lam[-1] * (1 + 1 / R) > lmax
+    ratio = lam[1:] / lam[:-1]
+    assert np.max(np.abs(ratio - (1 + 1 / R))) < 1e-12
+    # R = lambda / delta lambda at every point
+    assert np.max(np.abs(lam[:-1] / np.diff(lam) - R)) / R < 1e-7
+    assert len(nu) == int(np.floor(np.log(lmax / lmin) / np.log1p(1 / R))) + 1
+    # a single point, and the refused inputs
+    assert len(xsec.wavelength_grid(2.0, 2.0, 10.0)) == 1
+    for bad in ((0.0, 1.0, 10.0), (2.0, 1.0, 10.0), (1.0, 2.0, 0.0), (1.0, float("inf"), 5.0),
+                (1.0, 1e6, 1e9)):
+        with pytest.raises(xsec.XsError):
+            xsec.wavelength_grid(*bad)

@@ -379,3 +379,21 @@ def test_mid_full_size_sampled(ctx, f64):
     assert np.all(np.isfinite(sig)) and np.all(sig > 0)
     ctx.unload_lines(h)
     ctx.free_grid(g)
+
+
+def test_fixed_resolving_power_grid(ctx):
+    # a wavelength grid of fixed R = lambda / delta lambda over the tiny list's range
+    # (1000-1100 cm^-1 = 90.9-100 um), against the oracle at the same wavenumbers
+    X = _xsec()
+    W, L, _ = _tiny()
+    g, nu = ctx.set_grid_wavelength(1e4 / 1100.0, 1e4 / 1000.0, 4e5)
+    assert ctx.grid_len(g) == len(nu) and len(nu) > 30_000
+    h = ctx.load_lines(L, W.mass_amu)
+    sig = ctx.compute(h, g, [(0.5, 1200.0)], _opts(cut=W.cut_cm1))[0]
+    idx = np.arange(0, len(nu), 7)
+    ref = O.sigma(L, nu, 0.5, 1200.0, W.mass_amu, cut_cm1=W.cut_cm1, points=idx)
+    _check(sig[idx], ref, tol=1e-5, label=f"fixed R grid ({len(nu)} points)")
+    ctx.unload_lines(h)
+    ctx.free_grid(g)
+    with pytest.raises(X.XsError):
+        ctx.set_grid_wavelength(2.0, 1.0, 1e4)
