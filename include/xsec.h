@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define XS_ABI_VERSION 2
+#define XS_ABI_VERSION 3
 
 typedef enum {
   XS_OK = 0,
@@ -84,6 +84,8 @@ int xs_memory_used(xs_ctx *ctx, size_t *used, size_t *budget);
  * files"). nu0 float64 [cm^-1]; A_or_Sref float32 (Einstein A [s^-1], or the strength at
  * T_ref [cm/molecule] for XS_REF_STRENGTH); E_low float32 [cm^-1]; gamma_ref float32
  * [cm^-1/bar] at T_ref; n_T float32; g_up uint16 (>= 1; unused by the reference form).
+ * J_low uint16, the lower state's rotational quantum number, indexes the broadening
+ * tables of the species (NULL: 0 for every line; unused without tables).
  * The arrays need not be sorted: the library keeps a stable sort by nu0 (ties keep the
  * input order). n = 0 is allowed (every sigma is then 0). */
 typedef struct {
@@ -94,12 +96,19 @@ typedef struct {
   const float *gamma_ref;
   const float *n_T;
   const uint16_t *g_up;
+  const uint16_t *J_low;
 } xs_lines_desc;
 
 /* The species: strength form, molecular mass [amu], T_ref [K] (296 when 0),
  * P_ref [bar] (1 when 0), and Q(T) = q_a * T^q_b (XS_Q_POWER) or the linear
  * interpolation of the q_n nodes (q_T ascending, q_val) clamped at the ends
- * (XS_Q_TABLE; the table is copied). */
+ * (XS_Q_TABLE; the table is copied).
+ * Pressure broadening ("Compute line-strengths and -widths": several descriptions):
+ * n_broad = 0 gives gamma_L = gamma_ref (P/P_ref) (T_ref/T)^n_T with each line's own
+ * gamma_ref and n_T; n_broad > 0 broadening partners (at most 8) with volume mixing ratios
+ * broad_vmr[b] >= 0 and tables over J of broad_nj entries (at most 4096),
+ * gamma_L = (P/P_ref) sum_b broad_vmr[b] broad_gamma[b*nj + j] (T_ref/T)^broad_n[b*nj + j]
+ * with j = min(J_low, nj - 1) (the tables are copied; gamma >= 0, all finite). */
 typedef struct {
   int strength_form;
   double mass_amu;
@@ -110,6 +119,11 @@ typedef struct {
   const double *q_T;
   const double *q_val;
   size_t q_n;
+  int n_broad;
+  size_t broad_nj;
+  const double *broad_vmr;
+  const double *broad_gamma;
+  const double *broad_n;
 } xs_species_desc;
 
 /* Copy a line list into HBM (26 bytes per line, sorted by nu0). Errors: XS_EINVAL

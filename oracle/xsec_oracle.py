@@ -22,6 +22,11 @@ S, b_D, gamma_L or the cutoff; the textbook readings taken here are:
 * Doppler width (1/e half-width): b_D = (nu0/c) sqrt(2 k_B T / m)
 * Lorentz half-width, one broadener, no natural width:
       gamma_L = gamma_ref * (P / 1 bar) * (296 K / T)^n_T
+  or, with several broadening partners b (the paper supports "various pressure-broadening
+  descriptions"; here: volume mixing ratios and per-partner tables over the lower-state J,
+  the usual form of ExoMol broadening files):
+      gamma_L = (P / 1 bar) * sum_b vmr_b * gamma_b(J) * (296 K / T)^n_b(J),
+  J beyond a table taking its last entry
 * Voigt: V(d) = Re w((d + i gamma_L)/b_D) / (b_D sqrt(pi))
 * cutoff: plain truncation at |nu_j - nu0_i| <= cut_i (inclusive), no renormalisation;
   cut_i is either a fixed width or min(cap, mult * f_V,i), f_V the Voigt FWHM of Olivero
@@ -102,6 +107,19 @@ def lorentz_width(gamma_ref, n_T, P: float, T: float) -> np.ndarray:
     return g * (P / P_REF) * (T_REF / T) ** n
 
 
+def lorentz_width_partners(J, P: float, T: float, vmr, gamma_tab, n_tab) -> np.ndarray:
+    """gamma_L with broadening partners: (P/P_ref) * sum_b vmr_b gamma_b(J) (T_ref/T)^n_b(J),
+    the tables [partner][J] taking their last entry beyond their length."""
+    vmr = np.asarray(vmr, np.float64)
+    gt = np.asarray(gamma_tab, np.float64).reshape(len(vmr), -1)
+    nt = np.asarray(n_tab, np.float64).reshape(gt.shape)
+    j = np.minimum(np.asarray(J, np.int64), gt.shape[1] - 1)
+    total = np.zeros(j.shape, np.float64)
+    for b in range(len(vmr)):
+        total += vmr[b] * gt[b, j] * (T_REF / T) ** nt[b, j]
+    return total * (P / P_REF)
+
+
 def voigt_fwhm(gamma_L, b_D) -> np.ndarray:
     """Olivero-Longbothum approximation of the Voigt full width at half maximum."""
     fL = 2.0 * np.asarray(gamma_L, np.float64)
@@ -135,9 +153,11 @@ def line_parameters(lines: Dict[str, np.ndarray], P: float, T: float, mass_amu: 
                     strength_form: str = "einstein", q_a: float = 0.0343,
                     q_b: float = 1.5, table_T=None, table_Q=None,
                     cut_kind: str = "fixed", cut_cm1: float = 25.0,
-                    fwhm_mult: float = 100.0) -> Dict[str, np.ndarray]:
+                    fwhm_mult: float = 100.0,
+                    broadening: Optional[Dict[str, np.ndarray]] = None) -> Dict[str, np.ndarray]:
     """Per-line S, b_D, gamma_L and cut at one (P, T). `lines` holds the stored fields
-    nu0, A (Einstein A, or S_ref for the reference form), E_low, gamma, n_T, g_up."""
+    nu0, A (Einstein A, or S_ref for the reference form), E_low, gamma, n_T, g_up, and
+    J_low when `broadening` ({"vmr", "gamma", "n"}: partner tables over J) is given."""
     Q_T = partition_function(T, q_a, q_b, table_T, table_Q)
     if strength_form == "einstein":
         S = strength_einstein(lines["nu0"], lines["A"], lines["E_low"], lines["g_up"], T, Q_T)
@@ -147,7 +167,12 @@ def line_parameters(lines: Dict[str, np.ndarray], P: float, T: float, mass_amu: 
     else:
         raise ValueError(f"unknown strength form {strength_form!r}")
     bD = doppler_width(lines["nu0"], T, mass_amu)
-    gL = lorentz_width(lines["gamma"], lines["n_T"], P, T)
+    if broadening is None:
+        gL = lorentz_width(lines["gamma"], lines["n_T"], P, T)
+    else:
+        J = lines.get("J_low", np.zeros(len(lines["nu0"]), np.uint16))
+        gL = lorentz_width_partners(J, P, T, broadening["vmr"], broadening["gamma"],
+                                    broadening["n"])
     cut = line_cutoff(cut_kind, cut_cm1, fwhm_mult, gL, bD)
     return {"S": S, "b_D": bD, "gamma_L": gL, "cut": cut}
 
@@ -157,7 +182,8 @@ def sigma(lines: Dict[str, np.ndarray], grid: np.ndarray, P: float, T: float,
           mass_amu: float, cut_kind: str = "fixed", cut_cm1: float = 25.0,
           fwhm_mult: float = 100.0, strength_form: str = "einstein",
           q_a: float = 0.0343, q_b: float = 1.5, table_T=None, table_Q=None,
-          points: Optional[np.ndarray] = None, block_elems: int = 2_000_000) -> np.ndarray:
+          points: Optional[np.ndarray] = None, block_elems: int = 2_000_000,
+          broadening: Optional[Dict[str, np.ndarray]] = None) -> np.ndarray:
     """sigma at grid[points] (all grid points when points is None) [cm^2/molecule].
 
     For each grid point the contributing lines are exactly those with
@@ -169,7 +195,7 @@ def sigma(lines: Dict[str, np.ndarray], grid: np.ndarray, P: float, T: float,
     L = {k: np.asarray(v)[order] for k, v in lines.items()}
     nu0 = L["nu0"].astype(np.float64)
     par = line_parameters(L, P, T, mass_amu, strength_form, q_a, q_b, table_T, table_Q,
-                          cut_kind, cut_cm1, fwhm_mult)
+                          cut_kind, cut_cm1, fwhm_mult, broadening)
     S, bD, gL, cut = par["S"], par["b_D"], par["gamma_L"], par["cut"]
     cut_max = float(cut.max()) if len(cut) else 0.0
     grid = np.asarray(grid, np.float64)
@@ -206,13 +232,14 @@ def sigma(lines: Dict[str, np.ndarray], grid: np.ndarray, P: float, T: float,
 
 def count_evals(lines: Dict[str, np.ndarray], grid: np.ndarray, P: float, T: float,
                 mass_amu: float, cut_kind: str = "fixed", cut_cm1: float = 25.0,
-                fwhm_mult: float = 100.0, points: Optional[np.ndarray] = None) -> int:
+                fwhm_mult: float = 100.0, points: Optional[np.ndarray] = None,
+                broadening: Optional[Dict[str, np.ndarray]] = None) -> int:
     """Number of (line, grid point) pairs with |nu_j - nu0_i| <= cut_i."""
     nu0 = np.sort(np.asarray(lines["nu0"], np.float64), kind="stable")
     order = np.argsort(np.asarray(lines["nu0"]), kind="stable")
     par = line_parameters({k: np.asarray(v)[order] for k, v in lines.items()}, P, T,
                           mass_amu, cut_kind=cut_kind, cut_cm1=cut_cm1,
-                          fwhm_mult=fwhm_mult)
+                          fwhm_mult=fwhm_mult, broadening=broadening)
     cut = par["cut"]
     grid = np.asarray(grid, np.float64)
     js = np.arange(len(grid)) if points is None else np.asarray(points, np.int64)

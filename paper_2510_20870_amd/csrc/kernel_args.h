@@ -21,6 +21,7 @@ struct LinesDev {
   const float* gam;
   const float* nT;
   const uint16_t* g;
+  const uint16_t* J;   // lower-state J (nullptr: 0 for every line)
   int64_t n;
 };
 

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void xs_params_kernel(ParamArgs A) {
     const int64_t i = A.lo + t;
     const double nu0 = A.L.nu0[i];
     const LineParams lp = line_params(A.sp, pc, A.cut, nu0, A.L.A[i], A.L.E[i], A.L.gam[i],
-                                      A.L.nT[i], A.L.g[i]);
+                                      A.L.nT[i], A.L.g[i], A.L.J ? A.L.J[i] : (uint16_t)0);
     LineRec r;
     r.cut = lp.cut;
     r.ib = 1.0 / lp.bD;

@@ -40,7 +40,15 @@ struct SpeciesDev {
   const double* q_T;
   const double* q_val;
   int q_n;
-  // list statistics for the per-tile cutoff bound
+  // broadening partners (n_broad = 0: each line's gamma_ref and n_T): volume mixing
+  // ratios and tables over J, [n_broad][broad_nj]
+  int n_broad;
+  int broad_nj;
+  const double* broad_vmr;
+  const double* broad_gam;
+  const double* broad_n;
+  // list statistics for the per-tile cutoff bound: gamma_L <= (P/P_ref) gam_max
+  // (T_ref/T)^n for some n in [n_min, n_max]
   double gam_max, n_min, n_max;
 };
 
@@ -104,7 +112,7 @@ __host__ __device__ inline double voigt_fwhm(double gL, double bD) {
 __host__ __device__ inline LineParams line_params(const SpeciesDev& sp, const PtConst& pc,
                                                   const CutDev& cd, double nu0, float A,
                                                   float E, float gam, float nT,
-                                                  uint16_t g) {
+                                                  uint16_t g, uint16_t J) {
   LineParams lp;
   const double e = (double)E;
   if (sp.form == kEinstein) {
@@ -117,7 +125,18 @@ __host__ __device__ inline LineParams line_params(const SpeciesDev& sp, const Pt
     lp.S = (double)A * pc.q_ratio * boltz * stim;
   }
   lp.bD = nu0 / kCLight * pc.dopp;
-  lp.gL = (double)gam * pc.pfac * pow(pc.tratio, (double)nT);
+  if (sp.n_broad == 0) {
+    lp.gL = (double)gam * pc.pfac * pow(pc.tratio, (double)nT);
+  } else {
+    // the partners' widths at the line's J, weighted by their mixing ratios
+    const int j = (int)J < sp.broad_nj ? (int)J : sp.broad_nj - 1;
+    double s = 0.0;
+    for (int b = 0; b < sp.n_broad; ++b) {
+      const int t = b * sp.broad_nj + j;
+      s += sp.broad_vmr[b] * sp.broad_gam[t] * pow(pc.tratio, sp.broad_n[t]);
+    }
+    lp.gL = s * pc.pfac;
+  }
   if (cd.kind == kCutFixed) {
     lp.cut = cd.cut;
   } else {

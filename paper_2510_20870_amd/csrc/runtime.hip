@@ -549,6 +549,31 @@ int xs_load_lines(xs_ctx* c, const xs_lines_desc* d, const xs_species_desc* sp, 
   } else {
     return fail(XS_EINVAL, "unknown q_kind %d", sp->q_kind);
   }
+  // broadening partners: mixing ratios and tables over J
+  const int nb = sp->n_broad;
+  const size_t nj = nb > 0 ? sp->broad_nj : 0;
+  double bg_max = 0.0, bn_min = 0.0, bn_max = 0.0;
+  if (nb < 0 || nb > 8) return fail(XS_EINVAL, "n_broad must be in [0, 8] (got %d)", nb);
+  if (nb > 0) {
+    if (nj < 1 || nj > 4096 || !sp->broad_vmr || !sp->broad_gamma || !sp->broad_n)
+      return fail(XS_EINVAL, "broadening needs broad_vmr, broad_gamma, broad_n and "
+                             "1 <= broad_nj <= 4096");
+    for (int b = 0; b < nb; ++b) {
+      if (!(sp->broad_vmr[b] >= 0.0) || !isfinite(sp->broad_vmr[b]))
+        return fail(XS_EINVAL, "broad_vmr[%d] invalid", b);
+      double gb = 0.0;
+      for (size_t j = 0; j < nj; ++j) {
+        const double g = sp->broad_gamma[b * nj + j], nn = sp->broad_n[b * nj + j];
+        if (!(g >= 0.0) || !isfinite(g) || !isfinite(nn))
+          return fail(XS_EINVAL, "broadening table %d entry %zu invalid", b, j);
+        gb = std::max(gb, g);
+        if (b == 0 && j == 0) bn_min = bn_max = nn;
+        bn_min = std::min(bn_min, nn);
+        bn_max = std::max(bn_max, nn);
+      }
+      bg_max += sp->broad_vmr[b] * gb;
+    }
+  }
   // validate records; find whether they are sorted
   bool sorted = true;
   double gmax = 0.0, nmin = 0.0, nmax = 0.0;
@@ -582,7 +607,10 @@ int xs_load_lines(xs_ctx* c, const xs_lines_desc* d, const xs_species_desc* sp, 
   const size_t b_nu = al(n * 8), b_f = al(n * 4), b_g = al(n * 2);
   const size_t qn = sp->q_kind == XS_Q_TABLE ? sp->q_n : 0;
   const size_t b_q = al(qn * 8);
-  L->bytes = b_nu + 4 * b_f + b_g + 2 * b_q;
+  const bool has_j = nb > 0 && d->J_low;
+  const size_t b_j = has_j ? b_g : 0;
+  const size_t b_bv = al((size_t)nb * 8), b_bt = al((size_t)nb * nj * 8);
+  L->bytes = b_nu + 4 * b_f + b_g + 2 * b_q + b_j + b_bv + 2 * b_bt;
   int rc = c->dev_alloc(&L->base, L->bytes, "line list");
   if (rc) {
     delete L;
@@ -596,7 +624,11 @@ int xs_load_lines(xs_ctx* c, const xs_lines_desc* d, const xs_species_desc* sp, 
   float* n_d = (float*)p; p += b_f;
   uint16_t* u_d = (uint16_t*)p; p += b_g;
   double* qT_d = (double*)p; p += b_q;
-  double* qV_d = (double*)p;
+  double* qV_d = (double*)p; p += b_q;
+  uint16_t* j_d = (uint16_t*)p; p += b_j;
+  double* bv_d = (double*)p; p += b_bv;
+  double* bg_d = (double*)p; p += b_bt;
+  double* bn_d = (double*)p;
   auto put = [&](void* dst, const void* src, size_t esz) -> hipError_t {
     if (n == 0) return hipSuccess;
     if (sorted) return hipMemcpy(dst, src, n * esz, hipMemcpyHostToDevice);
@@ -614,6 +646,12 @@ int xs_load_lines(xs_ctx* c, const xs_lines_desc* d, const xs_species_desc* sp, 
   if (e == hipSuccess) e = put(u_d, d->g_up, 2);
   if (e == hipSuccess && qn) e = hipMemcpy(qT_d, sp->q_T, qn * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess && qn) e = hipMemcpy(qV_d, sp->q_val, qn * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess && has_j) e = put(j_d, d->J_low, 2);
+  if (e == hipSuccess && nb > 0) {
+    e = hipMemcpy(bv_d, sp->broad_vmr, (size_t)nb * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(bg_d, sp->broad_gamma, nb * nj * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(bn_d, sp->broad_n, nb * nj * 8, hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     c->dev_free(L->base, L->bytes);
     delete L;
@@ -625,6 +663,7 @@ int xs_load_lines(xs_ctx* c, const xs_lines_desc* d, const xs_species_desc* sp, 
   L->dev.gam = g_d;
   L->dev.nT = n_d;
   L->dev.g = u_d;
+  L->dev.J = has_j ? j_d : nullptr;
   L->dev.n = (int64_t)n;
   L->sp.form = sp->strength_form == XS_EINSTEIN_A ? kEinstein : kReference;
   L->sp.q_kind = sp->q_kind == XS_Q_POWER ? kQPower : kQTable;
@@ -636,9 +675,16 @@ int xs_load_lines(xs_ctx* c, const xs_lines_desc* d, const xs_species_desc* sp, 
   L->sp.q_T = qn ? qT_d : nullptr;
   L->sp.q_val = qn ? qV_d : nullptr;
   L->sp.q_n = (int)qn;
-  L->sp.gam_max = gmax;
-  L->sp.n_min = nmin;
-  L->sp.n_max = nmax;
+  L->sp.n_broad = nb;
+  L->sp.broad_nj = (int)nj;
+  L->sp.broad_vmr = nb > 0 ? bv_d : nullptr;
+  L->sp.broad_gam = nb > 0 ? bg_d : nullptr;
+  L->sp.broad_n = nb > 0 ? bn_d : nullptr;
+  // bounds of gamma_L for the per-tile cutoff bound: the lines' own gamma_ref and n_T, or
+  // with partners sum_b vmr_b max_j gamma_b and the tables' range of n
+  L->sp.gam_max = nb > 0 ? bg_max : gmax;
+  L->sp.n_min = nb > 0 ? bn_min : nmin;
+  L->sp.n_max = nb > 0 ? bn_max : nmax;
   // host index: every kSampleStride-th centre of the sorted list
   for (size_t i = 0; i < n; i += (size_t)kSampleStride)
     L->sample.push_back(sorted ? d->nu0[i] : d->nu0[order[i]]);

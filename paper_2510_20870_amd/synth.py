@@ -159,6 +159,25 @@ def wavelength_grid_um(lam_min: float, lam_max: float, resolving_power: float) -
     return lam_min * np.exp(np.arange(n, dtype=np.float64) / resolving_power)
 
 
+# ------------------------------------------------------------- broadening partners
+def j_low(E_low, B_rot: float = 10.0) -> np.ndarray:
+    """Lower-state J for synthetic lines: the rigid-rotor level nearest to E'' =
+    B J (J + 1) ~ B J^2, J = round(sqrt(E''/B)) with B = 10 cm^-1 (a light hydride), as
+    uint16."""
+    J = np.rint(np.sqrt(np.asarray(E_low, np.float64) / B_rot))
+    return np.minimum(J, 65535).astype(np.uint16)
+
+
+def broadening_partners(nj: int = 81) -> Dict[str, np.ndarray]:
+    """Two broadening partners with H2- and He-like tables over J = 0 .. nj-1 (synthetic
+    stand-ins for ExoMol broadening files): gamma falling slowly with J, n_T falling
+    linearly, volume mixing ratios 0.85 and 0.15."""
+    J = np.arange(nj, dtype=np.float64)
+    gamma = np.stack([0.09 / np.sqrt(1.0 + J / 15.0), 0.045 / np.sqrt(1.0 + J / 25.0)])
+    n = np.stack([0.65 - 0.003 * J, 0.50 - 0.002 * J])
+    return {"vmr": np.array([0.85, 0.15]), "gamma": gamma, "n": n}
+
+
 # ----------------------------------------------------------------------- P, T sets
 def pt_table(p_lo: float, p_hi: float, n_p: int, t_lo: float, t_hi: float,
              n_t: int) -> np.ndarray:

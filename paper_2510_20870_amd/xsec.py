@@ -46,14 +46,16 @@ class XsError(RuntimeError):
 class LinesDesc(C.Structure):
     _fields_ = [("n", C.c_size_t), ("nu0", C.c_void_p), ("A_or_Sref", C.c_void_p),
                 ("E_low", C.c_void_p), ("gamma_ref", C.c_void_p), ("n_T", C.c_void_p),
-                ("g_up", C.c_void_p)]
+                ("g_up", C.c_void_p), ("J_low", C.c_void_p)]
 
 
 class SpeciesDesc(C.Structure):
     _fields_ = [("strength_form", C.c_int), ("mass_amu", C.c_double), ("T_ref", C.c_double),
                 ("P_ref", C.c_double), ("q_kind", C.c_int), ("q_a", C.c_double),
                 ("q_b", C.c_double), ("q_T", C.c_void_p), ("q_val", C.c_void_p),
-                ("q_n", C.c_size_t)]
+                ("q_n", C.c_size_t), ("n_broad", C.c_int), ("broad_nj", C.c_size_t),
+                ("broad_vmr", C.c_void_p), ("broad_gamma", C.c_void_p),
+                ("broad_n", C.c_void_p)]
 
 
 class Pt(C.Structure):
@@ -385,7 +387,10 @@ class Context:
     def load_lines(self, lines: Dict[str, np.ndarray], mass_amu: float,
                    strength_form: int = XS_EINSTEIN_A, q_a: float = 0.0343, q_b: float = 1.5,
                    q_table: Optional[Sequence[Sequence[float]]] = None,
-                   T_ref: float = 296.0, P_ref: float = 1.0) -> int:
+                   T_ref: float = 296.0, P_ref: float = 1.0,
+                   broadening: Optional[Dict[str, np.ndarray]] = None) -> int:
+        """Load a line list. broadening (optional): {"vmr": [B], "gamma": [B][nj],
+        "n": [B][nj]} partner tables over J, with the lines' "J_low"."""
         arrs = {
             "nu0": np.ascontiguousarray(lines["nu0"], np.float64),
             "A": np.ascontiguousarray(lines["A"], np.float32),
@@ -394,9 +399,12 @@ class Context:
             "n_T": np.ascontiguousarray(lines["n_T"], np.float32),
             "g_up": np.ascontiguousarray(lines["g_up"], np.uint16),
         }
+        if "J_low" in lines:
+            arrs["J_low"] = np.ascontiguousarray(lines["J_low"], np.uint16)
         n = len(arrs["nu0"])
         d = LinesDesc(n, _ptr(arrs["nu0"]), _ptr(arrs["A"]), _ptr(arrs["E_low"]),
-                      _ptr(arrs["gamma"]), _ptr(arrs["n_T"]), _ptr(arrs["g_up"]))
+                      _ptr(arrs["gamma"]), _ptr(arrs["n_T"]), _ptr(arrs["g_up"]),
+                      _ptr(arrs["J_low"]) if "J_low" in arrs else None)
         if q_table is not None:
             qT = np.ascontiguousarray(q_table[0], np.float64)
             qV = np.ascontiguousarray(q_table[1], np.float64)
@@ -405,6 +413,14 @@ class Context:
         else:
             sp = SpeciesDesc(strength_form, mass_amu, T_ref, P_ref, XS_Q_POWER, q_a, q_b,
                              None, None, 0)
+        if broadening is not None:
+            bv = np.ascontiguousarray(broadening["vmr"], np.float64).ravel()
+            bg = np.ascontiguousarray(broadening["gamma"], np.float64).reshape(len(bv), -1)
+            bn = np.ascontiguousarray(broadening["n"], np.float64).reshape(bg.shape)
+            arrs.update(bv=bv, bg=bg, bn=bn)   # kept alive until the call returns
+            sp.n_broad = len(bv)
+            sp.broad_nj = bg.shape[1]
+            sp.broad_vmr, sp.broad_gamma, sp.broad_n = _ptr(bv), _ptr(bg), _ptr(bn)
         h = C.c_uint64()
         self._check(self._L.xs_load_lines(self.h, C.byref(d), C.byref(sp), C.byref(h)))
         return h.value

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
     # the binding covers every declared entry point
     assert set(decl) <= set(xsec.exported_symbols())
-    assert L.xs_abi_version() == 2
+    assert L.xs_abi_version() == 3
 
 
 def test_no_compute_without_device_is_a_clean_error():

@@ -397,3 +397,42 @@ def test_fixed_resolving_power_grid(ctx):
     ctx.free_grid(g)
     with pytest.raises(X.XsError):
         ctx.set_grid_wavelength(2.0, 1.0, 1e4)
+
+
+def test_broadening_partners(ctx):
+    # two partners with tables over J (J from the synthetic lower-state energies), fixed
+    # and FWHM cuts, FP32 and FP64 paths, against the oracle
+    W, L, grid = _tiny()
+    L = dict(L, J_low=synth.j_low(L["E_low"]))
+    bp = synth.broadening_partners()
+    h = ctx.load_lines(L, W.mass_amu, broadening=bp)
+    g = ctx.set_grid(grid)
+    pts = [(1.0, 1000.0), (30.0, 400.0), (1e-3, 2500.0)]
+    for kind, f64 in (("fixed", False), ("min_fwhm", False), ("fixed", True)):
+        sig = ctx.compute(h, g, pts, _opts(kind, 10.0, 100.0, f64=f64))
+        for k, (P, T) in enumerate(pts):
+            ref = O.sigma(L, grid, P, T, W.mass_amu, cut_kind=kind, cut_cm1=10.0,
+                          fwhm_mult=100.0, broadening=bp)
+            _check(sig[k], ref, tol=1e-5 if not f64 else 1e-10,
+                   label=f"partners {kind} f64={f64} P={P} T={T}")
+    # a single partner whose table holds each line's own gamma and n_T (line i at J = i)
+    # reproduces the per-line form
+    n = 4000
+    Ls = {key: v[:n] for key, v in L.items()}
+    Ls["J_low"] = np.arange(n, dtype=np.uint16)
+    own = {"vmr": [1.0], "gamma": Ls["gamma"].astype(np.float64)[None],
+           "n": Ls["n_T"].astype(np.float64)[None]}
+    h1 = ctx.load_lines(Ls, W.mass_amu)
+    h2 = ctx.load_lines(Ls, W.mass_amu, broadening=own)
+    a = ctx.compute(h1, g, pts, _opts(f64=True))
+    b = ctx.compute(h2, g, pts, _opts(f64=True))
+    assert np.allclose(a, b, rtol=1e-12, atol=0)
+    ctx.unload_lines(h1)
+    ctx.unload_lines(h2)
+    ctx.unload_lines(h)
+    ctx.free_grid(g)
+    X = _xsec()
+    with pytest.raises(X.XsError) as e:
+        ctx.load_lines(L, W.mass_amu, broadening={"vmr": [-0.1], "gamma": bp["gamma"][:1],
+                                                  "n": bp["n"][:1]})
+    assert e.value.code == X.XS_EINVAL

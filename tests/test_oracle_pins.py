@@ -158,6 +158,50 @@ def test_lorentz_special_cases():
     assert O.lorentz_width(0.05, 0.0, 2.0, 1500.0) == pytest.approx(0.1, rel=1e-15, abs=0)
 
 
+def test_broadening_partners_special_cases():
+    from paper_2510_20870_amd import synth
+    bp = synth.broadening_partners(nj=11)
+    J = np.array([0, 3, 10, 11, 400], np.uint16)        # the last two beyond the table
+    # at T = T_ref every temperature exponent drops out: (P/P_ref) sum_b vmr_b gamma_b(J)
+    g = O.lorentz_width_partners(J, 2.0, 296.0, bp["vmr"], bp["gamma"], bp["n"])
+    jj = np.minimum(J, 10)
+    hand = 2.0 * (0.85 * 0.09 / np.sqrt(1 + jj / 15.0) + 0.15 * 0.045 / np.sqrt(1 + jj / 25.0))
+    assert np.allclose(g, hand, rtol=1e-15, atol=0)
+    # J beyond the table takes its last entry
+    assert g[3] == g[2] and g[4] == g[2]
+    # one partner split into two with the same table changes nothing
+    one = O.lorentz_width_partners(J, 0.3, 1700.0, [1.0], bp["gamma"][:1], bp["n"][:1])
+    two = O.lorentz_width_partners(J, 0.3, 1700.0, [0.4, 0.6],
+                                   np.repeat(bp["gamma"][:1], 2, 0), np.repeat(bp["n"][:1], 2, 0))
+    assert np.allclose(one, two, rtol=1e-15, atol=0)
+    # a single partner with vmr 1 whose tables hold each line's own gamma and n_T is the
+    # one-broadener form, line by line
+    rng = np.random.default_rng(3)
+    tab_g = rng.uniform(0.03, 0.1, 20).astype(np.float32).astype(np.float64)
+    tab_n = rng.uniform(0.4, 0.8, 20).astype(np.float32).astype(np.float64)
+    Jl = rng.integers(0, 20, 500).astype(np.uint16)
+    per_line = O.lorentz_width(tab_g[Jl], tab_n[Jl], 5.0, 900.0)
+    partners = O.lorentz_width_partners(Jl, 5.0, 900.0, [1.0], tab_g[None], tab_n[None])
+    assert np.allclose(per_line, partners, rtol=1e-14, atol=0)
+    # and through line_parameters: the same widths, strengths and cuts
+    L = {"nu0": np.linspace(1000, 1010, 500), "A": np.full(500, 1.0, np.float32),
+         "E_low": np.full(500, 100.0, np.float32),
+         "gamma": tab_g[Jl].astype(np.float32), "n_T": tab_n[Jl].astype(np.float32),
+         "g_up": np.full(500, 3, np.uint16), "J_low": Jl}
+    a = O.line_parameters(L, 5.0, 900.0, 18.0, cut_kind="min_fwhm", cut_cm1=25.0)
+    b = O.line_parameters(L, 5.0, 900.0, 18.0, cut_kind="min_fwhm", cut_cm1=25.0,
+                          broadening={"vmr": [1.0], "gamma": tab_g[None], "n": tab_n[None]})
+    for key in ("S", "b_D", "gamma_L", "cut"):
+        assert np.allclose(a[key], b[key], rtol=1e-14, atol=0), key
+
+
+def test_j_low_recipe():
+    from paper_2510_20870_amd import synth
+    E = np.array([0.0, 10.0, 39.9, 40.1, 1e4, 1e12], np.float32)
+    # J = round(sqrt(E / 10)): 0, 1, 2 (sqrt 3.99 = 1.997), 2, 32, capped at 65535
+    assert synth.j_low(E).tolist() == [0, 1, 2, 2, 32, 65535]
+
+
 # ------------------------------------------------------------------ strengths
 def test_strength_from_einstein_b_route():
     """The integrated absorption cross-section from the Einstein-B coefficient, in SI,
