@@ -341,6 +341,18 @@ int xs_tune_cache_save(const char *path);
 int xs_set_kernel_timing(xs_ctx *ctx, int enable);
 int xs_kernel_time(xs_ctx *ctx, double *ms_sum, int *n_launches);
 
+/* Collision-induced absorption ("Download and read files", "Combine and save": the paper
+ * restructures CIA coefficients onto a wavelength- and temperature-dependent grid). The
+ * database gives, per temperature, coefficients alpha at its own increasing wavenumbers:
+ * n_blocks blocks, block k holding the nodes [offsets[k], offsets[k+1]) of nu_cm1 and
+ * alpha (host arrays, offsets of n_blocks + 1 entries, offsets[0] = 0; nu strictly
+ * increasing within a block). Every block is interpolated linearly in nu onto `grid`
+ * (zero outside the block's range, its end nodes included):
+ * out[k * n_grid + j] (host memory, float64, caller-owned). The temperatures are the
+ * caller's bookkeeping. XS_EINVAL for bad offsets or non-finite / unsorted nodes. */
+int xs_cia_regrid(xs_ctx *ctx, xs_grid_t grid, const size_t *offsets, size_t n_blocks,
+                  const double *nu_cm1, const double *alpha, double *out);
+
 /* The Voigt function K(x, y) = Re w(x + iy) as the kernels evaluate it, for n host
  * points: on the device (xs_eval_voigt) or compiled for the host (xs_eval_voigt_host).
  * precision: XS_FP32_KAHAN (FP32 tiers) or XS_FP64. */

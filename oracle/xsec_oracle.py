@@ -293,6 +293,16 @@ def sigma_parallel(lines, grid, workers: Optional[int] = None, chunk: int = 256,
     return np.concatenate(parts)
 
 
+# ----------------------------------------------------- collision-induced absorption
+def cia_regrid(grid: np.ndarray, blocks) -> np.ndarray:
+    """Collision-induced absorption restructured onto a grid ("Combine and save"): every
+    (nu, alpha) block (one per temperature, nu increasing) interpolated linearly in nu
+    onto `grid` by numpy.interp, zero outside the block's range. [n_blocks, n_grid]."""
+    grid = np.asarray(grid, np.float64)
+    return np.stack([np.interp(grid, np.asarray(nu, np.float64), np.asarray(a, np.float64),
+                               left=0.0, right=0.0) for nu, a in blocks])
+
+
 # --------------------------------------------------------------- acceptance metric
 def compare(sig: np.ndarray, ref: np.ndarray, rel_tol: float = 1e-4,
             floor: float = 1e-8, ref_max: Optional[float] = None) -> Dict[str, float]:

@@ -83,6 +83,10 @@ hipError_t launch_tile_p4(const TileArgs& A, bool f64, int W, hipStream_t st, di
 hipError_t launch_tile_p8(const TileArgs& A, bool f64, int W, hipStream_t st, dim3 grid);
 hipError_t launch_reduce(const double* part, double* out, int64_t n_grid, int n_pts, int split,
                          hipStream_t st);
+// collision-induced absorption: block k (nodes [off[k], off[k+1]) of nu, alpha) linearly
+// interpolated onto the grid, zero outside the block, out[k][j]
+hipError_t launch_cia(const double* grid, int64_t n_grid, const int64_t* off, int n_blocks,
+                      const double* nu, const double* alpha, double* out, hipStream_t st);
 hipError_t launch_eval_voigt(const double* x, const double* y, int64_t n, int f64,
                              double* out, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);

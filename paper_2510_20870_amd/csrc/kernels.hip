@@ -221,6 +221,39 @@ __global__ void xs_fill_uniform_kernel(double* __restrict__ g, int64_t n, double
   if (t < n) g[t] = __dadd_rn(a, __dmul_rn((double)t, h));
 }
 
+// Collision-induced absorption restructured onto the grid ("Combine and save": CIA
+// coefficients on a wavelength- and temperature-dependent grid): one thread per (block,
+// grid point); the bracketing nodes by binary search, linear interpolation between them,
+// zero outside the block's range (the end nodes included).
+__global__ void xs_cia_kernel(const double* __restrict__ grid, int64_t n_grid,
+                              const int64_t* __restrict__ off, int n_blocks,
+                              const double* __restrict__ nu, const double* __restrict__ alpha,
+                              double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_grid * n_blocks) return;
+  const int k = (int)(t / n_grid);
+  const int64_t j = t - (int64_t)k * n_grid;
+  const double v = grid[j];
+  const int64_t a = off[k], b = off[k + 1];
+  double r = 0.0;
+  if (b > a && v >= nu[a] && v <= nu[b - 1]) {
+    // last node <= v
+    int64_t lo = a, hi = b - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (nu[mid] <= v) lo = mid;
+      else hi = mid - 1;
+    }
+    if (lo == b - 1) {
+      r = alpha[lo];
+    } else {
+      const double f = (v - nu[lo]) / (nu[lo + 1] - nu[lo]);
+      r = alpha[lo] + f * (alpha[lo + 1] - alpha[lo]);
+    }
+  }
+  out[t] = r;
+}
+
 __global__ void xs_eval_voigt_kernel(const double* __restrict__ x, const double* __restrict__ y,
                                      int64_t n, int f64, double* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -299,6 +332,15 @@ hipError_t launch_fill_uniform(double* g, int64_t n, double a, double h, hipStre
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(xs_fill_uniform_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, n, a,
                      h);
+  return hipGetLastError();
+}
+
+hipError_t launch_cia(const double* grid, int64_t n_grid, const int64_t* off, int n_blocks,
+                      const double* nu, const double* alpha, double* out, hipStream_t st) {
+  const int64_t total = n_grid * n_blocks;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(xs_cia_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     grid, n_grid, off, n_blocks, nu, alpha, out);
   return hipGetLastError();
 }
 

@@ -1062,6 +1062,55 @@ void xs_graph_destroy(xs_graph* g) {
   delete g;
 }
 
+int xs_cia_regrid(xs_ctx* c, xs_grid_t gh, const size_t* off, size_t nb, const double* nu,
+                  const double* alpha, double* out) {
+  if (!c || !off || !out) return fail(XS_EINVAL, "NULL argument");
+  if (nb == 0 || nb > (1u << 20)) return fail(XS_EINVAL, "n_blocks must be in [1, 2^20]");
+  if (off[0] != 0) return fail(XS_EINVAL, "offsets[0] must be 0");
+  for (size_t k = 0; k < nb; ++k)
+    if (off[k + 1] < off[k]) return fail(XS_EINVAL, "offsets must not decrease (block %zu)", k);
+  const size_t n_nodes = off[nb];
+  if (n_nodes && (!nu || !alpha)) return fail(XS_EINVAL, "NULL node arrays");
+  for (size_t k = 0; k < nb; ++k)
+    for (size_t i = off[k]; i < off[k + 1]; ++i) {
+      if (!isfinite(nu[i]) || !isfinite(alpha[i]))
+        return fail(XS_EINVAL, "node %zu of block %zu not finite", i, k);
+      if (i > off[k] && !(nu[i] > nu[i - 1]))
+        return fail(XS_EINVAL, "block %zu: wavenumbers not increasing at node %zu", k, i);
+    }
+  GridRes* G;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    G = c->find_grid(gh);
+  }
+  if (!G) return fail(XS_ENOTFOUND, "unknown grid");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  const size_t b_off = ((nb + 1) * 8 + 255) & ~(size_t)255;
+  const size_t b_nodes = (n_nodes * 8 + 255) & ~(size_t)255;
+  const size_t b_out = (size_t)nb * G->n * 8;
+  const size_t total = b_off + 2 * b_nodes + b_out;
+  void* buf = nullptr;
+  int rc = c->dev_alloc(&buf, total, "CIA buffers");
+  if (rc) return rc;
+  char* p = (char*)buf;
+  int64_t* d_off = (int64_t*)p;
+  double* d_nu = (double*)(p + b_off);
+  double* d_al = (double*)(p + b_off + b_nodes);
+  double* d_out = (double*)(p + b_off + 2 * b_nodes);
+  std::vector<int64_t> o64(nb + 1);
+  for (size_t k = 0; k <= nb; ++k) o64[k] = (int64_t)off[k];
+  e = hipMemcpy(d_off, o64.data(), (nb + 1) * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess && n_nodes) e = hipMemcpy(d_nu, nu, n_nodes * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess && n_nodes) e = hipMemcpy(d_al, alpha, n_nodes * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = launch_cia(G->d, (int64_t)G->n, d_off, (int)nb, d_nu, d_al, d_out, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(out, d_out, b_out, hipMemcpyDeviceToHost);
+  c->dev_free(buf, total);
+  if (e != hipSuccess) return hip_fail(e, "CIA regrid");
+  return XS_OK;
+}
+
 int xs_eval_voigt(xs_ctx* c, const double* x, const double* y, size_t n, int precision,
                   double* K_out) {
   if (!c || (n && (!x || !y || !K_out))) return fail(XS_EINVAL, "NULL argument");

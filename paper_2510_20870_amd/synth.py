@@ -178,6 +178,29 @@ def broadening_partners(nj: int = 81) -> Dict[str, np.ndarray]:
     return {"vmr": np.array([0.85, 0.15]), "gamma": gamma, "n": n}
 
 
+# ------------------------------------------------------ collision-induced absorption
+def cia_blocks(temps: Sequence[float], nu_lo: float = 20.0, nu_hi: float = 10000.0,
+               seed: int = 0):
+    """Synthetic stand-in for a HITRAN-style CIA file: one block per temperature, nodes
+    at increasing wavenumbers with irregular steps U(0.5, 2) cm^-1 from a start and to an
+    end that vary by block, coefficients positive, smooth in nu with three bands whose
+    strength grows with T. [(nu, alpha), ...]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for T in temps:
+        lo = nu_lo + rng.uniform(0.0, 50.0)
+        hi = nu_hi - rng.uniform(0.0, 500.0)
+        steps = rng.uniform(0.5, 2.0, int((hi - lo) / 0.5) + 2)
+        nu = lo + np.concatenate([[0.0], np.cumsum(steps)])
+        nu = nu[nu <= hi]
+        t = T / 1000.0
+        alpha = 1e-46 * (np.exp(-(nu / 600.0) ** 2) * (1 + t)
+                         + 0.3 * t * np.exp(-((nu - 4160.0) / 300.0) ** 2)
+                         + 0.05 * t * t * np.exp(-((nu - 8300.0) / 400.0) ** 2) + 1e-4)
+        out.append((nu, alpha))
+    return out
+
+
 # ----------------------------------------------------------------------- P, T sets
 def pt_table(p_lo: float, p_hi: float, n_p: int, t_lo: float, t_hi: float,
              n_t: int) -> np.ndarray:

@@ -146,6 +146,8 @@ _SIGS = {
                              C.c_void_p], C.c_int),
     "xs_eval_bounds_host": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p],
                             C.c_int),
+    "xs_cia_regrid": ([C.c_void_p, C.c_uint64, C.c_void_p, C.c_size_t, C.c_void_p,
+                       C.c_void_p, C.c_void_p], C.c_int),
     "xs_wavelength_grid_host": ([C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_size_t,
                                  C.POINTER(C.c_size_t)], C.c_int),
     "xs_set_grid_wavelength": ([C.c_void_p, C.c_double, C.c_double, C.c_double,
@@ -449,6 +451,21 @@ class Context:
                                                    float(lambda_max_um), float(R),
                                                    C.byref(h), C.byref(n)))
         return h.value, wavelength_grid(lambda_min_um, lambda_max_um, R)
+
+    def cia_regrid(self, grid: int, blocks) -> np.ndarray:
+        """Collision-induced absorption: blocks = [(nu, alpha), ...] (one per temperature,
+        nu increasing), each interpolated linearly onto the grid (zero outside its range):
+        [n_blocks, n_grid]."""
+        nus = [np.ascontiguousarray(b[0], np.float64) for b in blocks]
+        als = [np.ascontiguousarray(b[1], np.float64) for b in blocks]
+        off = np.zeros(len(blocks) + 1, np.uint64)
+        off[1:] = np.cumsum([len(v) for v in nus])
+        nu = np.ascontiguousarray(np.concatenate(nus) if nus else np.zeros(0), np.float64)
+        al = np.ascontiguousarray(np.concatenate(als) if als else np.zeros(0), np.float64)
+        out = np.empty((len(blocks), self.grid_len(grid)), np.float64)
+        self._check(self._L.xs_cia_regrid(self.h, grid, _ptr(off), len(blocks), _ptr(nu),
+                                          _ptr(al), _ptr(out)))
+        return out
 
     def free_grid(self, h: int):
         self._check(self._L.xs_free_grid(self.h, h))

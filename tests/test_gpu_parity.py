@@ -436,3 +436,25 @@ def test_broadening_partners(ctx):
         ctx.load_lines(L, W.mass_amu, broadening={"vmr": [-0.1], "gamma": bp["gamma"][:1],
                                                   "n": bp["n"][:1]})
     assert e.value.code == X.XS_EINVAL
+
+
+def test_cia_regrid(ctx):
+    # irregular per-temperature blocks of different ranges onto a grid reaching beyond
+    # them, with grid points on nodes, against numpy.interp
+    X = _xsec()
+    temps = [200.0, 600.0, 1000.0, 2000.0, 3000.0]
+    blocks = synth.cia_blocks(temps, seed=4)
+    grid = np.unique(np.concatenate([np.linspace(0.0, 10500.0, 40_001), blocks[2][0][::97]]))
+    g = ctx.set_grid(grid[grid > 0])
+    gv = grid[grid > 0]
+    out = ctx.cia_regrid(g, blocks)
+    ref = O.cia_regrid(gv, blocks)
+    assert out.shape == (len(temps), len(gv))
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(out - ref)) / scale
+    print(f"[cia] max error {err:.3e} of the largest coefficient", flush=True)
+    assert err < 1e-13
+    assert np.array_equal(out == 0.0, ref == 0.0)
+    with pytest.raises(X.XsError):
+        ctx.cia_regrid(g, [(np.array([2.0, 1.0]), np.array([1.0, 1.0]))])
+    ctx.free_grid(g)

@@ -475,3 +475,24 @@ def test_planted_mistakes_are_caught(monkeypatch):
     with pytest.raises(AssertionError):
         test_doppler_width_matches_maxwell_velocity_variance()
     monkeypatch.setattr(O, "doppler_width", orig_d)
+
+
+def test_cia_regrid_is_linear_interpolation():
+    # linear data is reproduced exactly between the nodes, the nodes themselves exactly,
+    # and nothing outside a block's range
+    nu = np.array([10.0, 11.5, 13.0, 20.0, 21.0])
+    a = 3.0 * nu - 7.0
+    grid = np.array([5.0, 10.0, 10.75, 12.0, 16.5, 21.0, 21.5])
+    out = O.cia_regrid(grid, [(nu, a), (nu[:3], a[:3])])
+    inside = (grid >= 10.0) & (grid <= 21.0)
+    assert np.allclose(out[0][inside], 3.0 * grid[inside] - 7.0, rtol=1e-15, atol=1e-13)
+    assert np.all(out[0][~inside] == 0.0)
+    assert out[1][1] == a[0] and out[1][3] == 29.0 and np.all(out[1][4:] == 0.0)
+    # a block sampled from a smooth function converges at second order in the step
+    f = lambda v: np.sin(v / 3.0)
+    g = np.linspace(0.0, 30.0, 997)
+    errs = []
+    for h in (0.4, 0.2, 0.1):
+        x = np.arange(0.0, 30.0 + h / 2, h)
+        errs.append(np.max(np.abs(O.cia_regrid(g, [(x, f(x))])[0] - f(g))))
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5
