@@ -11,33 +11,37 @@
 //    of once per tile that visits it, and the transcendental FP64 code stays out of the
 //    register budget of the tile kernel.
 //
-// 2. xs_tile_kernel (VALU-bound). One work item = (grid tile, (P, T) point, line split).
-//    A tile is 64 * P consecutive grid points owned by ONE wavefront: lane l holds points
-//    j0 + 64 p + l for p < P, so each of the P rows is 64 consecutive points. Waves are
-//    independent: no workgroup barrier and no atomics on results. Per item the wave
+// 2. xs_tile_kernel (VALU-bound; tile_kernel.h, instantiated in tile_p*.hip). One work
+//    item = (grid tile, (P, T) point, line split). A tile is 64 * P consecutive grid
+//    points owned by ONE wavefront: lane l holds points j0 + 64 p + l for p < P, so each
+//    of the P rows is 64 consecutive points. Waves are independent: no workgroup barrier
+//    and no atomics on results. Per item the wave
 //      a. bounds the cutoff of every line that can reach the tile (cut_bound),
 //      b. finds the line window [lo, hi) by a 64-ary search on the sorted centres (one
 //         load per lane per level, five levels for 1e9 lines),
 //      c. walks the window in chunks of 64 lines: each lane loads one line's centre and
 //         record (coalesced), classifies the line against each row and writes a record to
-//         the wave's LDS slice; after a wave-level fence every lane reads the records back
-//         as LDS broadcasts and evaluates its points against each line,
+//         the wave's LDS slice grouped by mode; after a wave-level fence every lane reads
+//         the records back as LDS broadcasts and evaluates its points against each line,
 //      d. writes its sums: the final value, or a partial for the fixed-order reduction.
 //
-// Arithmetic of one (line, point) pair on the general path: d = nu_j - nu0 (FP64), the cut
-// test |d| <= cut (FP64), x = d / b_D (FP64, rounded once to FP32), K(x, y) from the FP32
-// asymptotic series outside |z| = 7 and in FP64 inside, then a Kahan-compensated FP32 add
-// (or a plain FP64 add on the FP64 path). Rows that lie entirely in the series region of a
-// line (the large majority) skip the FP64 offset and test: x = (nu_j - nu_end) / b_D + x_end
-// from the row's nearer end, in FP32 (relative error a few ulps since x does not change
-// sign along the row), with the shortest series the row's nearest point allows and the cut
-// applied as a lane bound found at staging time. FP32 contributions carry a power-of-two scale chosen per wavefront:
-// whenever a staged chunk holds a line stronger than any before, the scale is lowered so
-// the strongest line's scale is about 2^48 and the running sums are rescaled exactly, so
-// any absolute magnitude of sigma stays inside FP32 range; the scale is removed exactly
-// when the FP64 result is stored.
-
-
+// Arithmetic of one (line, point) pair: lines on one side of a row (the large majority)
+// take x = (nu_j - nu_end) / b_D + x_end from the row's nearer end in FP32 (x does not
+// change sign along the row, so there is no cancellation), the cheapest far-region form
+// the row's nearest point allows (a shifted Lorentzian, or the asymptotic series with 2 to
+// 6 terms) and the cut as a lane bound found at staging time with the FP64 test; rows a
+// line reaches inside |z| = 7 take x from the FP64 difference, the six-term series for
+// their points outside |z| = 7 and the FP64 Weideman core inside. Contributions are summed
+// in FP32 over blocks of 16 lines, each block added to a Kahan-compensated FP32 sum (a
+// plain FP64 sum on the FP64 path). FP32 contributions carry a power-of-two scale chosen
+// per wavefront: whenever a staged chunk holds a line stronger than any before, the scale
+// is lowered so the strongest line's scale is about 2^48 and the running sums are
+// rescaled exactly, so any absolute magnitude of sigma stays inside FP32 range; the scale
+// is removed exactly when the FP64 result is stored.
+//
+// Around them: the fixed-order reduction of split partials, the evaluation count by tier
+// (accounting), the main-contributor selection thresholds, the CIA regridding, fills and
+// the point evaluation of K used by the tests.
 
 #include "tile_kernel.h"
 

@@ -23,14 +23,15 @@
 //        K = (y / sqrt(pi)) / (x^2 + y^2 - 3/2)
 //    is within (3/2 + 2 y^2) u^2 relative of K; it is used where that bound is at most
 //    2e-7 (r^4 >= 5e6 (3/2 + 2 y^2)), which for y < 1.7 starts before |z| = 80.
-//  * core (|z| < 7): Weideman's (1994) rational series with N = 40 terms,
+//  * core (|z| < 7): Weideman's (1994) rational series with N terms,
 //        w(z) ~ 2 p(Z)/(L - iz)^2 + pi^{-1/2}/(L - iz),  Z = (L + iz)/(L - iz),
 //    L = 2^{-1/4} sqrt(N), evaluated in FP64: near the real axis Re w is tiny beside
-//    |w| (1e7 times smaller at y = 5e-7), and only FP64 keeps the cancellation below
-//    1e-8 relative there.
+//    |w| (1e7 times smaller at y = 5e-7), and only FP64 keeps the cancellation small
+//    there. The FP32 path takes N from y (16, 24, 32 or 40 terms, core_tier, each within
+//    2e-7); the FP64 path always N = 40 (8.5e-9).
 //
 // The FP64 path uses Gauss-Hermite quadrature (positive sums) outside |z| = 8 instead:
-// 4 nodes for |z| >= 40, 8 nodes for 8 <= |z| < 40, and the same Weideman core.
+// 4 nodes for |z| >= 40, 8 nodes for 8 <= |z| < 40, and the N = 40 Weideman core.
 #pragma once
 
 #include <hip/hip_runtime.h>
