@@ -197,7 +197,8 @@ int xs_compute(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts, 
                const xs_opts *opts, double *sigma_out, int out_on_device, void *stream);
 
 /* Number of (line, grid point) pairs inside the cutoff, per (P, T) point, counted on the
- * device with the same FP64 rule as xs_compute: counts_out[k] (host memory). */
+ * device with the same FP64 rule as xs_compute: counts_out[k] (host memory). With
+ * opts->select_eps > 0 only the pairs of the lines that selection keeps count. */
 int xs_count_evals(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts,
                    size_t npts, const xs_opts *opts, uint64_t *counts_out);
 

@@ -182,9 +182,10 @@ __global__ __launch_bounds__(kBlock) void xs_select_kernel(TileArgs A) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   double tau = 0.0;
-  if (acc > 0.0) {
+  const double budget = A.select_eps * acc;
+  // (a budget so small that its fixed-point unit would overflow drops nothing)
+  if (budget > 0x1p-960 && isfinite(budget)) {
     // bins: 0 for bounds below 2^elo, 1 + ilogb - elo for [2^elo, 2^eL), eL = ilogb(eps L)
-    const double budget = A.select_eps * acc;
     const int eL = ilogb(budget);
     const int elo = eL - 62;
     const double top = ldexp(1.0, eL), low = ldexp(1.0, elo);
