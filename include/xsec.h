@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define XS_ABI_VERSION 3
+#define XS_ABI_VERSION 4
 
 typedef enum {
   XS_OK = 0,
@@ -381,6 +381,19 @@ int xs_eval_series_host(const double *x, const double *y, size_t n, int variant,
  * may be NULL; y must be > 0 (XS_EINVAL otherwise). */
 int xs_eval_bounds_host(const double *x, const double *y, size_t n, double *K_lo,
                         double *K_hi);
+
+/* The FP32 path's polynomial for far lines, compiled for the host (FP32 arithmetic at the
+ * inputs rounded to FP32). A line whose shifted Lorentzian K = (y / sqrt(pi)) /
+ * (x^2 + y^2 - 3/2) holds over a whole tile, with every point of the tile inside the cut,
+ * is summed as a polynomial of degree 11 in the tile coordinate t in [-1, 1] when
+ * |X| >= 5 H + 1.25, X being x at the tile's centre and H the tile's half-width in
+ * Doppler units (section "Functionality of pyROX": the profile of every line inside the
+ * cutoff, here summed per tile instead of per point; truncation within 1.3e-7 relative).
+ * K_out[i]: that polynomial's K at x = X[i] + H[i] t[i]. Each case must meet the
+ * condition above, lie in the shifted-Lorentzian region at the tile's nearest point
+ * (|X| - H), have y > 0 and |t| <= 1 (XS_EINVAL otherwise). */
+int xs_eval_far_host(const double *X, const double *H, const double *y, const double *t,
+                     size_t n, double *K_out);
 
 #ifdef __cplusplus
 }

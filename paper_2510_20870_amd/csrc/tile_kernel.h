@@ -77,6 +77,29 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
+// Sum over the wavefront as a wave-uniform value: an inclusive scan with DPP (shifts by
+// 1, 2, 4, 8 inside each row of 16 lanes, then the broadcasts of lane 15 and lane 31 into
+// the rows above), whose last lane holds the total.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_add(float v) {
+  return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                                           0, __builtin_bit_cast(int, v), kCtrl, kRowMask,
+                                           0xf, false));
+}
+__device__ __forceinline__ float wave_total(float v) {
+  v = dpp_add<0x111, 0xf>(v);   // row_shr:1
+  v = dpp_add<0x112, 0xf>(v);   // row_shr:2
+  v = dpp_add<0x114, 0xf>(v);   // row_shr:4
+  v = dpp_add<0x118, 0xf>(v);   // row_shr:8
+  v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+// Far lines of a chunk are summed as one polynomial over the tile (far_coeffs) when at
+// least this many of its lines qualify (fewer cost less on the per-line walk).
+constexpr int kFarMinLines = 16;
+
 // Workgroups are dispatched round-robin over the 8 XCDs. Logical workgroups are grouped in
 // blocks of kXcdBlock consecutive ones (neighbouring tiles, which share most of their line
 // windows, so they reuse one XCD's L2), and the blocks are dealt round-robin to the XCDs,
@@ -471,6 +494,20 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     rowvals[wv][kWave * p + lane] = nu[p];
   }
   wave_sync();
+  // FP32 path: the tile's centre and half-width (over its valid points) for the far-line
+  // polynomial; a point's coordinate t in [-1, 1] is da32 * f_ih + f_t0 of its row
+  [[maybe_unused]] float f_h = 0.0f, f_ih = 0.0f, f_ca = 0.0f, f_cb = 0.0f, f_t0[P];
+  if constexpr (!F64) {
+    const double g0 = A.grid[it.j0];
+    const double nc = 0.5 * (g0 + it.nu_last), h = 0.5 * (it.nu_last - g0);
+    const double ih = h > 0.0 ? 1.0 / h : 0.0;
+    f_h = (float)h;
+    f_ih = (float)ih;
+    f_ca = (float)(nc - rows.ra[0]);       // centre from the first point
+    f_cb = (float)(nc - rows.rb[P - 1]);   // centre from the last point
+#pragma unroll
+    for (int p = 0; p < P; ++p) f_t0[p] = (float)((rows.ra[p] - nc) * ih);
+  }
   using acc_t = typename std::conditional<F64, double, float>::type;
   acc_t s[P], c[P];
 #pragma unroll
@@ -496,6 +533,29 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       r.c1 = (float)(scd * (double)r.y * (double)kInvSqrtPi);
       r.c2 = 1.5f * r.c1;
       r.c3 = -2.0f * r.y2 * r.c1;
+    }
+  };
+  // FP32 path: the far lines of a chunk (one per lane; c1 = 0 on the other lanes) summed
+  // as one polynomial over the tile: each coefficient of far_coeffs is summed over the
+  // wavefront as soon as the recurrence yields it, then the polynomial is evaluated at the
+  // lane's points and added to the compensated sums.
+  auto far_sum = [&](float c1, float x, float h, float y2s) {
+    if constexpr (!F64) {
+      const FarRec f = far_start(c1, x, h, y2s);
+      float bm2 = f.b0, bm1 = f.b1;
+      float B[kFarDeg + 1];
+      B[0] = wave_total(bm2);
+      B[1] = wave_total(bm1);
+#pragma unroll
+      for (int kk = 2; kk <= kFarDeg; ++kk) {
+        const float bk = far_next(f, bm1, bm2);
+        B[kk] = wave_total(bk);
+        bm2 = bm1;
+        bm1 = bk;
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        kahan_add(s[p], c[p], far_eval(B, fmaf(da32[p], f_ih, f_t0[p])));
     }
   };
   // Blocks of kChunk lines summed in plain FP32, each block then added to the
@@ -679,12 +739,69 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     Rec<F64, P> r;
     double sc64 = 0.0;
     int mode = kSkip, npairs = 0;
+    if constexpr (!F64) {
+      // A chunk of far lines only (the tests of stage_line and of the far split below, on
+      // the tile's first or last point: the whole tile inside the cut, in the series region
+      // with the shifted Lorentzian, far_ok at the tile's centre) skips the staging and the
+      // grouping; the result is the one the general path gives.
+      if (rows.valid[P - 1]) {
+        bool is_far = true;
+        float fx0 = 1.0f, fh0 = 0.0f;
+        if (i < it.e) {
+          const double nu0 = A.L.nu0[i];
+          const LineRec lr = A.recs[(int64_t)it.k * A.rec_n + (i - A.rec_lo)];
+          const double da = rows.ra[0] - nu0, db = rows.rb[P - 1] - nu0;
+          const bool left = da > 0.0;
+          r.y = (float)lr.y;
+          r.y2 = r.y * r.y - 1.5f;
+          sc64 = lr.sc;
+          is_far = left ? db <= lr.cut : (db < 0.0 && da >= -lr.cut);
+          if (is_far) {
+            const float y2 = r.y * r.y;
+            const float ib32 = (float)lr.ib;
+            const float xn = (float)((left ? da : db) * lr.ib);
+            const float r2n = fmaf(xn, xn, y2);
+            fh0 = f_h * ib32;
+            fx0 = fmaf(ib32, left ? f_ca : f_cb, xn);
+            is_far = r2n >= kFarR2 && asym_variant(y2, r2n) == 0 && far_ok(fx0, fh0);
+          }
+        }
+        if (__ballot(!is_far) == 0ull) {
+          set_scale(r, sc64);
+          far_sum(i < it.e ? r.c1 : 0.0f, fx0, fh0, i < it.e ? r.y2 : 0.0f);
+          continue;
+        }
+        sc64 = 0.0;
+      }
+    }
     if (i < it.e) {
       r = stage_line<F64, P>(A, it.k, rows, rowvals[wv], i, &sc64, &mode, &npairs, false);
     } else {
       r.cls = 0;
     }
     set_scale(r, sc64);
+    // FP32 path: lines of the unmasked shifted-Lorentzian modes far enough from the tile
+    // (far_ok at the tile's centre) are summed as one polynomial when the chunk holds
+    // enough of them; they then leave the per-line walk
+    [[maybe_unused]] float fc1 = 0.0f, fx = 1.0f, fhl = 0.0f, fy2 = 0.0f;
+    [[maybe_unused]] bool far_chunk = false;
+    if constexpr (!F64) {
+      bool far = false;
+      if (mode == series_mode(0, 0, 0) || mode == series_mode(1, 0, 0)) {
+        const float hl = f_h * r.ib32;
+        const float x = mode == series_mode(0, 0, 0) ? fmaf(r.ib32, f_ca, r.xr[0])
+                                                     : fmaf(r.ib32, f_cb, r.xr[P - 1]);
+        if (far_ok(x, hl)) {
+          far = true;
+          fc1 = r.c1;
+          fx = x;
+          fhl = hl;
+          fy2 = r.y2;   // y^2 - 3/2 in these modes
+        }
+      }
+      far_chunk = __popcll(__ballot(far)) >= kFarMinLines;
+      if (far_chunk && far) mode = kSkip;
+    }
     // Group the chunk's lines by mode (stable inside each mode) so that the walk below
     // runs every mode's lines in a loop of its own with no per-line dispatch; lines with
     // no point inside the cut are dropped. The order is fixed by the data alone.
@@ -717,6 +834,9 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       }
     }
     wave_sync();
+    if constexpr (!F64) {
+      if (far_chunk) far_sum(fc1, fx, fhl, fy2);
+    }
     if constexpr (F64) {
       for (int kk = gstart[kRows]; kk < gstart[kRows + 1]; ++kk) {
         const Rec<F64, P>& q = recs[wv][kk];

@@ -154,6 +154,58 @@ XS_HD float asym_scaled_v(int v, float y2, float r2) {
   }
 }
 
+// ------------------------------------------------- far lines as a polynomial over a tile
+// A line whose shifted Lorentzian holds on a whole grid range (every point of it inside
+// the cut) contributes c1 / ((X + H t)^2 + y2s) at the range's point t in [-1, 1]: X is x
+// at the range's centre, H its half-width in Doppler units, y2s = y^2 - 3/2. Its Taylor
+// series in t, sum_k b_k t^k, follows from multiplying out (Q0 + 2 X H t + H^2 t^2) f = c1:
+// b_0 = c1 / Q0, b_1 = -alpha b_0, b_k = -(alpha b_{k-1} + beta b_{k-2}) with Q0 = X^2 + y2s,
+// alpha = 2 X H / Q0, beta = H^2 / Q0. The roots of the quadratic lie at |t| >= 1 / rho,
+// rho = H / (|X| - sqrt(max(-y2s, 0))), which bounds |b_k| <= 1.05 (k + 1) rho^k b_0, and
+// the sum truncated after degree kFarDeg is within
+// (1 + rho)^2 (kFarDeg + 2) rho^(kFarDeg + 1) / (1 - rho)^2 (x 1.05) of f on the range:
+// with rho <= 1/5 (|X| >= 5 H + 1.25, and y2s >= -3/2), 1.3e-7 relative. The
+// coefficients of many lines add up, so a sum of such lines costs one polynomial per
+// point instead of one evaluation per line and point.
+constexpr int kFarDeg = 11;
+constexpr float kFarKappa = 5.0f;
+constexpr float kFarMargin = 1.25f;   // >= sqrt(3/2)
+
+// Whether a line at tile-centre x and half-width h (both Doppler units) may be expanded.
+XS_HD bool far_ok(float x, float h) { return fabsf(x) >= fmaf(kFarKappa, h, kFarMargin); }
+
+// The recurrence: far_start gives alpha, beta, b_0 and b_1; far_next b_k from the two
+// before it.
+struct FarRec {
+  float al, be, b0, b1;
+};
+XS_HD FarRec far_start(float c1, float x, float h, float y2s) {
+  const float q = rcp32(fmaf(x, x, y2s));
+  FarRec f;
+  f.al = 2.0f * x * h * q;
+  f.be = h * h * q;
+  f.b0 = c1 * q;
+  f.b1 = -f.al * f.b0;
+  return f;
+}
+XS_HD float far_next(const FarRec& f, float bm1, float bm2) {
+  return -fmaf(f.al, bm1, f.be * bm2);
+}
+XS_HD void far_coeffs(float c1, float x, float h, float y2s, float (&b)[kFarDeg + 1]) {
+  const FarRec f = far_start(c1, x, h, y2s);
+  b[0] = f.b0;
+  b[1] = f.b1;
+#pragma unroll
+  for (int k = 2; k <= kFarDeg; ++k) b[k] = far_next(f, b[k - 1], b[k - 2]);
+}
+
+XS_HD float far_eval(const float (&b)[kFarDeg + 1], float t) {
+  float v = b[kFarDeg];
+#pragma unroll
+  for (int k = kFarDeg - 1; k >= 0; --k) v = fmaf(v, t, b[k]);
+  return v;
+}
+
 // ---------------------------------------------------------------- FP64 tiers
 // FP64 path: 4-node quadrature for |z| >= 40, 8 nodes for 8 <= |z| < 40, Weideman core.
 XS_HD double voigt_far64(double r2, double y) {

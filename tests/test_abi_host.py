@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
     # the binding covers every declared entry point
     assert set(decl) <= set(xsec.exported_symbols())
-    assert L.xs_abi_version() == 3
+    assert L.xs_abi_version() == 4
 
 
 def test_no_compute_without_device_is_a_clean_error():
@@ -163,6 +163,56 @@ def test_selection_bounds_enclose_k():
     assert np.array_equal(lo2, lo[:100]) and np.array_equal(hi2, hi[:100])
     with pytest.raises(xsec.XsError):
         xsec.eval_bounds_host([1.0], [0.0])
+
+
+def _far_cases(n, seed):
+    # far lines as the tile kernel meets them: tile half-widths of 0.1..1e4 Doppler widths,
+    # centres from the expansion's threshold |X| = 5 H + 1.25 outwards, both sides, any t,
+    # kept where the nearest point of the tile takes the shifted Lorentzian
+    rng = np.random.default_rng(seed)
+    H = 10 ** rng.uniform(-1, 4, n)
+    y = 10 ** rng.uniform(-6, 3.3, n)
+    X = ((5 + 10 ** rng.uniform(-6, 1.5, n)) * H + 1.25) * (1 + 1e-6)
+    X *= np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    t = rng.uniform(-1, 1, n)
+    t[:200], t[200:400] = -1.0, 1.0
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    xn = np.abs(f32(X)) - f32(H)
+    r2n = xn * xn + f32(y) ** 2
+    ok = ((1.5 + 2 * f32(y) ** 2) / r2n ** 2 <= 1.9e-7) & (r2n >= 49.0)
+    return X[ok], H[ok], y[ok], t[ok]
+
+
+def test_far_line_polynomial():
+    # the degree-11 polynomial that sums far lines over a tile against the function it
+    # expands, the shifted Lorentzian (closed form, FP64 at the same FP32-rounded inputs),
+    # and against K itself (wofz): truncation <= 1.3e-7 plus FP32 rounding
+    X, H, y, t = _far_cases(400_000, 31)
+    assert len(X) > 100_000
+    K = xsec.eval_far_host(X, H, y, t)
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    Xf, Hf, yf, tf = f32(X), f32(H), f32(y), f32(t)
+    x = Xf + Hf * tf
+    sl = (yf / np.sqrt(np.pi)) / (x * x + yf * yf - 1.5)
+    rel = np.abs(K / sl - 1)
+    print(f"far polynomial vs shifted Lorentzian: max {rel.max():.3e}")
+    assert rel.max() < 4e-7
+    sub = np.random.default_rng(32).choice(len(x), 50_000, replace=False)
+    ref = wofz(x[sub] + 1j * yf[sub]).real
+    assert np.max(np.abs(K[sub] / ref - 1)) < 6e-7
+    # a tile of one point (H = 0) is the line's value at the centre
+    K0 = xsec.eval_far_host(X[:1000], 0.0 * H[:1000], y[:1000], t[:1000])
+    assert np.allclose(K0, (yf[:1000] / np.sqrt(np.pi)) / (Xf[:1000] ** 2 + yf[:1000] ** 2 - 1.5),
+                       rtol=3e-7, atol=0)
+    # the polynomial is the same function on both sides of the tile: mirroring X and t
+    Km = xsec.eval_far_host(-X[:1000], H[:1000], y[:1000], -t[:1000])
+    assert np.array_equal(Km, K[:1000])
+    # cases the kernel never expands are refused: inside the threshold, t outside the
+    # tile, the nearest point outside the shifted-Lorentzian region, y <= 0
+    for args in ((4.9 * 100 + 1.25, 100.0, 1.0, 0.0), (1e4, 10.0, 1.0, 1.01),
+                 (70.0, 0.5, 30.0, 0.0), (1e4, 10.0, 0.0, 0.0)):
+        with pytest.raises(xsec.XsError):
+            xsec.eval_far_host(*args)
 
 
 def test_series_variant_errors():
