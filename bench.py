@@ -409,6 +409,8 @@ def main():
                      "eval_mix": eval_mix,
                      "evals_per_launch": evals_per_launch,
                      "peak_basis": "256 CU x 64 lanes x FMA x 2.4 GHz (no packed FP32)",
+                     "flops_basis": "each evaluation at the direct cost of its tier; far "
+                                    "lines summed per tile as one polynomial cost less",
                      "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS,
                      "hbm_frac": (traffic / (k32 * 1e-3) / 1e9 / PEAK_HBM_GBS
                                   if traffic else None)},

@@ -165,7 +165,7 @@ typedef struct { double P_bar, T_K; } xs_pt;
  * points; split (1..256) divides each tile's line window into that many independent work
  * items whose partial sums are added in a fixed order; waves_per_simd is the
  * occupancy the tile kernel is compiled for: 3..6 waves per SIMD, 2 the compiler's own
- * choice, 0 automatic (the tuned value, else 6 on the FP32 path with 1 or 2 points per
+ * choice, 0 automatic (the tuned value, else 5 on the FP32 path with 1 or 2 points per
  * lane and the compiler's choice otherwise). The result does not depend on the launch
  * shape beyond FP32 rounding (bitwise for a fixed shape).
  * select_eps > 0 turns on main-contributor selection (named in "Functionality of pyROX"

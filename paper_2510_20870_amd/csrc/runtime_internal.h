@@ -140,11 +140,11 @@ int upload_pts(Ctx& c, const xs_pt* pts, size_t npts, hipStream_t st);
 // Tuning cache (tune.hip): launch shapes per workload class, process-wide.
 // Occupancy target of the tile kernel for the option value w (0 automatic, 2 the
 // compiler's own choice, 3..6 waves per SIMD); the returned 0 means no target. The
-// automatic value is 6 on the FP32 path with up to 2 points per lane (measured fastest on
-// the mid and large workloads: the spills it costs are in rarely taken code) and the
-// compiler's choice otherwise.
+// automatic value is 5 on the FP32 path with up to 2 points per lane (measured fastest
+// untuned on the mid and table workloads: 96 VGPRs with few spills; 6 waves cap the
+// kernel at 80 VGPRs and spill in the far-line code) and the compiler's choice otherwise.
 inline int waves_target(int w, int P, bool f64) {
-  if (w == 0) return (!f64 && P <= 2) ? 6 : 0;
+  if (w == 0) return (!f64 && P <= 2) ? 5 : 0;
   return w == 2 ? 0 : w;
 }
 // The option value of a target (2 for none).
@@ -152,7 +152,7 @@ inline int waves_option(int target) { return target == 0 ? 2 : target; }
 
 // A cached launch shape; W is an option value (2..6).
 struct TuneVal {
-  int P = 2, W = 6, ips = 4;
+  int P = 2, W = 5, ips = 4;
   double probe_ms = 0.0;
 };
 std::string tune_key(const Ctx& c, const LinesRes& L, const GridRes& G, size_t npts,
