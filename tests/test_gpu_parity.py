@@ -458,3 +458,56 @@ def test_cia_regrid(ctx):
     with pytest.raises(X.XsError):
         ctx.cia_regrid(g, [(np.array([2.0, 1.0]), np.array([1.0, 1.0]))])
     ctx.free_grid(g)
+
+
+def _far_threshold_lines(grid, T, mass, per_tile, tile):
+    # centres at the far-line switch of every tile: (nu_c - nu0) = 5 h + 1.25 b_D(nu0) on
+    # the left, mirrored on the right, nudged by -1e-9 .. 1e-9 relative so that both
+    # sides of the switch occur; nu_c and h over the tile's valid points
+    k = O.doppler_width(1.0, T, mass)
+    out = []
+    rng = np.random.default_rng(61)
+    for j0 in range(0, len(grid), tile):
+        g = grid[j0:j0 + tile]
+        nc, h = 0.5 * (g[0] + g[-1]), 0.5 * (g[-1] - g[0])
+        left = (nc - 5.0 * h) / (1.0 + 1.25 * k)
+        right = (nc + 5.0 * h) / (1.0 - 1.25 * k)
+        for c in (left, right):
+            out.append(c * (1.0 + rng.uniform(-1e-9, 1e-9, per_tile)))
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("gridkind", ["uniform", "ln"])
+def test_far_line_polynomial_parity(ctx, gridkind):
+    # lines far from every tile dominate (a dense list 30 cm^-1 around a short grid with a
+    # 25 cm^-1 cut), so most chunks are summed as one polynomial per tile, some lines sit
+    # exactly at the switch between the polynomial and the per-point evaluation, and the
+    # last tile is ragged (one point on the uniform grid: half-width 0)
+    if gridkind == "uniform":
+        grid = 1000.0 + 0.01 * np.arange(3 * 128 + 1, dtype=np.float64)
+    else:
+        grid = np.exp(np.linspace(np.log(990.0), np.log(1010.0), 2 * 128 + 37))
+    mass = 16.0
+    base = synth.make_lines(synth.ListSpec(60_000, grid[0] - 30.0, grid[-1] + 30.0, 62))
+    for (P, T) in ((0.1, 1500.0), (10.0, 300.0)):
+        L = {k: v.copy() for k, v in base.items()}
+        extra = _far_threshold_lines(grid, T, mass, 64, 128)
+        src = np.random.default_rng(63).integers(0, len(L["nu0"]), len(extra))
+        for key in L:
+            L[key] = np.concatenate([L[key], L[key][src] if key != "nu0" else extra])
+        order = np.argsort(L["nu0"], kind="stable")
+        L = {key: v[order] for key, v in L.items()}
+        h = ctx.load_lines(L, mass)
+        g = ctx.set_grid(grid)
+        ref = O.sigma(L, grid, P, T, mass, cut_cm1=25.0)
+        first = None
+        for Pl, split in ((2, 1), (1, 3), (4, 0), (0, 0)):
+            sig = ctx.compute(h, g, [(P, T)], _opts(P=Pl, split=split))[0]
+            _check(sig, ref, 1e-5, f"far {gridkind} P={P} T={T} pts/lane {Pl} split {split}")
+            if first is None:
+                first = sig
+                # deterministic
+                assert np.array_equal(ctx.compute(h, g, [(P, T)], _opts(P=Pl, split=split))[0],
+                                      sig)
+        ctx.unload_lines(h)
+        ctx.free_grid(g)
