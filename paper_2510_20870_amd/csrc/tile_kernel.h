@@ -99,6 +99,10 @@ __device__ __forceinline__ float wave_total(float v) {
 // Far lines of a chunk are summed as one polynomial over the tile (far_coeffs) when at
 // least this many of its lines qualify (fewer cost less on the per-line walk).
 constexpr int kFarMinLines = 16;
+// Consecutive chunks of far lines only add their coefficients per lane for at most this
+// many chunks before the sum over the wavefront (plain FP32 sums of terms of one sign:
+// the lines of such a run all lie on one side of the tile).
+constexpr int kFarRun = 8;
 
 // Workgroups are dispatched round-robin over the 8 XCDs. Logical workgroups are grouped in
 // blocks of kXcdBlock consecutive ones (neighbouring tiles, which share most of their line
@@ -535,27 +539,100 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       r.c3 = -2.0f * r.y2 * r.c1;
     }
   };
-  // FP32 path: the far lines of a chunk (one per lane; c1 = 0 on the other lanes) summed
-  // as one polynomial over the tile: each coefficient of far_coeffs is summed over the
-  // wavefront as soon as the recurrence yields it, then the polynomial is evaluated at the
-  // lane's points and added to the compensated sums.
-  auto far_sum = [&](float c1, float x, float h, float y2s) {
+  // FP32 path: far lines (one per lane; c1 = 0 on the other lanes) summed as one
+  // polynomial over the tile. far_add adds a line's coefficients (far_coeffs) to the lane's
+  // acc (or sets them, first); far_flush sums acc over the wavefront, evaluates the
+  // polynomial at the lane's points and adds it to the compensated sums.
+  auto far_add = [&](float (&acc)[kFarDeg + 1], bool first, float c1, float x, float h,
+                     float y2s) {
     if constexpr (!F64) {
       const FarRec f = far_start(c1, x, h, y2s);
       float bm2 = f.b0, bm1 = f.b1;
-      float B[kFarDeg + 1];
-      B[0] = wave_total(bm2);
-      B[1] = wave_total(bm1);
+      acc[0] = first ? bm2 : acc[0] + bm2;
+      acc[1] = first ? bm1 : acc[1] + bm1;
 #pragma unroll
       for (int kk = 2; kk <= kFarDeg; ++kk) {
         const float bk = far_next(f, bm1, bm2);
-        B[kk] = wave_total(bk);
+        acc[kk] = first ? bk : acc[kk] + bk;
         bm2 = bm1;
         bm1 = bk;
       }
+    }
+  };
+  auto far_flush = [&](const float (&acc)[kFarDeg + 1]) {
+    if constexpr (!F64) {
+      float B[kFarDeg + 1];
+#pragma unroll
+      for (int kk = 0; kk <= kFarDeg; ++kk) B[kk] = wave_total(acc[kk]);
 #pragma unroll
       for (int p = 0; p < P; ++p)
         kahan_add(s[p], c[p], far_eval(B, fmaf(da32[p], f_ih, f_t0[p])));
+    }
+  };
+  auto far_sum = [&](float c1, float x, float h, float y2s) {
+    float acc[kFarDeg + 1];
+    far_add(acc, true, c1, x, h, y2s);
+    far_flush(acc);
+  };
+  // Whether line j is a far line of the tile, by the tests of stage_line and of the far
+  // split in the chunk loop, taken on the tile's first or last point: the whole tile
+  // inside the cut, in the series region with the shifted Lorentzian, far_ok at the tile's
+  // centre. Also returns its x at the centre, H, y and FP64 scale.
+  auto far_line = [&](int64_t j, float* fx, float* fh, float* y, double* sc) -> bool {
+    const double nu0 = A.L.nu0[j];
+    const LineRec lr = A.recs[(int64_t)it.k * A.rec_n + (j - A.rec_lo)];
+    const double da = rows.ra[0] - nu0, db = rows.rb[P - 1] - nu0;
+    const bool left = da > 0.0;
+    *y = (float)lr.y;
+    *sc = lr.sc;
+    if (!(left ? db <= lr.cut : (db < 0.0 && da >= -lr.cut))) return false;
+    const float y2 = *y * *y;
+    const float ib32 = (float)lr.ib;
+    const float xn = (float)((left ? da : db) * lr.ib);
+    const float r2n = fmaf(xn, xn, y2);
+    *fh = f_h * ib32;
+    *fx = fmaf(ib32, left ? f_ca : f_cb, xn);
+    return r2n >= kFarR2 && asym_variant(y2, r2n) == 0 && far_ok(*fx, *fh);
+  };
+  // FP32 path without selection: a run of chunks of far lines only, from base on (left at
+  // the first chunk that holds another line); each adds its lines' coefficients per lane,
+  // summed over the wavefront every kFarRun chunks. The scale update is set_scale's, with
+  // the pending coefficients rescaled like the sums.
+  auto far_run = [&](int64_t& b) {
+    if constexpr (!F64 && !SEL) {
+      if (!rows.valid[P - 1]) return;
+      float acc[kFarDeg + 1];
+      int nrun = 0;
+      while (b < it.e) {
+        const int64_t j = b + lane;
+        float fx0 = 1.0f, fh0 = 0.0f, y = 0.0f;
+        double sc = 0.0;
+        const bool is_far = j >= it.e || far_line(j, &fx0, &fh0, &y, &sc);
+        if (__ballot(!is_far) != 0ull) break;
+        const int ex = wave_max(sc > 0.0 ? ilogb(sc) : kNoScale);
+        if (ex > e_ref) {
+          const int d = max(e_ref - ex, -1000);
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            s[p] = ldexpf(s[p], d);
+            c[p] = ldexpf(c[p], d);
+          }
+          if (nrun > 0) {
+#pragma unroll
+            for (int kk = 0; kk <= kFarDeg; ++kk) acc[kk] = ldexpf(acc[kk], d);
+          }
+          e_ref = ex;
+        }
+        const double scd = ldexp(sc, kScaleTarget - e_ref);
+        const float c1 = j < it.e ? (float)(scd * (double)y * (double)kInvSqrtPi) : 0.0f;
+        far_add(acc, nrun == 0, c1, fx0, fh0, j < it.e ? y * y - 1.5f : 0.0f);
+        b += kWave;
+        if (++nrun == kFarRun) {
+          far_flush(acc);
+          nrun = 0;
+        }
+      }
+      if (nrun > 0) far_flush(acc);
     }
   };
   // Blocks of kChunk lines summed in plain FP32, each block then added to the
@@ -708,6 +785,10 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   // lines are staged, 64 at a time. Without selection the chunks are consecutive lines.
   [[maybe_unused]] int q0 = 0, q1 = 0, nq = 0;
   for (int64_t base = it.b; SEL || base < it.e; base += SEL ? 0 : kWave) {
+    if constexpr (!F64 && !SEL) {
+      far_run(base);
+      if (base >= it.e) break;
+    }
     int64_t i = base + lane;   // this lane's line in the chunk (it.e or later: none)
     if constexpr (SEL) {
       const uint64_t lt = (1ull << lane) - 1ull;
@@ -739,34 +820,14 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     Rec<F64, P> r;
     double sc64 = 0.0;
     int mode = kSkip, npairs = 0;
-    if constexpr (!F64) {
-      // A chunk of far lines only (the tests of stage_line and of the far split below, on
-      // the tile's first or last point: the whole tile inside the cut, in the series region
-      // with the shifted Lorentzian, far_ok at the tile's centre) skips the staging and the
-      // grouping; the result is the one the general path gives.
+    if constexpr (!F64 && SEL) {
+      // a chunk of (kept) far lines only skips the staging and the grouping (without
+      // selection far_run has taken such chunks)
       if (rows.valid[P - 1]) {
-        bool is_far = true;
         float fx0 = 1.0f, fh0 = 0.0f;
-        if (i < it.e) {
-          const double nu0 = A.L.nu0[i];
-          const LineRec lr = A.recs[(int64_t)it.k * A.rec_n + (i - A.rec_lo)];
-          const double da = rows.ra[0] - nu0, db = rows.rb[P - 1] - nu0;
-          const bool left = da > 0.0;
-          r.y = (float)lr.y;
-          r.y2 = r.y * r.y - 1.5f;
-          sc64 = lr.sc;
-          is_far = left ? db <= lr.cut : (db < 0.0 && da >= -lr.cut);
-          if (is_far) {
-            const float y2 = r.y * r.y;
-            const float ib32 = (float)lr.ib;
-            const float xn = (float)((left ? da : db) * lr.ib);
-            const float r2n = fmaf(xn, xn, y2);
-            fh0 = f_h * ib32;
-            fx0 = fmaf(ib32, left ? f_ca : f_cb, xn);
-            is_far = r2n >= kFarR2 && asym_variant(y2, r2n) == 0 && far_ok(fx0, fh0);
-          }
-        }
+        const bool is_far = i >= it.e || far_line(i, &fx0, &fh0, &r.y, &sc64);
         if (__ballot(!is_far) == 0ull) {
+          r.y2 = r.y * r.y - 1.5f;
           set_scale(r, sc64);
           far_sum(i < it.e ? r.c1 : 0.0f, fx0, fh0, i < it.e ? r.y2 : 0.0f);
           continue;
