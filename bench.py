@@ -314,19 +314,40 @@ def main():
         fp64 = {"value": v64, "unit": "evals/s", "ms_per_step": wall64 / steps64 * 1e3,
                 "kernel_ms": k64, "steps": steps64, "fp32_speedup": value / v64}
         log(f"fp64 path: {wall64 / steps64 * 1e3:.3f} ms/step, {v64:.4e} evals/s")
+        # the FP64 path with main-contributor selection at the first eps (its evaluations
+        # cost the most, so dropping lines pays most there)
+        sel_eps = [float(v) for v in args.select_eps.split(",") if v.strip()]
+        if sel_eps:
+            sig64 = out.cpu().numpy()[0].copy()
+            o64s = ctx.opts(kind, W.cut_cm1, W.fwhm_mult, xsec.XS_FP64, args.pts_per_lane,
+                            args.split, args.waves_per_simd, sel_eps[0])
+            wall64s, k64s, _ = run(o64s, steps64, 1)
+            drop64 = (sig64 - out.cpu().numpy()[0]) / sig64
+            fp64["selection"] = {
+                "eps": sel_eps[0], "ms_per_step": wall64s / steps64 * 1e3, "kernel_ms": k64s,
+                "speedup_vs_full": wall64 / wall64s,
+                "kept_evals_frac": int(ctx.count_evals(h, g, [(P, T)], o64s)[0]) / evals,
+                "max_drop_vs_full": float(drop64.max()),
+                "min_drop_vs_full": float(drop64.min())}
+            log(f"fp64 selection eps {sel_eps[0]:g}: {wall64s / steps64 * 1e3:.3f} ms/step "
+                f"({wall64 / wall64s:.2f}x), max drop {drop64.max():.3e}")
 
     # main-contributor selection: the same workload with lines dropped within eps (not the
     # headline: fewer evaluations are done); drop against the full FP32 sum, kept share
+    # (the selecting kernel runs at the full path's points per lane and occupancy)
     selection = []
+    sel_P = args.pts_per_lane or (tuned["fp32"]["pts_per_lane"] if tuned else 0)
+    sel_W = args.waves_per_simd or (tuned["fp32"]["waves_per_simd"] if tuned else 0)
     for eps in [float(v) for v in args.select_eps.split(",") if v.strip()]:
-        o_sel = ctx.opts(kind, W.cut_cm1, W.fwhm_mult, xsec.XS_FP32_KAHAN, args.pts_per_lane,
-                         args.split, args.waves_per_simd, eps)
+        o_sel = ctx.opts(kind, W.cut_cm1, W.fwhm_mult, xsec.XS_FP32_KAHAN, sel_P,
+                         args.split, sel_W, eps)
         wall_s, k_s, _ = run(o_sel, args.steps, args.warmup)
         sig_s = out.cpu().numpy()[0].copy()
         kept = int(ctx.count_evals(h, g, [(P, T)], o_sel)[0])
         ms_s = wall_s / args.steps * 1e3
         drop = (sig32 - sig_s) / sig32
-        selection.append({"eps": eps, "ms_per_step": ms_s, "tile_kernel_ms": k_s,
+        selection.append({"eps": eps, "pts_per_lane": sel_P, "waves_per_simd": sel_W,
+                          "ms_per_step": ms_s, "tile_kernel_ms": k_s,
                           "speedup_vs_full": ms / ms_s, "kept_evals_frac": kept / evals,
                           "equivalent_evals_per_s": evals / (ms_s * 1e-3),
                           "max_drop_vs_full": float(drop.max()),

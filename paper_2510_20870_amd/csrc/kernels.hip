@@ -160,15 +160,17 @@ __global__ __launch_bounds__(kBlock) void xs_count_kernel(TileArgs A) {
 // to at most eps L. Dropping those lines changes sigma by at most eps sigma at every point
 // of the group. The bounds are binned by binary exponent into an exact integer histogram
 // (fixed point, rounded up), so tau does not depend on the order of the additions.
-// One wavefront per (group, point): A.n_tiles counts groups here.
+// One workgroup per (group, point), its waves taking interleaved 64-line slices of the
+// window: A.n_tiles counts groups here. L is the sum of the waves' partial sums in wave
+// order, and the histogram is shared (integer additions), so tau depends on the data only.
 template <int P>
 __global__ __launch_bounds__(kBlock) void xs_select_kernel(TileArgs A) {
-  __shared__ unsigned long long hist[kWavesPerWG][kWave];
+  __shared__ unsigned long long hist[kWave];
+  __shared__ double part[kWavesPerWG];
   const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x >> 6;
-  const int wave = __builtin_amdgcn_readfirstlane(wv);
-  const int64_t item = (int64_t)blockIdx.x * kWavesPerWG + wave;
-  if (item >= A.n_tiles * A.n_pt) return;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t item = blockIdx.x;
+  if (item >= A.n_tiles * A.n_pt) return;   // the whole workgroup
   const int k = (int)(item % A.n_pt);
   const int64_t group = item / A.n_pt;
   double t_first, t_last;
@@ -177,32 +179,37 @@ __global__ __launch_bounds__(kBlock) void xs_select_kernel(TileArgs A) {
   line_window(A, k, t_first, t_last, lane, &lo, &hi);
   const LineRec* rec = A.recs + (int64_t)k * A.rec_n - A.rec_lo;
   double acc = 0.0;
-  for (int64_t i = lo + lane; i < hi; i += kWave)
+  for (int64_t i = lo + (int64_t)wv * kWave + lane; i < hi; i += kBlock)
     acc += contrib_lower(A.L.nu0[i], rec[i], t_first, t_last);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) part[wv] = acc;
+  if (wv == 0) hist[lane] = 0ull;
+  __syncthreads();
+  double L = part[0];
+#pragma unroll
+  for (int w = 1; w < kWavesPerWG; ++w) L += part[w];
   double tau = 0.0;
-  const double budget = A.select_eps * acc;
-  // (a budget so small that its fixed-point unit would overflow drops nothing)
+  const double budget = A.select_eps * L;
+  // (a budget so small that its fixed-point unit would overflow drops nothing; the test
+  // has the same outcome in every wave)
   if (budget > 0x1p-960 && isfinite(budget)) {
     // bins: 0 for bounds below 2^elo, 1 + ilogb - elo for [2^elo, 2^eL), eL = ilogb(eps L)
     const int eL = ilogb(budget);
     const int elo = eL - 62;
     const double top = ldexp(1.0, eL), low = ldexp(1.0, elo);
     const double unit = ldexp(1.0, 40) / budget;   // histogram units per unit of sigma
-    hist[wv][lane] = 0ull;
-    wave_sync();
-    for (int64_t i = lo + lane; i < hi; i += kWave) {
+    for (int64_t i = lo + (int64_t)wv * kWave + lane; i < hi; i += kBlock) {
       const double c = contrib_upper(A.L.nu0[i], rec[i], t_first, t_last);
       if (c < top) {
         const int bin = c < low ? 0 : ilogb(c) - elo + 1;
-        atomicAdd(&hist[wv][bin], (unsigned long long)(c * unit) + 1ull);
+        atomicAdd(&hist[bin], (unsigned long long)(c * unit) + 1ull);
       }
     }
-    wave_sync();
+    __syncthreads();
     // the bins below b stay within the budget (2^40 units) for b = 0 .. b*: an exclusive
     // prefix sum over the bins, one bin per lane
-    const unsigned long long h = hist[wv][lane];
+    const unsigned long long h = hist[lane];
     unsigned long long incl = h;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
@@ -213,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void xs_select_kernel(TileArgs A) {
     const int bstar = __popcll(__ballot(ok)) - 1;
     tau = bstar == 0 ? 0.0 : ldexp(1.0, elo + bstar - 1);
   }
-  if (lane == 0) A.tau[(int64_t)k * A.tau_stride + group] = tau;
+  if (threadIdx.x == 0) A.tau[(int64_t)k * A.tau_stride + group] = tau;
 }
 
 __global__ void xs_fill_u64_kernel(unsigned long long* p, int64_t n) {
@@ -301,9 +308,9 @@ hipError_t launch_count(const TileArgs& A, int P, hipStream_t st, int64_t phys_w
 }
 
 hipError_t launch_select(const TileArgs& A, int P, hipStream_t st) {
-  const int64_t waves = A.n_tiles * A.n_pt;
-  if (waves <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((waves + kWavesPerWG - 1) / kWavesPerWG)), block(kBlock);
+  const int64_t items = A.n_tiles * A.n_pt;
+  if (items <= 0) return hipSuccess;
+  const dim3 grid((unsigned)items), block(kBlock);
   switch (P) {
     case 1: hipLaunchKernelGGL((xs_select_kernel<1>), grid, block, 0, st, A); break;
     case 2: hipLaunchKernelGGL((xs_select_kernel<2>), grid, block, 0, st, A); break;

@@ -194,6 +194,52 @@ __device__ __forceinline__ void sel_span(const TileArgs& A, int64_t t, double* g
   *g_last = A.grid[min(j0 + kSpan, A.n_grid) - 1];
 }
 
+// Far lines (FP32 path): a wave's tile of 64 P points from j0, over its valid points
+// [g0, nu_last]: the first and last of them, half-width and centre offsets in FP32, and
+// whether the tile's last row holds points (otherwise no line is a far line of it).
+struct FarTile {
+  double ra0, rbl;
+  float h, ca, cb;   // half-width, centre - first point, centre - last point
+  bool ok;
+};
+template <int P>
+__device__ __forceinline__ FarTile far_tile(const TileArgs& A, int64_t j0, double nu_last) {
+  FarTile t;
+  const double g0 = A.grid[j0];
+  const double nc = 0.5 * (g0 + nu_last);
+  t.ra0 = g0;
+  t.rbl = nu_last;
+  t.h = (float)(0.5 * (nu_last - g0));
+  t.ca = (float)(nc - g0);
+  t.cb = (float)(nc - nu_last);
+  t.ok = j0 + (int64_t)kWave * (P - 1) < A.n_grid;
+  return t;
+}
+// Whether a line (centre nu0, record lr) is a far line of the tile: the tests of stage_line
+// and of the far split of the tile kernel's chunk loop, on the tile's first or last point:
+// the whole tile inside the cut, the series region with the shifted Lorentzian at the
+// nearest point, far_ok at the centre; with x at the centre and H (Doppler units).
+struct FarLine {
+  bool far;
+  float x, h;
+};
+__device__ __forceinline__ FarLine far_line(const FarTile& ft, double nu0, const LineRec& lr) {
+  FarLine f{false, 1.0f, 0.0f};
+  if (!ft.ok) return f;
+  const double da = ft.ra0 - nu0, db = ft.rbl - nu0;
+  const bool left = da > 0.0;
+  if (!(left ? db <= lr.cut : (db < 0.0 && da >= -lr.cut))) return f;
+  const float y = (float)lr.y;
+  const float y2 = y * y;
+  const float ib32 = (float)lr.ib;
+  const float xn = (float)((left ? da : db) * lr.ib);
+  const float r2n = fmaf(xn, xn, y2);
+  const float h = ft.h * ib32;
+  const float x = fmaf(ib32, left ? ft.ca : ft.cb, xn);
+  if (r2n >= kFarR2 && asym_variant(y2, r2n) == 0 && far_ok(x, h)) f = FarLine{true, x, h};
+  return f;
+}
+
 template <int P>
 __device__ __forceinline__ bool decode_item(const TileArgs& A, int lane, ItemInfo& it) {
   const int64_t phys = blockIdx.x;
@@ -500,15 +546,13 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   wave_sync();
   // FP32 path: the tile's centre and half-width (over its valid points) for the far-line
   // polynomial; a point's coordinate t in [-1, 1] is da32 * f_ih + f_t0 of its row
-  [[maybe_unused]] float f_h = 0.0f, f_ih = 0.0f, f_ca = 0.0f, f_cb = 0.0f, f_t0[P];
+  [[maybe_unused]] const FarTile ft = far_tile<P>(A, it.j0, it.nu_last);
+  [[maybe_unused]] float f_ih = 0.0f, f_t0[P];
   if constexpr (!F64) {
     const double g0 = A.grid[it.j0];
     const double nc = 0.5 * (g0 + it.nu_last), h = 0.5 * (it.nu_last - g0);
     const double ih = h > 0.0 ? 1.0 / h : 0.0;
-    f_h = (float)h;
     f_ih = (float)ih;
-    f_ca = (float)(nc - rows.ra[0]);       // centre from the first point
-    f_cb = (float)(nc - rows.rb[P - 1]);   // centre from the last point
 #pragma unroll
     for (int p = 0; p < P; ++p) f_t0[p] = (float)((rows.ra[p] - nc) * ih);
   }
@@ -574,25 +618,19 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     far_add(acc, true, c1, x, h, y2s);
     far_flush(acc);
   };
-  // Whether line j is a far line of the tile, by the tests of stage_line and of the far
-  // split in the chunk loop, taken on the tile's first or last point: the whole tile
-  // inside the cut, in the series region with the shifted Lorentzian, far_ok at the tile's
-  // centre. Also returns its x at the centre, H, y and FP64 scale.
-  auto far_line = [&](int64_t j, float* fx, float* fh, float* y, double* sc) -> bool {
+  // Whether line j is a far line of the tile (far_line); also its x at the centre, H, y and
+  // FP64 scale.
+  auto far_line_j = [&](int64_t j, float& fx, float& fh, float& y, double& sc) -> bool {
     const double nu0 = A.L.nu0[j];
     const LineRec lr = A.recs[(int64_t)it.k * A.rec_n + (j - A.rec_lo)];
-    const double da = rows.ra[0] - nu0, db = rows.rb[P - 1] - nu0;
-    const bool left = da > 0.0;
-    *y = (float)lr.y;
-    *sc = lr.sc;
-    if (!(left ? db <= lr.cut : (db < 0.0 && da >= -lr.cut))) return false;
-    const float y2 = *y * *y;
-    const float ib32 = (float)lr.ib;
-    const float xn = (float)((left ? da : db) * lr.ib);
-    const float r2n = fmaf(xn, xn, y2);
-    *fh = f_h * ib32;
-    *fx = fmaf(ib32, left ? f_ca : f_cb, xn);
-    return r2n >= kFarR2 && asym_variant(y2, r2n) == 0 && far_ok(*fx, *fh);
+    y = (float)lr.y;
+    sc = lr.sc;
+    const FarLine f = far_line(ft, nu0, lr);
+    if (f.far) {
+      fx = f.x;
+      fh = f.h;
+    }
+    return f.far;
   };
   // FP32 path without selection: a run of chunks of far lines only, from base on (left at
   // the first chunk that holds another line); each adds its lines' coefficients per lane,
@@ -600,14 +638,14 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   // the pending coefficients rescaled like the sums.
   auto far_run = [&](int64_t& b) {
     if constexpr (!F64 && !SEL) {
-      if (!rows.valid[P - 1]) return;
+      if (!ft.ok) return;
       float acc[kFarDeg + 1];
       int nrun = 0;
       while (b < it.e) {
         const int64_t j = b + lane;
         float fx0 = 1.0f, fh0 = 0.0f, y = 0.0f;
         double sc = 0.0;
-        const bool is_far = j >= it.e || far_line(j, &fx0, &fh0, &y, &sc);
+        const bool is_far = j >= it.e || far_line_j(j, fx0, fh0, y, sc);
         if (__ballot(!is_far) != 0ull) break;
         const int ex = wave_max(sc > 0.0 ? ilogb(sc) : kNoScale);
         if (ex > e_ref) {
@@ -821,11 +859,11 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     double sc64 = 0.0;
     int mode = kSkip, npairs = 0;
     if constexpr (!F64 && SEL) {
-      // a chunk of (kept) far lines only skips the staging and the grouping (without
+      // a chunk of kept far lines only skips the staging and the grouping (without
       // selection far_run has taken such chunks)
-      if (rows.valid[P - 1]) {
+      if (ft.ok) {
         float fx0 = 1.0f, fh0 = 0.0f;
-        const bool is_far = i >= it.e || far_line(i, &fx0, &fh0, &r.y, &sc64);
+        const bool is_far = i >= it.e || far_line_j(i, fx0, fh0, r.y, sc64);
         if (__ballot(!is_far) == 0ull) {
           r.y2 = r.y * r.y - 1.5f;
           set_scale(r, sc64);
@@ -849,9 +887,9 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     if constexpr (!F64) {
       bool far = false;
       if (mode == series_mode(0, 0, 0) || mode == series_mode(1, 0, 0)) {
-        const float hl = f_h * r.ib32;
-        const float x = mode == series_mode(0, 0, 0) ? fmaf(r.ib32, f_ca, r.xr[0])
-                                                     : fmaf(r.ib32, f_cb, r.xr[P - 1]);
+        const float hl = ft.h * r.ib32;
+        const float x = mode == series_mode(0, 0, 0) ? fmaf(r.ib32, ft.ca, r.xr[0])
+                                                     : fmaf(r.ib32, ft.cb, r.xr[P - 1]);
         if (far_ok(x, hl)) {
           far = true;
           fc1 = r.c1;
