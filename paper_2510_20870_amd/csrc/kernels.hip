@@ -31,9 +31,13 @@
 // the row's nearest point allows (a shifted Lorentzian, or the asymptotic series with 2 to
 // 6 terms) and the cut as a lane bound found at staging time with the FP64 test; rows a
 // line reaches inside |z| = 7 take x from the FP64 difference, the six-term series for
-// their points outside |z| = 7 and the FP64 Weideman core inside. Contributions are summed
-// in FP32 over blocks of 16 lines, each block added to a Kahan-compensated FP32 sum (a
-// plain FP64 sum on the FP64 path). FP32 contributions carry a power-of-two scale chosen
+// their points outside |z| = 7 and the FP64 Weideman core inside. Lines far from the
+// tile on the FP32 path (the whole tile inside the cut, shifted Lorentzian, |x| at the
+// tile's centre at least five half-widths away) are not evaluated per point: their Taylor
+// coefficients in the tile coordinate are summed over the wavefront and the polynomial is
+// evaluated once per point (voigt.h, far_coeffs). Contributions are summed in FP32 over
+// blocks of 16 lines, each block added to a Kahan-compensated FP32 sum (a plain FP64 sum
+// on the FP64 path). FP32 contributions carry a power-of-two scale chosen
 // per wavefront: whenever a staged chunk holds a line stronger than any before, the scale
 // is lowered so the strongest line's scale is about 2^48 and the running sums are
 // rescaled exactly, so any absolute magnitude of sigma stays inside FP32 range; the scale
