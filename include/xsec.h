@@ -299,8 +299,9 @@ int xs_sched_simulate(size_t n, const double *arrive, const double *duration,
  * automatic split aims at (which sets the line range of one item, i.e. how many 64-line
  * LDS chunks a wavefront walks per item), and the occupancy the tile kernel is compiled
  * for (waves_per_simd). xs_autotune times candidate shapes on probe blocks of the given
- * workload (up to three grid blocks, up to three of its P-T points, every line that
- * reaches them) and stores the fastest in a process-wide cache under the workload's
+ * workload (up to three grid blocks, up to five of its P-T points evenly spaced over the
+ * batch, every line that reaches them) and stores the fastest in a process-wide cache
+ * under the workload's
  * class: device arch and CU count, precision, cutoff kind, the line density around the
  * grid middle (power of two of the lines within the cut) and the number of P-T points
  * (1, 2..16, more). Every later call with pts_per_lane, split and waves_per_simd all 0

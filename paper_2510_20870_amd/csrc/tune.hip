@@ -308,10 +308,12 @@ int xs_autotune(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t
   }
   const std::string key = tune_key(*c, *L, *G, npts, *opts);
 
-  // probe points: the first, middle and last P-T points
-  std::vector<xs_pt> pp{pts[0]};
-  if (npts > 2) pp.push_back(pts[npts / 2]);
-  if (npts > 1) pp.push_back(pts[npts - 1]);
+  // probe points: up to five, evenly spaced over the batch (the first and last included),
+  // so that a table's cheap and expensive points weigh in about as in the whole batch
+  // (with three, one high-pressure point outweighed the rest of a pressure table)
+  std::vector<xs_pt> pp;
+  const size_t np = std::min<size_t>(npts, 5);
+  for (size_t q = 0; q < np; ++q) pp.push_back(pts[np == 1 ? 0 : q * (npts - 1) / (np - 1)]);
   const int nprobe = (int)pp.size();
   rc = upload_pts(*c, pp.data(), pp.size(), nullptr);
   if (rc) return rc;
