@@ -566,8 +566,10 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   // line than any before lowers the scale, and the running sums are rescaled exactly
   auto set_scale = [&](Rec<F64, P>& r, double sc64) {
     if constexpr (!F64) {
-      const int ex = wave_max(sc64 > 0.0 ? ilogb(sc64) : kNoScale);
-      if (ex > e_ref) {
+      // (the wavefront maximum only when some line is stronger than all before)
+      const int exl = sc64 > 0.0 ? ilogb(sc64) : kNoScale;
+      if (__ballot(exl > e_ref) != 0ull) {
+        const int ex = wave_max(exl);
         const int d = max(e_ref - ex, -1000);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
@@ -585,19 +587,22 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   };
   // FP32 path: far lines (one per lane; c1 = 0 on the other lanes) summed as one
   // polynomial over the tile. far_add adds a line's coefficients (far_coeffs) to the lane's
-  // acc (or sets them, first); far_flush sums acc over the wavefront, evaluates the
-  // polynomial at the lane's points and adds it to the compensated sums.
-  auto far_add = [&](float (&acc)[kFarDeg + 1], bool first, float c1, float x, float h,
-                     float y2s) {
+  // acc; far_flush sums acc over the wavefront, evaluates the polynomial at the lane's
+  // points and adds it to the compensated sums.
+  auto far_zero = [&](float (&acc)[kFarDeg + 1]) {
+#pragma unroll
+    for (int kk = 0; kk <= kFarDeg; ++kk) acc[kk] = 0.0f;
+  };
+  auto far_add = [&](float (&acc)[kFarDeg + 1], float c1, float x, float h, float y2s) {
     if constexpr (!F64) {
       const FarRec f = far_start(c1, x, h, y2s);
       float bm2 = f.b0, bm1 = f.b1;
-      acc[0] = first ? bm2 : acc[0] + bm2;
-      acc[1] = first ? bm1 : acc[1] + bm1;
+      acc[0] += bm2;
+      acc[1] += bm1;
 #pragma unroll
       for (int kk = 2; kk <= kFarDeg; ++kk) {
         const float bk = far_next(f, bm1, bm2);
-        acc[kk] = first ? bk : acc[kk] + bk;
+        acc[kk] += bk;
         bm2 = bm1;
         bm1 = bk;
       }
@@ -615,7 +620,8 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   };
   auto far_sum = [&](float c1, float x, float h, float y2s) {
     float acc[kFarDeg + 1];
-    far_add(acc, true, c1, x, h, y2s);
+    far_zero(acc);
+    far_add(acc, c1, x, h, y2s);
     far_flush(acc);
   };
   // Whether line j is a far line of the tile (far_line); also its x at the centre, H, y and
@@ -640,6 +646,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     if constexpr (!F64 && !SEL) {
       if (!ft.ok) return;
       float acc[kFarDeg + 1];
+      far_zero(acc);
       int nrun = 0;
       while (b < it.e) {
         const int64_t j = b + lane;
@@ -647,26 +654,26 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
         double sc = 0.0;
         const bool is_far = j >= it.e || far_line_j(j, fx0, fh0, y, sc);
         if (__ballot(!is_far) != 0ull) break;
-        const int ex = wave_max(sc > 0.0 ? ilogb(sc) : kNoScale);
-        if (ex > e_ref) {
+        const int exl = sc > 0.0 ? ilogb(sc) : kNoScale;
+        if (__ballot(exl > e_ref) != 0ull) {
+          const int ex = wave_max(exl);
           const int d = max(e_ref - ex, -1000);
 #pragma unroll
           for (int p = 0; p < P; ++p) {
             s[p] = ldexpf(s[p], d);
             c[p] = ldexpf(c[p], d);
           }
-          if (nrun > 0) {
 #pragma unroll
-            for (int kk = 0; kk <= kFarDeg; ++kk) acc[kk] = ldexpf(acc[kk], d);
-          }
+          for (int kk = 0; kk <= kFarDeg; ++kk) acc[kk] = ldexpf(acc[kk], d);
           e_ref = ex;
         }
         const double scd = ldexp(sc, kScaleTarget - e_ref);
         const float c1 = j < it.e ? (float)(scd * (double)y * (double)kInvSqrtPi) : 0.0f;
-        far_add(acc, nrun == 0, c1, fx0, fh0, j < it.e ? y * y - 1.5f : 0.0f);
+        far_add(acc, c1, fx0, fh0, j < it.e ? y * y - 1.5f : 0.0f);
         b += kWave;
         if (++nrun == kFarRun) {
           far_flush(acc);
+          far_zero(acc);
           nrun = 0;
         }
       }
@@ -704,8 +711,8 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
         const int npk = incl[wv][ke - 1] - base;
         // one term count for the sub-batch: the largest its lines need (a loop of its own
         // per count, so the pass keeps one evaluation path)
-        const int tier = __builtin_amdgcn_readfirstlane(
-            wave_max(lane < ke - k ? core_tier((double)recs[wv][k + lane].y) : 0));
+        const int lt = lane < ke - k ? core_tier((double)recs[wv][k + lane].y) : 0;
+        const int tier = __ballot(lt >= 3) ? 3 : __ballot(lt >= 2) ? 2 : __ballot(lt >= 1) ? 1 : 0;
         auto packed = [&](auto nterms) {
           constexpr int N = decltype(nterms)::value;
           const double* wa = N == 16 ? kWeidA16 : N == 24 ? kWeidA24 : N == 32 ? kWeidA32
