@@ -223,12 +223,11 @@ struct FarLine {
   bool far;
   float x, h;
 };
+// (every test is evaluated and combined with &, so that the code has no branches)
 __device__ __forceinline__ FarLine far_line(const FarTile& ft, double nu0, const LineRec& lr) {
-  FarLine f{false, 1.0f, 0.0f};
-  if (!ft.ok) return f;
   const double da = ft.ra0 - nu0, db = ft.rbl - nu0;
   const bool left = da > 0.0;
-  if (!(left ? db <= lr.cut : (db < 0.0 && da >= -lr.cut))) return f;
+  const bool in_cut = left ? db <= lr.cut : ((db < 0.0) & (da >= -lr.cut));
   const float y = (float)lr.y;
   const float y2 = y * y;
   const float ib32 = (float)lr.ib;
@@ -236,8 +235,10 @@ __device__ __forceinline__ FarLine far_line(const FarTile& ft, double nu0, const
   const float r2n = fmaf(xn, xn, y2);
   const float h = ft.h * ib32;
   const float x = fmaf(ib32, left ? ft.ca : ft.cb, xn);
-  if (r2n >= kFarR2 && asym_variant(y2, r2n) == 0 && far_ok(x, h)) f = FarLine{true, x, h};
-  return f;
+  // asym_variant(y2, r2n) == 0 is the shifted-Lorentzian test
+  const bool far = ft.ok & in_cut & (r2n >= kFarR2) & shifted_lorentz_ok(y2, r2n) &
+                   far_ok(x, h);
+  return FarLine{far, far ? x : 1.0f, far ? h : 0.0f};
 }
 
 template <int P>
