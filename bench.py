@@ -59,9 +59,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def profiled_traffic():
-    """HBM bytes per tile-kernel launch from the committed counter profile, or None when
-    the kernel sources changed since it was taken."""
+def _counter_profile():
+    """The committed counter profile's text, or None when it is missing or the kernel
+    sources changed since it was taken."""
     import re
     try:
         with open(COUNTER_PROFILE) as fh:
@@ -69,10 +69,34 @@ def profiled_traffic():
     except OSError:
         return None
     m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
-    m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not (m_hash and m_bytes) or m_hash.group(1) != kernel_source_hash():
+    if not m_hash or m_hash.group(1) != kernel_source_hash():
         return None
-    return float(m_bytes.group(1))
+    return text
+
+
+def profiled_traffic():
+    """HBM bytes per tile-kernel launch from the committed counter profile, or None when
+    the kernel sources changed since it was taken."""
+    import re
+    text = _counter_profile()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text) if text else None
+    return float(m.group(1)) if m else None
+
+
+def profiled_issue():
+    """The tile kernel's measured VALU issue (VALUBusy %, VALU lane-instructions per
+    evaluation) from the committed counter profile, or None as for profiled_traffic."""
+    import re
+    text = _counter_profile()
+    if not text:
+        return None
+    m_busy = re.search(r"\| VALUBusy \(derived, %\) \| ([0-9.]+) \|", text)
+    m_ipe = re.search(r"VALU lane-instructions per line-point evaluation: ([0-9.]+)", text)
+    if not (m_busy and m_ipe):
+        return None
+    return {"valu_busy_pct": float(m_busy.group(1)),
+            "valu_lane_instr_per_eval": float(m_ipe.group(1)),
+            "source": os.path.relpath(COUNTER_PROFILE, ROOT)}
 
 
 def copy_probe():
@@ -434,7 +458,8 @@ def main():
                                     "lines summed per tile as one polynomial cost less",
                      "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS,
                      "hbm_frac": (traffic / (k32 * 1e-3) / 1e9 / PEAK_HBM_GBS
-                                  if traffic else None)},
+                                  if traffic else None),
+                     "issue": profiled_issue()},
         "fp64_path": fp64,
         "selection": selection,
         "serving": serving,
