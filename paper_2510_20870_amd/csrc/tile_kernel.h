@@ -627,9 +627,12 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   };
   // Whether line j is a far line of the tile (far_line); also its x at the centre, H, y and
   // FP64 scale.
+  // the line records of the item's (P, T) point, indexed by global line index (one base
+  // for the far-line loads, which keeps the loop-invariant scalars of that loop few)
+  const LineRec* const recs_k = A.recs + ((int64_t)it.k * A.rec_n - A.rec_lo);
   auto far_line_j = [&](int64_t j, float& fx, float& fh, float& y, double& sc) -> bool {
     const double nu0 = A.L.nu0[j];
-    const LineRec lr = A.recs[(int64_t)it.k * A.rec_n + (j - A.rec_lo)];
+    const LineRec lr = recs_k[j];
     y = (float)lr.y;
     sc = lr.sc;
     const FarLine f = far_line(ft, nu0, lr);
