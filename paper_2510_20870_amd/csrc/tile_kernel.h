@@ -315,13 +315,15 @@ __device__ __forceinline__ int lane_guess(const Rows<P>& rows, int p, double v) 
 // with the row classes; returns the FP64 profile scale in *sc64, the line's mode in
 // *mode_out and its number of core points (FP32 path) in *npairs_out. The lane ranges of
 // general rows are found only when `general` is set (their lines are staged again later).
+// recs_k: the line records of the item's (P, T) point, indexed by global line index.
 template <bool F64, int P>
-__device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, int k, const Rows<P>& rows,
+__device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, const LineRec* recs_k,
+                                                  const Rows<P>& rows,
                                                   const double* rowv, int64_t i,
                                                   double* sc64, int* mode_out,
                                                   int* npairs_out, bool general) {
   const double nu0 = A.L.nu0[i];
-  const LineRec lr = A.recs[(int64_t)k * A.rec_n + (i - A.rec_lo)];
+  const LineRec lr = recs_k[i];
   Rec<F64, P> r;
   r.nu0 = nu0;
   if constexpr (F64) r.cut = lr.cut;
@@ -628,7 +630,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   // Whether line j is a far line of the tile (far_line); also its x at the centre, H, y and
   // FP64 scale.
   // the line records of the item's (P, T) point, indexed by global line index (one base
-  // for the far-line loads, which keeps the loop-invariant scalars of that loop few)
+  // for every record load, which keeps the loop-invariant scalars of the line loops few)
   const LineRec* const recs_k = A.recs + ((int64_t)it.k * A.rec_n - A.rec_lo);
   auto far_line_j = [&](int64_t j, float& fx, float& fh, float& y, double& sc) -> bool {
     const double nu0 = A.L.nu0[j];
@@ -807,7 +809,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       double sc64 = 0.0;
       int mode = kSkip, npairs = 0;
       if (lane < nd) {
-        r = stage_line<F64, P>(A, it.k, rows, rowvals[wv], it.b + dlist[wv][lane], &sc64,
+        r = stage_line<F64, P>(A, recs_k, rows, rowvals[wv], it.b + dlist[wv][lane], &sc64,
                                &mode, &npairs, true);
       }
       set_scale(r, sc64);
@@ -845,7 +847,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
         const int64_t j = base + lane;
         bool keep = false;
         if (j < it.e) {
-          const LineRec lr = A.recs[(int64_t)it.k * A.rec_n + (j - A.rec_lo)];
+          const LineRec lr = recs_k[j];
           keep = contrib_upper(A.L.nu0[j], lr, g_first, g_last) >= tau;
         }
         const uint64_t km = __ballot(keep);
@@ -885,7 +887,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       }
     }
     if (i < it.e) {
-      r = stage_line<F64, P>(A, it.k, rows, rowvals[wv], i, &sc64, &mode, &npairs, false);
+      r = stage_line<F64, P>(A, recs_k, rows, rowvals[wv], i, &sc64, &mode, &npairs, false);
     } else {
       r.cls = 0;
     }
