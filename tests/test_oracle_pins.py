@@ -11,6 +11,7 @@ import pytest
 from scipy import integrate
 
 from oracle import xsec_oracle as O
+from paper_2510_20870_amd import synth
 
 SQPI = math.sqrt(math.pi)
 
@@ -424,6 +425,63 @@ def test_count_evals_matches_definition():
         assert O.count_evals(L, grid, 1e-3, 500.0, 16.0, cut_kind=kind, **kw) == brute
 
 
+def test_line_cutoff_min_fwhm_hand_values():
+    # cut = min(cap, mult * FWHM): hand values from the two pure limits, whose FWHM the
+    # profile fixes by itself (Gaussian 2 b_D sqrt(ln 2); Lorentzian 2 gamma_L, which the
+    # Olivero-Longbothum form gives to 0.5346 + sqrt(0.2166) = 1.0000031 of it)
+    two_sqrt_ln2 = 1.6651092223153954
+    # pure Doppler, below the cap: 100 x 2 x 0.01 x sqrt(ln 2)
+    c = O.line_cutoff("min_fwhm", 25.0, 100.0, [0.0], [0.01])
+    assert c[0] == pytest.approx(1.6651092223153954, rel=1e-14, abs=0)
+    # pure Doppler, above the cap (100 x 0.333 = 33.3 cm^-1): the cap
+    c = O.line_cutoff("min_fwhm", 25.0, 100.0, [0.0], [0.2])
+    assert c[0] == 25.0
+    # pure Lorentz, below and above the cap: 100 x 2 gamma_L
+    c = O.line_cutoff("min_fwhm", 25.0, 100.0, [0.05, 0.3], [0.0, 0.0])
+    assert c[0] == pytest.approx(10.0, rel=4e-6, abs=0)
+    assert c[1] == 25.0
+    # another multiplier and cap: 30 x FWHM against a cap of 2
+    c = O.line_cutoff("min_fwhm", 2.0, 30.0, [0.0, 0.0, 0.02], [0.01, 0.1, 0.0])
+    assert c[0] == pytest.approx(30 * 0.01 * two_sqrt_ln2, rel=1e-14, abs=0)
+    assert c[1] == 2.0
+    assert c[2] == pytest.approx(1.2, rel=4e-6, abs=0)
+    # a mixed line: mult times the true full width at half maximum of the oracle's own
+    # profile (root finding on wofz), within the 0.02 % accuracy Olivero and Longbothum
+    # quote
+    from scipy.optimize import brentq
+    for bD, g in ((0.01, 0.004), (0.003, 0.02), (0.05, 0.05)):
+        peak = O.voigt(0.0, bD, g)
+        h = brentq(lambda t: O.voigt(t, bD, g) - 0.5 * peak, 0.0, 10 * (bD + g), xtol=1e-15)
+        c = O.line_cutoff("min_fwhm", 1e3, 100.0, [g], [bD])
+        assert c[0] == pytest.approx(100.0 * 2.0 * h, rel=3e-4, abs=0)
+    # the fixed rule ignores the widths
+    assert np.all(O.line_cutoff("fixed", 7.5, 100.0, [0.1, 0.0], [0.0, 3.0]) == 7.5)
+
+
+def test_sigma_parallel_matches_sigma():
+    # the process-pool driver returns what sigma() returns at the same points: many
+    # blocks of a non-contiguous, unsorted-in-blocks selection, ragged last block
+    L = synth.make_lines(synth.ListSpec(20_000, 1000.0, 1010.0, 9))
+    grid = synth.uniform_grid(999.0, 1011.0, 0.002)
+    rng = np.random.default_rng(3)
+    pts = np.unique(np.concatenate([rng.choice(len(grid), 300, replace=False),
+                                    np.arange(2000, 2150), [0, len(grid) - 1]]))
+    kw = dict(P=0.2, T=900.0, mass_amu=18.0, cut_cm1=2.5)
+    ref = O.sigma(L, grid, points=pts, **kw)
+    par = O.sigma_parallel(L, grid, workers=3, chunk=37, points=pts, **kw)
+    assert par.shape == ref.shape
+    # the candidate ranges differ with the blocking, so the FP64 sums may differ in
+    # their last bits (at most a few hundred terms per point)
+    np.testing.assert_allclose(par, ref, rtol=1e-13, atol=0)
+    assert np.all(ref > 0)
+    # the FWHM rule goes through the same driver
+    kw2 = dict(P=1e-3, T=400.0, mass_amu=18.0, cut_kind="min_fwhm", cut_cm1=25.0,
+               fwhm_mult=100.0)
+    np.testing.assert_allclose(O.sigma_parallel(L, grid, workers=2, chunk=50, points=pts,
+                                                **kw2),
+                               O.sigma(L, grid, points=pts, **kw2), rtol=1e-13, atol=0)
+
+
 def test_compare_metric():
     ref = np.array([1.0, 0.5, 1e-9, 1e-12])
     ok = O.compare(ref * (1 + 5e-5), ref)
@@ -475,6 +533,35 @@ def test_planted_mistakes_are_caught(monkeypatch):
     with pytest.raises(AssertionError):
         test_doppler_width_matches_maxwell_velocity_variance()
     monkeypatch.setattr(O, "doppler_width", orig_d)
+    # (4) max instead of min in the FWHM cutoff; (5) the half width instead of the full
+    # width; (6) the multiplier applied to the cap instead of the width
+    orig_c = O.line_cutoff
+    bad_cuts = (
+        lambda kind, cut, mult, gL, bD: np.maximum(float(cut), mult * O.voigt_fwhm(gL, bD))
+        if kind == "min_fwhm" else orig_c(kind, cut, mult, gL, bD),
+        lambda kind, cut, mult, gL, bD: np.minimum(float(cut),
+                                                   mult * 0.5 * O.voigt_fwhm(gL, bD))
+        if kind == "min_fwhm" else orig_c(kind, cut, mult, gL, bD),
+        lambda kind, cut, mult, gL, bD: np.minimum(mult * float(cut), O.voigt_fwhm(gL, bD))
+        if kind == "min_fwhm" else orig_c(kind, cut, mult, gL, bD),
+    )
+    for bad in bad_cuts:
+        monkeypatch.setattr(O, "line_cutoff", bad)
+        with pytest.raises(AssertionError):
+            test_line_cutoff_min_fwhm_hand_values()
+    monkeypatch.setattr(O, "line_cutoff", orig_c)
+    # (7) a block of points dropped (left at zero) by the process-pool driver
+    orig_p = O.sigma_parallel
+
+    def bad_parallel(lines, grid, workers=None, chunk=256, points=None, **kw):
+        out = orig_p(lines, grid, workers=workers, chunk=chunk, points=points, **kw)
+        out[chunk:2 * chunk] = 0.0
+        return out
+
+    monkeypatch.setattr(O, "sigma_parallel", bad_parallel)
+    with pytest.raises(AssertionError):
+        test_sigma_parallel_matches_sigma()
+    monkeypatch.setattr(O, "sigma_parallel", orig_p)
 
 
 def test_cia_regrid_is_linear_interpolation():
