@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define XS_ABI_VERSION 4
+#define XS_ABI_VERSION 5
 
 typedef enum {
   XS_OK = 0,
@@ -58,6 +58,7 @@ enum { XS_EINSTEIN_A = 0, XS_REF_STRENGTH = 1 };  /* strength form              
 enum { XS_Q_POWER = 0, XS_Q_TABLE = 1 };          /* partition-function form         */
 enum { XS_CUT_FIXED = 0, XS_CUT_MIN_FWHM = 1 };   /* line-wing cutoff rule           */
 enum { XS_FP32_KAHAN = 0, XS_FP64 = 1 };          /* arithmetic of the profile sum   */
+enum { XS_F64 = 0, XS_F32 = 1 };                  /* element type of sigma outputs   */
 
 typedef struct xs_ctx xs_ctx;     /* opaque; one per device                              */
 typedef uint64_t xs_lines_t;      /* resident line list                                  */
@@ -130,7 +131,7 @@ typedef struct {
  * (NaN/negative fields, g_up = 0 with the Einstein form, bad species), XS_ENOMEM. */
 int xs_load_lines(xs_ctx *ctx, const xs_lines_desc *lines, const xs_species_desc *species,
                   xs_lines_t *out);
-/* Release a line list. XS_EBUSY while serving requests still reference it. */
+/* Release a line list. XS_EBUSY while serving requests or graphs still reference it. */
 int xs_unload_lines(xs_ctx *ctx, xs_lines_t lines);
 /* Number of lines and resident bytes of a list. */
 int xs_lines_info(xs_ctx *ctx, xs_lines_t lines, size_t *n, size_t *bytes);
@@ -153,6 +154,7 @@ int xs_wavelength_grid_host(double lambda_min_um, double lambda_max_um, double R
                             double *nu_out, size_t cap, size_t *n_out);
 int xs_set_grid_wavelength(xs_ctx *ctx, double lambda_min_um, double lambda_max_um,
                            double R, xs_grid_t *out, size_t *n_out);
+/* Release a grid. XS_EBUSY while serving requests or graphs still reference it. */
 int xs_free_grid(xs_ctx *ctx, xs_grid_t grid);
 /* Number of points of a resident grid. */
 int xs_grid_info(xs_ctx *ctx, xs_grid_t grid, size_t *n);
@@ -173,7 +175,9 @@ typedef struct { double P_bar, T_K; } xs_pt;
  * the grid and (P, T) point, lines are dropped when the sum of their contributions' upper
  * bounds over the tile stays within select_eps times a lower bound of sigma over the tile,
  * so that sigma changes by at most select_eps * sigma at every point (plus the FP32
- * rounding of the kept lines); 0 computes every line. Must be in [0, 1). */
+ * rounding of the kept lines); 0 computes every line. Must be in [0, 1).
+ * out_dtype: the element type of sigma outputs, XS_F64 (float64) or XS_F32 (float32, the
+ * FP64 sum rounded once to nearest); the arithmetic is the same for both. */
 typedef struct {
   int cutoff_kind;
   double cut_cm1;
@@ -183,10 +187,12 @@ typedef struct {
   int split;
   int waves_per_simd;
   double select_eps;
+  int out_dtype;
 } xs_opts;
 
 /* sigma(nu_j; P_k, T_k) for k < npts on every point of `grid`, written to
- * sigma_out[k * n_grid + j] (float64, row-major [npts][n_grid]). With out_on_device != 0,
+ * sigma_out[k * n_grid + j] (row-major [npts][n_grid] of float64, or of float32 with
+ * opts->out_dtype = XS_F32). With out_on_device != 0,
  * sigma_out is device memory, the work is enqueued on `stream` (a hipStream_t, NULL =
  * the null stream) and the call returns without waiting; otherwise sigma_out is host
  * memory and the call returns when it is filled. Each output element is produced by one
@@ -194,7 +200,7 @@ typedef struct {
  * Errors: XS_EINVAL (P or T <= 0 or not finite, bad options), XS_ENOTFOUND, XS_ENOMEM,
  * XS_EDEVICE. */
 int xs_compute(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts, size_t npts,
-               const xs_opts *opts, double *sigma_out, int out_on_device, void *stream);
+               const xs_opts *opts, void *sigma_out, int out_on_device, void *stream);
 
 /* Number of (line, grid point) pairs inside the cutoff, per (P, T) point, counted on the
  * device with the same FP64 rule as xs_compute: counts_out[k] (host memory). With
@@ -214,9 +220,13 @@ int xs_count_evals_by_tier(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const 
 
 /* Batched computation captured once in a hipGraph (its point table and scratch are owned
  * by the graph) and replayed by xs_graph_launch on any stream; sigma_dev is device memory
- * of npts * n_grid float64. */
+ * of npts * n_grid elements of opts->out_dtype. Every batch of P-T points the plan needs
+ * (xs_compute's batching) is captured into the one graph. While a graph exists, its line
+ * list and grid stay referenced: xs_unload_lines and xs_free_grid fail with XS_EBUSY.
+ * xs_destroy releases the device resources of the context's remaining graphs; their
+ * handles then only accept xs_graph_destroy (xs_graph_launch fails with XS_EINVAL). */
 int xs_graph_create(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts,
-                    size_t npts, const xs_opts *opts, double *sigma_dev, xs_graph **out);
+                    size_t npts, const xs_opts *opts, void *sigma_dev, xs_graph **out);
 int xs_graph_launch(xs_graph *g, void *stream);
 void xs_graph_destroy(xs_graph *g);
 
@@ -260,12 +270,12 @@ int xs_serve_pause(xs_ctx *ctx, int paused);
  * (valid once the request is done). *out receives the request handle. Errors at submit:
  * XS_EINVAL, XS_ENOTFOUND, XS_ENOMEM (the footprint exceeds the whole arena). */
 int xs_submit(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts, size_t npts,
-              const xs_opts *opts, double *sigma_out, int out_on_device, xs_req_t *out);
+              const xs_opts *opts, void *sigma_out, int out_on_device, xs_req_t *out);
 /* The same for the uniform grid nu_j = nu_start + j * step, j < n_points, built on the
  * device inside the request's arena memory (no grid handle, no allocation). */
 int xs_submit_window(xs_ctx *ctx, xs_lines_t lines, double nu_start, double step,
                      size_t n_points, const xs_pt *pts, size_t npts, const xs_opts *opts,
-                     double *sigma_out, int out_on_device, xs_req_t *out);
+                     void *sigma_out, int out_on_device, xs_req_t *out);
 /* *done = 1 once the request has finished (successfully, failed or cancelled). */
 int xs_poll(xs_ctx *ctx, xs_req_t req, int *done);
 /* Wait for the request (timeout_s < 0: no limit). Returns the request's final status
@@ -276,8 +286,10 @@ int xs_wait(xs_ctx *ctx, xs_req_t req, double timeout_s);
  * in flight (its output is then incomplete); both end with XS_ECANCELLED. A finished
  * request is not affected. Returns XS_OK. */
 int xs_cancel(xs_ctx *ctx, xs_req_t req);
-/* Submit, admission and completion times in seconds on a monotonic clock (a time not yet
- * reached is returned as -1). Completion is when the output is in sigma_out. */
+/* Submit, admission and completion times in seconds on the monotonic clock
+ * (CLOCK_MONOTONIC, the clock of std::chrono::steady_clock on Linux; a time not yet
+ * reached is returned as -1). Submit is stamped on entry to xs_submit, completion when
+ * the output is in sigma_out. */
 int xs_request_times(xs_ctx *ctx, xs_req_t req, double *t_submit, double *t_admit,
                      double *t_done);
 /* Forget a finished request (XS_EBUSY while it is pending). */

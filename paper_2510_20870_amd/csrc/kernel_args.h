@@ -58,6 +58,7 @@ struct TileArgs {
   int64_t rec_lo, rec_n;
   double* out;            // split == 1: sigma rows [n_pts][n_grid] (row pt0 + k);
                           // else partials [n_pt][split][n_grid] of this batch
+  int out_f32;            // split == 1 only: out holds float rows instead of double
   unsigned long long* counts;  // count kernel only: [n_pts][kNEvalTiers]
   // main-contributor selection (nullptr: off): per (P, T) point of the batch and group of
   // kSelGroup neighbouring tiles (tile / kSelGroup), the contribution bound below which a
@@ -81,8 +82,9 @@ hipError_t launch_tile_p1(const TileArgs& A, bool f64, int W, hipStream_t st, di
 hipError_t launch_tile_p2(const TileArgs& A, bool f64, int W, hipStream_t st, dim3 grid);
 hipError_t launch_tile_p4(const TileArgs& A, bool f64, int W, hipStream_t st, dim3 grid);
 hipError_t launch_tile_p8(const TileArgs& A, bool f64, int W, hipStream_t st, dim3 grid);
-hipError_t launch_reduce(const double* part, double* out, int64_t n_grid, int n_pts, int split,
-                         hipStream_t st);
+// out: float rows when out_f32, else double rows
+hipError_t launch_reduce(const double* part, void* out, int out_f32, int64_t n_grid, int n_pts,
+                         int split, hipStream_t st);
 // collision-induced absorption: block k (nodes [off[k], off[k+1]) of nu, alpha) linearly
 // interpolated onto the grid, zero outside the block, out[k][j]
 hipError_t launch_cia(const double* grid, int64_t n_grid, const int64_t* off, int n_blocks,

@@ -71,9 +71,11 @@ __global__ __launch_bounds__(256) void xs_params_kernel(ParamArgs A) {
   }
 }
 
-// Fixed-order reduction of split partials: out[k][j] = sum_s part[k][s][j], s ascending.
+// Fixed-order reduction of split partials: out[k][j] = sum_s part[k][s][j], s ascending,
+// stored as OUT (double, or float rounded once from the FP64 sum).
+template <typename OUT>
 __global__ __launch_bounds__(256) void xs_reduce_kernel(const double* __restrict__ part,
-                                                        double* __restrict__ out,
+                                                        OUT* __restrict__ out,
                                                         int64_t n_grid, int n_pts, int split) {
   const int64_t total = (int64_t)n_pts * n_grid;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
@@ -82,7 +84,7 @@ __global__ __launch_bounds__(256) void xs_reduce_kernel(const double* __restrict
     const double* p = part + k * split * n_grid + j;
     double acc = 0.0;
     for (int s = 0; s < split; ++s) acc += p[(int64_t)s * n_grid];
-    out[t] = acc;
+    out[t] = (OUT)acc;
   }
 }
 
@@ -325,14 +327,18 @@ hipError_t launch_select(const TileArgs& A, int P, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const double* part, double* out, int64_t n_grid, int n_pts, int split,
-                         hipStream_t st) {
+hipError_t launch_reduce(const double* part, void* out, int out_f32, int64_t n_grid, int n_pts,
+                         int split, hipStream_t st) {
   const int64_t total = (int64_t)n_pts * n_grid;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(xs_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, part, out,
-                     n_grid, n_pts, split);
+  if (out_f32)
+    hipLaunchKernelGGL(xs_reduce_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, part,
+                       (float*)out, n_grid, n_pts, split);
+  else
+    hipLaunchKernelGGL(xs_reduce_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       part, (double*)out, n_grid, n_pts, split);
   return hipGetLastError();
 }
 

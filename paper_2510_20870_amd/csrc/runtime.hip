@@ -116,6 +116,8 @@ int validate_opts(const xs_opts* o) {
     return fail(XS_EINVAL, "waves_per_simd must be 0 or 2..6 (got %d)", o->waves_per_simd);
   if (!(o->select_eps >= 0.0 && o->select_eps < 1.0))
     return fail(XS_EINVAL, "select_eps must be in [0, 1) (got %g)", o->select_eps);
+  if (o->out_dtype != XS_F64 && o->out_dtype != XS_F32)
+    return fail(XS_EINVAL, "unknown out_dtype %d", o->out_dtype);
   return XS_OK;
 }
 
@@ -265,7 +267,7 @@ int upload_order(Ctx& c, const Plan& p, hipStream_t st) {
 }
 
 int enqueue_step(const LinesRes& L, const GridRes& G, const xs_opts& o, const Plan& p,
-                 const double* pts_dev, const int* order_dev, double* out_dev, void* rec_dev,
+                 const double* pts_dev, const int* order_dev, void* out_dev, void* rec_dev,
                  void* part_dev, hipStream_t st, int pt0, int nb, int64_t c0, int64_t c1,
                  bool with_params, bool with_reduce, unsigned long long* counts,
                  KernelTimer* tm) {
@@ -346,7 +348,8 @@ int enqueue_step(const LinesRes& L, const GridRes& G, const xs_opts& o, const Pl
       e = launch_count(A, p.P, st, phys);
       if (e != hipSuccess) return hip_fail(e, "count kernel launch");
     } else {
-      A.out = (A.split == 1) ? out_dev : (double*)part_dev;
+      A.out = (A.split == 1) ? (double*)out_dev : (double*)part_dev;
+      A.out_f32 = A.split == 1 && o.out_dtype == XS_F32;
       e = launch_tile(A, p.P, f64, p.W, st, phys);
       if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
     }
@@ -354,15 +357,16 @@ int enqueue_step(const LinesRes& L, const GridRes& G, const xs_opts& o, const Pl
     if (rc) return rc;
   }
   if (with_reduce && !counts && p.split > 1) {
-    e = launch_reduce((const double*)part_dev, out_dev + (int64_t)pt0 * (int64_t)G.n,
-                      (int64_t)G.n, nb, p.split, st);
+    e = launch_reduce((const double*)part_dev,
+                      (char*)out_dev + (size_t)pt0 * G.n * out_elem_bytes(o),
+                      o.out_dtype == XS_F32, (int64_t)G.n, nb, p.split, st);
     if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
   }
   return XS_OK;
 }
 
 int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Plan& p,
-                 const double* pts_dev, const int* order_dev, double* out_dev, void* rec_dev,
+                 const double* pts_dev, const int* order_dev, void* out_dev, void* rec_dev,
                  void* part_dev, hipStream_t st, unsigned long long* counts,
                  KernelTimer* tm) {
   for (int pt0 = 0; pt0 < p.npts; pt0 += p.pt_batch) {
@@ -449,6 +453,7 @@ void xs_destroy(xs_ctx* c) {
   (void)hipSetDevice(c->device);
   serve_shutdown(c);
   (void)hipDeviceSynchronize();
+  graphs_release_all(c);
   for (auto& kv : c->lines) free_lines_res(*c, kv.second);
   for (auto& kv : c->grids) {
     c->dev_free(kv.second->d, kv.second->bytes);
@@ -704,7 +709,7 @@ int xs_unload_lines(xs_ctx* c, xs_lines_t h) {
   LinesRes* L = c->find_lines(h);
   if (!L) return fail(XS_ENOTFOUND, "unknown line list %llu", (unsigned long long)h);
   if (L->refs.load() > 0)
-    return fail(XS_EBUSY, "line list %llu is referenced by %d pending request(s)",
+    return fail(XS_EBUSY, "line list %llu is referenced by %d pending request(s) or graph(s)",
                 (unsigned long long)h, L->refs.load());
   c->lines.erase(h);
   (void)hipDeviceSynchronize();
@@ -795,8 +800,9 @@ int xs_free_grid(xs_ctx* c, xs_grid_t h) {
   std::lock_guard<std::mutex> lk(c->mu);
   GridRes* G = c->find_grid(h);
   if (!G) return fail(XS_ENOTFOUND, "unknown grid %llu", (unsigned long long)h);
-  if (G->refs.load() > 0) return fail(XS_EBUSY, "grid %llu is referenced by pending requests",
-                                      (unsigned long long)h);
+  if (G->refs.load() > 0)
+    return fail(XS_EBUSY, "grid %llu is referenced by pending requests or graphs",
+                (unsigned long long)h);
   c->grids.erase(h);
   (void)hipDeviceSynchronize();
   c->dev_free(G->d, G->bytes);
@@ -814,7 +820,7 @@ int xs_grid_info(xs_ctx* c, xs_grid_t h, size_t* n) {
 }
 
 int xs_compute(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t npts,
-               const xs_opts* opts, double* sigma_out, int out_on_device, void* stream) {
+               const xs_opts* opts, void* sigma_out, int out_on_device, void* stream) {
   if (!c) return fail(XS_EINVAL, "ctx is NULL");
   if (!sigma_out) return fail(XS_EINVAL, "sigma_out is NULL");
   int rc = validate_opts(opts);
@@ -841,7 +847,7 @@ int xs_compute(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t 
   const Plan p = make_plan(*c, *L, *G, npts, *opts);
   rc = upload_pts(*c, pts, npts, st);
   if (rc) return rc;
-  const size_t out_bytes = npts * G->n * sizeof(double);
+  const size_t out_bytes = npts * G->n * out_elem_bytes(*opts);
   rc = c->scratch(c->rec_buf, p.rec_bytes(), "line records");
   if (rc) return rc;
   void* part = nullptr;
@@ -850,11 +856,11 @@ int xs_compute(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t 
     if (rc) return rc;
     part = c->part_buf.ptr;
   }
-  double* out_dev = sigma_out;
+  void* out_dev = sigma_out;
   if (!out_on_device) {
     rc = c->scratch(c->out_buf, out_bytes, "output staging");
     if (rc) return rc;
-    out_dev = (double*)c->out_buf.ptr;
+    out_dev = c->out_buf.ptr;
   }
   rc = upload_order(*c, p, st);
   if (rc) return rc;
@@ -941,7 +947,9 @@ int xs_count_evals_by_tier(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* 
 }
 
 struct xs_graph {
-  xs_ctx* ctx = nullptr;
+  xs_ctx* ctx = nullptr;       // nullptr once the context has been destroyed
+  LinesRes* L = nullptr;       // referenced while the graph exists
+  GridRes* G = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   void* pts = nullptr;
@@ -954,73 +962,103 @@ struct xs_graph {
   size_t order_bytes = 0;
 };
 
+}  // extern "C"
+
+namespace xs {
+// Device resources of a graph (the struct itself stays with the caller's handle).
+void graph_release(xs_graph* g) {
+  xs_ctx* c = g->ctx;
+  if (!c) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  g->exec = nullptr;
+  g->graph = nullptr;
+  if (g->pts) c->dev_free(g->pts, g->pts_bytes);
+  if (g->part) c->dev_free(g->part, g->part_bytes);
+  if (g->rec) c->dev_free(g->rec, g->rec_bytes);
+  if (g->order) c->dev_free(g->order, g->order_bytes);
+  g->pts = g->part = g->rec = g->order = nullptr;
+  if (g->L) g->L->refs.fetch_sub(1);
+  if (g->G) g->G->refs.fetch_sub(1);
+  g->L = nullptr;
+  g->G = nullptr;
+}
+
+// xs_destroy: release every graph still alive; their handles only accept destroy.
+void graphs_release_all(xs_ctx* c) {
+  std::vector<xs_graph*> gs;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    gs.assign(c->graphs.begin(), c->graphs.end());
+    c->graphs.clear();
+  }
+  for (xs_graph* g : gs) {
+    graph_release(g);
+    g->ctx = nullptr;
+  }
+}
+}  // namespace xs
+
+extern "C" {
+
 int xs_graph_create(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t npts,
-                    const xs_opts* opts, double* sigma_dev, xs_graph** out) {
+                    const xs_opts* opts, void* sigma_dev, xs_graph** out) {
   if (!c || !out || !sigma_dev) return fail(XS_EINVAL, "NULL argument");
   *out = nullptr;
   int rc = validate_opts(opts);
   if (rc) return rc;
   rc = validate_pts(pts, npts);
   if (rc) return rc;
-  LinesRes* L;
-  GridRes* G;
-  {
-    std::lock_guard<std::mutex> lk(c->mu);
-    L = c->find_lines(lh);
-    G = c->find_grid(gh);
-  }
-  if (!L || !G) return fail(XS_ENOTFOUND, "unknown line list or grid");
-  hipError_t e = hipSetDevice(c->device);
-  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  const Plan p = make_plan(*c, *L, *G, npts, *opts);
   xs_graph* g = new xs_graph();
   g->ctx = c;
+  {
+    // the line list and grid stay referenced while the graph exists
+    std::lock_guard<std::mutex> lk(c->mu);
+    g->L = c->find_lines(lh);
+    g->G = c->find_grid(gh);
+    if (!g->L || !g->G) {
+      delete g;
+      return fail(XS_ENOTFOUND, "unknown line list or grid");
+    }
+    g->L->refs.fetch_add(1);
+    g->G->refs.fetch_add(1);
+  }
+  LinesRes* L = g->L;
+  GridRes* G = g->G;
+  auto give_up = [&](int code) {
+    graph_release(g);
+    delete g;
+    return code;
+  };
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return give_up(hip_fail(e, "hipSetDevice"));
+  const Plan p = make_plan(*c, *L, *G, npts, *opts);
   g->pts_bytes = npts * 2 * sizeof(double);
   rc = c->dev_alloc(&g->pts, g->pts_bytes, "graph point table");
-  if (rc) {
-    delete g;
-    return rc;
-  }
+  if (rc) return give_up(rc);
   std::vector<double> h(2 * npts);
   for (size_t k = 0; k < npts; ++k) {
     h[2 * k] = pts[k].P_bar;
     h[2 * k + 1] = pts[k].T_K;
   }
   e = hipMemcpy(g->pts, h.data(), g->pts_bytes, hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    xs_graph_destroy(g);
-    return hip_fail(e, "graph point table upload");
-  }
+  if (e != hipSuccess) return give_up(hip_fail(e, "graph point table upload"));
   if (p.split > 1) {
     g->part_bytes = p.part_bytes(G->n);
     rc = c->dev_alloc(&g->part, g->part_bytes, "graph partials");
-    if (rc) {
-      xs_graph_destroy(g);
-      return rc;
-    }
+    if (rc) return give_up(rc);
   }
   g->rec_bytes = p.rec_bytes();
   rc = c->dev_alloc(&g->rec, g->rec_bytes, "graph line records");
-  if (rc) {
-    xs_graph_destroy(g);
-    return rc;
-  }
+  if (rc) return give_up(rc);
   g->order_bytes = p.tile_order.size() * sizeof(int);
   rc = c->dev_alloc(&g->order, g->order_bytes, "graph tile order");
-  if (rc == XS_OK) {
-    e = hipMemcpy(g->order, p.tile_order.data(), g->order_bytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) rc = hip_fail(e, "graph tile order upload");
-  }
-  if (rc) {
-    xs_graph_destroy(g);
-    return rc;
-  }
+  if (rc) return give_up(rc);
+  e = hipMemcpy(g->order, p.tile_order.data(), g->order_bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return give_up(hip_fail(e, "graph tile order upload"));
   hipStream_t cs = nullptr;
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-  if (e != hipSuccess) {
-    xs_graph_destroy(g);
-    return hip_fail(e, "hipStreamCreate");
-  }
+  if (e != hipSuccess) return give_up(hip_fail(e, "hipStreamCreate"));
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     rc = enqueue_path(*L, *G, *opts, p, (const double*)g->pts, (const int*)g->order, sigma_dev,
@@ -1035,16 +1073,18 @@ int xs_graph_create(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, si
     e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) rc = hip_fail(e, "hipGraphInstantiate");
   }
-  if (rc) {
-    xs_graph_destroy(g);
-    return rc;
+  if (rc) return give_up(rc);
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->graphs.insert(g);
   }
   *out = g;
   return XS_OK;
 }
 
 int xs_graph_launch(xs_graph* g, void* stream) {
-  if (!g || !g->exec) return fail(XS_EINVAL, "graph is NULL");
+  if (!g) return fail(XS_EINVAL, "graph is NULL");
+  if (!g->ctx || !g->exec) return fail(XS_EINVAL, "the graph's context has been destroyed");
   hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   return XS_OK;
@@ -1052,13 +1092,15 @@ int xs_graph_launch(xs_graph* g, void* stream) {
 
 void xs_graph_destroy(xs_graph* g) {
   if (!g) return;
-  (void)hipDeviceSynchronize();
-  if (g->exec) (void)hipGraphExecDestroy(g->exec);
-  if (g->graph) (void)hipGraphDestroy(g->graph);
-  if (g->pts) g->ctx->dev_free(g->pts, g->pts_bytes);
-  if (g->part) g->ctx->dev_free(g->part, g->part_bytes);
-  if (g->rec) g->ctx->dev_free(g->rec, g->rec_bytes);
-  if (g->order) g->ctx->dev_free(g->order, g->order_bytes);
+  if (xs_ctx* c = g->ctx) {
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    {
+      std::lock_guard<std::mutex> lk(c->mu);
+      c->graphs.erase(g);
+    }
+    graph_release(g);
+  }
   delete g;
 }
 

@@ -5,6 +5,7 @@
 
 #include <atomic>
 #include <mutex>
+#include <set>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -25,7 +26,7 @@ struct LinesRes {
   void* base = nullptr;     // one device allocation holding every array
   size_t bytes = 0;
   size_t n = 0;
-  std::atomic<int> refs{0}; // pending serving requests
+  std::atomic<int> refs{0}; // pending serving requests and live graphs
   std::vector<double> q_T_host, q_val_host;
   std::vector<double> sample;   // nu0 of every kSampleStride-th line (host index)
 };
@@ -41,7 +42,7 @@ struct GridRes {
   size_t bytes = 0;
   double first = 0.0, last = 0.0;   // host copies of the end points
   std::vector<double> host;         // host copy of the grid
-  std::atomic<int> refs{0};
+  std::atomic<int> refs{0};         // pending serving requests and live graphs
 };
 
 struct Plan {
@@ -103,6 +104,7 @@ struct xs_ctx {
   xs::Server* server = nullptr;
   std::mutex serve_mu;                   // guards starting the server
   xs::KernelTimer* timer = nullptr;      // non-null while kernel timing is enabled
+  std::set<xs_graph*> graphs;            // live graphs (guarded by mu)
 
   bool reserve(size_t bytes);
   void release(size_t bytes);
@@ -161,9 +163,9 @@ bool tune_get(const std::string& key, TuneVal* v);
 void tune_put(const std::string& key, const TuneVal& v);
 // Enqueue the whole path on `st`: per batch of (P, T) points the parameter kernel, the
 // tile kernel and (split > 1) the fixed-order reduction; with counts != nullptr the count
-// kernel instead of tile + reduction.
+// kernel instead of tile + reduction. out_dev holds rows of o.out_dtype elements.
 int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Plan& p,
-                 const double* pts_dev, const int* order_dev, double* out_dev, void* rec_dev,
+                 const double* pts_dev, const int* order_dev, void* out_dev, void* rec_dev,
                  void* part_dev, hipStream_t st, unsigned long long* counts = nullptr,
                  KernelTimer* tm = nullptr);
 // One step of the path for the batch of points [pt0, pt0 + nb): the parameter kernel
@@ -171,12 +173,17 @@ int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Pl
 // required), and the fixed-order reduction of the batch (with_reduce, split > 1). The
 // steps of one batch must run in this order.
 int enqueue_step(const LinesRes& L, const GridRes& G, const xs_opts& o, const Plan& p,
-                 const double* pts_dev, const int* order_dev, double* out_dev, void* rec_dev,
+                 const double* pts_dev, const int* order_dev, void* out_dev, void* rec_dev,
                  void* part_dev, hipStream_t st, int pt0, int nb, int64_t c0, int64_t c1,
                  bool with_params, bool with_reduce, unsigned long long* counts = nullptr,
                  KernelTimer* tm = nullptr);
 // Upload the plan's tile order into the context buffer (skipped when unchanged).
 int upload_order(Ctx& c, const Plan& p, hipStream_t st);
+
+// Bytes of one sigma element for the output type of the options.
+inline size_t out_elem_bytes(const xs_opts& o) {
+  return o.out_dtype == XS_F32 ? sizeof(float) : sizeof(double);
+}
 
 inline void free_lines_res(Ctx& c, LinesRes* L) {
   c.dev_free(L->base, L->bytes);
@@ -184,5 +191,7 @@ inline void free_lines_res(Ctx& c, LinesRes* L) {
 }
 
 void serve_shutdown(Ctx* c);
+// Release the device resources of every graph of the context (xs_destroy).
+void graphs_release_all(Ctx* c);
 
 }  // namespace xs

@@ -135,7 +135,7 @@ struct Request {
   double nu_start = 0.0, step = 0.0;
   xs_opts o{};
   std::vector<double> pt_pairs;   // (P, T) interleaved
-  double* out = nullptr;
+  void* out = nullptr;
   bool out_dev = false;
   Plan plan;
   std::vector<Step> steps;
@@ -267,7 +267,7 @@ int Server::enqueue_next(Request& r, Lane& ln) {
     r.uploaded = true;
   }
   const Step& s = r.steps[r.next];
-  double* out_dev = r.out_dev ? r.out : (double*)(blk + r.o_out);
+  void* out_dev = r.out_dev ? r.out : (void*)(blk + r.o_out);
   void* part = r.plan.split > 1 ? (void*)(blk + r.o_part) : nullptr;
   int rc = enqueue_step(*r.L, *r.G, r.o, r.plan, (const double*)(blk + r.o_pts),
                         (const int*)(blk + r.o_order), out_dev, blk + r.o_rec, part, ln.st,
@@ -330,7 +330,7 @@ void Server::loop() {
       for (size_t k = 0; k < done.size(); ++k) {
         Request& r = *done[k];
         if (res[k].first != XS_OK || r.out_dev) continue;
-        const size_t ob = r.pt_pairs.size() / 2 * r.G->n * sizeof(double);
+        const size_t ob = r.pt_pairs.size() / 2 * r.G->n * out_elem_bytes(r.o);
         const hipError_t e = hipMemcpy(r.out, base + r.off + r.o_out, ob, hipMemcpyDeviceToHost);
         if (e != hipSuccess) {
           hip_fail(e, "result download");
@@ -510,7 +510,9 @@ static Request* find_req(Server* s, xs_req_t id) {
 // Common part of xs_submit / xs_submit_window: G == nullptr means a window request.
 static int submit(Ctx* c, xs_lines_t lh, xs_grid_t gh, bool window, double nu_start,
                   double step, size_t n_points, const xs_pt* pts, size_t npts,
-                  const xs_opts* opts, double* sigma_out, int out_on_device, xs_req_t* out) {
+                  const xs_opts* opts, void* sigma_out, int out_on_device, xs_req_t* out) {
+  // the request's latency counts from here (planning and queueing included)
+  const double t_submit = now_s();
   if (!c || !out || !sigma_out) return fail(XS_EINVAL, "NULL argument");
   int rc = validate_opts(opts);
   if (rc) return rc;
@@ -569,7 +571,7 @@ static int submit(Ctx* c, xs_lines_t lh, xs_grid_t gh, bool window, double nu_st
   };
   r->o_rec = part(r->plan.rec_bytes());
   r->o_part = part(r->plan.part_bytes(n));
-  r->o_out = part(r->out_dev ? 0 : npts * n * sizeof(double));
+  r->o_out = part(r->out_dev ? 0 : npts * n * out_elem_bytes(*opts));
   r->o_grid = part(window ? n * sizeof(double) : 0);
   r->o_pts = part(npts * 2 * sizeof(double));
   r->o_order = part(r->plan.tile_order.size() * sizeof(int));
@@ -586,7 +588,7 @@ static int submit(Ctx* c, xs_lines_t lh, xs_grid_t gh, bool window, double nu_st
   }
   std::lock_guard<std::mutex> lk(s->mu);
   r->id = s->next_id++;
-  r->t_submit = now_s();
+  r->t_submit = t_submit;
   s->reqs[r->id] = r;
   s->queue.push_back({r->id, r->bytes, 0});
   *out = r->id;
@@ -668,14 +670,14 @@ int xs_serve_pause(xs_ctx* c, int paused) {
 }
 
 int xs_submit(xs_ctx* c, xs_lines_t lines, xs_grid_t grid, const xs_pt* pts, size_t npts,
-              const xs_opts* opts, double* sigma_out, int out_on_device, xs_req_t* out) {
+              const xs_opts* opts, void* sigma_out, int out_on_device, xs_req_t* out) {
   return submit(c, lines, grid, false, 0.0, 0.0, 0, pts, npts, opts, sigma_out, out_on_device,
                 out);
 }
 
 int xs_submit_window(xs_ctx* c, xs_lines_t lines, double nu_start, double step,
                      size_t n_points, const xs_pt* pts, size_t npts, const xs_opts* opts,
-                     double* sigma_out, int out_on_device, xs_req_t* out) {
+                     void* sigma_out, int out_on_device, xs_req_t* out) {
   return submit(c, lines, 0, true, nu_start, step, n_points, pts, npts, opts, sigma_out,
                 out_on_device, out);
 }

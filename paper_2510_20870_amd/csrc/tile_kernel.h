@@ -1014,7 +1014,8 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       double v;
       if constexpr (F64) v = s[p];
       else v = ldexp((double)s[p] - (double)c[p], e_ref - kScaleTarget);
-      A.out[row * A.n_grid + j] = v;
+      if (A.out_f32) ((float*)A.out)[row * A.n_grid + j] = (float)v;
+      else A.out[row * A.n_grid + j] = v;
     }
   }
 }

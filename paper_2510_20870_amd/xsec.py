@@ -23,6 +23,7 @@ XS_EINSTEIN_A, XS_REF_STRENGTH = 0, 1
 XS_Q_POWER, XS_Q_TABLE = 0, 1
 XS_CUT_FIXED, XS_CUT_MIN_FWHM = 0, 1
 XS_FP32_KAHAN, XS_FP64 = 0, 1
+XS_F64, XS_F32 = 0, 1            # element type of sigma outputs
 XS_N_EVAL_TIERS = 9
 # names of the evaluation tiers counted by Context.count_evals_by_tier
 EVAL_TIERS = ("lorentz_shifted", "series2", "series3", "series4", "series6",
@@ -65,7 +66,8 @@ class Pt(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("cutoff_kind", C.c_int), ("cut_cm1", C.c_double), ("fwhm_mult", C.c_double),
                 ("precision", C.c_int), ("pts_per_lane", C.c_int), ("split", C.c_int),
-                ("waves_per_simd", C.c_int), ("select_eps", C.c_double)]
+                ("waves_per_simd", C.c_int), ("select_eps", C.c_double),
+                ("out_dtype", C.c_int)]
 
 
 class ServeOpts(C.Structure):
@@ -241,6 +243,10 @@ def eval_bounds_host(x, y):
     if rc:
         raise XsError(rc, lib().xs_last_error(None).decode())
     return lo, hi
+
+
+def _out_np_dtype(opts: "Opts"):
+    return np.float32 if opts.out_dtype == XS_F32 else np.float64
 
 
 def _dev_ptr(t) -> int:
@@ -487,9 +493,10 @@ class Context:
     @staticmethod
     def opts(cutoff_kind: int = XS_CUT_FIXED, cut_cm1: float = 25.0, fwhm_mult: float = 100.0,
              precision: int = XS_FP32_KAHAN, pts_per_lane: int = 0, split: int = 0,
-             waves_per_simd: int = 0, select_eps: float = 0.0) -> Opts:
+             waves_per_simd: int = 0, select_eps: float = 0.0,
+             out_dtype: int = XS_F64) -> Opts:
         return Opts(cutoff_kind, cut_cm1, fwhm_mult, precision, pts_per_lane, split,
-                    waves_per_simd, float(select_eps))
+                    waves_per_simd, float(select_eps), int(out_dtype))
 
     @staticmethod
     def _pts(pts) -> C.Array:
@@ -500,12 +507,13 @@ class Context:
         return arr
 
     def compute(self, lines: int, grid: int, pts, opts: Opts, out=None, stream=None):
-        """sigma[npts, n_grid]. With `out` a device tensor (or pointer) the work is enqueued
-        on `stream` and `out` is returned; otherwise a host numpy array is returned."""
+        """sigma[npts, n_grid] (float64, or float32 with opts.out_dtype = XS_F32). With
+        `out` a device tensor (or pointer) the work is enqueued on `stream` and `out` is
+        returned; otherwise a host numpy array is returned."""
         p = self._pts(pts)
         if out is None:
             n_grid = self.grid_len(grid)
-            host = np.empty((len(p), n_grid), np.float64)
+            host = np.empty((len(p), n_grid), _out_np_dtype(opts))
             self._check(self._L.xs_compute(self.h, lines, grid, p, len(p), C.byref(opts),
                                            _ptr(host), 0, None))
             return host
@@ -556,10 +564,10 @@ class Context:
         [npts, n_grid], or a device tensor (written by the server's streams)."""
         p = self._pts(pts)
         if out is None:
-            out = np.empty((len(p), self.grid_len(grid)), np.float64)
+            out = np.empty((len(p), self.grid_len(grid)), _out_np_dtype(opts))
         on_dev = not isinstance(out, np.ndarray)
-        if not on_dev and (out.dtype != np.float64 or not out.flags.c_contiguous):
-            raise ValueError("host out must be C-contiguous float64")
+        if not on_dev and (out.dtype != _out_np_dtype(opts) or not out.flags.c_contiguous):
+            raise ValueError(f"host out must be C-contiguous {_out_np_dtype(opts).__name__}")
         h = C.c_uint64()
         self._check(self._L.xs_submit(self.h, lines, grid, p, len(p), C.byref(opts),
                                       _dev_ptr(out) if on_dev else _ptr(out), int(on_dev),
@@ -571,8 +579,10 @@ class Context:
         """Queue sigma on the uniform grid nu_start + j*step, j < n_points."""
         p = self._pts(pts)
         if out is None:
-            out = np.empty((len(p), n_points), np.float64)
+            out = np.empty((len(p), n_points), _out_np_dtype(opts))
         on_dev = not isinstance(out, np.ndarray)
+        if not on_dev and (out.dtype != _out_np_dtype(opts) or not out.flags.c_contiguous):
+            raise ValueError(f"host out must be C-contiguous {_out_np_dtype(opts).__name__}")
         h = C.c_uint64()
         self._check(self._L.xs_submit_window(self.h, lines, float(nu_start), float(step),
                                              int(n_points), p, len(p), C.byref(opts),

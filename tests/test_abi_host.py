@@ -28,7 +28,24 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
     # the binding covers every declared entry point
     assert set(decl) <= set(xsec.exported_symbols())
-    assert L.xs_abi_version() == 4
+    hdr = open(os.path.join(ROOT, "include", "xsec.h")).read()
+    assert L.xs_abi_version() == int(re.search(r"#define XS_ABI_VERSION (\d+)", hdr).group(1))
+
+
+def test_binding_structs_follow_the_header():
+    # the ctypes structures list the fields of the header's structs, in order
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "xsec.h")).read(),
+                 flags=re.S)
+    for cname, py in (("xs_opts", xsec.Opts), ("xs_lines_desc", xsec.LinesDesc),
+                      ("xs_species_desc", xsec.SpeciesDesc), ("xs_serve_opts", xsec.ServeOpts)):
+        end = re.search(r"\}\s*" + cname + r"\s*;", src).start()
+        body = src[src.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+        names = []
+        for decl in body.split(";"):
+            decl = re.sub(r"\[.*?\]", "", decl).strip()
+            if decl:
+                names += [re.split(r"[\s*]+", n.strip())[-1] for n in decl.split(",")]
+        assert names == [f[0] for f in py._fields_], (cname, names)
 
 
 def test_no_compute_without_device_is_a_clean_error():
