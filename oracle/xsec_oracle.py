@@ -303,6 +303,48 @@ def cia_regrid(grid: np.ndarray, blocks) -> np.ndarray:
                                left=0.0, right=0.0) for nu, a in blocks])
 
 
+# ------------------------------------------------------------------ output regridding
+def regrid_linear(dst, src_x, src_y) -> np.ndarray:
+    """Cross-sections resampled onto another grid (results on any user grid, "Similar
+    tools"): the piecewise-linear function through (src_x, src_y) at the points dst, zero
+    outside [src_x[0], src_x[-1]]."""
+    return np.interp(np.asarray(dst, np.float64), np.asarray(src_x, np.float64),
+                     np.asarray(src_y, np.float64), left=0.0, right=0.0)
+
+
+def regrid_bin_edges(dst) -> np.ndarray:
+    """Edges of the bins of the destination points: midpoints between neighbours, the
+    first and last bins mirrored to the same half-widths (one point: no bins)."""
+    d = np.asarray(dst, np.float64)
+    mid = 0.5 * (d[1:] + d[:-1])
+    return np.concatenate([[d[0] - (mid[0] - d[0])], mid, [d[-1] + (d[-1] - mid[-1])]])
+
+
+def regrid_bin_mean(dst, src_x, src_y) -> np.ndarray:
+    """The mean of the piecewise-linear function through (src_x, src_y) over each
+    destination point's bin (regrid_bin_edges), the bin clipped to the source range; 0 for
+    a bin outside it. From the antiderivative F of the function: (F(b) - F(a)) / (b - a),
+    F exact (quadratic) between the nodes. A single destination point takes the whole
+    source range as its bin."""
+    x = np.asarray(src_x, np.float64)
+    y = np.asarray(src_y, np.float64)
+    d = np.asarray(dst, np.float64)
+    C = np.concatenate([[0.0], np.cumsum(0.5 * (y[1:] + y[:-1]) * np.diff(x))])
+
+    def F(v):
+        i = np.clip(np.searchsorted(x, v, "right") - 1, 0, len(x) - 2)
+        yv = np.interp(v, x, y)
+        return C[i] + 0.5 * (y[i] + yv) * (v - x[i])
+
+    e = regrid_bin_edges(d) if len(d) > 1 else np.array([x[0], x[-1]])
+    a = np.clip(e[:-1], x[0], x[-1])
+    b = np.clip(e[1:], x[0], x[-1])
+    out = np.zeros(len(d))
+    ok = b > a
+    out[ok] = (F(b[ok]) - F(a[ok])) / (b[ok] - a[ok])
+    return out
+
+
 # --------------------------------------------------------------- acceptance metric
 def compare(sig: np.ndarray, ref: np.ndarray, rel_tol: float = 1e-4,
             floor: float = 1e-8, ref_max: Optional[float] = None) -> Dict[str, float]:

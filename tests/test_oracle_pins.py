@@ -583,3 +583,54 @@ def test_cia_regrid_is_linear_interpolation():
         x = np.arange(0.0, 30.0 + h / 2, h)
         errs.append(np.max(np.abs(O.cia_regrid(g, [(x, f(x))])[0] - f(g))))
     assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5
+
+
+def test_regrid_linear_pins():
+    # linear data is reproduced exactly at any point inside the source range, the nodes
+    # exactly, zero outside
+    x = np.array([1.0, 1.5, 2.25, 4.0, 7.0])
+    y = 2.0 * x - 1.0
+    d = np.array([0.5, 1.0, 1.2, 3.3, 6.99, 7.0, 7.5])
+    out = O.regrid_linear(d, x, y)
+    inside = (d >= 1.0) & (d <= 7.0)
+    assert np.allclose(out[inside], 2.0 * d[inside] - 1.0, rtol=1e-15, atol=1e-14)
+    assert np.all(out[~inside] == 0.0)
+    assert O.regrid_linear([2.25], x, y)[0] == y[2]
+
+
+def test_regrid_bin_mean_pins():
+    rng = np.random.default_rng(8)
+    x = np.sort(rng.uniform(100.0, 200.0, 400))
+    d = np.sort(rng.uniform(90.0, 210.0, 37))
+    e = O.regrid_bin_edges(d)
+    # edges: midpoints, the end bins mirrored
+    assert np.allclose(e[1:-1], 0.5 * (d[1:] + d[:-1]), rtol=1e-15)
+    assert e[0] == pytest.approx(2 * d[0] - e[1]) and e[-1] == pytest.approx(2 * d[-1] - e[-2])
+    # linear data: the mean over [a, b] is the value at its midpoint (bins clipped to the
+    # source range); constant data stays constant
+    y = 0.3 * x + 5.0
+    out = O.regrid_bin_mean(d, x, y)
+    a = np.clip(e[:-1], x[0], x[-1])
+    b = np.clip(e[1:], x[0], x[-1])
+    ok = b > a
+    assert np.allclose(out[ok], 0.3 * 0.5 * (a[ok] + b[ok]) + 5.0, rtol=1e-13)
+    assert np.all(out[~ok] == 0.0)
+    assert np.allclose(O.regrid_bin_mean(d, x, np.full(len(x), 2.5))[ok], 2.5, rtol=1e-13)
+    # any data: means x widths add up to the integral over the covered range (trapezoids
+    # of the source nodes there), and each mean agrees with a fine midpoint quadrature of
+    # the interpolant
+    y = np.exp(np.sin(x / 3.0)) + rng.uniform(0, 0.1, len(x))
+    out = O.regrid_bin_mean(d, x, y)
+    total = float(np.sum(out * (b - a)))
+    inner = (x >= a[ok][0]) & (x <= b[ok][-1])
+    xs = np.concatenate([[a[ok][0]], x[inner], [b[ok][-1]]])
+    ys = np.interp(xs, x, y)
+    assert total == pytest.approx(float(np.sum(0.5 * (ys[1:] + ys[:-1]) * np.diff(xs))),
+                                  rel=1e-12)
+    for k in np.nonzero(ok)[0][::5]:
+        t = a[k] + (b[k] - a[k]) * (np.arange(200_000) + 0.5) / 200_000
+        assert out[k] == pytest.approx(float(np.mean(np.interp(t, x, y))), rel=1e-8)
+    # a single destination point: the mean over the whole source range
+    one = O.regrid_bin_mean([150.0], x, y)[0]
+    assert one == pytest.approx(float(np.sum(0.5 * (y[1:] + y[:-1]) * np.diff(x))) /
+                                (x[-1] - x[0]), rel=1e-12)
