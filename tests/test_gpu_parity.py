@@ -327,7 +327,105 @@ def test_graph_replay_matches_compute(ctx):
         assert np.array_equal(out.cpu().numpy(), eager), rep
         # eager work between replays
         _ = ctx.compute(h, g, [(5.0, 2000.0)], o)
+    for k, (P, T) in enumerate(pts):
+        _check(eager[k], O.sigma(L, grid, P, T, W.mass_amu, cut_cm1=W.cut_cm1), tol=1e-5,
+               label=f"graph P={P} T={T}")
     gr.close()
+    ctx.unload_lines(h)
+    ctx.free_grid(g)
+
+
+def test_graph_several_batches_vs_oracle():
+    """A graph whose plan needs one batch per P-T point (a context whose memory budget
+    holds the records of one point only), with FP32 output: every replay equals eager
+    compute bitwise and the oracle to the FP32 budget; the graph keeps its list and grid
+    referenced; destroying the context leaves the handle valid for destroy only."""
+    import torch
+    X = _xsec()
+    W, L, grid = _tiny()
+    grid = grid[:6001]
+    pts = [(1.0, 1000.0), (1e-4, 300.0), (30.0, 2500.0), (0.05, 700.0)]
+    # list 0.26 MB + grid 48 KB; one point's records (32 B x 1e4 lines) and partials
+    # (3 x 6001 x 8 B) fit a quarter of what is left, two do not
+    small = X.Context(0, hbm_budget_bytes=1_600_000)
+    h = small.load_lines(L, W.mass_amu)
+    g = small.set_grid(grid)
+    o = _opts("min_fwhm", 10.0, 100.0, split=3)
+    o.out_dtype = X.XS_F32
+    eager = small.compute(h, g, pts, o)
+    assert eager.dtype == np.float32
+    out = torch.zeros((len(pts), len(grid)), dtype=torch.float32, device="cuda")
+    gr = small.graph_create(h, g, pts, o, out)
+    for rep in range(3):
+        out.fill_(-1.0)
+        gr.launch(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager), rep
+        _ = small.compute(h, g, pts[1:2], o)
+    for k, (P, T) in enumerate(pts):
+        ref = O.sigma(L, grid, P, T, W.mass_amu, cut_kind="min_fwhm", cut_cm1=10.0,
+                      fwhm_mult=100.0)
+        _check(eager[k].astype(np.float64), ref, tol=1e-5, label=f"graph batches P={P} T={T}")
+    # the graph holds its list and grid
+    with pytest.raises(X.XsError) as e:
+        small.unload_lines(h)
+    assert e.value.code == X.XS_EBUSY
+    with pytest.raises(X.XsError) as e:
+        small.free_grid(g)
+    assert e.value.code == X.XS_EBUSY
+    small.close()
+    with pytest.raises(X.XsError) as e:
+        gr.launch(torch.cuda.current_stream())
+    assert e.value.code == X.XS_EINVAL
+    gr.close()
+
+
+@pytest.mark.parametrize("split", [1, 3])
+def test_fp32_output(ctx, split):
+    """out_dtype XS_F32: the FP64 result rounded once to float32, on host and device
+    outputs."""
+    import torch
+    X = _xsec()
+    W, L, grid = _tiny()
+    h = ctx.load_lines(L, W.mass_amu)
+    g = ctx.set_grid(grid)
+    pts = [(1.0, 1000.0), (3e-3, 400.0)]
+    o64 = _opts(cut=W.cut_cm1, split=split)
+    o32 = _opts(cut=W.cut_cm1, split=split)
+    o32.out_dtype = X.XS_F32
+    s64 = ctx.compute(h, g, pts, o64)
+    s32 = ctx.compute(h, g, pts, o32)
+    assert s32.dtype == np.float32 and s32.shape == s64.shape
+    assert np.array_equal(s32, s64.astype(np.float32))
+    dev = torch.empty((len(pts), len(grid)), dtype=torch.float32, device="cuda")
+    ctx.compute(h, g, pts, o32, out=dev, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert np.array_equal(dev.cpu().numpy(), s32)
+    for k, (P, T) in enumerate(pts):
+        ref = O.sigma(L, grid, P, T, W.mass_amu, cut_cm1=W.cut_cm1)
+        _check(s32[k].astype(np.float64), ref, tol=1e-5, label=f"f32 out P={P}")
+    bad = _opts(cut=W.cut_cm1)
+    bad.out_dtype = 7
+    with pytest.raises(X.XsError) as e:
+        ctx.compute(h, g, pts, bad)
+    assert e.value.code == X.XS_EINVAL
+    ctx.unload_lines(h)
+    ctx.free_grid(g)
+
+
+def test_fp64_path_fwhm_cut(ctx):
+    """The plain FP64 GPU path with the FWHM cutoff, over the pressure range of the table
+    workload, against the oracle."""
+    W, L, grid = _tiny()
+    pts = synth.pt_table(1e-5, 1e2, 4, 300.0, 3000.0, 2)
+    h = ctx.load_lines(L, W.mass_amu)
+    g = ctx.set_grid(grid)
+    sig = ctx.compute(h, g, pts, _opts("min_fwhm", 25.0, 100.0, f64=True))
+    for k, (P, T) in enumerate(pts):
+        ref = O.sigma(L, grid, P, T, W.mass_amu, cut_kind="min_fwhm", cut_cm1=25.0,
+                      fwhm_mult=100.0)
+        st = _check(sig[k], ref, tol=1e-7, label=f"fp64 fwhm P={P:.1e} T={T:.0f}")
+        assert st["max_rel"] < 1e-7
     ctx.unload_lines(h)
     ctx.free_grid(g)
 

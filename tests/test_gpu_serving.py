@@ -211,3 +211,51 @@ def test_shutdown_with_queued_requests(torch_gpu):
     rs = [ctx.submit_window(h, 520.0, 0.01, 1000, [(1.0, 1000.0)], _opts()) for _ in range(4)]
     assert not any(r.poll() for r in rs)
     ctx.close()     # cancels the queued requests and stops the server cleanly
+
+
+@pytest.mark.timeout(300)
+def test_full_scale_request_vs_oracle(torch_gpu):
+    """Requests of the serving stream's largest kind: the 1e8-line list (44 amu, 500-10000
+    cm^-1) resident, windows of 2e5 and 1.2e5 points at 0.01 cm^-1, low and high pressure,
+    one with float32 output; sampled windows of each result against the oracle (lines
+    regenerated for each window)."""
+    import parity_windows as PW
+    X = _x()
+    spec, mass = synth.SERVING_LISTS[3]
+    L = synth.make_lines(spec, workers=synth.default_workers())
+    ctx = X.Context(0)
+    h = ctx.load_lines(L, mass)
+    del L
+    o = _opts(cut=25.0)
+    o32 = _opts(cut=25.0)
+    o32.out_dtype = X.XS_F32
+    reqs = [(3000.0, 200_000, (2e-4, 2200.0), o), (7100.5, 120_000, (40.0, 450.0), o32)]
+    subs = [ctx.submit_window(h, start, 0.01, n, [pt], oo) for start, n, pt, oo in reqs]
+    outs = [r.wait()[0].astype(np.float64) for r in subs]
+    for r in subs:
+        r.release()
+
+    class _W:   # the request's workload as the window helper sees it
+        lines = spec
+        mass_amu = mass
+        cut_kind = "fixed"
+        cut_cm1 = 25.0
+        fwhm_mult = 100.0
+        q_a = 0.0343
+        q_b = 1.5
+
+    for (start, n, (P, T), oo), sig in zip(reqs, outs):
+        grid = start + 0.01 * np.arange(n, dtype=np.float64)
+        rng = np.random.default_rng(int(start))
+        windows = [np.arange(s0, s0 + 16) for s0 in
+                   np.sort(rng.choice(n - 16, 4, replace=False))] + [np.arange(n - 16, n)]
+        top_idx, j = PW.argmax_window(sig)
+        ref = PW.oracle_jobs(_W, grid, [(idx, P, T) for idx in windows] + [(top_idx, P, T)],
+                             synth.default_workers())
+        m, rel = PW.floor_basis(sig, top_idx, j, ref[-1], 1e-5)
+        for idx, rw in zip(windows, ref[:-1]):
+            st = O.compare(sig[idx], rw, rel_tol=1e-5, ref_max=m)
+            print(f"[serving] request at {start} ({n} points) P={P} T={T} window {idx[0]}: "
+                  f"max_rel {st['max_rel']:.3e}", flush=True)
+            assert st["violations"] == 0, st
+    ctx.close()
