@@ -1,23 +1,33 @@
 """Benchmark: Voigt line-point evaluations per second on one MI355X.
 
-Workload (default): 1e7 synthetic lines over 500-10000 cm^-1 (mass 16 amu), a uniform
-0.01 cm^-1 grid of 9.5e5 points, one (P, T) = (0.1 bar, 1500 K), fixed 25 cm^-1 cutoff,
-FP32 Voigt evaluation with Kahan-compensated sums and FP64 centres/offsets. One step is one
-full xs_compute of that cross-section with the line list and grid resident in HBM.
+Headline workload (default, the largest single-GPU configuration): 1e9 synthetic lines
+over 100-30000 cm^-1 (mass 16 amu, 26 GB resident in HBM), a 3e6-point grid uniform in
+ln(nu), 24 (P, T) points (6 pressures log-spaced 1e-4..1e2 bar x 4 temperatures
+500..3000 K), fixed 25 cm^-1 cutoff, FP32 Voigt evaluation with Kahan-compensated sums and
+FP64 centres/offsets. One step is one xs_compute of one (P, T) point of the table, the
+points taken in a fixed rotation that spreads any run of consecutive steps over the
+pressures and temperatures; inputs are resident in HBM before the timed region. Line-point
+evaluations are counted on the host from the sorted centres (searchsorted; the cut is
+fixed, so every point of the table has the same count).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
+                    [--no-extra] [--serving-requests N] [--workload large|mid|table]
 
-Prints one JSON line. The plain FP64 GPU path is timed beside it ("fp64_path"), the FP64
-CPU oracle is timed on a bounded sample of the same workload on this host's cores
-("cpu_baseline"), and the GPU result is checked against the oracle on that sample
-("max_rel_err"). Kernel duration for the roofline comes from HIP events recorded on the
-stream the kernel runs on.
+Prints one JSON line. Beside the headline: the plain FP64 GPU path on points of the same
+table ("fp64_path"), the whole 24-point table in one batched call ("table_call"), the
+mid-size single-point and the 120-point table workloads ("extra"), the serving stream
+("serving": p50/p99 latency and throughput at offered loads 0.5, 0.8 and 0.95 of the
+measured saturation, latency counted from each request's scheduled arrival), and the FP64
+CPU oracle timed on a bounded sample of the headline workload on this host's cores
+("cpu_baseline"), which also checks the GPU result there ("parity"). Kernel duration for
+the roofline comes from HIP events recorded on the stream the kernel runs on.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -26,9 +36,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work of one line-point evaluation by the tier the point needs (FMA = 2 FLOPs,
-# reciprocal = 1; FP32 in the far region, FP64 in the core; counted per point by
-# xs_count_evals_by_tier):
+# Model of the algorithmic work of one line-point evaluation by the tier the point needs
+# (FMA = 2 FLOPs, reciprocal = 1; FP32 in the far region, FP64 in the core; counted per
+# point by xs_count_evals_by_tier). Used only when no counter profile of the current
+# kernel sources is committed:
 #   shifted Lorentzian: x = off/b_D + x_row 2, r^2 - 3/2 2, 1/r^2 1, += c1 u 2         -> 7
 #   two-term series:    x 2, r^2 2, u 1, u(c1 + u(c2 + u c3)) + t 6                    -> 11
 #   3 / 4 / 6 terms:    x 2, r^2 2, u 1, w 1, the V_k recurrence and the sum, += c1 K  -> 19/25/35
@@ -40,14 +51,18 @@ sys.path.insert(0, ROOT)
 FLOPS_BY_TIER = (7.0, 11.0, 19.0, 25.0, 35.0, 35.0 + 7 * 15, 35.0 + 7 * 23, 35.0 + 7 * 31,
                  35.0 + 7 * 39)
 KAHAN_FLOPS_PER_EVAL = 4.0 / 16.0
-# VALU peak without packed FP32 (the build disables packed FP32 instructions): 256 CUs x
-# 4 SIMDs x 16 lanes x 1 FMA (2 FLOPs) per clock x 2.4 GHz; the published 157.3 TFLOP/s
-# needs packed FP32.
-PEAK_ALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# Published MI355X vector peaks: FP32 157.3 TFLOP/s (packed FP32 FMA), FP64 78.6 TFLOP/s.
+# Without packed FP32 instructions (this build disables them) FP32 FMA issues at the FP64
+# rate: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOPs x 2.4 GHz = 78.6 TFLOP/s.
 PEAK_FP32_PACKED_TFLOPS = 157.3
+PEAK_ALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# VALU issue ceiling: 256 CUs x 64 lanes x 2.4 GHz lane-instructions per second
+PEAK_VALU_LANE_INSTR = 256 * 64 * 2.4e9
 PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("tile_kernel.h", "voigt.h", "physics.h", "kernel_args.h", "weideman_coef.h")
-COUNTER_PROFILE = os.path.join(ROOT, "profiles", "tile_kernel_mid_counters.md")
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+COUNTER_PROFILE = os.path.join(PROFILE_DIR, "tile_kernel_large_counters.md")
+METRIC = "Voigt line-point evals/s at <=1e-4 rel err vs FP64; p50/p99 request latency"
 
 
 def kernel_source_hash() -> str:
@@ -59,44 +74,21 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def _counter_profile():
-    """The committed counter profile's text, or None when it is missing or the kernel
-    sources changed since it was taken."""
-    import re
+def counter_profile(path=None):
+    """Figures of the committed counter profile of the tile kernel ("key: value" lines),
+    or None when it is missing or the kernel sources changed since it was taken."""
     try:
-        with open(COUNTER_PROFILE) as fh:
+        with open(path or COUNTER_PROFILE) as fh:
             text = fh.read()
     except OSError:
         return None
     m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
     if not m_hash or m_hash.group(1) != kernel_source_hash():
         return None
-    return text
-
-
-def profiled_traffic():
-    """HBM bytes per tile-kernel launch from the committed counter profile, or None when
-    the kernel sources changed since it was taken."""
-    import re
-    text = _counter_profile()
-    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text) if text else None
-    return float(m.group(1)) if m else None
-
-
-def profiled_issue():
-    """The tile kernel's measured VALU issue (VALUBusy %, VALU lane-instructions per
-    evaluation) from the committed counter profile, or None as for profiled_traffic."""
-    import re
-    text = _counter_profile()
-    if not text:
-        return None
-    m_busy = re.search(r"\| VALUBusy \(derived, %\) \| ([0-9.]+) \|", text)
-    m_ipe = re.search(r"VALU lane-instructions per line-point evaluation: ([0-9.]+)", text)
-    if not (m_busy and m_ipe):
-        return None
-    return {"valu_busy_pct": float(m_busy.group(1)),
-            "valu_lane_instr_per_eval": float(m_ipe.group(1)),
-            "source": os.path.relpath(COUNTER_PROFILE, ROOT)}
+    out = {}
+    for key, val in re.findall(r"^([a-z_0-9]+):\s*([-+0-9.eE]+)\s*$", text, re.M):
+        out[key] = float(val)
+    return out
 
 
 def copy_probe():
@@ -116,36 +108,160 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def host_evals(nu0, grid, cut):
+    """In-cut (line, grid point) pairs for a fixed cut, from the sorted centres."""
+    total = 0
+    for j0 in range(0, len(grid), 1 << 20):
+        g = grid[j0:j0 + (1 << 20)]
+        total += int(np.sum(np.searchsorted(nu0, g + cut, "right") -
+                            np.searchsorted(nu0, g - cut, "left")))
+    return total
+
+
+def rotation(n):
+    """Order of the table's points over consecutive steps: a stride that is prime to n,
+    so that any run of steps spreads over pressures and temperatures."""
+    stride = next(s for s in (7, 5, 11, 13, 3, 1) if np.gcd(s, n) == 1 and s < max(n, 2))
+    return [(k * stride) % n for k in range(n)]
+
+
+def describe(W, grid, pts):
+    P = sorted({p for p, _ in pts})
+    T = sorted({t for _, t in pts})
+    cut = (f"cut {W.cut_cm1:g} cm^-1" if W.cut_kind == "fixed"
+           else f"cut min({W.cut_cm1:g} cm^-1, {W.fwhm_mult:g} x Voigt FWHM)")
+    return (f"{W.name}: {W.lines.n:.0e} lines {W.lines.nu_lo:g}-{W.lines.nu_hi:g} cm^-1 "
+            f"({W.mass_amu:g} amu), {len(grid)}-point "
+            f"{'ln(nu)' if W.grid_kind == 'ln' else 'uniform'} grid, {len(pts)} (P, T) points "
+            f"({len(P)} P {P[0]:g}..{P[-1]:g} bar x {len(T)} T {T[0]:g}..{T[-1]:g} K), one "
+            f"point per step in rotation, {cut}")
+
+
+def fp32_opts(xsec, ctx, W, args, precision=None, eps=0.0):
+    kind = xsec.XS_CUT_FIXED if W.cut_kind == "fixed" else xsec.XS_CUT_MIN_FWHM
+    return ctx.opts(kind, W.cut_cm1, W.fwhm_mult,
+                    xsec.XS_FP32_KAHAN if precision is None else precision,
+                    args.pts_per_lane, args.split, args.waves_per_simd, eps)
+
+
+# ------------------------------------------------------------------ oracle sample
+_POOL = {}
+
+
+def _oracle_job(a):
+    from oracle import xsec_oracle as O
+    key, P, T = a
+    Lw, idx = _POOL["windows"][key]
+    return O.sigma(Lw, _POOL["grid"], P, T, points=idx, **_POOL["kw"])
+
+
+def oracle_windows(W, grid, jobs, workers):
+    """The FP64 oracle at grid[idx] for each (idx, P, T) job, the lines regenerated for
+    each window from the bucketed generator; process pool over the jobs. Returns the
+    results, the wall time of the pool and the line-point evaluations it made."""
+    import multiprocessing as mp
+    from paper_2510_20870_amd import synth
+    windows, keys = {}, []
+    n_eval = 0
+    for idx, _, _ in jobs:
+        key = (int(idx[0]), int(idx[-1]), len(idx))
+        if key not in windows:
+            lo = grid[idx[0]] - W.cut_cm1 * 1.001
+            hi = grid[idx[-1]] + W.cut_cm1 * 1.001
+            windows[key] = (synth.lines_in_window(W.lines, lo, hi), np.asarray(idx))
+        keys.append(key)
+        if W.cut_kind == "fixed":
+            n_eval += host_evals(windows[key][0]["nu0"], grid[idx], W.cut_cm1)
+    _POOL.update(grid=grid, windows=windows,
+                 kw=dict(mass_amu=W.mass_amu, cut_kind=W.cut_kind, cut_cm1=W.cut_cm1,
+                         fwhm_mult=W.fwhm_mult, q_a=W.q_a, q_b=W.q_b))
+    args = [(key, float(P), float(T)) for key, (_, P, T) in zip(keys, jobs)]
+    t = time.perf_counter()
+    try:
+        with mp.get_context("fork").Pool(workers) as pool:
+            res = pool.map(_oracle_job, args, chunksize=1)
+    finally:
+        _POOL.clear()
+    return res, time.perf_counter() - t, n_eval
+
+
+def parity_vs_oracle(W, grid, sig_rows, pts, n_windows, width, workers, seed=2024):
+    """Every point's GPU spectrum against the oracle on n_windows windows of `width` grid
+    points, the acceptance floor (1e-8 of the maximum) taken from the oracle at the GPU
+    maximum. Returns (parity summary, oracle timing of the windows)."""
+    from oracle import xsec_oracle as O
+    rng = np.random.default_rng(seed)
+    starts = np.sort(rng.choice(len(grid) - width, n_windows, replace=False))
+    windows = [np.arange(s, s + width) for s in starts]
+    tops = []
+    for row in sig_rows:
+        j = int(np.argmax(row))
+        tops.append((np.arange(max(0, j - 3), min(len(grid), j + 4)), j))
+    jobs = [(idx, P, T) for (P, T) in pts for idx in windows]
+    res, wall, n_eval = oracle_windows(W, grid, jobs, workers)
+    top_res, _, _ = oracle_windows(W, grid, [(tops[k][0], P, T)
+                                             for k, (P, T) in enumerate(pts)], workers)
+    worst, viol, top_rel = 0.0, 0, 0.0
+    p99 = []
+    for k in range(len(pts)):
+        idx, j = tops[k]
+        ref_top = top_res[k]
+        kk = int(np.nonzero(idx == j)[0][0])
+        rel_top = abs(sig_rows[k][j] - ref_top[kk]) / ref_top[kk]
+        top_rel = max(top_rel, rel_top)
+        if not rel_top <= 1e-4:
+            viol += 1
+        m = float(ref_top.max())
+        for w, widx in enumerate(windows):
+            st = O.compare(sig_rows[k][widx], res[k * len(windows) + w], ref_max=m)
+            worst = max(worst, st["max_rel"])
+            p99.append(st["p99_rel"])
+            viol += st["violations"]
+    summary = {"points": len(pts), "windows": n_windows, "grid_points_per_window": width,
+               "max_rel": worst, "p99_rel": float(np.max(p99)) if p99 else 0.0,
+               "max_rel_at_maximum": top_rel, "violations": viol,
+               "floor": "1e-8 of the oracle value at each spectrum's GPU maximum"}
+    return summary, {"wall_s": wall, "evals": n_eval}
+
+
+# ------------------------------------------------------------------ serving
 def serving_run(ctx, lists, reqs, opts, on_time=True):
-    """Submit `reqs` (synth.Request) at their arrival times (on_time) or all at once;
-    returns per-request (latency s, evals) and the span from first submit to last done."""
+    """Submit `reqs` (synth.Request) at their arrival times (on_time) or all at once.
+    Latency runs from the scheduled arrival (on_time; the submitter's own lateness is
+    counted) or from submission (a closed batch) to completion; returns the latencies,
+    the span from the first arrival to the last completion and the largest lateness of a
+    submission behind its schedule."""
     import threading
-    t0 = time.perf_counter()
     handles = [None] * len(reqs)
-    done_evt = threading.Event()
+    sched = np.zeros(len(reqs))
+    lag = [0.0]
+    t0 = [0.0]
 
     def submitter():
+        # xs_request_times uses CLOCK_MONOTONIC, as time.monotonic does
+        t0[0] = time.monotonic()
         for k, r in enumerate(reqs):
-            if on_time:
-                dt = r.t_arrival - (time.perf_counter() - t0)
-                if dt > 0:
-                    time.sleep(dt)
+            due = t0[0] + (r.t_arrival if on_time else 0.0)
+            dt = due - time.monotonic()
+            if dt > 0:
+                time.sleep(dt)
+            lag[0] = max(lag[0], time.monotonic() - due)
+            sched[k] = due
             handles[k] = ctx.submit_window(lists[r.list_id], r.nu_min, r.step, r.n_points,
                                            [(r.P_bar, r.T_K)], opts)
-        done_evt.set()
 
     th = threading.Thread(target=submitter)
     th.start()
     th.join()
     lat = np.zeros(len(reqs))
-    first, last = np.inf, -np.inf
+    last = -np.inf
     for k, h in enumerate(handles):
         h.wait()
         ts, ta, td = h.times()
-        lat[k] = td - ts
-        first, last = min(first, ts), max(last, td)
+        lat[k] = td - (sched[k] if on_time else ts)
+        last = max(last, td)
         h.release()
-    return lat, last - first
+    return lat, last - t0[0], lag[0]
 
 
 def request_evals(nu0_by_list, reqs, cut):
@@ -153,10 +269,8 @@ def request_evals(nu0_by_list, reqs, cut):
     sorted centres."""
     ev = np.zeros(len(reqs))
     for k, r in enumerate(reqs):
-        nu0 = nu0_by_list[r.list_id]
         g = r.nu_min + r.step * np.arange(r.n_points, dtype=np.float64)
-        ev[k] = float(np.sum(np.searchsorted(nu0, g + cut, "right") -
-                             np.searchsorted(nu0, g - cut, "left")))
+        ev[k] = host_evals(nu0_by_list[r.list_id], g, cut)
     return ev
 
 
@@ -175,63 +289,336 @@ def serving_bench(n_requests, loads, seed=1, gen_workers=0):
     log(f"serving: loaded {len(lists)} lists in {time.time() - t:.1f} s")
     opts = ctx.opts(xsec.XS_CUT_FIXED, 25.0)
     ctx.serve_start()
-    # warm-up, then saturation: a closed batch submitted at once
     warm = synth.request_stream(16, 1.0, seed=seed + 100)
     serving_run(ctx, lists, warm, opts, on_time=False)
     sat_reqs = synth.request_stream(max(64, n_requests // 2), 1.0, seed=seed + 200)
-    lat, span = serving_run(ctx, lists, sat_reqs, opts, on_time=False)
+    lat, span, _ = serving_run(ctx, lists, sat_reqs, opts, on_time=False)
     sat_rate = len(sat_reqs) / span
     ev_sat = request_evals(nu0s, sat_reqs, 25.0)
     log(f"serving: saturation {sat_rate:.1f} req/s, {ev_sat.sum() / span:.4e} evals/s")
     out = {"lists": [s.n for s, _ in synth.SERVING_LISTS],
            "saturation_req_per_s": sat_rate, "saturation_evals_per_s": ev_sat.sum() / span,
-           "loads": []}
-    for load in loads:
-        reqs = synth.request_stream(n_requests, load * sat_rate, seed=seed)
-        lat, span = serving_run(ctx, lists, reqs, opts, on_time=True)
+           "latency_from": "scheduled arrival", "loads": []}
+    for i, load in enumerate(loads):
+        reqs = synth.request_stream(n_requests, load * sat_rate, seed=seed + i)
+        lat, span, lag = serving_run(ctx, lists, reqs, opts, on_time=True)
         ev = request_evals(nu0s, reqs, 25.0)
         rec = {"offered_load": load, "rate_hz": load * sat_rate, "requests": n_requests,
                "p50_ms": float(np.percentile(lat, 50) * 1e3),
                "p99_ms": float(np.percentile(lat, 99) * 1e3),
                "mean_ms": float(lat.mean() * 1e3),
+               "max_submit_lag_ms": lag * 1e3,
                "req_per_s": n_requests / span, "evals_per_s": float(ev.sum() / span)}
         log(f"serving: load {load}: p50 {rec['p50_ms']:.2f} ms p99 {rec['p99_ms']:.2f} ms, "
-            f"{rec['req_per_s']:.1f} req/s, {rec['evals_per_s']:.4e} evals/s")
+            f"{rec['req_per_s']:.1f} req/s, {rec['evals_per_s']:.4e} evals/s, "
+            f"submit lag <= {rec['max_submit_lag_ms']:.2f} ms")
         out["loads"].append(rec)
     ctx.close()
     return out
+
+
+# ------------------------------------------------------------------ workloads
+def load(xsec, ctx, W, gen_workers):
+    from paper_2510_20870_amd import synth
+    t0 = time.time()
+    L = synth.make_lines(W.lines, workers=gen_workers or synth.default_workers())
+    grid = W.grid()
+    log(f"{W.name}: generated {W.lines.n:.0e} lines, {len(grid)} grid points in "
+        f"{time.time() - t0:.1f} s")
+    t0 = time.time()
+    h = ctx.load_lines(L, W.mass_amu, q_a=W.q_a, q_b=W.q_b)
+    g = ctx.set_grid(grid)
+    nu0 = L["nu0"]
+    del L
+    log(f"{W.name}: resident in {time.time() - t0:.1f} s")
+    return h, g, grid, nu0
+
+
+def timed_steps(torch, ctx, h, g, pts, order, opts, out_rows, steps, warmup):
+    """warmup untimed steps, then `steps` timed steps; step k computes point order[k mod n]
+    (warm-up steps take the points before the timed ones in the rotation). Returns the
+    wall time, the tile-kernel ms per launch (HIP events on the launch stream), the number
+    of launches and the per-step device time (torch events on the same stream)."""
+    stream = torch.cuda.current_stream()
+    n = len(order)
+    for k in range(-warmup, 0):
+        i = order[k % n]
+        ctx.compute(h, g, [pts[i]], opts, out=out_rows[i:i + 1], stream=stream)
+    torch.cuda.synchronize()
+    ctx.set_kernel_timing(True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(steps):
+        i = order[k % n]
+        ctx.compute(h, g, [pts[i]], opts, out=out_rows[i:i + 1], stream=stream)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    kms, launches = ctx.kernel_time()
+    ctx.set_kernel_timing(False)
+    per_step = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    return wall, kms / max(1, launches), launches, per_step
+
+
+def roofline(prof, evals_per_launch, kernel_ms, flops_model):
+    """The tile kernel's position: counter-derived VALU FLOP/s (from the committed profile
+    of the current kernel sources) against the published FP32 vector peak, the VALU issue
+    fraction, and HBM traffic; the tier model's FLOPs only when no such profile exists."""
+    sec = kernel_ms * 1e-3
+    r = {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_FP32_PACKED_TFLOPS,
+         "kernel": "xs_tile_kernel", "kernel_ms_per_launch": kernel_ms,
+         "evals_per_launch": evals_per_launch}
+    if prof and prof.get("evals_per_launch"):
+        fpe = prof["valu_flops_per_launch"] / prof["evals_per_launch"]
+        ipe = prof["valu_lane_instr_per_launch"] / prof["evals_per_launch"]
+        achieved = fpe * evals_per_launch / sec / 1e12
+        r.update(achieved=achieved, frac=achieved / PEAK_FP32_PACKED_TFLOPS,
+                 flops_per_eval=fpe,
+                 flops_basis="VALU FLOPs counted by SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_"
+                             "{F32,F64} (64 lanes per instruction, FMA = 2) per evaluation, "
+                             "from the committed counter profile, x evaluations per launch "
+                             "/ the live launch time",
+                 frac_of_nonpacked_peak=achieved / PEAK_ALU_TFLOPS,
+                 valu_issue_frac=ipe * evals_per_launch / sec / PEAK_VALU_LANE_INSTR,
+                 valu_lane_instr_per_eval=ipe,
+                 valu_busy_pct=prof.get("valu_busy_pct"),
+                 traffic=prof.get("traffic_bytes_per_launch"),
+                 profile=os.path.relpath(COUNTER_PROFILE, ROOT))
+    else:
+        achieved = flops_model * evals_per_launch / sec / 1e12 if flops_model else None
+        r.update(achieved=achieved,
+                 frac=achieved / PEAK_FP32_PACKED_TFLOPS if achieved else None,
+                 flops_per_eval=flops_model,
+                 flops_basis="tier model (no counter profile of the current kernel sources)",
+                 traffic=None)
+    if r.get("traffic"):
+        r["hbm_frac"] = r["traffic"] / sec / 1e9 / PEAK_HBM_GBS
+    r["peak_basis"] = ("published FP32 vector peak (packed FMA); frac_of_nonpacked_peak "
+                       "against 256 CU x 64 lanes x FMA x 2.4 GHz = 78.6 TFLOP/s")
+    return r
+
+
+def model_flops(ctx, h, g, pts, opts, xsec):
+    tiers = np.zeros(xsec.XS_N_EVAL_TIERS)
+    for p in pts:
+        tiers += ctx.count_evals_by_tier(h, g, [p], opts)[0].astype(np.float64)
+    evals = tiers.sum()
+    fpe = float(tiers @ np.array(FLOPS_BY_TIER)) / evals + KAHAN_FLOPS_PER_EVAL
+    return fpe, {n: float(c / evals) for n, c in zip(xsec.EVAL_TIERS, tiers)}, int(evals)
+
+
+def bench_large(args, torch, xsec, synth):
+    """The headline: the 24-point table of the 1e9-line list, one point per step."""
+    W = synth.WORKLOADS[args.workload]
+    pts = [tuple(map(float, p)) for p in W.pt_array()]
+    ctx = xsec.Context(0)
+    info = ctx.device_info()
+    h, g, grid, nu0 = load(xsec, ctx, W, args.gen_workers)
+    o32 = fp32_opts(xsec, ctx, W, args)
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        xsec.tune_cache_load(args.tune_cache)
+    key = ctx.tune_key(h, g, 1, o32)
+    hit = xsec.tune_cache_get(key)
+    shape = ({"pts_per_lane": hit[0], "waves_per_simd": hit[1], "items_per_slot": hit[2],
+              "key": key, "source": "cache"} if hit else {"key": key, "source": "default"})
+    if W.cut_kind == "fixed":
+        evals_pt = host_evals(nu0, grid, W.cut_cm1)
+        evals = [evals_pt] * len(pts)
+        if not args.no_check_count:
+            dev = int(ctx.count_evals(h, g, [pts[0]], o32)[0])
+            if abs(dev - evals_pt) > 1e-6 * evals_pt:
+                raise SystemExit(f"eval count mismatch: device {dev}, host {evals_pt}")
+    else:
+        evals = [int(c) for c in ctx.count_evals(h, g, pts, o32)]
+    del nu0
+    log(f"{W.name}: {evals[0]:.4e} line-point evals per point, launch shape {shape}")
+    flops_model = None
+    if counter_profile() is None:
+        # no counter profile of these kernel sources: price the first timed point's
+        # evaluations by their tiers
+        flops_model, mix, _ = model_flops(ctx, h, g, [pts[rotation(len(pts))[0]]], o32, xsec)
+        log(f"no counter profile of the current kernel sources: tier model "
+            f"{flops_model:.2f} FLOPs/eval, mix {mix}")
+    order = rotation(len(pts))
+    out_rows = torch.empty((len(pts), len(grid)), dtype=torch.float64, device="cuda")
+    wall, k_ms, nl, per_step = timed_steps(torch, ctx, h, g, pts, order, o32, out_rows,
+                                           args.steps, args.warmup)
+    step_pts = [order[k % len(order)] for k in range(args.steps)]
+    n_eval = sum(evals[i] for i in step_pts)
+    value = n_eval / wall
+    log(f"{W.name}: fp32+kahan {wall / args.steps * 1e3:.1f} ms/step, tile kernel "
+        f"{k_ms:.1f} ms/launch ({nl} launches), {value:.4e} evals/s")
+    res = {"value": value, "ms_per_step": wall / args.steps * 1e3, "wall": wall,
+           "evals_per_launch": n_eval / max(1, nl), "kernel_ms": k_ms, "launches": nl,
+           "per_step_ms": per_step, "step_points": step_pts, "launch_shape": shape,
+           "device": info, "W": W, "grid": grid, "pts": pts, "flops_model": flops_model}
+    # every point's spectrum (the warm-up steps cover the points the timed ones leave)
+    done = set(step_pts) | {order[k % len(order)] for k in range(-args.warmup, 0)}
+    for i in range(len(pts)):
+        if i not in done:
+            ctx.compute(h, g, [pts[i]], o32, out=out_rows[i:i + 1],
+                        stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    res["sig"] = out_rows.cpu().numpy()
+    del out_rows
+    if not args.no_table_call:
+        # the whole table in one batched call (the library batches the points itself)
+        out = torch.empty((len(pts), len(grid)), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctx.compute(h, g, pts, o32, out=out, stream=torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t
+        same = bool(torch.equal(out, torch.from_numpy(res["sig"]).cuda()))
+        res["table_call"] = {"points": len(pts), "seconds": tc,
+                             "evals_per_s": sum(evals) / tc,
+                             "bitwise_equal_to_single_point_calls": same}
+        log(f"{W.name}: whole table in one call {tc:.2f} s ({sum(evals) / tc:.4e} evals/s)")
+        del out
+    if not args.no_fp64:
+        o64 = fp32_opts(xsec, ctx, W, args, precision=xsec.XS_FP64)
+        sub = order[:3]
+        out = torch.empty((len(pts), len(grid)), dtype=torch.float64, device="cuda")
+        w64, k64, _, ps64 = timed_steps(torch, ctx, h, g, pts, sub, o64, out, len(sub), 1)
+        v64 = sum(evals[i] for i in sub) / w64
+        # the FP32 path on the same points: the timed steps that computed them
+        f32_ms = [per_step[k] for k in range(args.steps) if step_pts[k] in sub][:len(sub)]
+        v32_same = (sum(evals[i] for i in sub[:len(f32_ms)]) / (sum(f32_ms) * 1e-3)
+                    if f32_ms else None)
+        res["fp64"] = {"value": v64, "unit": "evals/s", "points": [pts[i] for i in sub],
+                       "ms_per_step": w64 / len(sub) * 1e3, "kernel_ms": k64,
+                       "fp32_value_same_points": v32_same,
+                       "fp32_speedup": (v32_same / v64) if v32_same else value / v64}
+        log(f"{W.name}: fp64 path {w64 / len(sub) * 1e3:.1f} ms/step, {v64:.4e} evals/s")
+        del out
+    ctx.close()
+    return res
+
+
+def bench_mid(args, torch, xsec, synth):
+    W = synth.WORKLOADS["mid"]
+    P, T = W.pts[0]
+    ctx = xsec.Context(0)
+    h, g, grid, nu0 = load(xsec, ctx, W, args.gen_workers)
+    evals = host_evals(nu0, grid, W.cut_cm1)
+    o32 = ctx.opts(xsec.XS_CUT_FIXED, W.cut_cm1)
+    out = torch.empty((1, len(grid)), dtype=torch.float64, device="cuda")
+    wall, k_ms, nl, _ = timed_steps(torch, ctx, h, g, [(P, T)], [0], o32, out, 20, 3)
+    r = {"workload": "mid: 1e7 lines 500-10000 cm^-1, 950000-point uniform grid (0.01 "
+                     "cm^-1), P=0.1 bar T=1500 K, cut 25 cm^-1, one point per step",
+         "evals_per_step": evals, "evals_per_s": evals * 20 / wall,
+         "ms_per_step": wall / 20 * 1e3, "kernel_ms": k_ms}
+    sig32 = out.cpu().numpy()[0].copy()
+    o64 = ctx.opts(xsec.XS_CUT_FIXED, W.cut_cm1, precision=xsec.XS_FP64)
+    w64, k64, _, _ = timed_steps(torch, ctx, h, g, [(P, T)], [0], o64, out, 5, 1)
+    r["fp64_path"] = {"evals_per_s": evals * 5 / w64, "ms_per_step": w64 / 5 * 1e3,
+                      "kernel_ms": k64, "fp32_speedup": (evals * 20 / wall) / (evals * 5 / w64)}
+    log(f"mid: {r['ms_per_step']:.3f} ms/step ({r['evals_per_s']:.4e} evals/s), fp64 "
+        f"{r['fp64_path']['ms_per_step']:.2f} ms/step")
+    sel = []
+    for eps in [float(v) for v in args.select_eps.split(",") if v.strip()]:
+        for prec, name in ((xsec.XS_FP32_KAHAN, "fp32"), (xsec.XS_FP64, "fp64")):
+            if prec == xsec.XS_FP64 and eps != float(args.select_eps.split(",")[0]):
+                continue
+            o_s = ctx.opts(xsec.XS_CUT_FIXED, W.cut_cm1, precision=prec, select_eps=eps)
+            n = 20 if name == "fp32" else 5
+            ws, ks, _, _ = timed_steps(torch, ctx, h, g, [(P, T)], [0], o_s, out, n, 1)
+            full = r["ms_per_step"] if name == "fp32" else r["fp64_path"]["ms_per_step"]
+            rec = {"eps": eps, "path": name, "ms_per_step": ws / n * 1e3,
+                   "speedup_vs_full": full / (ws / n * 1e3),
+                   "kept_evals_frac": int(ctx.count_evals(h, g, [(P, T)], o_s)[0]) / evals}
+            if name == "fp32":
+                drop = (sig32 - out.cpu().numpy()[0]) / sig32
+                rec["max_drop_vs_full"] = float(drop.max())
+            sel.append(rec)
+            log(f"mid selection {name} eps {eps:g}: {rec['ms_per_step']:.2f} ms/step "
+                f"({rec['speedup_vs_full']:.2f}x)")
+    r["selection"] = sel
+    ctx.close()
+    return r
+
+
+def bench_table(args, torch, xsec, synth):
+    """The 120-point P-T table of the 1e8-line list in one batched call."""
+    W = synth.WORKLOADS["table"]
+    pts = [tuple(map(float, p)) for p in W.pt_array()]
+    ctx = xsec.Context(0)
+    h, g, grid, nu0 = load(xsec, ctx, W, args.gen_workers)
+    del nu0
+    o32 = ctx.opts(xsec.XS_CUT_MIN_FWHM, W.cut_cm1, W.fwhm_mult)
+    evals = [int(c) for c in ctx.count_evals(h, g, pts, o32)]
+    out = torch.empty((len(pts), len(grid)), dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+    ctx.compute(h, g, pts, o32, out=out, stream=st)
+    torch.cuda.synchronize()
+    ctx.set_kernel_timing(True)
+    t = time.perf_counter()
+    ctx.compute(h, g, pts, o32, out=out, stream=st)
+    torch.cuda.synchronize()
+    tc = time.perf_counter() - t
+    kms, nl = ctx.kernel_time()
+    ctx.set_kernel_timing(False)
+    r = {"workload": "table: 1e8 lines 500-12000 cm^-1, 1e6-point ln(nu) grid, 12 P x 10 T "
+                     "in one call, cut min(25 cm^-1, 100 FWHM)",
+         "seconds": tc, "evals": sum(evals), "evals_per_s": sum(evals) / tc,
+         "tile_kernel_s": kms * 1e-3, "tile_launches": nl}
+    log(f"table: {tc:.2f} s per call ({sum(evals) / tc:.4e} evals/s), tile kernels "
+        f"{kms * 1e-3:.2f} s over {nl} launches")
+    if not args.no_fp64:
+        sub = [0, 64, 119]
+        o64 = ctx.opts(xsec.XS_CUT_MIN_FWHM, W.cut_cm1, W.fwhm_mult, precision=xsec.XS_FP64)
+        t32, t64 = 0.0, 0.0
+        for o, name in ((o32, 32), (o64, 64)):
+            ctx.compute(h, g, [pts[i] for i in sub], o, out=out, stream=st)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ctx.compute(h, g, [pts[i] for i in sub], o, out=out, stream=st)
+            torch.cuda.synchronize()
+            if name == 32:
+                t32 = time.perf_counter() - t
+            else:
+                t64 = time.perf_counter() - t
+        ev = sum(evals[i] for i in sub)
+        r["fp64_path"] = {"points": [pts[i] for i in sub], "evals_per_s": ev / t64,
+                          "fp32_evals_per_s_same_points": ev / t32, "fp32_speedup": t64 / t32}
+        log(f"table: 3 points fp32 {t32:.2f} s, fp64 {t64:.2f} s")
+    ctx.close()
+    return r
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mid")
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--workload", default="large", choices=("large", "mid", "table", "tiny"))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--cpu-points", type=int, default=131072,
-                    help="grid points in the oracle sample (16 windows)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the mid-size and P-T table workloads")
+    ap.add_argument("--no-table-call", action="store_true",
+                    help="skip the whole-table batched call of the headline workload")
+    ap.add_argument("--no-check-count", action="store_true",
+                    help="skip the device count of evaluations (host count only)")
+    ap.add_argument("--cpu-windows", type=int, default=8,
+                    help="oracle windows per (P, T) point of the headline workload")
+    ap.add_argument("--cpu-width", type=int, default=24, help="grid points per window")
     ap.add_argument("--pts-per-lane", type=int, default=0)
     ap.add_argument("--split", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="use the default launch shape (no tuning cache, no tuning)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2510_20870_amd",
                                                          "tune_cache.json"),
-                    help="tuning cache to load (JSON written by --save-tune)")
-    ap.add_argument("--retune", action="store_true",
-                    help="tune the launch shapes even when the cache holds them")
-    ap.add_argument("--save-tune", default="", help="write the tuning cache here")
+                    help="tuning cache to load (JSON written by xs_tune_cache_save)")
     ap.add_argument("--gen-workers", type=int, default=0,
-                    help="processes generating the synthetic list (0 = one per core, max 16)")
-    ap.add_argument("--serving-requests", type=int, default=300,
+                    help="processes generating the synthetic lists (0 = one per core, max 16)")
+    ap.add_argument("--serving-requests", type=int, default=2000,
                     help="requests per offered load in the serving measurement (0 = skip)")
-    ap.add_argument("--serving-loads", default="0.8",
+    ap.add_argument("--serving-loads", default="0.5,0.8,0.95",
                     help="offered loads, fractions of the measured saturation rate")
-    ap.add_argument("--select-eps", default="1e-4,1e-5",
-                    help="main-contributor selection tolerances timed beside the full sum "
-                         "(comma-separated; empty: none)")
+    ap.add_argument("--select-eps", default="1e-4",
+                    help="main-contributor selection tolerances timed on the mid workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the plain-copy calibration kernel (for HBM counters)")
     args = ap.parse_args()
@@ -248,225 +635,67 @@ def main():
     import torch
     from paper_2510_20870_amd import synth, xsec
 
-    W = synth.WORKLOADS[args.workload]
-    if len(W.pts) != 1:
-        raise SystemExit("bench workload must have one (P, T) point")
-    P, T = W.pts[0]
-    t0 = time.time()
-    L = synth.make_lines(W.lines, workers=args.gen_workers or synth.default_workers())
-    grid = W.grid()
-    log(f"generated {W.lines.n} lines, {len(grid)} grid points in {time.time() - t0:.1f} s")
+    H = bench_large(args, torch, xsec, synth)
+    W, grid, pts = H["W"], H["grid"], H["pts"]
+    prof = counter_profile()
+    roof = roofline(prof, H["evals_per_launch"], H["kernel_ms"], H.get("flops_model"))
 
-    ctx = xsec.Context(0)
-    info = ctx.device_info()
-    h = ctx.load_lines(L, W.mass_amu)
-    g = ctx.set_grid(grid)
-    kind = xsec.XS_CUT_FIXED if W.cut_kind == "fixed" else xsec.XS_CUT_MIN_FWHM
-    o32 = ctx.opts(kind, W.cut_cm1, W.fwhm_mult, xsec.XS_FP32_KAHAN, args.pts_per_lane,
-                   args.split, args.waves_per_simd)
-    o64 = ctx.opts(kind, W.cut_cm1, W.fwhm_mult, xsec.XS_FP64, args.pts_per_lane, args.split,
-                   args.waves_per_simd)
-
-    # launch shapes for this workload class: from the tuning cache when it holds the class,
-    # else tuned now (outside the timing); --retune forces tuning
-    tuned = None
-    if not args.no_autotune and not (args.pts_per_lane or args.split or args.waves_per_simd):
-        if args.tune_cache and os.path.exists(args.tune_cache):
-            xsec.tune_cache_load(args.tune_cache)
-        tuned = {}
-        paths = [("fp32", o32)] + ([] if args.no_fp64 else [("fp64", o64)])
-        for name, o in paths:
-            key = ctx.tune_key(h, g, 1, o)
-            hit = xsec.tune_cache_get(key)
-            if hit is not None and not args.retune:
-                tuned[name] = {"pts_per_lane": hit[0], "waves_per_simd": hit[1],
-                               "items_per_slot": hit[2], "key": key, "source": "cache"}
-            else:
-                t = time.time()
-                tuned[name] = dict(ctx.autotune(h, g, [(P, T)], o), source="tuned")
-                log(f"autotuned {name} in {time.time() - t:.1f} s")
-        log(f"launch shapes: {tuned}")
-        if args.save_tune:
-            xsec.tune_cache_save(args.save_tune)
-    tiers = ctx.count_evals_by_tier(h, g, [(P, T)], o32)[0]
-    evals = int(tiers.sum())
-    tiers = tiers.astype(np.float64)
-    flops_per_eval = float(tiers @ np.array(FLOPS_BY_TIER)) / evals + KAHAN_FLOPS_PER_EVAL
-    eval_mix = {n: float(c / evals) for n, c in zip(xsec.EVAL_TIERS, tiers)}
-    log(f"evaluation tiers: {eval_mix}; {flops_per_eval:.3f} algorithmic FLOPs per eval")
-    if W.cut_kind == "fixed":
-        # independent count from the sorted centres (searchsorted), the harness's rule
-        nu0 = L["nu0"]
-        lo = np.searchsorted(nu0, grid - W.cut_cm1, "left")
-        hi = np.searchsorted(nu0, grid + W.cut_cm1, "right")
-        host_count = int(np.sum(hi - lo))
-        if abs(host_count - evals) > 1e-6 * evals:
-            raise SystemExit(f"eval count mismatch: device {evals}, host {host_count}")
-    log(f"line-point evals per step: {evals:.4e}")
-
-    stream = torch.cuda.current_stream()
-    out = torch.empty((1, len(grid)), dtype=torch.float64, device="cuda")
-
-    def run(opts, steps, warmup):
-        for _ in range(warmup):
-            ctx.compute(h, g, [(P, T)], opts, out=out, stream=stream)
-        torch.cuda.synchronize()
-        # tile-kernel launches are bracketed by HIP events on the stream they run on
-        ctx.set_kernel_timing(True)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(steps):
-            ctx.compute(h, g, [(P, T)], opts, out=out, stream=stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t
-        kms, launches = ctx.kernel_time()
-        ctx.set_kernel_timing(False)
-        return wall, kms / max(1, launches), launches
-
-    wall32, k32, nl32 = run(o32, args.steps, args.warmup)
-    sig32 = out.cpu().numpy()[0].copy()
-    ms = wall32 / args.steps * 1e3
-    value = evals * args.steps / wall32
-    log(f"fp32+kahan: {ms:.3f} ms/step, tile kernel {k32:.3f} ms/launch ({nl32} launches), "
-        f"{value:.4e} evals/s")
-
-    fp64 = None
-    if not args.no_fp64:
-        steps64 = max(3, args.steps // 4)
-        wall64, k64, _ = run(o64, steps64, 1)
-        v64 = evals * steps64 / wall64
-        fp64 = {"value": v64, "unit": "evals/s", "ms_per_step": wall64 / steps64 * 1e3,
-                "kernel_ms": k64, "steps": steps64, "fp32_speedup": value / v64}
-        log(f"fp64 path: {wall64 / steps64 * 1e3:.3f} ms/step, {v64:.4e} evals/s")
-        # the FP64 path with main-contributor selection at the first eps (its evaluations
-        # cost the most, so dropping lines pays most there)
-        sel_eps = [float(v) for v in args.select_eps.split(",") if v.strip()]
-        if sel_eps:
-            sig64 = out.cpu().numpy()[0].copy()
-            o64s = ctx.opts(kind, W.cut_cm1, W.fwhm_mult, xsec.XS_FP64, args.pts_per_lane,
-                            args.split, args.waves_per_simd, sel_eps[0])
-            wall64s, k64s, _ = run(o64s, steps64, 1)
-            drop64 = (sig64 - out.cpu().numpy()[0]) / sig64
-            fp64["selection"] = {
-                "eps": sel_eps[0], "ms_per_step": wall64s / steps64 * 1e3, "kernel_ms": k64s,
-                "speedup_vs_full": wall64 / wall64s,
-                "kept_evals_frac": int(ctx.count_evals(h, g, [(P, T)], o64s)[0]) / evals,
-                "max_drop_vs_full": float(drop64.max()),
-                "min_drop_vs_full": float(drop64.min())}
-            log(f"fp64 selection eps {sel_eps[0]:g}: {wall64s / steps64 * 1e3:.3f} ms/step "
-                f"({wall64 / wall64s:.2f}x), max drop {drop64.max():.3e}")
-
-    # main-contributor selection: the same workload with lines dropped within eps (not the
-    # headline: fewer evaluations are done); drop against the full FP32 sum, kept share
-    # (the selecting kernel runs at the full path's points per lane and occupancy)
-    selection = []
-    sel_P = args.pts_per_lane or (tuned["fp32"]["pts_per_lane"] if tuned else 0)
-    sel_W = args.waves_per_simd or (tuned["fp32"]["waves_per_simd"] if tuned else 0)
-    for eps in [float(v) for v in args.select_eps.split(",") if v.strip()]:
-        o_sel = ctx.opts(kind, W.cut_cm1, W.fwhm_mult, xsec.XS_FP32_KAHAN, sel_P,
-                         args.split, sel_W, eps)
-        wall_s, k_s, _ = run(o_sel, args.steps, args.warmup)
-        sig_s = out.cpu().numpy()[0].copy()
-        kept = int(ctx.count_evals(h, g, [(P, T)], o_sel)[0])
-        ms_s = wall_s / args.steps * 1e3
-        drop = (sig32 - sig_s) / sig32
-        selection.append({"eps": eps, "pts_per_lane": sel_P, "waves_per_simd": sel_W,
-                          "ms_per_step": ms_s, "tile_kernel_ms": k_s,
-                          "speedup_vs_full": ms / ms_s, "kept_evals_frac": kept / evals,
-                          "equivalent_evals_per_s": evals / (ms_s * 1e-3),
-                          "max_drop_vs_full": float(drop.max()),
-                          "min_drop_vs_full": float(drop.min()), "_sig": sig_s})
-        log(f"selection eps {eps:g}: {ms_s:.3f} ms/step ({ms / ms_s:.2f}x), kept "
-            f"{kept / evals:.3f} of the evaluations, max drop {drop.max():.3e}")
-
-    # oracle on a bounded sample: 16 windows of contiguous points
-    cpu = None
-    max_rel = None
+    cpu, parity = None, None
     if not args.no_cpu:
-        from oracle import xsec_oracle as O
-        rng = np.random.default_rng(2024)
-        win = max(1, args.cpu_points // 16)
-        starts = np.sort(rng.choice(len(grid) - win, 16, replace=False))
-        idx = np.unique(np.concatenate([np.arange(s, s + win) for s in starts]))
-        n_eval_sample = O.count_evals(L, grid, P, T, W.mass_amu, W.cut_kind, W.cut_cm1,
-                                      W.fwhm_mult, points=idx)
         workers = synth.default_workers()
-        t = time.perf_counter()
-        ref = O.sigma_parallel(L, grid, workers=workers, chunk=max(32, win // 4), points=idx,
-                               P=P, T=T, mass_amu=W.mass_amu, cut_kind=W.cut_kind,
-                               cut_cm1=W.cut_cm1, fwhm_mult=W.fwhm_mult)
-        tc = time.perf_counter() - t
-        st = O.compare(sig32[idx], ref, ref_max=float(sig32.max()))
-        max_rel = st["max_rel"]
-        cpu = {"value": n_eval_sample / tc, "unit": "evals/s", "cores": workers,
+        parity, otime = parity_vs_oracle(W, grid, H["sig"], pts, args.cpu_windows,
+                                         args.cpu_width, workers)
+        cpu = {"value": otime["evals"] / otime["wall_s"], "unit": "evals/s", "cores": workers,
                "kind": "oracle",
-               "sample": f"{len(idx)} grid points in 16 windows of {win} ({n_eval_sample:.3e} "
-                         f"line-point evals) of the same workload, {tc:.1f} s"}
-        log(f"oracle: {n_eval_sample / tc:.4e} evals/s on {workers} cores; "
-            f"parity max_rel {st['max_rel']:.3e} violations {st['violations']}")
-        if st["violations"]:
-            log("PARITY VIOLATIONS", st)
-        for sel in selection:
-            ss = O.compare(sel["_sig"][idx], ref, rel_tol=sel["eps"] + 1e-5,
-                           ref_max=float(sig32.max()))
-            sel["max_rel_vs_oracle"] = ss["max_rel"]
-            sel["oracle_violations"] = ss["violations"]
-    for sel in selection:
-        del sel["_sig"]
+               "sample": f"{args.cpu_windows} windows x {args.cpu_width} grid points x "
+                         f"{len(pts)} (P, T) points of the headline workload "
+                         f"({otime['evals']:.3e} line-point evals), {otime['wall_s']:.1f} s"}
+        log(f"oracle: {cpu['value']:.4e} evals/s on {workers} cores; parity max_rel "
+            f"{parity['max_rel']:.3e} violations {parity['violations']}")
+        if parity["violations"]:
+            log("PARITY VIOLATIONS", parity)
+    del H["sig"]
+
+    extra = {}
+    if not args.no_extra:
+        extra["mid"] = bench_mid(args, torch, xsec, synth)
+        extra["table"] = bench_table(args, torch, xsec, synth)
 
     serving = None
     if args.serving_requests > 0:
-        del L
-        ctx.unload_lines(h)
         serving = serving_bench(args.serving_requests,
                                 [float(x) for x in args.serving_loads.split(",")],
                                 gen_workers=args.gen_workers)
 
-    # one tile launch covers the whole grid at the one (P, T) point: evals per launch
-    evals_per_launch = evals * args.steps / max(1, nl32)
-    achieved = evals_per_launch * flops_per_eval / (k32 * 1e-3) / 1e12
-    traffic = profiled_traffic()
     res = {
-        "metric": "Voigt line-point evals/s at <=1e-4 rel err vs FP64; p50/p99 request latency",
-        "value": value,
+        "metric": METRIC,
+        "value": H["value"],
         "unit": "evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": H["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{W.name}: {W.lines.n:.0e} lines {W.lines.nu_lo:g}-"
-                               f"{W.lines.nu_hi:g} cm^-1, {len(grid)} grid points, "
-                               f"P={P} bar T={T} K, cut {W.cut_cm1} cm^-1",
-                   "lines": W.lines.n, "grid_points": len(grid), "pt_points": 1,
-                   "evals_per_step": evals, "precision": "fp32 voigt + kahan, fp64 offsets",
-                   "launch_shape": tuned["fp32"] if tuned else "default",
-                   "device": info},
-        "max_rel_err": max_rel,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
-                     "traffic": traffic, "kernel": "xs_tile_kernel",
-                     "kernel_ms_per_launch": k32, "flops_per_eval": flops_per_eval,
-                     "eval_mix": eval_mix,
-                     "evals_per_launch": evals_per_launch,
-                     "peak_basis": "256 CU x 64 lanes x FMA x 2.4 GHz (no packed FP32)",
-                     "flops_basis": "each evaluation at the direct cost of its tier; far "
-                                    "lines summed per tile as one polynomial cost less",
-                     "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS,
-                     "hbm_frac": (traffic / (k32 * 1e-3) / 1e9 / PEAK_HBM_GBS
-                                  if traffic else None),
-                     "issue": profiled_issue()},
-        "fp64_path": fp64,
-        "selection": selection,
+        "config": {"workload": describe(W, grid, pts),
+                   "lines": W.lines.n, "grid_points": len(grid), "pt_points": len(pts),
+                   "evals_per_step": H["evals_per_launch"],
+                   "precision": "fp32 voigt + kahan, fp64 offsets and core",
+                   "launch_shape": H["launch_shape"], "device": H["device"]},
+        "max_rel_err": parity["max_rel"] if parity else None,
+        "parity": parity,
+        "roofline": roof,
+        "fp64_path": H.get("fp64"),
+        "table_call": H.get("table_call"),
+        "per_step_ms": H["per_step_ms"],
+        "extra": extra,
         "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":
