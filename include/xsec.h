@@ -202,6 +202,27 @@ typedef struct {
 int xs_compute(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts, size_t npts,
                const xs_opts *opts, void *sigma_out, int out_on_device, void *stream);
 
+/* Allocation-free variant of xs_compute, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * It computes what xs_compute computes with the same kernels (bitwise the same result
+ * for the same launch shape), into device memory sigma_dev (npts * n_grid elements of
+ * opts->out_dtype), enqueued on `stream` (a hipStream_t, NULL = the null stream); it
+ * returns without waiting and calls no allocation routine: the point table, the line
+ * records and the split partials live in one static device array of
+ * XS_NOALLOC_SCRATCH_BYTES per GPU, held from the library's first context on that GPU
+ * until the process ends, and the tiles are issued in ascending order. Limit: the point
+ * table plus the records and partials of one batch of P-T points (32 bytes per line that
+ * can reach the grid and per point, plus 8 bytes per grid point and split when the line
+ * window of a tile is split) must fit that array, else XS_ENOMEM (larger tables are run
+ * in several batches inside the call). Every call on one GPU, from any context or
+ * thread, shares that GPU's array, and a call leaves its contents behind: calls whose
+ * device work overlaps in time (different streams without ordering between them) race
+ * and give wrong results; calls on one stream are ordered. Nothing in the array needs to
+ * start at zero (each call writes what it reads). Errors as xs_compute. */
+#define XS_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int xs_compute_noalloc(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts,
+                       size_t npts, const xs_opts *opts, void *sigma_dev, void *stream);
+
 /* Number of (line, grid point) pairs inside the cutoff, per (P, T) point, counted on the
  * device with the same FP64 rule as xs_compute: counts_out[k] (host memory). With
  * opts->select_eps > 0 only the pairs of the lines that selection keeps count. */

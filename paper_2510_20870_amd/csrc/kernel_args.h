@@ -13,6 +13,9 @@ constexpr int kWavesPerWG = 4;
 constexpr int kBlock = kWave * kWavesPerWG;
 constexpr int kMaxSplit = 256;
 constexpr int kSelGroup = 4;   // tiles per main-contributor selection group
+// Device scratch of the allocation-free entry point (one array per device, kernels.hip).
+constexpr size_t kNoAllocScratchBytes = (size_t)256 << 20;
+constexpr int kPtsPerFill = 64;   // P-T pairs per fill launch (passed as kernel arguments)
 
 struct LinesDev {
   const double* nu0;
@@ -92,6 +95,12 @@ hipError_t launch_cia(const double* grid, int64_t n_grid, const int64_t* off, in
 hipError_t launch_eval_voigt(const double* x, const double* y, int64_t n, int f64,
                              double* out, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);
+// dst[0 .. 2 n) = pairs[0 .. 2 n), the values passed as kernel arguments (no copy from
+// host memory), kPtsPerFill pairs per launch
+hipError_t launch_fill_pts(double* dst, const double* pairs, int64_t n, hipStream_t st);
+// Device address of the allocation-free scratch array on the current device (called once
+// per device, with that device current).
+hipError_t noalloc_scratch_address(void** out);
 // g[j] = a + j * h (FP64, one rounding per operation, no contraction)
 hipError_t launch_fill_uniform(double* g, int64_t n, double a, double h, hipStream_t st);
 

@@ -47,6 +47,8 @@
 // (accounting), the main-contributor selection thresholds, the CIA regridding, fills and
 // the point evaluation of K used by the tests.
 
+#include <algorithm>
+
 #include "tile_kernel.h"
 
 namespace xs {
@@ -234,6 +236,27 @@ __global__ void xs_fill_u64_kernel(unsigned long long* p, int64_t n) {
   if (t < n) p[t] = 0ull;
 }
 
+// Scratch of the allocation-free entry point: the point table, line records and split
+// partials of one call live here instead of in allocated memory. Each device that loads
+// the library holds its own copy until the process ends; host code reaches it only
+// through the address noalloc_scratch_address() returns for the current device (the
+// array's name is not a device address on the host).
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch_address(void** out) {
+  return hipGetSymbolAddress(out, HIP_SYMBOL(scratch));
+}
+
+struct PtsBlock {
+  int n;
+  double v[2 * kPtsPerFill];
+};
+
+__global__ void xs_fill_pts_kernel(double* __restrict__ dst, PtsBlock b) {
+  const int t = threadIdx.x;
+  if (t < 2 * b.n) dst[t] = b.v[t];
+}
+
 __global__ void xs_fill_uniform_kernel(double* __restrict__ g, int64_t n, double a, double h) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) g[t] = __dadd_rn(a, __dmul_rn((double)t, h));
@@ -347,6 +370,19 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(xs_fill_u64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                      p, n);
   return hipGetLastError();
+}
+
+hipError_t launch_fill_pts(double* dst, const double* pairs, int64_t n, hipStream_t st) {
+  for (int64_t k0 = 0; k0 < n; k0 += kPtsPerFill) {
+    PtsBlock b;
+    b.n = (int)std::min<int64_t>(kPtsPerFill, n - k0);
+    for (int i = 0; i < 2 * b.n; ++i) b.v[i] = pairs[2 * k0 + i];
+    hipLaunchKernelGGL(xs_fill_pts_kernel, dim3(1), dim3(2 * kPtsPerFill), 0, st, dst + 2 * k0,
+                       b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_fill_uniform(double* g, int64_t n, double a, double h, hipStream_t st) {

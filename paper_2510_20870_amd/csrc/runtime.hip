@@ -408,9 +408,29 @@ int upload_pts(Ctx& c, const xs_pt* pts, size_t npts, hipStream_t st) {
   return XS_OK;
 }
 
+// Address of the allocation-free scratch array on `device` (the current device), taken
+// once per device and kept for the process.
+int noalloc_scratch_for(int device, void** out) {
+  static std::mutex mu;
+  static std::unordered_map<int, void*> addr;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(device);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    const hipError_t e = noalloc_scratch_address(&p);
+    if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    it = addr.emplace(device, p).first;
+  }
+  *out = it->second;
+  return XS_OK;
+}
+
 }  // namespace xs
 
 using namespace xs;
+
+static_assert(XS_NOALLOC_SCRATCH_BYTES == kNoAllocScratchBytes,
+              "allocation-free scratch size of the ABI and the kernels");
 
 extern "C" {
 
@@ -443,6 +463,12 @@ int xs_create(int device, size_t hbm_budget_bytes, xs_ctx** out) {
   if (e != hipSuccess) {
     xs_destroy(c);
     return hip_fail(e, "hipEventCreate");
+  }
+  // the allocation-free entry point's scratch on this device (on failure only that entry
+  // point is unavailable; it reports the reason)
+  if (noalloc_scratch_for(device, &c->noalloc_scratch) != XS_OK) {
+    c->noalloc_error = g_last_error;
+    g_last_error.clear();
   }
   *out = c;
   return XS_OK;
@@ -878,6 +904,56 @@ int xs_compute(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t 
     if (e != hipSuccess) return hip_fail(e, "result download");
   }
   return XS_OK;
+}
+
+int xs_compute_noalloc(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* pts, size_t npts,
+                       const xs_opts* opts, void* sigma_dev, void* stream) {
+  if (!c) return fail(XS_EINVAL, "ctx is NULL");
+  if (!sigma_dev) return fail(XS_EINVAL, "sigma_dev is NULL");
+  int rc = validate_opts(opts);
+  if (rc) return rc;
+  rc = validate_pts(pts, npts);
+  if (rc) return rc;
+  LinesRes* L;
+  GridRes* G;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    L = c->find_lines(lh);
+    G = c->find_grid(gh);
+  }
+  if (!L) return fail(XS_ENOTFOUND, "unknown line list %llu", (unsigned long long)lh);
+  if (!G) return fail(XS_ENOTFOUND, "unknown grid %llu", (unsigned long long)gh);
+  if (!c->noalloc_scratch)
+    return fail(XS_EDEVICE, "no scratch array on this device: %s", c->noalloc_error.c_str());
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  // scratch layout: point table | line records (and selection thresholds) | partials
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t pts_area = al(npts * 2 * sizeof(double));
+  if (pts_area >= kNoAllocScratchBytes)
+    return fail(XS_ENOMEM, "%zu P-T points exceed the scratch of %zu bytes", npts,
+                kNoAllocScratchBytes);
+  const Plan p = make_plan(*c, *L, *G, npts, *opts, kNoAllocScratchBytes - pts_area);
+  const size_t rec_area = al(p.rec_bytes());
+  const size_t need = pts_area + rec_area + p.part_bytes(G->n);
+  if (need > kNoAllocScratchBytes)
+    return fail(XS_ENOMEM,
+                "one P-T point needs %zu bytes of scratch (records of %lld lines, %d split "
+                "partials of %zu grid points), more than the %zu bytes of the "
+                "allocation-free scratch", need, (long long)p.rec_n, p.split, G->n,
+                kNoAllocScratchBytes);
+  char* base = (char*)c->noalloc_scratch;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<double> pairs(2 * npts);
+  for (size_t k = 0; k < npts; ++k) {
+    pairs[2 * k] = pts[k].P_bar;
+    pairs[2 * k + 1] = pts[k].T_K;
+  }
+  e = launch_fill_pts((double*)base, pairs.data(), (int64_t)npts, st);
+  if (e != hipSuccess) return hip_fail(e, "point table fill");
+  // tiles in ascending order (no order table to upload; results do not depend on it)
+  return enqueue_path(*L, *G, *opts, p, (const double*)base, nullptr, sigma_dev,
+                      base + pts_area, p.split > 1 ? base + pts_area + rec_area : nullptr, st);
 }
 
 static_assert(XS_N_EVAL_TIERS == kNEvalTiers, "evaluation tiers of the ABI and the kernels");

@@ -105,6 +105,8 @@ struct xs_ctx {
   std::mutex serve_mu;                   // guards starting the server
   xs::KernelTimer* timer = nullptr;      // non-null while kernel timing is enabled
   std::set<xs_graph*> graphs;            // live graphs (guarded by mu)
+  void* noalloc_scratch = nullptr;       // this device's allocation-free scratch array
+  std::string noalloc_error;             // why it is missing (nullptr above)
 
   bool reserve(size_t bytes);
   void release(size_t bytes);

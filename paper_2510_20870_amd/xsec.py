@@ -104,6 +104,8 @@ _SIGS = {
     "xs_grid_info": ([C.c_void_p, C.c_uint64, C.POINTER(C.c_size_t)], C.c_int),
     "xs_compute": ([C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(Pt), C.c_size_t,
                     C.POINTER(Opts), C.c_void_p, C.c_int, C.c_void_p], C.c_int),
+    "xs_compute_noalloc": ([C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(Pt), C.c_size_t,
+                            C.POINTER(Opts), C.c_void_p, C.c_void_p], C.c_int),
     "xs_count_evals": ([C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(Pt), C.c_size_t,
                         C.POINTER(Opts), C.c_void_p], C.c_int),
     "xs_count_evals_by_tier": ([C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(Pt),
@@ -519,6 +521,14 @@ class Context:
             return host
         self._check(self._L.xs_compute(self.h, lines, grid, p, len(p), C.byref(opts),
                                        _dev_ptr(out), 1, _stream_handle(stream)))
+        return out
+
+    def compute_noalloc(self, lines: int, grid: int, pts, opts: Opts, out, stream=None):
+        """xs_compute_noalloc: sigma into the device tensor (or pointer) `out`, enqueued on
+        `stream`, with no device allocation (the library's static scratch array)."""
+        p = self._pts(pts)
+        self._check(self._L.xs_compute_noalloc(self.h, lines, grid, p, len(p), C.byref(opts),
+                                               _dev_ptr(out), _stream_handle(stream)))
         return out
 
     def count_evals(self, lines: int, grid: int, pts, opts: Opts) -> np.ndarray:
