@@ -323,25 +323,24 @@ def regrid_bin_edges(dst) -> np.ndarray:
 def regrid_bin_mean(dst, src_x, src_y) -> np.ndarray:
     """The mean of the piecewise-linear function through (src_x, src_y) over each
     destination point's bin (regrid_bin_edges), the bin clipped to the source range; 0 for
-    a bin outside it. From the antiderivative F of the function: (F(b) - F(a)) / (b - a),
-    F exact (quadratic) between the nodes. A single destination point takes the whole
-    source range as its bin."""
+    a bin outside it. The integral over [a, b] is the trapezoid sum over the function's own
+    pieces inside the bin (the nodes strictly inside, and the function's values at a and
+    b), which is exact for a piecewise-linear function. A single destination point takes
+    the whole source range as its bin."""
     x = np.asarray(src_x, np.float64)
     y = np.asarray(src_y, np.float64)
     d = np.asarray(dst, np.float64)
-    C = np.concatenate([[0.0], np.cumsum(0.5 * (y[1:] + y[:-1]) * np.diff(x))])
-
-    def F(v):
-        i = np.clip(np.searchsorted(x, v, "right") - 1, 0, len(x) - 2)
-        yv = np.interp(v, x, y)
-        return C[i] + 0.5 * (y[i] + yv) * (v - x[i])
-
     e = regrid_bin_edges(d) if len(d) > 1 else np.array([x[0], x[-1]])
-    a = np.clip(e[:-1], x[0], x[-1])
-    b = np.clip(e[1:], x[0], x[-1])
     out = np.zeros(len(d))
-    ok = b > a
-    out[ok] = (F(b[ok]) - F(a[ok])) / (b[ok] - a[ok])
+    for k in range(len(d)):
+        a, b = max(e[k], x[0]), min(e[k + 1], x[-1])
+        if not b > a:
+            continue
+        i0 = int(np.searchsorted(x, a, "right"))   # first node > a
+        i1 = int(np.searchsorted(x, b, "left"))    # first node >= b
+        xs = np.concatenate([[a], x[i0:i1], [b]])
+        ys = np.interp(xs, x, y)
+        out[k] = float(np.sum(0.5 * (ys[1:] + ys[:-1]) * np.diff(xs))) / (b - a)
     return out
 
 
