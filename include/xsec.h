@@ -388,6 +388,27 @@ int xs_kernel_time(xs_ctx *ctx, double *ms_sum, int *n_launches);
 int xs_cia_regrid(xs_ctx *ctx, xs_grid_t grid, const size_t *offsets, size_t n_blocks,
                   const double *nu_cm1, const double *alpha, double *out);
 
+/* Output regridding (section "Similar tools": results on any user wavelength or
+ * wavenumber grid, which fixes the spectral resolution): n_rows cross-section rows computed
+ * on resident grid `src` (at least 2 points), sigma_src[r * n_src + j] (float64), resampled
+ * onto resident grid `dst` into out[r * n_dst + k] (float64), e.g. onto a fixed resolving
+ * power grid from xs_set_grid_wavelength. Each row is read as the piecewise-linear
+ * function through its grid nodes, zero outside [src_0, src_(n-1)].
+ *   XS_REGRID_LINEAR:   that function at each destination point;
+ *   XS_REGRID_BIN_MEAN: its mean over each destination point's bin: from the midpoint
+ *     with the previous destination point to the midpoint with the next one (the first and
+ *     last bins mirrored to the same half-widths; a single destination point takes the
+ *     whole source range), clipped to the source range; 0 for a bin wholly outside it.
+ *     The integral over a bin is exact for the piecewise-linear function, so bin means
+ *     times bin widths add up to its integral over the bins' union.
+ * With on_device != 0 both buffers are device memory and the work is enqueued on `stream`
+ * (hipStream_t, NULL = the null stream); otherwise both are host memory and the call
+ * returns when out is filled. Errors: XS_EINVAL (NULL, bad mode, n_rows outside
+ * [1, 2^20], a source grid of one point), XS_ENOTFOUND, XS_ENOMEM, XS_EDEVICE. */
+enum { XS_REGRID_LINEAR = 0, XS_REGRID_BIN_MEAN = 1 };
+int xs_regrid(xs_ctx *ctx, xs_grid_t src, xs_grid_t dst, const double *sigma_src,
+              size_t n_rows, int mode, double *out, int on_device, void *stream);
+
 /* The Voigt function K(x, y) = Re w(x + iy) as the kernels evaluate it, for n host
  * points: on the device (xs_eval_voigt) or compiled for the host (xs_eval_voigt_host).
  * precision: XS_FP32_KAHAN (FP32 tiers) or XS_FP64. */

@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libxsec.so")
 ARCH = os.environ.get("XSEC_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["kernels.hip", "tile_p1.hip", "tile_p2.hip", "tile_p4.hip", "tile_p8.hip",
-           "runtime.hip", "serve.hip", "tune.hip"]
+           "runtime.hip", "serve.hip", "tune.hip", "regrid.hip"]
 
 # -ffp-contract=off: no implicit FMA anywhere (the cutoff test must match a plain FP64
 # evaluation; explicit fma()/fmaf() calls are kept). Packed FP32 instructions are disabled.

@@ -24,6 +24,7 @@ XS_Q_POWER, XS_Q_TABLE = 0, 1
 XS_CUT_FIXED, XS_CUT_MIN_FWHM = 0, 1
 XS_FP32_KAHAN, XS_FP64 = 0, 1
 XS_F64, XS_F32 = 0, 1            # element type of sigma outputs
+XS_REGRID_LINEAR, XS_REGRID_BIN_MEAN = 0, 1
 XS_N_EVAL_TIERS = 9
 # names of the evaluation tiers counted by Context.count_evals_by_tier
 EVAL_TIERS = ("lorentz_shifted", "series2", "series3", "series4", "series6",
@@ -152,6 +153,8 @@ _SIGS = {
                           C.c_void_p], C.c_int),
     "xs_eval_bounds_host": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p],
                             C.c_int),
+    "xs_regrid": ([C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p, C.c_size_t, C.c_int,
+                   C.c_void_p, C.c_int, C.c_void_p], C.c_int),
     "xs_cia_regrid": ([C.c_void_p, C.c_uint64, C.c_void_p, C.c_size_t, C.c_void_p,
                        C.c_void_p, C.c_void_p], C.c_int),
     "xs_wavelength_grid_host": ([C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_size_t,
@@ -486,6 +489,22 @@ class Context:
         out = np.empty((len(blocks), self.grid_len(grid)), np.float64)
         self._check(self._L.xs_cia_regrid(self.h, grid, _ptr(off), len(blocks), _ptr(nu),
                                           _ptr(al), _ptr(out)))
+        return out
+
+    def regrid(self, src_grid: int, dst_grid: int, sigma, mode: int = XS_REGRID_BIN_MEAN,
+               out=None, stream=None):
+        """Rows of sigma on src_grid resampled onto dst_grid (float64): a host array in,
+        a new host array out; or device tensors (out required), enqueued on `stream`."""
+        n_dst = self.grid_len(dst_grid)
+        if isinstance(sigma, np.ndarray):
+            src = np.ascontiguousarray(sigma, np.float64).reshape(-1, self.grid_len(src_grid))
+            host = np.empty((src.shape[0], n_dst), np.float64)
+            self._check(self._L.xs_regrid(self.h, src_grid, dst_grid, _ptr(src), src.shape[0],
+                                          int(mode), _ptr(host), 0, None))
+            return host
+        n_rows = int(sigma.numel()) // self.grid_len(src_grid)
+        self._check(self._L.xs_regrid(self.h, src_grid, dst_grid, _dev_ptr(sigma), n_rows,
+                                      int(mode), _dev_ptr(out), 1, _stream_handle(stream)))
         return out
 
     def free_grid(self, h: int):
