@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define XS_ABI_VERSION 5
+#define XS_ABI_VERSION 6
 
 typedef enum {
   XS_OK = 0,
@@ -177,7 +177,14 @@ typedef struct { double P_bar, T_K; } xs_pt;
  * so that sigma changes by at most select_eps * sigma at every point (plus the FP32
  * rounding of the kept lines); 0 computes every line. Must be in [0, 1).
  * out_dtype: the element type of sigma outputs, XS_F64 (float64) or XS_F32 (float32, the
- * FP64 sum rounded once to nearest); the arithmetic is the same for both. */
+ * FP64 sum rounded once to nearest); the arithmetic is the same for both.
+ * tile_group: how the tiles of a workgroup share work. 1: each wavefront sums the far
+ * lines of its own tile. 4: the four wavefronts of a workgroup take four neighbouring
+ * tiles, and the lines far from the whole four-tile span, with that span inside their
+ * cut, are expanded once about the span's centre, the expansion split among the four
+ * wavefronts and added in a fixed order (FP32 path, fixed cut, no selection, 1 or 2
+ * points per lane; XS_EINVAL otherwise). 0: automatic (4 where it applies and the cut
+ * spans at least 15 half-widths of a four-tile span at the grid's middle, else 1). */
 typedef struct {
   int cutoff_kind;
   double cut_cm1;
@@ -188,6 +195,7 @@ typedef struct {
   int waves_per_simd;
   double select_eps;
   int out_dtype;
+  int tile_group;
 } xs_opts;
 
 /* sigma(nu_j; P_k, T_k) for k < npts on every point of `grid`, written to

@@ -13,6 +13,8 @@ constexpr int kWavesPerWG = 4;
 constexpr int kBlock = kWave * kWavesPerWG;
 constexpr int kMaxSplit = 256;
 constexpr int kSelGroup = 4;   // tiles per main-contributor selection group
+// Tiles of a workgroup that share one far-field expansion (one tile per wavefront).
+constexpr int kGroup = kWavesPerWG;
 // Device scratch of the allocation-free entry point (one array per device, kernels.hip).
 constexpr size_t kNoAllocScratchBytes = (size_t)256 << 20;
 constexpr int kPtsPerFill = 64;   // P-T pairs per fill launch (passed as kernel arguments)
@@ -53,10 +55,12 @@ struct TileArgs {
   const double* pts;      // [n_pts][2], whole table
   int pt0, n_pt;          // this batch
   int split;
-  int64_t n_tiles;
+  int group;              // 1: a work item is one tile (one wavefront); kGroup: a work
+                          // item is kGroup neighbouring tiles (one workgroup)
+  int64_t n_tiles;        // units issued: tiles, or groups of kGroup tiles
   int64_t n_items;        // n_tiles * n_pt * split
-  int64_t n_wg;           // logical workgroups (ceil(n_items / 4))
-  const int* tile_order;  // issue order of the tiles (nullptr: ascending)
+  int64_t n_wg;           // logical workgroups (ceil(n_items / 4), or n_items grouped)
+  const int* tile_order;  // issue order of the units (nullptr: ascending)
   const LineRec* recs;    // [n_pt][rec_n] records of lines [rec_lo, rec_lo + rec_n)
   int64_t rec_lo, rec_n;
   double* out;            // split == 1: sigma rows [n_pts][n_grid] (row pt0 + k);

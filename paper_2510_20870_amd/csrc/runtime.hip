@@ -118,6 +118,13 @@ int validate_opts(const xs_opts* o) {
     return fail(XS_EINVAL, "select_eps must be in [0, 1) (got %g)", o->select_eps);
   if (o->out_dtype != XS_F64 && o->out_dtype != XS_F32)
     return fail(XS_EINVAL, "unknown out_dtype %d", o->out_dtype);
+  if (o->tile_group != 0 && o->tile_group != 1 && o->tile_group != kGroup)
+    return fail(XS_EINVAL, "tile_group must be 0, 1 or %d (got %d)", kGroup, o->tile_group);
+  if (o->tile_group == kGroup &&
+      (o->precision != XS_FP32_KAHAN || o->cutoff_kind != XS_CUT_FIXED || o->select_eps > 0.0 ||
+       o->pts_per_lane > 2))
+    return fail(XS_EINVAL, "tile_group %d needs the FP32 path, a fixed cut, no selection and "
+                           "at most 2 points per lane", kGroup);
   return XS_OK;
 }
 
@@ -178,16 +185,30 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
   const int64_t tile = (int64_t)kWave * p.P;
   p.n_tiles = ((int64_t)G.n + tile - 1) / tile;
   p.npts = (int)npts;
+  // grouped far field: explicit, or automatic where lines far from a whole group of
+  // kGroup tiles make up most of a tile's window (the cut spans at least 15 half-widths
+  // of a group at the grid's middle)
+  const bool can_group = !f64 && o.cutoff_kind == XS_CUT_FIXED && o.select_eps == 0.0 &&
+                         p.P <= 2;
+  if (o.tile_group == kGroup) {
+    p.group = kGroup;
+  } else if (o.tile_group == 0 && can_group && G.n >= 2) {
+    const size_t m = std::min<size_t>(G.n / 2, G.n - 2);
+    const double hv = 0.5 * (double)(kGroup * tile) * (G.host[m + 1] - G.host[m]);
+    p.group = o.cut_cm1 >= 15.0 * hv ? kGroup : 1;
+  }
+  const int64_t unit = tile * p.group;
+  p.n_units = ((int64_t)G.n + unit - 1) / unit;
   int64_t hi = 0;
   line_range(L, G, o, &p.rec_lo, &hi);
   p.rec_n = hi - p.rec_lo;
-  // line windows of the tiles (from the sampled index, within the largest cut)
+  // line windows of the units (from the sampled index, within the largest cut)
   const std::vector<double>& sm = L.sample;
   std::vector<int64_t>& cost = p.tile_cost;
-  cost.assign(p.n_tiles, 0);
+  cost.assign(p.n_units, 0);
   int64_t max_cost = 0;
-  for (int64_t t = 0; t < p.n_tiles; ++t) {
-    const int64_t j0 = t * tile, j1 = std::min<int64_t>(j0 + tile, (int64_t)G.n) - 1;
+  for (int64_t t = 0; t < p.n_units; ++t) {
+    const int64_t j0 = t * unit, j1 = std::min<int64_t>(j0 + unit, (int64_t)G.n) - 1;
     const double lo = G.host[j0] - o.cut_cm1, hi = G.host[j1] + o.cut_cm1;
     cost[t] = (int64_t)(std::upper_bound(sm.begin(), sm.end(), hi) -
                         std::lower_bound(sm.begin(), sm.end(), lo));
@@ -198,9 +219,10 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
     p.split = o.split;
   } else {
     // a few work items per resident wavefront slot (4 SIMDs x 7 waves per CU; 4 by
-    // default, or the tuned count), so the last round of waves is short
-    const int64_t base = p.n_tiles * (int64_t)npts;
-    const int64_t target = (int64_t)c.n_cu * 28 * ips;
+    // default, or the tuned count), so the last round of waves is short; a grouped item
+    // occupies kGroup slots
+    const int64_t base = p.n_units * (int64_t)npts;
+    const int64_t target = (int64_t)c.n_cu * 28 * ips / p.group;
     int64_t sp = (target + base - 1) / base;
     sp = std::max<int64_t>(1, std::min<int64_t>(sp, 64));
     // and, if asked, no item longer than max_item_lines lines, so that no wave holds its
@@ -227,10 +249,10 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
   // expensive work items start first
   // coarse cost classes (ratio 2^(1/4)) keep neighbouring tiles of similar cost together,
   // so that they still share their line windows in one XCD's L2
-  std::vector<int> cls(p.n_tiles);
-  for (int64_t t = 0; t < p.n_tiles; ++t)
+  std::vector<int> cls(p.n_units);
+  for (int64_t t = 0; t < p.n_units; ++t)
     cls[t] = (int)std::floor(4.0 * std::log2(1.0 + (double)cost[t]));
-  p.tile_order.resize(p.n_tiles);
+  p.tile_order.resize(p.n_units);
   std::iota(p.tile_order.begin(), p.tile_order.end(), 0);
   std::stable_sort(p.tile_order.begin(), p.tile_order.end(),
                    [&](int a, int b) { return cls[a] > cls[b]; });
@@ -327,9 +349,10 @@ int enqueue_step(const LinesRes& L, const GridRes& G, const xs_opts& o, const Pl
     A.pt0 = pt0;
     A.n_pt = nb;
     A.split = counts ? 1 : p.split;
+    A.group = p.group;
     A.n_tiles = c1 - c0;
     A.n_items = A.n_tiles * nb * A.split;
-    A.n_wg = (A.n_items + kWavesPerWG - 1) / kWavesPerWG;
+    A.n_wg = p.group > 1 ? A.n_items : (A.n_items + kWavesPerWG - 1) / kWavesPerWG;
     A.tile_order = order_dev + c0;
     A.recs = (const LineRec*)rec_dev;
     A.rec_lo = p.rec_lo;
@@ -372,7 +395,7 @@ int enqueue_path(const LinesRes& L, const GridRes& G, const xs_opts& o, const Pl
   for (int pt0 = 0; pt0 < p.npts; pt0 += p.pt_batch) {
     const int nb = std::min(p.pt_batch, p.npts - pt0);
     const int rc = enqueue_step(L, G, o, p, pts_dev, order_dev, out_dev, rec_dev, part_dev, st,
-                                pt0, nb, 0, p.n_tiles, true, true, counts, tm);
+                                pt0, nb, 0, p.n_units, true, true, counts, tm);
     if (rc) return rc;
   }
   return XS_OK;
@@ -996,6 +1019,7 @@ int xs_count_evals_by_tier(xs_ctx* c, xs_lines_t lh, xs_grid_t gh, const xs_pt* 
   }
   xs_opts o = *opts;
   o.split = 1;
+  o.tile_group = 1;   // the count kernel walks single tiles
   const Plan p = make_plan(*c, *L, *G, npts, o);
   rc = upload_pts(*c, pts, npts, st);
   if (rc) return rc;

@@ -50,12 +50,14 @@ struct Plan {
   int split = 1;           // line splits per tile
   int W = 0;               // occupancy target of the tile kernel (0, 3 or 4 waves/SIMD)
   int64_t n_tiles = 0;
+  int group = 1;           // tiles per work item (kGroup: grouped far field)
+  int64_t n_units = 0;     // units of the issue order: tiles, or groups of `group` tiles
   int64_t rec_lo = 0;      // lines [rec_lo, rec_lo + rec_n) can reach the grid
   int64_t rec_n = 0;
   int npts = 0;
   int pt_batch = 1;        // (P, T) points per parameter/tile launch pair
-  std::vector<int> tile_order;   // tiles by decreasing estimated work
-  std::vector<int64_t> tile_cost;  // sampled line count in each tile's window (x 1024)
+  std::vector<int> tile_order;   // units by decreasing estimated work
+  std::vector<int64_t> tile_cost;  // sampled line count in each unit's window (x 1024)
   bool tuned = false;              // launch shape from the tuning cache
   double select_eps = 0.0;         // main-contributor selection (0: off)
   // line records [pt_batch][rec_n] (32 B), then with selection the thresholds of the

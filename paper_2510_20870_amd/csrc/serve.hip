@@ -203,18 +203,19 @@ struct Server {
 // windows) rank requests.
 void Server::build_steps(Request& r) const {
   const Plan& p = r.plan;
-  const double pts_per_tile = (double)(kWave * p.P);
+  // units of the issue order: tiles, or groups of p.group tiles (one wavefront per tile)
+  const double pts_per_unit = (double)(kWave * p.P * p.group);
   for (int pt0 = 0; pt0 < p.npts; pt0 += p.pt_batch) {
     const int nb = std::min(p.pt_batch, p.npts - pt0);
-    const int64_t items_per_tile = (int64_t)nb * p.split;
+    const int64_t items_per_unit = (int64_t)nb * p.split * p.group;
     int64_t c0 = 0;
     double acc = 0.0;
     bool first = true;
-    for (int64_t i = 0; i < p.n_tiles; ++i) {
+    for (int64_t i = 0; i < p.n_units; ++i) {
       acc += (double)(p.tile_cost[p.tile_order[i]] + 1) * (double)kSampleStride *
-             pts_per_tile * nb;
-      if ((i + 1 - c0) * items_per_tile >= step_items || i + 1 == p.n_tiles) {
-        r.steps.push_back({pt0, nb, c0, i + 1, first, i + 1 == p.n_tiles, acc});
+             pts_per_unit * nb;
+      if ((i + 1 - c0) * items_per_unit >= step_items || i + 1 == p.n_units) {
+        r.steps.push_back({pt0, nb, c0, i + 1, first, i + 1 == p.n_units, acc});
         first = false;
         c0 = i + 1;
         acc = 0.0;

@@ -140,6 +140,29 @@ __device__ int64_t wave_search(const double* __restrict__ a, int64_t n, double k
   return lo + __popcll(__ballot(before));
 }
 
+// First index i in [0, n) with pred(a[i]), for a predicate that is false and then true
+// along the array (n if none): the same 64-ary search with the predicate in place of the
+// comparison with a key.
+template <class F>
+__device__ int64_t wave_search_pred(const double* __restrict__ a, int64_t n, F pred,
+                                    int lane) {
+  int64_t lo = 0, hi = n;   // the answer lies in [lo, hi]
+  while (hi - lo > kWave) {
+    const int64_t span = hi - lo;
+    const int64_t idx = lo + span * (lane + 1) / (kWave + 1);
+    const uint64_t mask = __ballot(!pred(a[idx]));
+    const int c = __popcll(mask);
+    const int64_t nlo = (c > 0) ? lo + span * c / (kWave + 1) + 1 : lo;
+    const int64_t nhi = (c < kWave) ? lo + span * (c + 1) / (kWave + 1) : hi;
+    lo = nlo;
+    hi = nhi;
+  }
+  const int64_t idx = lo + lane;
+  bool before = false;
+  if (idx < hi) before = !pred(a[idx]);
+  return lo + __popcll(__ballot(before));
+}
+
 struct ItemInfo {
   int64_t j0;        // first grid index of the tile
   int64_t tile;      // the tile
@@ -263,6 +286,99 @@ __device__ __forceinline__ bool decode_item(const TileArgs& A, int lane, ItemInf
   const int64_t cnt = hi > lo ? hi - lo : 0;
   it.b = lo + cnt * it.s / A.split;
   it.e = lo + cnt * (it.s + 1) / A.split;
+  return true;
+}
+
+// Grouped far field (tile_group = kGroup): the kGroup wavefronts of a workgroup take
+// kGroup neighbouring tiles of one (P, T) point and split. The group's grid span [ga, gb]
+// (centre c, half-width hv) sets its line window for the fixed cut, and the window is cut
+// by nu0 into five consecutive ranges: lines whose cut covers only part of the span, on
+// the left [lo, i1); far lines on the left whose cut covers the whole span [i1, i2); lines
+// near the span [i2, i3); far lines on the right that cover the span [i3, i4); lines that
+// cover only part of it on the right [i4, hi). "Far" is a distance R from the centre,
+// chosen from bounds of the window's Doppler widths and y so that every line beyond it
+// meets the conditions of the tile polynomial for the whole span: |X| >= 5 H + 1.25 in the
+// line's Doppler units, and the shifted Lorentzian within its bound at the span's nearest
+// point. The two far ranges are summed as one polynomial over the span, their chunks
+// dealt to the wavefronts in turn; the other three ranges go through each wavefront's
+// per-tile path (restricted to the lines that can reach its tile). The ranges depend on
+// nu0 alone, so each line is taken exactly once. A split divides the group window for
+// the far lines and each tile's own window for the per-tile path (so that every
+// wavefront's share of the per-tile work sits at the same place in its window, and the
+// wavefronts of a workgroup stay balanced).
+struct GroupGeo {
+  int64_t j_first;          // first grid index of the span
+  double c, ihv;            // centre and 1 / half-width (0 for a one-point span)
+  float hv32;               // half-width
+  int64_t i1, i2, i3, i4;   // range boundaries (global line indices)
+  int64_t fb, fe;           // this item's part of the group window (its far lines)
+};
+
+template <int P>
+__device__ __forceinline__ bool decode_group(const TileArgs& A, int lane, int wave,
+                                             ItemInfo& it, GroupGeo& gg) {
+  const int64_t wg = xcd_logical_wg(blockIdx.x);
+  if (wg >= A.n_items) return false;   // one work item per workgroup
+  it.s = (int)(wg % A.split);
+  const int64_t r = wg / A.split;
+  it.k = (int)(r % A.n_pt);
+  const int64_t unit = A.tile_order ? (int64_t)A.tile_order[r / A.n_pt] : r / A.n_pt;
+  constexpr int64_t kTilePts = (int64_t)kWave * P;
+  gg.j_first = unit * kGroup * kTilePts;
+  const int64_t j_last = min(gg.j_first + kGroup * kTilePts, A.n_grid) - 1;
+  it.tile = unit * kGroup + wave;
+  it.j0 = it.tile * kTilePts;   // past the grid's end for the last group's spare waves
+  it.nu_last = A.grid[min(it.j0 + kTilePts, A.n_grid) - 1];
+  const double ga = A.grid[gg.j_first], gb = A.grid[j_last];
+  gg.c = 0.5 * (ga + gb);
+  const double hv = 0.5 * (gb - ga);
+  gg.ihv = hv > 0.0 ? 1.0 / hv : 0.0;
+  gg.hv32 = (float)hv;
+  const double cut = A.cut.cut;
+  const double* base = A.L.nu0 + A.rec_lo;
+  const int64_t lo = wave_search<false>(base, A.rec_n, ga - cut - fabs(ga) * 0x1p-48, lane);
+  const int64_t hi = wave_search<true>(base, A.rec_n, gb + cut + fabs(gb) * 0x1p-48, lane);
+  // bounds over the window: b_D <= kd (gb + cut), b_D >= kd nu0(first line), y <= ymax
+  const int pt = A.pt0 + it.k;
+  const PtConst pc = make_pt(A.sp, A.pts[2 * pt], A.pts[2 * pt + 1]);
+  const double kd = pc.dopp / kCLight;
+  const double bmax = kd * (gb + cut) * (1.0 + 1e-12);
+  const double bmin = kd * (hi > lo ? base[lo] : ga);
+  const double tmax = fmax(pow(pc.tratio, A.sp.n_min), pow(pc.tratio, A.sp.n_max));
+  const double ymax = A.sp.gam_max * pc.pfac * tmax / bmin;
+  // the shifted Lorentzian's bound (3/2 + 2 y^2) <= eps r^4 holds for
+  // x^2 >= sqrt((3/2 + 2 y^2) / eps) - y^2, which grows with y up to y^2 = 1/(2 eps) - 3/4
+  const double eps = (double)kL1Eps;
+  const double y2 = fmin(ymax * ymax, 0.5 / eps - 0.75);
+  const double x2 = fmax(sqrt((1.5 + 2.0 * y2) / eps) - y2, (double)kFarR2);
+  const double R = fmax(5.0 * hv + (double)kFarMargin * bmax, hv + sqrt(x2) * bmax) *
+                   (1.0 + 1e-6);
+  const double cl = gg.c - R, cr = gg.c + R;
+  const double* w = base + lo;
+  const int64_t n = hi - lo;
+  const int64_t i1 = lo + wave_search_pred(w, n, [&](double v) { return gb - v <= cut; }, lane);
+  int64_t i2 = lo + wave_search_pred(w, n, [&](double v) { return v >= cl; }, lane);
+  int64_t i3 = lo + wave_search_pred(w, n, [&](double v) { return v > cr; }, lane);
+  int64_t i4 = lo + wave_search_pred(w, n, [&](double v) { return v - ga > cut; }, lane);
+  i2 = max(i2, i1);
+  i3 = max(i2, min(i3, i4));
+  i4 = max(i3, i4);
+  gg.i1 = A.rec_lo + i1;
+  gg.i2 = A.rec_lo + i2;
+  gg.i3 = A.rec_lo + i3;
+  gg.i4 = A.rec_lo + i4;
+  const int64_t cnt = hi > lo ? hi - lo : 0;
+  gg.fb = A.rec_lo + lo + cnt * it.s / A.split;
+  gg.fe = A.rec_lo + lo + cnt * (it.s + 1) / A.split;
+  // this wave's part of its own tile's window (none for a spare wave past the grid)
+  it.b = it.e = 0;
+  if (it.j0 < A.n_grid) {
+    int64_t lo_t, hi_t;
+    line_window(A, it.k, A.grid[it.j0], it.nu_last, lane, &lo_t, &hi_t);
+    const int64_t ct = hi_t > lo_t ? hi_t - lo_t : 0;
+    it.b = lo_t + ct * it.s / A.split;
+    it.e = lo_t + ct * (it.s + 1) / A.split;
+  }
   return true;
 }
 
@@ -505,8 +621,10 @@ constexpr int kChunk = 16;
 // W > 0 asks the compiler for at least W waves per SIMD (capping VGPRs at 512/W).
 // SEL: main-contributor selection (a variant of its own, so that the kernel without it
 // keeps its register allocation).
-template <int P, bool F64, int W, bool SEL>
+// GRP: the grouped far field (tile_group = kGroup; FP32 path without selection only).
+template <int P, bool F64, int W, bool SEL, bool GRP = false>
 __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileArgs A) {
+  static_assert(!GRP || (!F64 && !SEL && P <= 2), "grouped far field: FP32, P <= 2");
   __shared__ Rec<F64, P> recs[kWavesPerWG][kWave];
   __shared__ double rowvals[kWavesPerWG][kWave * P];
   __shared__ int incl[kWavesPerWG][kWave];           // packed core points, inclusive prefix
@@ -518,7 +636,20 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x >> 6;
   ItemInfo it;
-  if (!decode_item<P>(A, lane, it)) return;
+  [[maybe_unused]] GroupGeo gg;
+  // the exponents of the group's partial sums (one per wavefront)
+  [[maybe_unused]] __shared__ int grp_e[GRP ? kGroup : 1];
+  // the wave index is wave-uniform; say so, so that the tile and everything derived from
+  // it stay scalar
+  [[maybe_unused]] const int wvu = __builtin_amdgcn_readfirstlane(wv);
+  if constexpr (GRP) {
+    if (!decode_group<P>(A, lane, wvu, it, gg)) return;   // the whole workgroup
+  } else {
+    if (!decode_item<P>(A, lane, it)) return;
+  }
+  // a spare wave of the last group has no tile (its reads below use a valid index)
+  const bool tile_ok = it.j0 < A.n_grid;
+  const int64_t j0r = tile_ok ? it.j0 : A.n_grid - 1;
   // main-contributor selection: the drop threshold of the tile's group (0: every line is
   // kept)
   double tau = 0.0, g_first = 0.0, g_last = 0.0;
@@ -549,10 +680,10 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   wave_sync();
   // FP32 path: the tile's centre and half-width (over its valid points) for the far-line
   // polynomial; a point's coordinate t in [-1, 1] is da32 * f_ih + f_t0 of its row
-  [[maybe_unused]] const FarTile ft = far_tile<P>(A, it.j0, it.nu_last);
+  [[maybe_unused]] const FarTile ft = far_tile<P>(A, j0r, it.nu_last);
   [[maybe_unused]] float f_ih = 0.0f, f_t0[P];
   if constexpr (!F64) {
-    const double g0 = A.grid[it.j0];
+    const double g0 = A.grid[j0r];
     const double nc = 0.5 * (g0 + it.nu_last), h = 0.5 * (it.nu_last - g0);
     const double ih = h > 0.0 ? 1.0 / h : 0.0;
     f_ih = (float)ih;
@@ -632,6 +763,8 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   // the line records of the item's (P, T) point, indexed by global line index (one base
   // for every record load, which keeps the loop-invariant scalars of the line loops few)
   const LineRec* const recs_k = A.recs + ((int64_t)it.k * A.rec_n - A.rec_lo);
+  // end of the line range being walked (the item's, or one of a group's ranges)
+  int64_t e_cur = it.e;
   auto far_line_j = [&](int64_t j, float& fx, float& fh, float& y, double& sc) -> bool {
     const double nu0 = A.L.nu0[j];
     const LineRec lr = recs_k[j];
@@ -654,11 +787,11 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       float acc[kFarDeg + 1];
       far_zero(acc);
       int nrun = 0;
-      while (b < it.e) {
+      while (b < e_cur) {
         const int64_t j = b + lane;
         float fx0 = 1.0f, fh0 = 0.0f, y = 0.0f;
         double sc = 0.0;
-        const bool is_far = j >= it.e || far_line_j(j, fx0, fh0, y, sc);
+        const bool is_far = j >= e_cur || far_line_j(j, fx0, fh0, y, sc);
         if (__ballot(!is_far) != 0ull) break;
         const int exl = sc > 0.0 ? ilogb(sc) : kNoScale;
         if (__ballot(exl > e_ref) != 0ull) {
@@ -674,8 +807,8 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
           e_ref = ex;
         }
         const double scd = ldexp(sc, kScaleTarget - e_ref);
-        const float c1 = j < it.e ? (float)(scd * (double)y * (double)kInvSqrtPi) : 0.0f;
-        far_add(acc, c1, fx0, fh0, j < it.e ? y * y - 1.5f : 0.0f);
+        const float c1 = j < e_cur ? (float)(scd * (double)y * (double)kInvSqrtPi) : 0.0f;
+        far_add(acc, c1, fx0, fh0, j < e_cur ? y * y - 1.5f : 0.0f);
         b += kWave;
         if (++nrun == kFarRun) {
           far_flush(acc);
@@ -835,18 +968,19 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
   // overflow; compacted through incl, which is free between passes), so that only kept
   // lines are staged, 64 at a time. Without selection the chunks are consecutive lines.
   [[maybe_unused]] int q0 = 0, q1 = 0, nq = 0;
-  for (int64_t base = it.b; SEL || base < it.e; base += SEL ? 0 : kWave) {
+  auto walk = [&](int64_t first) {
+  for (int64_t base = first; SEL || base < e_cur; base += SEL ? 0 : kWave) {
     if constexpr (!F64 && !SEL) {
       far_run(base);
-      if (base >= it.e) break;
+      if (base >= e_cur) break;
     }
-    int64_t i = base + lane;   // this lane's line in the chunk (it.e or later: none)
+    int64_t i = base + lane;   // this lane's line in the chunk (e_cur or later: none)
     if constexpr (SEL) {
       const uint64_t lt = (1ull << lane) - 1ull;
-      while (nq < kWave && base < it.e) {
+      while (nq < kWave && base < e_cur) {
         const int64_t j = base + lane;
         bool keep = false;
-        if (j < it.e) {
+        if (j < e_cur) {
           const LineRec lr = recs_k[j];
           keep = contrib_upper(A.L.nu0[j], lr, g_first, g_last) >= tau;
         }
@@ -864,7 +998,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
         base += kWave;
       }
       if (nq == 0) break;
-      i = lane < nq ? it.b + q0 : it.e;
+      i = lane < nq ? it.b + q0 : e_cur;
       q0 = q1;
       nq = max(nq - kWave, 0);
     }
@@ -876,17 +1010,17 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       // selection far_run has taken such chunks)
       if (ft.ok) {
         float fx0 = 1.0f, fh0 = 0.0f;
-        const bool is_far = i >= it.e || far_line_j(i, fx0, fh0, r.y, sc64);
+        const bool is_far = i >= e_cur || far_line_j(i, fx0, fh0, r.y, sc64);
         if (__ballot(!is_far) == 0ull) {
           r.y2 = r.y * r.y - 1.5f;
           set_scale(r, sc64);
-          far_sum(i < it.e ? r.c1 : 0.0f, fx0, fh0, i < it.e ? r.y2 : 0.0f);
+          far_sum(i < e_cur ? r.c1 : 0.0f, fx0, fh0, i < e_cur ? r.y2 : 0.0f);
           continue;
         }
         sc64 = 0.0;
       }
     }
-    if (i < it.e) {
+    if (i < e_cur) {
       r = stage_line<F64, P>(A, recs_k, rows, rowvals[wv], i, &sc64, &mode, &npairs, false);
     } else {
       r.cls = 0;
@@ -1003,7 +1137,108 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       ndef = left;
     }
   }
+  };
+  if constexpr (GRP) {
+    // this wave's part of its tile's window without the group's far lines
+    const int64_t r0[3] = {it.b, max(gg.i2, it.b), max(gg.i4, it.b)};
+    const int64_t r1[3] = {min(gg.i1, it.e), min(gg.i3, it.e), it.e};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      e_cur = r1[q];
+      if (r0[q] < e_cur) walk(r0[q]);
+    }
+  } else {
+    walk(it.b);
+  }
   if (!F64 && ndef > 0) deferred_pass(ndef);
+
+  // grouped far field: the group's far lines summed as one polynomial over its span,
+  // their 64-line chunks dealt to the wavefronts in turn; each wavefront evaluates its
+  // partial polynomial at every point of the span (Kahan sums per point), and after a
+  // workgroup barrier each adds the kGroup partials of its own points in wave order
+  [[maybe_unused]] double gv[P];
+  if constexpr (GRP) {
+    constexpr int kRows = kGroup * P;
+    const int64_t L1 = max(gg.i1, gg.fb), L2 = min(gg.i2, gg.fe);
+    const int64_t R1 = max(gg.i3, gg.fb), R2 = min(gg.i4, gg.fe);
+    const int64_t ncl = L2 > L1 ? (L2 - L1 + kWave - 1) / kWave : 0;
+    const int64_t ncr = R2 > R1 ? (R2 - R1 + kWave - 1) / kWave : 0;
+    float gt[kRows], gs[kRows], gc[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      const int64_t j = gg.j_first + kWave * r + lane;
+      gt[r] = j < A.n_grid ? (float)((A.grid[j] - gg.c) * gg.ihv) : 0.0f;
+      gs[r] = 0.0f;
+      gc[r] = 0.0f;
+    }
+    int e_g = kNoScale;
+    float acc[kFarDeg + 1];
+    far_zero(acc);
+    int nrun = 0;
+    auto gflush = [&]() {
+      float B[kFarDeg + 1];
+#pragma unroll
+      for (int kk = 0; kk <= kFarDeg; ++kk) B[kk] = wave_total(acc[kk]);
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) kahan_add(gs[r], gc[r], far_eval(B, gt[r]));
+    };
+    for (int64_t q = wvu; q < ncl + ncr; q += kGroup) {
+      const bool left = q < ncl;
+      const int64_t j = (left ? L1 + q * kWave : R1 + (q - ncl) * kWave) + lane;
+      const bool ok = j < (left ? L2 : R2);
+      double sc = 0.0;
+      float X = 1.0f, h = 0.0f, y = 0.0f;
+      if (ok) {
+        const double nu0 = A.L.nu0[j];
+        const LineRec lr = recs_k[j];
+        X = (float)((gg.c - nu0) * lr.ib);
+        h = gg.hv32 * (float)lr.ib;
+        y = (float)lr.y;
+        sc = lr.sc;
+      }
+      const int exl = sc > 0.0 ? ilogb(sc) : kNoScale;
+      if (__ballot(exl > e_g) != 0ull) {
+        const int ex = wave_max(exl);
+        const int d = max(e_g - ex, -1000);
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+          gs[r] = ldexpf(gs[r], d);
+          gc[r] = ldexpf(gc[r], d);
+        }
+#pragma unroll
+        for (int kk = 0; kk <= kFarDeg; ++kk) acc[kk] = ldexpf(acc[kk], d);
+        e_g = ex;
+      }
+      const float c1 =
+          ok ? (float)(ldexp(sc, kScaleTarget - e_g) * (double)y * (double)kInvSqrtPi) : 0.0f;
+      far_add(acc, c1, X, h, ok ? y * y - 1.5f : 0.0f);
+      if (++nrun == kFarRun) {
+        gflush();
+        far_zero(acc);
+        nrun = 0;
+      }
+    }
+    if (nrun > 0) gflush();
+    // exchange through this wave's record slots (no longer used)
+    static_assert(sizeof(recs[0]) >= (size_t)kRows * kWave * sizeof(double),
+                  "record slots hold a wave's partial sums of the span");
+    typedef double __attribute__((may_alias)) alias_double;
+    alias_double* xb = reinterpret_cast<alias_double*>(&recs[wv][0]);
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) xb[r * kWave + lane] = (double)gs[r] - (double)gc[r];
+    if (lane == 0) grp_e[wvu] = e_g;
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < kGroup; ++w) {
+        const alias_double* xw = reinterpret_cast<const alias_double*>(&recs[w][0]);
+        v += ldexp(xw[(wvu * P + p) * kWave + lane], grp_e[w] - kScaleTarget);
+      }
+      gv[p] = v;
+    }
+  }
 
   const int64_t row = (A.split == 1) ? (int64_t)(A.pt0 + it.k)
                                      : ((int64_t)it.k * A.split + it.s);
@@ -1014,21 +1249,32 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       double v;
       if constexpr (F64) v = s[p];
       else v = ldexp((double)s[p] - (double)c[p], e_ref - kScaleTarget);
+      if constexpr (GRP) v += gv[p];
       if (A.out_f32) ((float*)A.out)[row * A.n_grid + j] = (float)v;
       else A.out[row * A.n_grid + j] = v;
     }
   }
 }
 
-template <int P, bool F64, bool SEL>
+template <int P, bool F64, bool SEL, bool GRP = false>
 static hipError_t launch_tile_ws(const TileArgs& A, int W, hipStream_t st, dim3 grid) {
   const dim3 block(kBlock);
   switch (W) {
-    case 0: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 0, SEL>), grid, block, 0, st, A); break;
-    case 3: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 3, SEL>), grid, block, 0, st, A); break;
-    case 4: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 4, SEL>), grid, block, 0, st, A); break;
-    case 5: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 5, SEL>), grid, block, 0, st, A); break;
-    case 6: hipLaunchKernelGGL((xs_tile_kernel<P, F64, 6, SEL>), grid, block, 0, st, A); break;
+    case 0:
+      hipLaunchKernelGGL((xs_tile_kernel<P, F64, 0, SEL, GRP>), grid, block, 0, st, A);
+      break;
+    case 3:
+      hipLaunchKernelGGL((xs_tile_kernel<P, F64, 3, SEL, GRP>), grid, block, 0, st, A);
+      break;
+    case 4:
+      hipLaunchKernelGGL((xs_tile_kernel<P, F64, 4, SEL, GRP>), grid, block, 0, st, A);
+      break;
+    case 5:
+      hipLaunchKernelGGL((xs_tile_kernel<P, F64, 5, SEL, GRP>), grid, block, 0, st, A);
+      break;
+    case 6:
+      hipLaunchKernelGGL((xs_tile_kernel<P, F64, 6, SEL, GRP>), grid, block, 0, st, A);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1038,6 +1284,13 @@ static hipError_t launch_tile_ws(const TileArgs& A, int W, hipStream_t st, dim3 
 // set.
 template <int P, bool F64>
 static hipError_t launch_tile_w(const TileArgs& A, int W, hipStream_t st, dim3 grid) {
+  if (A.group > 1) {
+    // grouped far field: FP32 path without selection, 1 or 2 points per lane
+    if constexpr (!F64 && P <= 2) {
+      if (!A.tau) return launch_tile_ws<P, false, false, true>(A, W, st, grid);
+    }
+    return hipErrorInvalidValue;
+  }
   return A.tau ? launch_tile_ws<P, F64, true>(A, W, st, grid)
                : launch_tile_ws<P, F64, false>(A, W, st, grid);
 }

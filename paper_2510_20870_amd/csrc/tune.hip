@@ -205,8 +205,9 @@ struct Block {
 int time_candidate(Ctx& c, const LinesRes& L, const GridRes& G, const xs_opts& o,
                    const std::vector<Block>& blocks, int nprobe, const Plan& full,
                    KernelTimer& tm, double* ms_out) {
-  const int64_t tile = (int64_t)kWave * full.P;
-  const int64_t round_items = (int64_t)c.n_cu * 28;
+  // units of the order: tiles, or groups of full.group tiles (one workgroup each)
+  const int64_t tile = (int64_t)kWave * full.P * full.group;
+  const int64_t round_items = (int64_t)c.n_cu * 28 / full.group;
   double total = 0.0;
   for (const Block& b : blocks) {
     Plan p = full;

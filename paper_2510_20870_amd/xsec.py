@@ -68,7 +68,7 @@ class Opts(C.Structure):
     _fields_ = [("cutoff_kind", C.c_int), ("cut_cm1", C.c_double), ("fwhm_mult", C.c_double),
                 ("precision", C.c_int), ("pts_per_lane", C.c_int), ("split", C.c_int),
                 ("waves_per_simd", C.c_int), ("select_eps", C.c_double),
-                ("out_dtype", C.c_int)]
+                ("out_dtype", C.c_int), ("tile_group", C.c_int)]
 
 
 class ServeOpts(C.Structure):
@@ -515,9 +515,9 @@ class Context:
     def opts(cutoff_kind: int = XS_CUT_FIXED, cut_cm1: float = 25.0, fwhm_mult: float = 100.0,
              precision: int = XS_FP32_KAHAN, pts_per_lane: int = 0, split: int = 0,
              waves_per_simd: int = 0, select_eps: float = 0.0,
-             out_dtype: int = XS_F64) -> Opts:
+             out_dtype: int = XS_F64, tile_group: int = 0) -> Opts:
         return Opts(cutoff_kind, cut_cm1, fwhm_mult, precision, pts_per_lane, split,
-                    waves_per_simd, float(select_eps), int(out_dtype))
+                    waves_per_simd, float(select_eps), int(out_dtype), int(tile_group))
 
     @staticmethod
     def _pts(pts) -> C.Array:

@@ -609,3 +609,40 @@ def test_far_line_polynomial_parity(ctx, gridkind):
                                       sig)
         ctx.unload_lines(h)
         ctx.free_grid(g)
+
+
+@pytest.mark.parametrize("gridkind", ["uniform", "ln"])
+def test_grouped_far_field(ctx, gridkind):
+    """tile_group 4 (the lines far from a whole group of four tiles summed once per group):
+    dense lines 30 cm^-1 around short grids whose last group is ragged (a spare wave and a
+    one-point tile), low to high pressure (at 100 bar the shifted Lorentzian's bound sets
+    the far radius), 1 and 2 points per lane, splits 1 and 3; against the oracle, the same
+    as the per-tile sums to the FP32 budget, and bitwise repeatable."""
+    X = _xsec()
+    if gridkind == "uniform":
+        grid = 1000.0 + 0.01 * np.arange(3 * 256 + 65, dtype=np.float64)
+    else:
+        grid = np.exp(np.linspace(np.log(990.0), np.log(1010.0), 5 * 256 + 129))
+    mass = 16.0
+    L = synth.make_lines(synth.ListSpec(80_000, grid[0] - 30.0, grid[-1] + 30.0, 71))
+    h = ctx.load_lines(L, mass)
+    g = ctx.set_grid(grid)
+    for (P, T) in ((1e-4, 500.0), (0.1, 1500.0), (100.0, 2500.0)):
+        ref = O.sigma(L, grid, P, T, mass, cut_cm1=25.0)
+        one = ctx.compute(h, g, [(P, T)], _opts(P=1, split=1))[0]
+        for Pl, split in ((1, 1), (2, 3), (1, 3), (2, 1)):
+            o = _opts(P=Pl, split=split)
+            o.tile_group = 4
+            sig = ctx.compute(h, g, [(P, T)], o)[0]
+            _check(sig, ref, 1e-5, f"group {gridkind} P={P} T={T} pts/lane {Pl} split {split}")
+            st = O.compare(sig, one, rel_tol=2e-6)
+            assert st["violations"] == 0, st
+            assert np.array_equal(ctx.compute(h, g, [(P, T)], o)[0], sig)
+    # where it does not apply, an explicit group is refused
+    for bad in (_opts("min_fwhm", 25.0, 100.0), _opts(f64=True), _opts(P=4)):
+        bad.tile_group = 4
+        with pytest.raises(X.XsError) as e:
+            ctx.compute(h, g, [(0.1, 1500.0)], bad)
+        assert e.value.code == X.XS_EINVAL
+    ctx.unload_lines(h)
+    ctx.free_grid(g)
