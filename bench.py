@@ -49,7 +49,7 @@ sys.path.insert(0, ROOT)
 # plus the Kahan-compensated fold of each 16-line partial (4 FLOPs per point per 16
 # lines).
 FLOPS_BY_TIER = (7.0, 11.0, 19.0, 25.0, 35.0, 35.0 + 7 * 15, 35.0 + 7 * 23, 35.0 + 7 * 31,
-                 35.0 + 7 * 39)
+                 35.0 + 7 * 39, 65.0)
 KAHAN_FLOPS_PER_EVAL = 4.0 / 16.0
 # Published MI355X vector peaks: FP32 157.3 TFLOP/s (packed FP32 FMA), FP64 78.6 TFLOP/s.
 # Without packed FP32 instructions (this build disables them) FP32 FMA issues at the FP64
@@ -413,6 +413,9 @@ def bench_large(args, torch, xsec, synth):
     """The headline: the 24-point table of the 1e9-line list, one point per step."""
     W = synth.WORKLOADS[args.workload]
     pts = [tuple(map(float, p)) for p in W.pt_array()]
+    if args.points:
+        # a subset of the table's points (e.g. one pressure class, for a profile)
+        pts = [pts[int(i)] for i in args.points.split(",")]
     ctx = xsec.Context(0)
     info = ctx.device_info()
     h, g, grid, nu0 = load(xsec, ctx, W, args.gen_workers)
@@ -594,6 +597,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--workload", default="large", choices=("large", "mid", "table", "tiny"))
+    ap.add_argument("--points", default="",
+                    help="comma-separated indices of the workload's (P, T) points to time "
+                         "(default: all)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-extra", action="store_true",

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define XS_ABI_VERSION 6
+#define XS_ABI_VERSION 7
 
 typedef enum {
   XS_OK = 0,
@@ -241,9 +241,13 @@ int xs_count_evals(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *p
  * x^2 + y^2 and y, the tiers of the Voigt approximation described with
  * xs_eval_series_host): tiers 0..4 are the far-region variants (shifted Lorentzian, then
  * the asymptotic series with 2, 3, 4, 6 terms), tiers 5..8 the FP64 core with 16, 24, 32,
- * 40 terms. counts_out: npts * XS_N_EVAL_TIERS host values, [k][tier]. Accounting only
- * (the algorithmic work of a launch); the sum over tiers is xs_count_evals. */
-#define XS_N_EVAL_TIERS 9
+ * 40 terms, tier 9 the FP32 small-y core. Core points with y < 0.1 count in tier 9 and
+ * the others by y in tier 5 (y >= 1) or 6, so tiers 7 and 8 stay empty; the kernels still
+ * take the FP64 core with 24 to 40 terms for lines of y < 0.1 that share a sub-batch of
+ * 64 lines with a line of y >= 0.1. counts_out: npts * XS_N_EVAL_TIERS host values,
+ * [k][tier]. Accounting only (the algorithmic work of a launch); the sum over tiers is
+ * xs_count_evals. */
+#define XS_N_EVAL_TIERS 10
 int xs_count_evals_by_tier(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *pts,
                            size_t npts, const xs_opts *opts, uint64_t *counts_out);
 
@@ -419,7 +423,8 @@ int xs_regrid(xs_ctx *ctx, xs_grid_t src, xs_grid_t dst, const double *sigma_src
 
 /* The Voigt function K(x, y) = Re w(x + iy) as the kernels evaluate it, for n host
  * points: on the device (xs_eval_voigt) or compiled for the host (xs_eval_voigt_host).
- * precision: XS_FP32_KAHAN (FP32 tiers) or XS_FP64. */
+ * precision: XS_FP32_KAHAN (FP32 tiers: inside x^2 + y^2 < 49 the FP32 small-y core for
+ * y < 0.1, else the FP64 core) or XS_FP64. */
 int xs_eval_voigt(xs_ctx *ctx, const double *x, const double *y, size_t n, int precision,
                   double *K_out);
 int xs_eval_voigt_host(const double *x, const double *y, size_t n, int precision,

@@ -93,8 +93,8 @@ __global__ __launch_bounds__(256) void xs_reduce_kernel(const double* __restrict
 // Count of (line, point) pairs inside the cutoff, per (P, T) point and evaluation tier;
 // same traversal and the same FP64 cut test as the tile kernel. The tier is the one the
 // point itself needs (its own FP32 r^2 and y): the far-region variants 0..kNVar-1, then
-// the FP64 core with its y-dependent term count (kNVar + core_tier). counts is
-// [n_pt][kNEvalTiers].
+// the core (kNVar + core_eval_tier: the FP64 core's y-dependent term counts, the FP32
+// small-y core). counts is [n_pt][kNEvalTiers].
 template <int P>
 __global__ __launch_bounds__(kBlock) void xs_count_kernel(TileArgs A) {
   __shared__ double cen[kWavesPerWG][kWave], cut[kWavesPerWG][kWave];
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void xs_count_kernel(TileArgs A) {
       const double q0 = cen[wv][kk], qc = cut[wv][kk];
       const float y = (float)ys[wv][kk];
       const float y2 = y * y;
-      const int core = kNVar + core_tier(ys[wv][kk]);
+      const int core = kNVar + core_eval_tier(y);
 #pragma unroll
       for (int p = 0; p < P; ++p) {
         const double d = nu[p] - q0;

@@ -234,12 +234,14 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
     p.split = (int)std::min<int64_t>(sp, kMaxSplit);
   }
   // (P, T) points per batch: the records of a batch (32 B per line and point) and its
-  // partials stay under a quarter of the free budget and 16 GiB
+  // partials stay under a third of the free budget and 64 GiB (fewer, longer launches:
+  // the tail of each tile launch, where the last work items run alone, is paid once
+  // per batch)
   size_t cap = cap_bytes;
   if (cap == 0) {
     const size_t used = c.used.load();
     const size_t free_b = c.budget > used ? c.budget - used : 0;
-    cap = std::min<size_t>((size_t)16 << 30, free_b / 4);
+    cap = std::min<size_t>((size_t)64 << 30, free_b / 3);
   }
   const size_t per_pt = std::max<size_t>(
       1, (size_t)p.rec_n * 32 + (p.split > 1 ? (size_t)p.split * G.n * 8 : 0) +

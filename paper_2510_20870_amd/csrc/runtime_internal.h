@@ -128,7 +128,7 @@ int hip_fail(hipError_t e, const char* what);
 int validate_opts(const xs_opts* o);
 int validate_pts(const xs_pt* pts, size_t npts);
 // Launch plan; cap_bytes bounds the records and partials of one batch of (P, T) points
-// (0: min(16 GiB, a quarter of the free budget)); max_item_lines > 0 caps the line range
+// (0: min(64 GiB, a third of the free budget)); max_item_lines > 0 caps the line range
 // of a work item when the split is automatic. The launch shape (P, split) depends only on
 // the inputs, the options and max_item_lines, never on the memory left.
 // items_per_slot > 0 sets the work items per resident wavefront slot of the automatic

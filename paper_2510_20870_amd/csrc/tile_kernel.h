@@ -848,10 +848,15 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
         const int ke =
             first_true(k + 1, g1, [&](int kk) { return incl[wv][kk] - base > kCoreQ; });
         const int npk = incl[wv][ke - 1] - base;
-        // one term count for the sub-batch: the largest its lines need (a loop of its own
-        // per count, so the pass keeps one evaluation path)
-        const int lt = lane < ke - k ? core_tier((double)recs[wv][k + lane].y) : 0;
-        const int tier = __ballot(lt >= 3) ? 3 : __ballot(lt >= 2) ? 2 : __ballot(lt >= 1) ? 1 : 0;
+        // one evaluation path for the sub-batch (a loop of its own per path): the FP32
+        // small-y core when every line has y < kTaylorY, else the FP64 core with the
+        // largest term count its lines need
+        const float ly = lane < ke - k ? recs[wv][k + lane].y : 0.0f;
+        const int lt = lane < ke - k ? core_tier((double)ly) : 0;
+        const int tier = __ballot(lane < ke - k && !(ly < kTaylorY)) == 0ull ? -1
+                         : __ballot(lt >= 3) ? 3 : __ballot(lt >= 2) ? 2
+                         : __ballot(lt >= 1) ? 1 : 0;
+        // N = 0: the small-y core
         auto packed = [&](auto nterms) {
           constexpr int N = decltype(nterms)::value;
           const double* wa = N == 16 ? kWeidA16 : N == 24 ? kWeidA24 : N == 32 ? kWeidA32
@@ -882,11 +887,15 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
                 acc += n;
               }
               const double d = rowvals[wv][kWave * row + j] - q.nu0;
-              cval[wv][g] = q.sc * (float)voigt_core64_n<N>(wa, wl, d * q.ib, (double)q.y);
+              if constexpr (N == 0)
+                cval[wv][g] = q.sc * voigt_core_small(d * q.ib, q.y);
+              else
+                cval[wv][g] = q.sc * (float)voigt_core64_n<N>(wa, wl, d * q.ib, (double)q.y);
             }
           }
         };
         switch (tier) {
+          case -1: packed(std::integral_constant<int, 0>{}); break;
           case 0: packed(std::integral_constant<int, 16>{}); break;
           case 1: packed(std::integral_constant<int, 24>{}); break;
           case 2: packed(std::integral_constant<int, 32>{}); break;

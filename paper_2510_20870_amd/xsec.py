@@ -25,10 +25,10 @@ XS_CUT_FIXED, XS_CUT_MIN_FWHM = 0, 1
 XS_FP32_KAHAN, XS_FP64 = 0, 1
 XS_F64, XS_F32 = 0, 1            # element type of sigma outputs
 XS_REGRID_LINEAR, XS_REGRID_BIN_MEAN = 0, 1
-XS_N_EVAL_TIERS = 9
+XS_N_EVAL_TIERS = 10
 # names of the evaluation tiers counted by Context.count_evals_by_tier
 EVAL_TIERS = ("lorentz_shifted", "series2", "series3", "series4", "series6",
-              "core16", "core24", "core32", "core40")
+              "core16", "core24", "core32", "core40", "core_small_y")
 
 _STATUS = {0: "XS_OK", -1: "XS_EINVAL", -2: "XS_ENOMEM", -3: "XS_EDEVICE",
            -4: "XS_ENOTFOUND", -5: "XS_EUNSORTED", -6: "XS_EBUSY", -7: "XS_ECANCELLED",

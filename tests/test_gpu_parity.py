@@ -72,6 +72,31 @@ def test_voigt_device_error_map(ctx):
     assert r64.max() < 3e-8
 
 
+def test_voigt_device_small_y_core(ctx):
+    # inside |z| < 7 with y < 0.1 the FP32 path takes the FP32 small-y core (Dawson
+    # Taylor expansion about a node, the device's exp2); above, the FP64 core
+    from scipy.special import wofz
+    X = _xsec()
+    rng = np.random.default_rng(5)
+    n = 400_000
+    y = np.concatenate([10 ** rng.uniform(-9, -1, n),
+                        0.1 * (1 + rng.uniform(-1e-6, 1e-6, n // 8)),
+                        rng.uniform(0.05, 0.2, n // 4)])
+    x = rng.uniform(0.0, 7.0, y.size) * np.where(rng.random(y.size) < 0.5, -1.0, 1.0)
+    m = x * x + y * y < 49.0
+    x, y = x[m], y[m]
+    ref = wofz(x + 1j * y).real
+    k32 = ctx.eval_voigt(x, y, X.XS_FP32_KAHAN)
+    r32 = np.abs(k32 - ref) / ref
+    i = int(r32.argmax())
+    print(f"[small-y core] device max rel {r32.max():.3e} at x={x[i]:.5f} y={y[i]:.3e}",
+          flush=True)
+    assert r32.max() < 4e-7
+    # the host build of the same code differs only by the exp routine
+    kh = X.eval_voigt_host(x, y, X.XS_FP32_KAHAN)
+    assert np.max(np.abs(k32 - kh) / ref) < 3e-7
+
+
 def _tiny():
     W = synth.WORKLOADS["tiny"]
     return W, synth.make_lines(W.lines), W.grid()
@@ -140,11 +165,12 @@ def _tiers_fp64(L, grid, P, T, mass, cut):
     """Evaluation tier of every in-cut pair, classified in FP64 from the oracle's line
     parameters with the documented thresholds: far region x^2 + y^2 >= 49 split into the
     shifted Lorentzian ((3/2 + 2 y^2) / r^4 <= 2e-7) and the asymptotic series with 2, 3,
-    4, 6 terms (r^2 >= 6400, 400, 169, 49); the core by y (>= 1, 0.01, 1e-5, below)."""
+    4, 6 terms (r^2 >= 6400, 400, 169, 49); the core by y (FP64 core with 16 terms for
+    y >= 1, 24 for y >= 0.1, the FP32 small-y core below)."""
     par = O.line_parameters(L, P, T, mass, cut_cm1=cut)
     nu0 = np.asarray(L["nu0"], np.float64)
     y = par["gamma_L"] / par["b_D"]
-    counts = np.zeros(9, np.int64)
+    counts = np.zeros(10, np.int64)
     for j0 in range(0, len(grid), 512):
         d = grid[j0:j0 + 512, None] - nu0[None, :]
         m = np.abs(d) <= cut
@@ -154,9 +180,9 @@ def _tiers_fp64(L, grid, P, T, mass, cut):
         far = np.where((1.5 + 2 * yy * yy) / (r2 * r2) <= 2e-7, 0,
                        np.where(r2 >= 6400, 1, np.where(r2 >= 400, 2,
                                 np.where(r2 >= 169, 3, 4))))
-        core = np.where(yy >= 1.0, 5, np.where(yy >= 0.01, 6, np.where(yy >= 1e-5, 7, 8)))
+        core = np.where(yy >= 1.0, 5, np.where(yy >= 0.1, 6, 9))
         t = np.where(r2 >= 49.0, far, core)
-        counts += np.bincount(t[m], minlength=9)
+        counts += np.bincount(t[m], minlength=10)
     return counts
 
 
