@@ -46,6 +46,8 @@ sys.path.insert(0, ROOT)
 #   FP64 core (N terms): offset and x 2, setup (D, 1/D by two Newton steps, Z) 19,
 #                        N - 1 complex Horner steps 7 each, Re of the result 12, scale
 #                        and add 2                                                      -> 35 + 7(N-1)
+#   FP32 small-y core:   offset and x 2, node and d 4, node derivatives 10, Taylor sums
+#                        and Im F 24, Gaussian part and cosine 20, scale and add 5      -> 65
 # plus the Kahan-compensated fold of each 16-line partial (4 FLOPs per point per 16
 # lines).
 FLOPS_BY_TIER = (7.0, 11.0, 19.0, 25.0, 35.0, 35.0 + 7 * 15, 35.0 + 7 * 23, 35.0 + 7 * 31,
@@ -59,7 +61,8 @@ PEAK_ALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # VALU issue ceiling: 256 CUs x 64 lanes x 2.4 GHz lane-instructions per second
 PEAK_VALU_LANE_INSTR = 256 * 64 * 2.4e9
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ("tile_kernel.h", "voigt.h", "physics.h", "kernel_args.h", "weideman_coef.h")
+KERNEL_SOURCES = ("tile_kernel.h", "voigt.h", "physics.h", "kernel_args.h", "weideman_coef.h",
+                  "dawson_table.h")
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 COUNTER_PROFILE = os.path.join(PROFILE_DIR, "tile_kernel_large_counters.md")
 METRIC = "Voigt line-point evals/s at <=1e-4 rel err vs FP64; p50/p99 request latency"
