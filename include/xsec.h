@@ -451,17 +451,20 @@ int xs_eval_bounds_host(const double *x, const double *y, size_t n, double *K_lo
                         double *K_hi);
 
 /* The FP32 path's polynomial for far lines, compiled for the host (FP32 arithmetic at the
- * inputs rounded to FP32). A line whose shifted Lorentzian K = (y / sqrt(pi)) /
- * (x^2 + y^2 - 3/2) holds over a whole tile, with every point of the tile inside the cut,
- * is summed as a polynomial of degree 11 in the tile coordinate t in [-1, 1] when
- * |X| >= 5 H + 1.25, X being x at the tile's centre and H the tile's half-width in
- * Doppler units (section "Functionality of pyROX": the profile of every line inside the
- * cutoff, here summed per tile instead of per point; truncation within 1.3e-7 relative).
- * K_out[i]: that polynomial's K at x = X[i] + H[i] t[i]. Each case must meet the
- * condition above, lie in the shifted-Lorentzian region at the tile's nearest point
- * (|X| - H), have y > 0 and |t| <= 1 (XS_EINVAL otherwise). */
+ * inputs rounded to FP32). A line whose doubly shifted Lorentzian K = (y / sqrt(pi)) /
+ * (r^2 - 3/2 + 2 y^2 / r^2), r^2 = x^2 + y^2, holds over a whole tile (r^2 >= 2738.6 at
+ * its nearest point, any y), with every point of the tile inside the cut, is summed as a
+ * polynomial of degree 11 in the tile coordinate t in [-1, 1] when |X| >= 5 H + 1.25, X
+ * being x at the tile's centre and H the tile's half-width in Doppler units (section
+ * "Functionality of pyROX": the profile of every line inside the cutoff, here summed per
+ * tile instead of per point). Where the shifted Lorentzian (y / sqrt(pi)) /
+ * (x^2 + y^2 - 3/2) also holds at the nearest point, its expansion (truncation within
+ * 1.3e-7) is taken, else the doubly shifted one's. K_out[i]: that polynomial's K at
+ * x = X[i] + H[i] t[i]; kind_out (may be NULL): 0 for the shifted, 1 for the doubly
+ * shifted expansion. Each case must meet the conditions above, have y > 0 and |t| <= 1
+ * (XS_EINVAL otherwise). */
 int xs_eval_far_host(const double *X, const double *H, const double *y, const double *t,
-                     size_t n, double *K_out);
+                     size_t n, double *K_out, int *kind_out);
 
 #ifdef __cplusplus
 }

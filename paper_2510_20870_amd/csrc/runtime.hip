@@ -1318,7 +1318,7 @@ int xs_eval_series_host(const double* x, const double* y, size_t n, int variant,
 }
 
 int xs_eval_far_host(const double* X, const double* H, const double* y, const double* t,
-                     size_t n, double* K_out) {
+                     size_t n, double* K_out, int* kind_out) {
   if (n && (!X || !H || !y || !t || !K_out)) return fail(XS_EINVAL, "NULL argument");
   for (size_t i = 0; i < n; ++i) {
     const float xf = (float)X[i], hf = (float)H[i], yf = (float)y[i], tf = (float)t[i];
@@ -1326,12 +1326,15 @@ int xs_eval_far_host(const double* X, const double* H, const double* y, const do
     const float xn = fabsf(xf) - hf;   // the nearest point of the tile
     const float r2n = fmaf(xn, xn, y2);
     if (!(yf > 0.0f) || !(hf >= 0.0f) || !(fabsf(tf) <= 1.0f) || !far_ok(xf, hf) ||
-        !(r2n >= kT6R2) || asym_variant(y2, r2n) != 0)
+        !(xn >= 0.0f) || !dshift_ok(r2n))
       return fail(XS_EINVAL, "case %zu (X %g, H %g, y %g, t %g) is not a far line", i, X[i],
                   H[i], y[i], t[i]);
+    const bool ds = !shifted_lorentz_ok(y2, r2n);
     float b[kFarDeg + 1];
-    far_coeffs((float)kInvSqrtPi * yf, xf, hf, y2 - 1.5f, b);
+    if (ds) far_coeffs_ds((float)kInvSqrtPi * yf, xf, hf, y2, b);
+    else far_coeffs((float)kInvSqrtPi * yf, xf, hf, y2 - 1.5f, b);
     K_out[i] = (double)far_eval(b, tf);
+    if (kind_out) kind_out[i] = ds ? 1 : 0;
   }
   return XS_OK;
 }

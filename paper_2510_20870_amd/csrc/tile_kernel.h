@@ -240,10 +240,12 @@ __device__ __forceinline__ FarTile far_tile(const TileArgs& A, int64_t j0, doubl
 }
 // Whether a line (centre nu0, record lr) is a far line of the tile: the tests of stage_line
 // and of the far split of the tile kernel's chunk loop, on the tile's first or last point:
-// the whole tile inside the cut, the series region with the shifted Lorentzian at the
-// nearest point, far_ok at the centre; with x at the centre and H (Doppler units).
+// the whole tile inside the cut, the doubly shifted Lorentzian valid at the nearest point,
+// far_ok at the centre; with x at the centre and H (Doppler units), and whether the line
+// needs the doubly shifted expansion (ds: the shifted Lorentzian fails at the nearest
+// point).
 struct FarLine {
-  bool far;
+  bool far, ds;
   float x, h;
 };
 // (every test is evaluated and combined with &, so that the code has no branches)
@@ -258,10 +260,9 @@ __device__ __forceinline__ FarLine far_line(const FarTile& ft, double nu0, const
   const float r2n = fmaf(xn, xn, y2);
   const float h = ft.h * ib32;
   const float x = fmaf(ib32, left ? ft.ca : ft.cb, xn);
-  // asym_variant(y2, r2n) == 0 is the shifted-Lorentzian test
-  const bool far = ft.ok & in_cut & (r2n >= kFarR2) & shifted_lorentz_ok(y2, r2n) &
-                   far_ok(x, h);
-  return FarLine{far, far ? x : 1.0f, far ? h : 0.0f};
+  const bool far = ft.ok & in_cut & dshift_ok(r2n) & far_ok(x, h);
+  const bool ds = far & !shifted_lorentz_ok(y2, r2n);
+  return FarLine{far, ds, far ? x : 1.0f, far ? h : 0.0f};
 }
 
 template <int P>
@@ -296,10 +297,10 @@ __device__ __forceinline__ bool decode_item(const TileArgs& A, int lane, ItemInf
 // the left [lo, i1); far lines on the left whose cut covers the whole span [i1, i2); lines
 // near the span [i2, i3); far lines on the right that cover the span [i3, i4); lines that
 // cover only part of it on the right [i4, hi). "Far" is a distance R from the centre,
-// chosen from bounds of the window's Doppler widths and y so that every line beyond it
-// meets the conditions of the tile polynomial for the whole span: |X| >= 5 H + 1.25 in the
-// line's Doppler units, and the shifted Lorentzian within its bound at the span's nearest
-// point. The two far ranges are summed as one polynomial over the span, their chunks
+// chosen from a bound of the window's Doppler widths so that every line beyond it meets
+// the conditions of the tile polynomial for the whole span: |X| >= 5 H + 1.25 in the
+// line's Doppler units, and the doubly shifted Lorentzian within its bound at the span's
+// nearest point (which holds for every y there). The two far ranges are summed as one polynomial over the span, their chunks
 // dealt to the wavefronts in turn; the other three ranges go through each wavefront's
 // per-tile path (restricted to the lines that can reach its tile). The ranges depend on
 // nu0 alone, so each line is taken exactly once. A split divides the group window for
@@ -338,19 +339,14 @@ __device__ __forceinline__ bool decode_group(const TileArgs& A, int lane, int wa
   const double* base = A.L.nu0 + A.rec_lo;
   const int64_t lo = wave_search<false>(base, A.rec_n, ga - cut - fabs(ga) * 0x1p-48, lane);
   const int64_t hi = wave_search<true>(base, A.rec_n, gb + cut + fabs(gb) * 0x1p-48, lane);
-  // bounds over the window: b_D <= kd (gb + cut), b_D >= kd nu0(first line), y <= ymax
+  // bound over the window: b_D <= kd (gb + cut)
   const int pt = A.pt0 + it.k;
   const PtConst pc = make_pt(A.sp, A.pts[2 * pt], A.pts[2 * pt + 1]);
   const double kd = pc.dopp / kCLight;
   const double bmax = kd * (gb + cut) * (1.0 + 1e-12);
-  const double bmin = kd * (hi > lo ? base[lo] : ga);
-  const double tmax = fmax(pow(pc.tratio, A.sp.n_min), pow(pc.tratio, A.sp.n_max));
-  const double ymax = A.sp.gam_max * pc.pfac * tmax / bmin;
-  // the shifted Lorentzian's bound (3/2 + 2 y^2) <= eps r^4 holds for
-  // x^2 >= sqrt((3/2 + 2 y^2) / eps) - y^2, which grows with y up to y^2 = 1/(2 eps) - 3/4
-  const double eps = (double)kL1Eps;
-  const double y2 = fmin(ymax * ymax, 0.5 / eps - 0.75);
-  const double x2 = fmax(sqrt((1.5 + 2.0 * y2) / eps) - y2, (double)kFarR2);
+  // the doubly shifted Lorentzian holds where r^4 >= (3/2) / eps, for any y; x^2 at
+  // least that bound is enough
+  const double x2 = sqrt(1.5 / (double)kL1Eps);
   const double R = fmax(5.0 * hv + (double)kFarMargin * bmax, hv + sqrt(x2) * bmax) *
                    (1.0 + 1e-6);
   const double cl = gg.c - R, cr = gg.c + R;
@@ -720,25 +716,46 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     }
   };
   // FP32 path: far lines (one per lane; c1 = 0 on the other lanes) summed as one
-  // polynomial over the tile. far_add adds a line's coefficients (far_coeffs) to the lane's
-  // acc; far_flush sums acc over the wavefront, evaluates the polynomial at the lane's
-  // points and adds it to the compensated sums.
+  // polynomial over the tile. far_add adds a line's coefficients to the lane's acc: those
+  // of the shifted Lorentzian (far_coeffs), or, when ds is set (wave-uniform: some line of
+  // the chunk needs it), those of the doubly shifted one (far_coeffs_ds), which hold for
+  // every far line; y2 is y^2. far_flush sums acc over the wavefront, evaluates the
+  // polynomial at the lane's points and adds it to the compensated sums.
   auto far_zero = [&](float (&acc)[kFarDeg + 1]) {
 #pragma unroll
     for (int kk = 0; kk <= kFarDeg; ++kk) acc[kk] = 0.0f;
   };
-  auto far_add = [&](float (&acc)[kFarDeg + 1], float c1, float x, float h, float y2s) {
+  auto far_add = [&](float (&acc)[kFarDeg + 1], float c1, float x, float h, float y2,
+                     bool ds) {
     if constexpr (!F64) {
-      const FarRec f = far_start(c1, x, h, y2s);
-      float bm2 = f.b0, bm1 = f.b1;
-      acc[0] += bm2;
-      acc[1] += bm1;
+      if (ds) {
+        const FarRecD f = fard_start(c1, x, h, y2);
+        float bm4 = f.b0, bm3 = f.b1, bm2 = f.b2, bm1 = f.b3;
+        acc[0] += bm4;
+        acc[1] += bm3;
+        acc[2] += bm2;
+        acc[3] += bm1;
 #pragma unroll
-      for (int kk = 2; kk <= kFarDeg; ++kk) {
-        const float bk = far_next(f, bm1, bm2);
-        acc[kk] += bk;
-        bm2 = bm1;
-        bm1 = bk;
+        for (int kk = 4; kk <= kFarDeg; ++kk) {
+          const float bk = fard_next(f, bm1, bm2, bm3, bm4);
+          acc[kk] += bk;
+          bm4 = bm3;
+          bm3 = bm2;
+          bm2 = bm1;
+          bm1 = bk;
+        }
+      } else {
+        const FarRec f = far_start(c1, x, h, y2 - 1.5f);
+        float bm2 = f.b0, bm1 = f.b1;
+        acc[0] += bm2;
+        acc[1] += bm1;
+#pragma unroll
+        for (int kk = 2; kk <= kFarDeg; ++kk) {
+          const float bk = far_next(f, bm1, bm2);
+          acc[kk] += bk;
+          bm2 = bm1;
+          bm1 = bk;
+        }
       }
     }
   };
@@ -752,20 +769,21 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
         kahan_add(s[p], c[p], far_eval(B, fmaf(da32[p], f_ih, f_t0[p])));
     }
   };
-  auto far_sum = [&](float c1, float x, float h, float y2s) {
+  auto far_sum = [&](float c1, float x, float h, float y2, bool ds) {
     float acc[kFarDeg + 1];
     far_zero(acc);
-    far_add(acc, c1, x, h, y2s);
+    far_add(acc, c1, x, h, y2, ds);
     far_flush(acc);
   };
-  // Whether line j is a far line of the tile (far_line); also its x at the centre, H, y and
-  // FP64 scale.
+  // Whether line j is a far line of the tile (far_line); also its x at the centre, H, y,
+  // FP64 scale and whether it needs the doubly shifted expansion.
   // the line records of the item's (P, T) point, indexed by global line index (one base
   // for every record load, which keeps the loop-invariant scalars of the line loops few)
   const LineRec* const recs_k = A.recs + ((int64_t)it.k * A.rec_n - A.rec_lo);
   // end of the line range being walked (the item's, or one of a group's ranges)
   int64_t e_cur = it.e;
-  auto far_line_j = [&](int64_t j, float& fx, float& fh, float& y, double& sc) -> bool {
+  auto far_line_j = [&](int64_t j, float& fx, float& fh, float& y, double& sc,
+                        bool& ds) -> bool {
     const double nu0 = A.L.nu0[j];
     const LineRec lr = recs_k[j];
     y = (float)lr.y;
@@ -775,6 +793,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       fx = f.x;
       fh = f.h;
     }
+    ds = f.ds;
     return f.far;
   };
   // FP32 path without selection: a run of chunks of far lines only, from base on (left at
@@ -791,7 +810,8 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
         const int64_t j = b + lane;
         float fx0 = 1.0f, fh0 = 0.0f, y = 0.0f;
         double sc = 0.0;
-        const bool is_far = j >= e_cur || far_line_j(j, fx0, fh0, y, sc);
+        bool ds = false;
+        const bool is_far = j >= e_cur || far_line_j(j, fx0, fh0, y, sc, ds);
         if (__ballot(!is_far) != 0ull) break;
         const int exl = sc > 0.0 ? ilogb(sc) : kNoScale;
         if (__ballot(exl > e_ref) != 0ull) {
@@ -808,7 +828,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
         }
         const double scd = ldexp(sc, kScaleTarget - e_ref);
         const float c1 = j < e_cur ? (float)(scd * (double)y * (double)kInvSqrtPi) : 0.0f;
-        far_add(acc, c1, fx0, fh0, j < e_cur ? y * y - 1.5f : 0.0f);
+        far_add(acc, c1, fx0, fh0, j < e_cur ? y * y : 0.0f, __ballot(ds) != 0ull);
         b += kWave;
         if (++nrun == kFarRun) {
           far_flush(acc);
@@ -1019,11 +1039,13 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       // selection far_run has taken such chunks)
       if (ft.ok) {
         float fx0 = 1.0f, fh0 = 0.0f;
-        const bool is_far = i >= e_cur || far_line_j(i, fx0, fh0, r.y, sc64);
+        bool ds = false;
+        const bool is_far = i >= e_cur || far_line_j(i, fx0, fh0, r.y, sc64, ds);
         if (__ballot(!is_far) == 0ull) {
-          r.y2 = r.y * r.y - 1.5f;
+          r.y2 = r.y * r.y;
           set_scale(r, sc64);
-          far_sum(i < e_cur ? r.c1 : 0.0f, fx0, fh0, i < e_cur ? r.y2 : 0.0f);
+          far_sum(i < e_cur ? r.c1 : 0.0f, fx0, fh0, i < e_cur ? r.y2 : 0.0f,
+                  __ballot(ds) != 0ull);
           continue;
         }
         sc64 = 0.0;
@@ -1035,26 +1057,33 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       r.cls = 0;
     }
     set_scale(r, sc64);
-    // FP32 path: lines of the unmasked shifted-Lorentzian modes far enough from the tile
-    // (far_ok at the tile's centre) are summed as one polynomial when the chunk holds
-    // enough of them; they then leave the per-line walk
+    // FP32 path: lines of the unmasked series modes far enough from the tile (far_ok at
+    // the tile's centre, the doubly shifted Lorentzian valid at its nearest point) are
+    // summed as one polynomial when the chunk holds enough of them; they then leave the
+    // per-line walk
     [[maybe_unused]] float fc1 = 0.0f, fx = 1.0f, fhl = 0.0f, fy2 = 0.0f;
-    [[maybe_unused]] bool far_chunk = false;
+    [[maybe_unused]] bool far_chunk = false, far_ds = false;
     if constexpr (!F64) {
-      bool far = false;
-      if (mode == series_mode(0, 0, 0) || mode == series_mode(1, 0, 0)) {
+      bool far = false, ds = false;
+      const int ms = mode - kSeries;   // series modes: side * 2 kNVar + masked * kNVar + var
+      if (ms >= 0 && ms % (2 * kNVar) < kNVar) {
+        const bool left = ms < 2 * kNVar;
         const float hl = ft.h * r.ib32;
-        const float x = mode == series_mode(0, 0, 0) ? fmaf(r.ib32, ft.ca, r.xr[0])
-                                                     : fmaf(r.ib32, ft.cb, r.xr[P - 1]);
-        if (far_ok(x, hl)) {
+        const float xn = left ? r.xr[0] : r.xr[P - 1];
+        const float x = fmaf(r.ib32, left ? ft.ca : ft.cb, xn);
+        const float y2 = r.y * r.y;
+        const float r2n = fmaf(xn, xn, y2);
+        if (dshift_ok(r2n) && far_ok(x, hl)) {
           far = true;
+          ds = !shifted_lorentz_ok(y2, r2n);
           fc1 = r.c1;
           fx = x;
           fhl = hl;
-          fy2 = r.y2;   // y^2 - 3/2 in these modes
+          fy2 = y2;
         }
       }
       far_chunk = __popcll(__ballot(far)) >= kFarMinLines;
+      far_ds = __ballot(ds) != 0ull;
       if (far_chunk && far) mode = kSkip;
     }
     // Group the chunk's lines by mode (stable inside each mode) so that the walk below
@@ -1090,7 +1119,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
     }
     wave_sync();
     if constexpr (!F64) {
-      if (far_chunk) far_sum(fc1, fx, fhl, fy2);
+      if (far_chunk) far_sum(fc1, fx, fhl, fy2, far_ds);
     }
     if constexpr (F64) {
       for (int kk = gstart[kRows]; kk < gstart[kRows + 1]; ++kk) {
@@ -1220,7 +1249,11 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       }
       const float c1 =
           ok ? (float)(ldexp(sc, kScaleTarget - e_g) * (double)y * (double)kInvSqrtPi) : 0.0f;
-      far_add(acc, c1, X, h, ok ? y * y - 1.5f : 0.0f);
+      // the doubly shifted expansion when a line's nearest point of the span is outside the
+      // shifted Lorentzian's region
+      const float xn = fabsf(X) - h;
+      const bool ds = ok && !shifted_lorentz_ok(y * y, fmaf(xn, xn, y * y));
+      far_add(acc, c1, X, h, ok ? y * y : 0.0f, __ballot(ds) != 0ull);
       if (++nrun == kFarRun) {
         gflush();
         far_zero(acc);

@@ -142,6 +142,15 @@ XS_HD bool shifted_lorentz_ok(float y2, float r2) {
   return r2 * r2 * kL1Eps >= fmaf(2.0f, y2, 1.5f);
 }
 
+// Doubly shifted Lorentzian K sqrt(pi) / y = 1 / (r^2 - 3/2 + 2 y^2 / r^2): with
+// s = 3/2 - 2w it is u (1 + s u + s^2 u^2 + ...), which matches the series through its
+// u^2 term (a_1 V_1 = 3/2 - 2w = s) for every y; the first difference,
+// (a_2 V_2 - s^2) u^3 = (3/2 - 9w + 8w^2) u^3, is at most 3/2 u^2 relative (w in [0, 1]),
+// so the form holds to kL1Eps wherever 3/2 / r^4 <= kL1Eps (|z| >= 52.3), whatever y
+// (measured against the reference Faddeeva routine: 2.0e-7 at that radius). Far lines
+// whose y is too large for the shifted Lorentzian are expanded in this form.
+XS_HD bool dshift_ok(float r2) { return r2 * r2 * kL1Eps >= 1.5f; }
+
 // Series variants of the far region, cheapest first: 0 = shifted Lorentzian, 1..4 =
 // NT = 2, 3, 4, 6 terms. For a fixed y the variant a point needs does not increase with
 // r^2, so a variant chosen at the point nearest to a line serves every farther point.
@@ -210,6 +219,55 @@ XS_HD void far_coeffs(float c1, float x, float h, float y2s, float (&b)[kFarDeg 
   b[1] = f.b1;
 #pragma unroll
   for (int k = 2; k <= kFarDeg; ++k) b[k] = far_next(f, b[k - 1], b[k - 2]);
+}
+
+// The same expansion for the doubly shifted Lorentzian, for lines whose y is too large for
+// the shifted one (the nearest point of the range must satisfy dshift_ok instead):
+// f = c1 R / (R^2 - 3/2 R + 2 y^2), R(t) = (X + H t)^2 + y^2 = R0 (1 + r1 t + r2 t^2),
+// r1 = 2 X H / R0, r2 = H^2 / R0. With e1 = 3/2 / R0 and e2 = 2 y^2 / R0^2 the denominator
+// is R0^2 (D0 + D1 t + D2 t^2 + D3 t^3 + D4 t^4), D0 = 1 - e1 + e2, D1 = r1 (2 - e1),
+// D2 = r1^2 + r2 (2 - e1), D3 = 2 r1 r2, D4 = r2^2, and the numerator c1 R0 (1 + r1 t +
+// r2 t^2), so b_k = n_k - sum_j d_j b_(k-j) with d_j = D_j / D0 and n = c1 / (R0 D0)
+// (1, r1, r2, 0, ...). The roots of R^2 - 3/2 R + 2 y^2 in R are real and in (0, 3/2)
+// for y^2 < 9/32, else complex with |R| = sqrt(2) y; the four poles in t solve
+// (X + H t)^2 = R - y^2, and every such X + H t has a real part of magnitude at most
+// sqrt(3/2) (below 0.71 in the complex case), so |X| >= 5 H + 1.25 keeps them at
+// |t| >= 5 as for the shifted Lorentzian. Truncation after kFarDeg: measured
+// below 6.3e-8 in FP64 over tile half-widths of 0.1-1e4 Doppler widths and y up to 3e4;
+// FP32 rounding of the four-term recurrence brings the total to 5.3e-7.
+struct FarRecD {
+  float d1, d2, d3, d4, b0, b1, b2, b3;
+};
+XS_HD FarRecD fard_start(float c1, float x, float h, float y2) {
+  const float q = rcp32(fmaf(x, x, y2));
+  const float r1 = 2.0f * x * h * q, r2 = h * h * q;
+  const float e1 = 1.5f * q;
+  const float e2 = 2.0f * y2 * q * q;
+  const float ie = 2.0f - e1;
+  const float iD = rcp32((1.0f - e1) + e2);
+  FarRecD f;
+  f.d1 = r1 * ie * iD;
+  f.d2 = fmaf(r1, r1, r2 * ie) * iD;
+  f.d3 = 2.0f * r1 * r2 * iD;
+  f.d4 = r2 * r2 * iD;
+  const float n0 = c1 * q * iD;
+  f.b0 = n0;
+  f.b1 = fmaf(-f.d1, f.b0, n0 * r1);
+  f.b2 = fmaf(-f.d1, f.b1, fmaf(-f.d2, f.b0, n0 * r2));
+  f.b3 = -fmaf(f.d1, f.b2, fmaf(f.d2, f.b1, f.d3 * f.b0));
+  return f;
+}
+XS_HD float fard_next(const FarRecD& f, float bm1, float bm2, float bm3, float bm4) {
+  return -fmaf(f.d1, bm1, fmaf(f.d2, bm2, fmaf(f.d3, bm3, f.d4 * bm4)));
+}
+XS_HD void far_coeffs_ds(float c1, float x, float h, float y2, float (&b)[kFarDeg + 1]) {
+  const FarRecD f = fard_start(c1, x, h, y2);
+  b[0] = f.b0;
+  b[1] = f.b1;
+  b[2] = f.b2;
+  b[3] = f.b3;
+#pragma unroll
+  for (int k = 4; k <= kFarDeg; ++k) b[k] = fard_next(f, b[k - 1], b[k - 2], b[k - 3], b[k - 4]);
 }
 
 XS_HD float far_eval(const float (&b)[kFarDeg + 1], float t) {

@@ -150,7 +150,7 @@ _SIGS = {
     "xs_eval_series_host": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p,
                              C.c_void_p], C.c_int),
     "xs_eval_far_host": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
-                          C.c_void_p], C.c_int),
+                          C.c_void_p, C.c_void_p], C.c_int),
     "xs_eval_bounds_host": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p],
                             C.c_int),
     "xs_regrid": ([C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p, C.c_size_t, C.c_int,
@@ -215,15 +215,18 @@ def eval_series_host(x, y, variant: int = -1):
     return out, var
 
 
-def eval_far_host(X, H, y, t):
+def eval_far_host(X, H, y, t, with_kind: bool = False):
     """The tile kernel's polynomial for far lines on the host: K at x = X + H t from the
-    degree-11 expansion over a tile of half-width H centred at X (Doppler units)."""
+    degree-11 expansion over a tile of half-width H centred at X (Doppler units); with
+    with_kind also the expansion taken per case (0 shifted, 1 doubly shifted Lorentzian)."""
     X, H, y, t = (np.ascontiguousarray(a, np.float64) for a in np.broadcast_arrays(X, H, y, t))
     out = np.empty_like(X)
-    rc = lib().xs_eval_far_host(_ptr(X), _ptr(H), _ptr(y), _ptr(t), X.size, _ptr(out))
+    kind = np.empty(X.shape, np.int32)
+    rc = lib().xs_eval_far_host(_ptr(X), _ptr(H), _ptr(y), _ptr(t), X.size, _ptr(out),
+                                _ptr(kind))
     if rc:
         raise XsError(rc, lib().xs_last_error(None).decode())
-    return out
+    return (out, kind) if with_kind else out
 
 
 def wavelength_grid(lambda_min_um: float, lambda_max_um: float, R: float) -> np.ndarray:

@@ -207,7 +207,8 @@ def test_far_line_polynomial():
     # and against K itself (wofz): truncation <= 1.3e-7 plus FP32 rounding
     X, H, y, t = _far_cases(400_000, 31)
     assert len(X) > 100_000
-    K = xsec.eval_far_host(X, H, y, t)
+    K, kind = xsec.eval_far_host(X, H, y, t, with_kind=True)
+    assert not kind.any()   # the shifted Lorentzian's expansion wherever it holds
     f32 = lambda a: a.astype(np.float32).astype(np.float64)
     Xf, Hf, yf, tf = f32(X), f32(H), f32(y), f32(t)
     x = Xf + Hf * tf
@@ -226,11 +227,70 @@ def test_far_line_polynomial():
     Km = xsec.eval_far_host(-X[:1000], H[:1000], y[:1000], -t[:1000])
     assert np.array_equal(Km, K[:1000])
     # cases the kernel never expands are refused: inside the threshold, t outside the
-    # tile, the nearest point outside the shifted-Lorentzian region, y <= 0
+    # tile, the nearest point inside |z| = 52.3 (where no form with one term holds),
+    # y <= 0
     for args in ((4.9 * 100 + 1.25, 100.0, 1.0, 0.0), (1e4, 10.0, 1.0, 1.01),
-                 (70.0, 0.5, 30.0, 0.0), (1e4, 10.0, 0.0, 0.0)):
+                 (52.0, 0.5, 0.1, 0.0), (1e4, 10.0, 0.0, 0.0)):
         with pytest.raises(xsec.XsError):
             xsec.eval_far_host(*args)
+
+
+def test_doubly_shifted_lorentzian():
+    # 1 / (r^2 - 3/2 + 2 y^2 / r^2) against wofz for every y where r^2 >= sqrt(1.5 / 2e-7):
+    # the bound (3/2) u^2 of its first neglected term, independent of y
+    rng = np.random.default_rng(41)
+    r2 = np.sqrt(1.5 / 2e-7) * 10 ** rng.uniform(0, 3, 400_000)
+    y = np.maximum(np.sqrt(r2) * rng.uniform(0, 1, r2.size) ** 2, 1e-7)
+    x = np.sqrt(np.maximum(r2 - y * y, 0.0))
+    ds = (y / np.sqrt(np.pi)) / (r2 - 1.5 + 2 * y * y / r2)
+    rel = np.abs(ds / wofz(x + 1j * y).real - 1)
+    assert rel.max() < 2.05e-7, rel.max()
+    assert np.all(rel <= 1.5 / r2 ** 2 * 1.03 + 1e-15)
+
+
+def _far_cases_ds(n, seed):
+    # far lines whose y is too large for the shifted Lorentzian at the tile's nearest point
+    # (high pressures): y up to 3e4, nearest point at r^2 >= 2738.6
+    rng = np.random.default_rng(seed)
+    H = 10 ** rng.uniform(-1, 4, n)
+    y = 10 ** rng.uniform(-0.5, 4.5, n)
+    X = ((5 + 10 ** rng.uniform(-6, 1.5, n)) * H + 1.25) * (1 + 1e-6)
+    X *= np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    t = rng.uniform(-1, 1, n)
+    t[:200], t[200:400] = -1.0, 1.0
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    xn = np.abs(f32(X)) - f32(H)
+    r2n = xn * xn + f32(y) ** 2
+    ok = (xn >= 0) & (r2n * r2n * 2e-7 >= 1.5 * (1 + 1e-5)) & \
+         ((1.5 + 2 * f32(y) ** 2) / r2n ** 2 > 2.1e-7)
+    return X[ok], H[ok], y[ok], t[ok]
+
+
+def test_far_line_polynomial_doubly_shifted():
+    # the far expansion of the doubly shifted Lorentzian (four-term recurrence) against its
+    # closed form at the FP32-rounded inputs and against wofz
+    X, H, y, t = _far_cases_ds(400_000, 43)
+    assert len(X) > 100_000
+    K, kind = xsec.eval_far_host(X, H, y, t, with_kind=True)
+    assert kind.all()
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    Xf, Hf, yf, tf = f32(X), f32(H), f32(y), f32(t)
+    x = Xf + Hf * tf
+    r2 = x * x + yf * yf
+    ds = (yf / np.sqrt(np.pi)) / (r2 - 1.5 + 2 * yf * yf / r2)
+    rel = np.abs(K / ds - 1)
+    print(f"doubly shifted far polynomial vs closed form: max {rel.max():.3e}")
+    assert rel.max() < 6e-7
+    sub = np.random.default_rng(44).choice(len(x), 50_000, replace=False)
+    ref = wofz(x[sub] + 1j * yf[sub]).real
+    assert np.max(np.abs(K[sub] / ref - 1)) < 7e-7
+    # mirror symmetry, and one point (H = 0) is the closed form at the centre
+    Km = xsec.eval_far_host(-X[:1000], H[:1000], y[:1000], -t[:1000])
+    assert np.array_equal(Km, K[:1000])
+    K0 = xsec.eval_far_host(X[:1000], 0.0 * H[:1000], y[:1000], t[:1000])
+    r20 = Xf[:1000] ** 2 + yf[:1000] ** 2
+    ref0 = (yf[:1000] / np.sqrt(np.pi)) / (r20 - 1.5 + 2 * yf[:1000] ** 2 / r20)
+    assert np.max(np.abs(K0 / ref0 - 1)) < 4e-7
 
 
 def test_series_variant_errors():
