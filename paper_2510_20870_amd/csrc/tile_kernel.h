@@ -936,7 +936,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
               const int a = (int)((info >> 14) & 127u), n = (int)((info >> 21) & 127u);
               // x from the FP64 difference: x changes sign along a general row, so the
               // offset form would cancel
-              const float x = (float)((nu[p] - q.nu0) * q.ib);
+              const float x = (float)((rowvals[wv][kWave * p + lane] - q.nu0) * q.ib);
               const float f = q.c1 * asym_scaled<6>(q.y2, fmaf(x, x, q.y2));
               const bool in_cut = lane >= lo && lane < hi;
               const bool in_core = lane >= a && lane < a + n;
@@ -1128,7 +1128,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
 #pragma unroll
         for (int p = 0; p < P; ++p) {
           if (((cls >> (2 * p)) & 3) == 0) continue;
-          const double d = nu[p] - q.nu0;
+          const double d = rowvals[wv][kWave * p + lane] - q.nu0;
           if (fabs(d) <= q.cut) s[p] += q.sc * voigt_k64(d * q.ib, q.y);
         }
       }
