@@ -936,7 +936,10 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
               const int a = (int)((info >> 14) & 127u), n = (int)((info >> 21) & 127u);
               // x from the FP64 difference: x changes sign along a general row, so the
               // offset form would cancel
-              const float x = (float)((rowvals[wv][kWave * p + lane] - q.nu0) * q.ib);
+              // (the per-tile kernel reads the point's grid value from LDS: keeping it in
+              // registers made it spill at 6 waves per SIMD; the grouped one keeps it)
+              const double nup = GRP ? nu[p] : rowvals[wv][kWave * p + lane];
+              const float x = (float)((nup - q.nu0) * q.ib);
               const float f = q.c1 * asym_scaled<6>(q.y2, fmaf(x, x, q.y2));
               const bool in_cut = lane >= lo && lane < hi;
               const bool in_core = lane >= a && lane < a + n;
