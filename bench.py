@@ -46,11 +46,12 @@ sys.path.insert(0, ROOT)
 #   FP64 core (N terms): offset and x 2, setup (D, 1/D by two Newton steps, Z) 19,
 #                        N - 1 complex Horner steps 7 each, Re of the result 12, scale
 #                        and add 2                                                      -> 35 + 7(N-1)
+#                        (the 20-24-term tier priced at N = 22)
 #   FP32 small-y core:   offset and x 2, node and d 4, node derivatives 10, Taylor sums
 #                        and Im F 24, Gaussian part and cosine 20, scale and add 5      -> 65
 # plus the Kahan-compensated fold of each 16-line partial (4 FLOPs per point per 16
 # lines).
-FLOPS_BY_TIER = (7.0, 11.0, 19.0, 25.0, 35.0, 35.0 + 7 * 15, 35.0 + 7 * 23, 35.0 + 7 * 31,
+FLOPS_BY_TIER = (7.0, 11.0, 19.0, 25.0, 35.0, 35.0 + 7 * 15, 35.0 + 7 * 21, 35.0 + 7 * 31,
                  35.0 + 7 * 39, 65.0)
 KAHAN_FLOPS_PER_EVAL = 4.0 / 16.0
 # Published MI355X vector peaks: FP32 157.3 TFLOP/s (packed FP32 FMA), FP64 78.6 TFLOP/s.

@@ -240,11 +240,11 @@ int xs_count_evals(xs_ctx *ctx, xs_lines_t lines, xs_grid_t grid, const xs_pt *p
 /* The same pairs split by the evaluation tier each point needs on the FP32 path (its own
  * x^2 + y^2 and y, the tiers of the Voigt approximation described with
  * xs_eval_series_host): tiers 0..4 are the far-region variants (shifted Lorentzian, then
- * the asymptotic series with 2, 3, 4, 6 terms), tiers 5..8 the FP64 core with 16, 24, 32,
- * 40 terms, tier 9 the FP32 small-y core. Core points with y < 0.1 count in tier 9 and
- * the others by y in tier 5 (y >= 1) or 6, so tiers 7 and 8 stay empty; the kernels still
- * take the FP64 core with 24 to 40 terms for lines of y < 0.1 that share a sub-batch of
- * 64 lines with a line of y >= 0.1. counts_out: npts * XS_N_EVAL_TIERS host values,
+ * the asymptotic series with 2, 3, 4, 6 terms), tiers 5..8 the FP64 core with 16, 20-24,
+ * 32, 40 terms, tier 9 the FP32 small-y core. Core points with y < 0.1 count in tier 9 and
+ * the others by y in tier 5 (y >= 1) or 6 (20 terms for y >= 0.3, 22 for y >= 0.1), so
+ * tiers 7 and 8 stay empty; the kernels still take the FP64 core with 24 to 40 terms for
+ * lines of y < 0.1 that share a sub-batch of 64 lines with a line of y >= 0.1. counts_out: npts * XS_N_EVAL_TIERS host values,
  * [k][tier]. Accounting only (the algorithmic work of a launch); the sum over tiers is
  * xs_count_evals. */
 #define XS_N_EVAL_TIERS 10

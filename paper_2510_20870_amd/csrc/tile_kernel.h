@@ -873,16 +873,20 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
         // largest term count its lines need
         const float ly = lane < ke - k ? recs[wv][k + lane].y : 0.0f;
         const int lt = lane < ke - k ? core_tier((double)ly) : 0;
-        const int tier = __ballot(lane < ke - k && !(ly < kTaylorY)) == 0ull ? -1
-                         : __ballot(lt >= 3) ? 3 : __ballot(lt >= 2) ? 2
-                         : __ballot(lt >= 1) ? 1 : 0;
-        // N = 0: the small-y core
-        auto packed = [&](auto nterms) {
-          constexpr int N = decltype(nterms)::value;
-          const double* wa = N == 16 ? kWeidA16 : N == 24 ? kWeidA24 : N == 32 ? kWeidA32
-                                                                               : kWeidA;
-          const double wl = N == 16 ? kWeidL16 : N == 24 ? kWeidL24 : N == 32 ? kWeidL32
-                                                                            : kWeidL;
+        int tier = -1;
+        if (__ballot(lane < ke - k && !(ly < kTaylorY)) != 0ull) {
+          tier = 0;
+          for (int cc = 1; cc < kCoreTiers; ++cc)
+            if (__ballot(lt >= cc) != 0ull) tier = cc;
+        }
+        // KIND 0: the small-y core; 16, 20: Weideman's series with that many terms,
+        // unrolled (the coefficients are constants); 1: the series with the tier's term
+        // count known at run time (the rarer counts)
+        auto packed = [&](auto kind) {
+          constexpr int KIND = decltype(kind)::value;
+          const double* wa = core_coef(max(tier, 0));
+          const int wn = core_terms(max(tier, 0));
+          const double wl = core_L(max(tier, 0));
           for (int r0 = 0; r0 < npk; r0 += kWave) {
             const int g = r0 + lane;
             if (g < npk) {
@@ -907,20 +911,23 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
                 acc += n;
               }
               const double d = rowvals[wv][kWave * row + j] - q.nu0;
-              if constexpr (N == 0)
+              if constexpr (KIND == 0)
                 cval[wv][g] = q.sc * voigt_core_small(d * q.ib, q.y);
+              else if constexpr (KIND == 16)
+                cval[wv][g] = q.sc * (float)voigt_core64_n<16>(kWeidA16, kWeidL16, d * q.ib,
+                                                               (double)q.y);
+              else if constexpr (KIND == 20)
+                cval[wv][g] = q.sc * (float)voigt_core64_n<20>(kWeidA20, kWeidL20, d * q.ib,
+                                                               (double)q.y);
               else
-                cval[wv][g] = q.sc * (float)voigt_core64_n<N>(wa, wl, d * q.ib, (double)q.y);
+                cval[wv][g] = q.sc * (float)voigt_core64_rt(wa, wn, wl, d * q.ib, (double)q.y);
             }
           }
         };
-        switch (tier) {
-          case -1: packed(std::integral_constant<int, 0>{}); break;
-          case 0: packed(std::integral_constant<int, 16>{}); break;
-          case 1: packed(std::integral_constant<int, 24>{}); break;
-          case 2: packed(std::integral_constant<int, 32>{}); break;
-          default: packed(std::integral_constant<int, 40>{}); break;
-        }
+        if (tier < 0) packed(std::integral_constant<int, 0>{});
+        else if (tier == 0) packed(std::integral_constant<int, 16>{});
+        else if (tier == 1) packed(std::integral_constant<int, 20>{});
+        else packed(std::integral_constant<int, 1>{});
         wave_sync();
         int off = 0;   // packed points of the sub-batch's lines walked so far
         run(k, ke, [&](const Rec<false, P>& q, float (&t)[P]) {

@@ -27,8 +27,8 @@
 //        w(z) ~ 2 p(Z)/(L - iz)^2 + pi^{-1/2}/(L - iz),  Z = (L + iz)/(L - iz),
 //    L = 2^{-1/4} sqrt(N), evaluated in FP64: near the real axis Re w is tiny beside
 //    |w| (1e7 times smaller at y = 5e-7), and only FP64 keeps the cancellation small
-//    there. The FP32 path takes N from y (16, 24, 32 or 40 terms, core_tier, each within
-//    2e-7); the FP64 path always N = 40 (8.5e-9).
+//    there. The FP32 path takes N from y (16, 20, 22, 24, 32 or 40 terms, core_tier, each
+//    within 2.3e-7); the FP64 path always N = 40 (8.5e-9).
 //  * small-y core (|z| < 7, y < 0.1, FP32 path): with F Dawson's function,
 //    w = exp(-z^2) + (2i/sqrt(pi)) F(z), so
 //        K = exp(y^2 - x^2) cos(2xy) - (2/sqrt(pi)) Im F(x + iy),
@@ -334,19 +334,66 @@ XS_HD double voigt_core64(double x, double y) {
   return voigt_core64_n<kWeidN>(kWeidA, kWeidL, x, y);
 }
 
+// The same series with the term count n known only at run time (one loop for every
+// count; a wave-uniform n keeps the coefficient loads scalar).
+XS_HD double voigt_core64_rt(const double* a, int n, double L, double x, double y) {
+  const double lpy = L + y;
+  const double D = fma(lpy, lpy, x * x);
+  const double iD = rcp64(D);
+  const double zr = (L * L - y * y - x * x) * iD;
+  const double zi = 2.0 * L * x * iD;
+  double pr = a[n - 1], pi = 0.0;
+  // every term count in use is even, so n - 1 steps are one and then pairs; four steps per
+  // trip halve the waits on the (scalar) coefficient loads
+  int k = n - 2;
+  for (; k >= 0 && ((k + 1) & 3) != 0; --k) {
+    const double tr = fma(pr, zr, fma(-pi, zi, a[k]));
+    pi = fma(pr, zi, pi * zr);
+    pr = tr;
+  }
+  for (; k >= 3; k -= 4) {
+    const double a0 = a[k], a1 = a[k - 1], a2 = a[k - 2], a3 = a[k - 3];
+    double tr = fma(pr, zr, fma(-pi, zi, a0));
+    pi = fma(pr, zi, pi * zr);
+    pr = tr;
+    tr = fma(pr, zr, fma(-pi, zi, a1));
+    pi = fma(pr, zi, pi * zr);
+    pr = tr;
+    tr = fma(pr, zr, fma(-pi, zi, a2));
+    pi = fma(pr, zi, pi * zr);
+    pr = tr;
+    tr = fma(pr, zr, fma(-pi, zi, a3));
+    pi = fma(pr, zi, pi * zr);
+    pr = tr;
+  }
+  const double re2 = fma(lpy, lpy, -x * x);
+  const double t = 2.0 * fma(pr, re2, -2.0 * pi * x * lpy) * iD;
+  return fma(lpy, kInvSqrtPi, t) * iD;
+}
+
 // Core tiers of the FP32 path: the truncation error of Weideman's series inside |z| < 7
 // grows as y falls, so the term count follows y. Measured worst relative error of Re w
-// over x^2 + y^2 < 49 against the reference Faddeeva routine: N = 16 for y >= 1 (2e-7),
-// 24 for y >= 0.01 (2e-7), 32 for y >= 1e-5 (2e-7), 40 below (8e-9 down to y = 5e-7).
-XS_HD int core_tier(double y) { return y >= 1.0 ? 0 : y >= 0.01 ? 1 : y >= 1e-5 ? 2 : 3; }
+// over x^2 + y^2 < 49 against the reference Faddeeva routine: N = 16 for y >= 1 (2.3e-7),
+// 20 for y >= 0.3 (9.8e-8), 22 for y >= 0.1 (4.5e-8), 24 for y >= 0.01 (2.3e-7), 32 for
+// y >= 1e-5 (2e-7), 40 below (8e-9 down to y = 5e-7). Tiers in increasing term count.
+constexpr int kCoreTiers = 6;
+XS_HD int core_tier(double y) {
+  return y >= 1.0 ? 0 : y >= 0.3 ? 1 : y >= 0.1 ? 2 : y >= 0.01 ? 3 : y >= 1e-5 ? 4 : 5;
+}
+XS_HD int core_terms(int tier) {
+  return tier == 0 ? 16 : tier == 1 ? 20 : tier == 2 ? 22 : tier == 3 ? 24 : tier == 4 ? 32 : 40;
+}
+XS_HD const double* core_coef(int tier) {
+  return tier == 0 ? kWeidA16 : tier == 1 ? kWeidA20 : tier == 2 ? kWeidA22
+         : tier == 3 ? kWeidA24 : tier == 4 ? kWeidA32 : kWeidA;
+}
+XS_HD double core_L(int tier) {
+  return tier == 0 ? kWeidL16 : tier == 1 ? kWeidL20 : tier == 2 ? kWeidL22
+         : tier == 3 ? kWeidL24 : tier == 4 ? kWeidL32 : kWeidL;
+}
 
 XS_HD double voigt_core64_tier(int tier, double x, double y) {
-  switch (tier) {
-    case 0: return voigt_core64_n<16>(kWeidA16, kWeidL16, x, y);
-    case 1: return voigt_core64_n<24>(kWeidA24, kWeidL24, x, y);
-    case 2: return voigt_core64_n<32>(kWeidA32, kWeidL32, x, y);
-    default: return voigt_core64(x, y);
-  }
+  return voigt_core64_rt(core_coef(tier), core_terms(tier), core_L(tier), x, y);
 }
 
 // exp in FP32: v_exp_f32 (2^a, about 1 ulp) on the device, the C library on the host.
@@ -394,9 +441,13 @@ XS_HD float voigt_core_small(double xd, float y) {
   return fmaf(-2.0f * (float)kInvSqrtPi, imF, g);
 }
 
-// Accounting tier of a core point on the FP32 path (offset from kNVar): 0..3 the FP64
-// core's term counts, 4 the small-y core.
-XS_HD int core_eval_tier(float y) { return y < kTaylorY ? 4 : core_tier((double)y); }
+// Accounting tier of a core point on the FP32 path (offset from kNVar): 0 the FP64 core
+// with 16 terms (y >= 1), 1 with 20-24 terms (0.1 <= y < 1), 2 and 3 (32 and 40 terms)
+// only where a sub-batch mixes both sides of y = 0.1, so never for a point alone, 4 the
+// small-y core.
+XS_HD int core_eval_tier(float y) {
+  return y < kTaylorY ? 4 : core_tier((double)y) == 0 ? 0 : 1;
+}
 
 XS_HD float voigt_k32(double xd, float y) {
   const float x = (float)xd;

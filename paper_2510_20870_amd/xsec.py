@@ -28,7 +28,7 @@ XS_REGRID_LINEAR, XS_REGRID_BIN_MEAN = 0, 1
 XS_N_EVAL_TIERS = 10
 # names of the evaluation tiers counted by Context.count_evals_by_tier
 EVAL_TIERS = ("lorentz_shifted", "series2", "series3", "series4", "series6",
-              "core16", "core24", "core32", "core40", "core_small_y")
+              "core16", "core20_24", "core32", "core40", "core_small_y")
 
 _STATUS = {0: "XS_OK", -1: "XS_EINVAL", -2: "XS_ENOMEM", -3: "XS_EDEVICE",
            -4: "XS_ENOTFOUND", -5: "XS_EUNSORTED", -6: "XS_EBUSY", -7: "XS_ECANCELLED",

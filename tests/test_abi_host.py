@@ -91,10 +91,10 @@ def test_voigt_fp32_error_map():
 
 def test_voigt_fp32_core_tiers():
     # inside |z| < 7 the FP32 path takes the FP32 small-y core below y = 0.1 and above it
-    # the FP64 core with a term count from y; every tier, including both sides of each
-    # switch point, stays within the FP32 budget
+    # the FP64 core with a term count from y (22 terms, 20 from y = 0.3, 16 from y = 1);
+    # every tier, including both sides of each switch point, stays within the FP32 budget
     rng = np.random.default_rng(7)
-    edges = [1e-9, 1e-5, 0.01, 0.1, 1.0, 7.0]
+    edges = [1e-9, 1e-5, 0.01, 0.1, 0.3, 1.0, 7.0]
     ys, xs_ = [], []
     for lo, hi in zip(edges[:-1], edges[1:]):
         ys.append(10 ** rng.uniform(np.log10(lo), np.log10(hi), 40_000))
