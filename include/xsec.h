@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define XS_ABI_VERSION 7
+#define XS_ABI_VERSION 8
 
 typedef enum {
   XS_OK = 0,
@@ -184,7 +184,18 @@ typedef struct { double P_bar, T_K; } xs_pt;
  * cut, are expanded once about the span's centre, the expansion split among the four
  * wavefronts and added in a fixed order (FP32 path, fixed cut, no selection, 1 or 2
  * points per lane; XS_EINVAL otherwise). 0: automatic (4 where it applies and the cut
- * spans at least 15 half-widths of a four-tile span at the grid's middle, else 1). */
+ * spans at least 3 kappa half-widths of a four-tile span at the grid's middle, kappa the far
+ * threshold below, else 1).
+ * tol: the error budget of the FP32 path's cheaper far forms, relative to each line's
+ * contribution at each point (section "Functionality of pyROX" leaves the accuracy of the
+ * profile to the implementation): 0 is the default budget 2e-7; otherwise tol must lie
+ * in [2e-7, 1e-5] (XS_EINVAL). It sets where the shifted Lorentzian
+ * (3/2 + 2 y^2) / r^4 <= tol, the doubly shifted Lorentzian 3/2 / r^4 <= tol and the
+ * far-line polynomials |X| >= kappa H + 1.25 take over, kappa = 5 at the default and
+ * 3.72 at 1e-5 (the polynomial's truncation within 0.65 tol, the rest for its FP32
+ * recurrence); the other forms keep their own error (within 6e-7), and the FP32 sums add
+ * theirs (below 1e-6). So sigma's relative error stays below tol + 2e-6. The FP64 path
+ * ignores it. */
 typedef struct {
   int cutoff_kind;
   double cut_cm1;
@@ -196,6 +207,7 @@ typedef struct {
   double select_eps;
   int out_dtype;
   int tile_group;
+  double tol;
 } xs_opts;
 
 /* sigma(nu_j; P_k, T_k) for k < npts on every point of `grid`, written to
@@ -436,10 +448,12 @@ int xs_eval_voigt_host(const double *x, const double *y, size_t n, int precision
  * variant its nearest point needs.
  *   variant 0: shifted Lorentzian (y / sqrt(pi)) / (x^2 + y^2 - 3/2);
  *   variant 1, 2, 3, 4: the asymptotic series of w with 2, 3, 4, 6 terms;
- *   variant -1: per point, the variant the kernel picks for a nearest point there.
+ *   variant -1: per point, the variant the kernel picks for a nearest point there under
+ *   error budget `tol` (as xs_opts.tol: 0 the default 2e-7; the shifted Lorentzian where
+ *   (3/2 + 2 y^2) / r^4 <= tol).
  * x, y, K_out: n host values; variant_out (NULL or n ints) receives the variant used.
- * Points with x^2 + y^2 < 49 or y <= 0 give XS_EINVAL. */
-int xs_eval_series_host(const double *x, const double *y, size_t n, int variant,
+ * Points with x^2 + y^2 < 49 or y <= 0, or an invalid tol, give XS_EINVAL. */
+int xs_eval_series_host(const double *x, const double *y, size_t n, int variant, double tol,
                         double *K_out, int *variant_out);
 
 /* The bounds of K(x, y) that main-contributor selection uses (FP32 arithmetic with
@@ -452,19 +466,21 @@ int xs_eval_bounds_host(const double *x, const double *y, size_t n, double *K_lo
 
 /* The FP32 path's polynomial for far lines, compiled for the host (FP32 arithmetic at the
  * inputs rounded to FP32). A line whose doubly shifted Lorentzian K = (y / sqrt(pi)) /
- * (r^2 - 3/2 + 2 y^2 / r^2), r^2 = x^2 + y^2, holds over a whole tile (r^2 >= 2738.6 at
- * its nearest point, any y), with every point of the tile inside the cut, is summed as a
- * polynomial of degree 11 in the tile coordinate t in [-1, 1] when |X| >= 5 H + 1.25, X
- * being x at the tile's centre and H the tile's half-width in Doppler units (section
+ * (r^2 - 3/2 + 2 y^2 / r^2), r^2 = x^2 + y^2, holds over a whole tile (3/2 / r^4 <= eps at
+ * its nearest point, any y: r^2 >= 2738.6 at the default budget), with every point of the
+ * tile inside the cut, is summed as a polynomial of degree 11 in the tile coordinate
+ * t in [-1, 1] when |X| >= kappa H + 1.25, X being x at the tile's centre and H the tile's
+ * half-width in Doppler units; eps and kappa are those of budget `tol` (as xs_opts.tol: 0
+ * the default, eps = 2e-7 and kappa = 5) (section
  * "Functionality of pyROX": the profile of every line inside the cutoff, here summed per
  * tile instead of per point). Where the shifted Lorentzian (y / sqrt(pi)) /
  * (x^2 + y^2 - 3/2) also holds at the nearest point, its expansion (truncation within
- * 1.3e-7) is taken, else the doubly shifted one's. K_out[i]: that polynomial's K at
- * x = X[i] + H[i] t[i]; kind_out (may be NULL): 0 for the shifted, 1 for the doubly
- * shifted expansion. Each case must meet the conditions above, have y > 0 and |t| <= 1
- * (XS_EINVAL otherwise). */
+ * 1.3e-7 at the default budget) is taken, else the doubly shifted one's. K_out[i]: that
+ * polynomial's K at x = X[i] + H[i] t[i]; kind_out (may be NULL): 0 for the shifted, 1 for
+ * the doubly shifted expansion. Each case must meet the conditions above, have y > 0 and
+ * |t| <= 1, and tol must be valid (XS_EINVAL otherwise). */
 int xs_eval_far_host(const double *X, const double *H, const double *y, const double *t,
-                     size_t n, double *K_out, int *kind_out);
+                     size_t n, double tol, double *K_out, int *kind_out);
 
 #ifdef __cplusplus
 }

@@ -73,6 +73,9 @@ struct TileArgs {
   double* tau;
   int64_t tau_stride;     // groups of the whole grid
   double select_eps;      // select kernel: the allowed relative error
+  // error budget of the shifted forms (shifted_lorentz_ok, dshift_ok) and the far-line
+  // threshold kappa (far_ok) for that budget
+  float l1_eps, far_kappa;
 };
 
 // Launchers (kernels.hip). phys_wg = number of workgroups launched: n_wg rounded up to a

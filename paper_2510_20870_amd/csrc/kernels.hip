@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void xs_count_kernel(TileArgs A) {
         if (fabs(d) <= qc) {
           const float x = (float)(d * ibs[wv][kk]);
           const float r2 = fmaf(x, x, y2);
-          const int tier = r2 >= kT6R2 ? asym_variant(y2, r2) : core;
+          const int tier = r2 >= kT6R2 ? asym_variant(y2, r2, A.l1_eps) : core;
 #pragma unroll
           for (int t = 0; t < kNEvalTiers; ++t) cnt[t] += (tier == t) ? 1ull : 0ull;
         }

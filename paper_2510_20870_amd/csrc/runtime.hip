@@ -97,8 +97,27 @@ xs::GridRes* xs_ctx::find_grid(xs_grid_t h) {
 
 namespace xs {
 
+// The error budget of a tolerance argument: kTolDefault for 0, else tol itself, which must
+// lie in [kTolDefault, kTolMax].
+static int tol_budget(double tol, float* eps) {
+  if (tol == 0.0) {
+    *eps = kTolDefault;
+    return XS_OK;
+  }
+  const float t = (float)tol;   // the budget is compared in FP32, as the kernels use it
+  if (!(t >= kTolDefault && t <= kTolMax))
+    return fail(XS_EINVAL, "tol must be 0 or in [%g, %g] (got %g)", (double)kTolDefault,
+                (double)kTolMax, tol);
+  *eps = t;
+  return XS_OK;
+}
+
+float opts_eps(const xs_opts& o) { return o.tol == 0.0 ? kTolDefault : (float)o.tol; }
+
 int validate_opts(const xs_opts* o) {
   if (!o) return fail(XS_EINVAL, "opts is NULL");
+  float eps;
+  if (int rc = tol_budget(o->tol, &eps)) return rc;
   if (o->cutoff_kind != XS_CUT_FIXED && o->cutoff_kind != XS_CUT_MIN_FWHM)
     return fail(XS_EINVAL, "unknown cutoff_kind %d", o->cutoff_kind);
   if (!(o->cut_cm1 > 0.0) || !isfinite(o->cut_cm1))
@@ -195,7 +214,7 @@ Plan make_plan(Ctx& c, const LinesRes& L, const GridRes& G, size_t npts, const x
   } else if (o.tile_group == 0 && can_group && G.n >= 2) {
     const size_t m = std::min<size_t>(G.n / 2, G.n - 2);
     const double hv = 0.5 * (double)(kGroup * tile) * (G.host[m + 1] - G.host[m]);
-    p.group = o.cut_cm1 >= 15.0 * hv ? kGroup : 1;
+    p.group = o.cut_cm1 >= 3.0 * (double)far_kappa(opts_eps(o)) * hv ? kGroup : 1;
   }
   const int64_t unit = tile * p.group;
   p.n_units = ((int64_t)G.n + unit - 1) / unit;
@@ -359,6 +378,8 @@ int enqueue_step(const LinesRes& L, const GridRes& G, const xs_opts& o, const Pl
     A.recs = (const LineRec*)rec_dev;
     A.rec_lo = p.rec_lo;
     A.rec_n = p.rec_n;
+    A.l1_eps = opts_eps(o);
+    A.far_kappa = far_kappa(A.l1_eps);
     if (p.select_eps > 0.0) {
       // main-contributor selection: the kernels drop the lines below their group's
       // threshold
@@ -1300,17 +1321,19 @@ int xs_eval_bounds_host(const double* x, const double* y, size_t n, double* K_lo
   return XS_OK;
 }
 
-int xs_eval_series_host(const double* x, const double* y, size_t n, int variant,
+int xs_eval_series_host(const double* x, const double* y, size_t n, int variant, double tol,
                         double* K_out, int* variant_out) {
   if (n && (!x || !y || !K_out)) return fail(XS_EINVAL, "NULL argument");
   if (variant < -1 || variant >= kNVar) return fail(XS_EINVAL, "unknown variant %d", variant);
+  float eps;
+  if (int rc = tol_budget(tol, &eps)) return rc;
   for (size_t i = 0; i < n; ++i) {
     const float xf = (float)x[i], yf = (float)y[i];
     const float y2 = yf * yf;
     const float r2 = fmaf(xf, xf, y2);
     if (!(yf > 0.0f) || !(r2 >= kT6R2))
       return fail(XS_EINVAL, "point %zu (x %g, y %g) outside the series region", i, x[i], y[i]);
-    const int v = variant < 0 ? asym_variant(y2, r2) : variant;
+    const int v = variant < 0 ? asym_variant(y2, r2, eps) : variant;
     K_out[i] = (double)((float)kInvSqrtPi * yf * asym_scaled_v(v, y2, r2));
     if (variant_out) variant_out[i] = v;
   }
@@ -1318,18 +1341,21 @@ int xs_eval_series_host(const double* x, const double* y, size_t n, int variant,
 }
 
 int xs_eval_far_host(const double* X, const double* H, const double* y, const double* t,
-                     size_t n, double* K_out, int* kind_out) {
+                     size_t n, double tol, double* K_out, int* kind_out) {
   if (n && (!X || !H || !y || !t || !K_out)) return fail(XS_EINVAL, "NULL argument");
+  float eps;
+  if (int rc = tol_budget(tol, &eps)) return rc;
+  const float kappa = far_kappa(eps);
   for (size_t i = 0; i < n; ++i) {
     const float xf = (float)X[i], hf = (float)H[i], yf = (float)y[i], tf = (float)t[i];
     const float y2 = yf * yf;
     const float xn = fabsf(xf) - hf;   // the nearest point of the tile
     const float r2n = fmaf(xn, xn, y2);
-    if (!(yf > 0.0f) || !(hf >= 0.0f) || !(fabsf(tf) <= 1.0f) || !far_ok(xf, hf) ||
-        !(xn >= 0.0f) || !dshift_ok(r2n))
+    if (!(yf > 0.0f) || !(hf >= 0.0f) || !(fabsf(tf) <= 1.0f) || !far_ok(xf, hf, kappa) ||
+        !(xn >= 0.0f) || !dshift_ok(r2n, eps))
       return fail(XS_EINVAL, "case %zu (X %g, H %g, y %g, t %g) is not a far line", i, X[i],
                   H[i], y[i], t[i]);
-    const bool ds = !shifted_lorentz_ok(y2, r2n);
+    const bool ds = !shifted_lorentz_ok(y2, r2n, eps);
     float b[kFarDeg + 1];
     if (ds) far_coeffs_ds((float)kInvSqrtPi * yf, xf, hf, y2, b);
     else far_coeffs((float)kInvSqrtPi * yf, xf, hf, y2 - 1.5f, b);

@@ -223,6 +223,7 @@ __device__ __forceinline__ void sel_span(const TileArgs& A, int64_t t, double* g
 struct FarTile {
   double ra0, rbl;
   float h, ca, cb;   // half-width, centre - first point, centre - last point
+  float eps, kappa;  // the launch's error budget and far threshold
   bool ok;
 };
 template <int P>
@@ -235,6 +236,8 @@ __device__ __forceinline__ FarTile far_tile(const TileArgs& A, int64_t j0, doubl
   t.h = (float)(0.5 * (nu_last - g0));
   t.ca = (float)(nc - g0);
   t.cb = (float)(nc - nu_last);
+  t.eps = A.l1_eps;
+  t.kappa = A.far_kappa;
   t.ok = j0 + (int64_t)kWave * (P - 1) < A.n_grid;
   return t;
 }
@@ -260,8 +263,8 @@ __device__ __forceinline__ FarLine far_line(const FarTile& ft, double nu0, const
   const float r2n = fmaf(xn, xn, y2);
   const float h = ft.h * ib32;
   const float x = fmaf(ib32, left ? ft.ca : ft.cb, xn);
-  const bool far = ft.ok & in_cut & dshift_ok(r2n) & far_ok(x, h);
-  const bool ds = far & !shifted_lorentz_ok(y2, r2n);
+  const bool far = ft.ok & in_cut & dshift_ok(r2n, ft.eps) & far_ok(x, h, ft.kappa);
+  const bool ds = far & !shifted_lorentz_ok(y2, r2n, ft.eps);
   return FarLine{far, ds, far ? x : 1.0f, far ? h : 0.0f};
 }
 
@@ -298,8 +301,8 @@ __device__ __forceinline__ bool decode_item(const TileArgs& A, int lane, ItemInf
 // near the span [i2, i3); far lines on the right that cover the span [i3, i4); lines that
 // cover only part of it on the right [i4, hi). "Far" is a distance R from the centre,
 // chosen from a bound of the window's Doppler widths so that every line beyond it meets
-// the conditions of the tile polynomial for the whole span: |X| >= 5 H + 1.25 in the
-// line's Doppler units, and the doubly shifted Lorentzian within its bound at the span's
+// the conditions of the tile polynomial for the whole span: |X| >= kappa H + 1.25 in the
+// line's Doppler units (kappa = 5 at the default error budget), and the doubly shifted Lorentzian within its bound at the span's
 // nearest point (which holds for every y there). The two far ranges are summed as one polynomial over the span, their chunks
 // dealt to the wavefronts in turn; the other three ranges go through each wavefront's
 // per-tile path (restricted to the lines that can reach its tile). The ranges depend on
@@ -346,8 +349,9 @@ __device__ __forceinline__ bool decode_group(const TileArgs& A, int lane, int wa
   const double bmax = kd * (gb + cut) * (1.0 + 1e-12);
   // the doubly shifted Lorentzian holds where r^4 >= (3/2) / eps, for any y; x^2 at
   // least that bound is enough
-  const double x2 = sqrt(1.5 / (double)kL1Eps);
-  const double R = fmax(5.0 * hv + (double)kFarMargin * bmax, hv + sqrt(x2) * bmax) *
+  const double x2 = sqrt(1.5 / (double)A.l1_eps);
+  const double R = fmax((double)A.far_kappa * hv + (double)kFarMargin * bmax,
+                        hv + sqrt(x2) * bmax) *
                    (1.0 + 1e-6);
   const double cl = gg.c - R, cr = gg.c + R;
   const double* w = base + lo;
@@ -480,7 +484,7 @@ __device__ __forceinline__ Rec<F64, P> stage_line(const TileArgs& A, const LineR
                     : first_true_near(0, n - 1, lane_guess(rows, p, nu0 - cut),
                                       [&](int j) { return rv[j] - nu0 >= -cut; });
             }
-            info = (unsigned)bnd | ((unsigned)asym_variant(y2, r2n) << 8);
+            info = (unsigned)bnd | ((unsigned)asym_variant(y2, r2n, A.l1_eps) << 8);
           }
         }
         if (!F64 && c == 1 && general) {
@@ -1083,9 +1087,9 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
         const float x = fmaf(r.ib32, left ? ft.ca : ft.cb, xn);
         const float y2 = r.y * r.y;
         const float r2n = fmaf(xn, xn, y2);
-        if (dshift_ok(r2n) && far_ok(x, hl)) {
+        if (dshift_ok(r2n, A.l1_eps) && far_ok(x, hl, A.far_kappa)) {
           far = true;
-          ds = !shifted_lorentz_ok(y2, r2n);
+          ds = !shifted_lorentz_ok(y2, r2n, A.l1_eps);
           fc1 = r.c1;
           fx = x;
           fhl = hl;
@@ -1262,7 +1266,7 @@ __global__ __launch_bounds__(kBlock, (W > 0 ? W : 1)) void xs_tile_kernel(TileAr
       // the doubly shifted expansion when a line's nearest point of the span is outside the
       // shifted Lorentzian's region
       const float xn = fabsf(X) - h;
-      const bool ds = ok && !shifted_lorentz_ok(y * y, fmaf(xn, xn, y * y));
+      const bool ds = ok && !shifted_lorentz_ok(y * y, fmaf(xn, xn, y * y), A.l1_eps);
       far_add(acc, c1, X, h, ok ? y * y : 0.0f, __ballot(ds) != 0ull);
       if (++nrun == kFarRun) {
         gflush();

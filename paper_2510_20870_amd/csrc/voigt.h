@@ -136,20 +136,26 @@ XS_HD float asym2_m(float m2y2, float r2) {
   return u * fmaf(u, fmaf(m2y2, u, 1.5f), 1.0f);
 }
 
-// Shifted-Lorentzian region: (3/2 + 2 y^2) / r^4 <= kL1Eps.
-constexpr float kL1Eps = 2e-7f;
-XS_HD bool shifted_lorentz_ok(float y2, float r2) {
-  return r2 * r2 * kL1Eps >= fmaf(2.0f, y2, 1.5f);
+// Error budget eps of the shifted forms and of the far-line polynomials, relative to each
+// line's contribution: kTolDefault unless a launch asks for a looser one (at most kTolMax).
+constexpr float kTolDefault = 2e-7f;
+constexpr float kTolMax = 1e-5f;
+constexpr float kL1Eps = kTolDefault;
+
+// Shifted-Lorentzian region: (3/2 + 2 y^2) / r^4 <= eps.
+XS_HD bool shifted_lorentz_ok(float y2, float r2, float eps) {
+  return r2 * r2 * eps >= fmaf(2.0f, y2, 1.5f);
 }
 
 // Doubly shifted Lorentzian K sqrt(pi) / y = 1 / (r^2 - 3/2 + 2 y^2 / r^2): with
 // s = 3/2 - 2w it is u (1 + s u + s^2 u^2 + ...), which matches the series through its
 // u^2 term (a_1 V_1 = 3/2 - 2w = s) for every y; the first difference,
 // (a_2 V_2 - s^2) u^3 = (3/2 - 9w + 8w^2) u^3, is at most 3/2 u^2 relative (w in [0, 1]),
-// so the form holds to kL1Eps wherever 3/2 / r^4 <= kL1Eps (|z| >= 52.3), whatever y
-// (measured against the reference Faddeeva routine: 2.0e-7 at that radius). Far lines
-// whose y is too large for the shifted Lorentzian are expanded in this form.
-XS_HD bool dshift_ok(float r2) { return r2 * r2 * kL1Eps >= 1.5f; }
+// so the form holds to eps wherever 3/2 / r^4 <= eps (|z| >= 52.3 for eps = 2e-7, 19.7 for
+// 1e-5), whatever y (measured against the reference Faddeeva routine: 2.0e-7 at the first
+// radius). Far lines whose y is too large for the shifted Lorentzian are expanded in this
+// form.
+XS_HD bool dshift_ok(float r2, float eps) { return r2 * r2 * eps >= 1.5f; }
 
 // Series variants of the far region, cheapest first: 0 = shifted Lorentzian, 1..4 =
 // NT = 2, 3, 4, 6 terms. For a fixed y the variant a point needs does not increase with
@@ -159,9 +165,9 @@ constexpr int kNVar = 5;
 // counts of the FP64 core (core_tier), then the FP32 small-y core (core_eval_tier).
 constexpr int kNEvalTiers = kNVar + 5;
 
-// The variant a point at r2 >= kT6R2 needs.
-XS_HD int asym_variant(float y2, float r2) {
-  if (shifted_lorentz_ok(y2, r2)) return 0;
+// The variant a point at r2 >= kT6R2 needs (eps: the shifted Lorentzian's budget).
+XS_HD int asym_variant(float y2, float r2, float eps) {
+  if (shifted_lorentz_ok(y2, r2, eps)) return 0;
   return r2 >= kT2R2 ? 1 : r2 >= kT3R2 ? 2 : r2 >= kT4R2 ? 3 : 4;
 }
 
@@ -188,13 +194,38 @@ XS_HD float asym_scaled_v(int v, float y2, float r2) {
 // (1 + rho)^2 (kFarDeg + 2) rho^(kFarDeg + 1) / (1 - rho)^2 (x 1.05) of f on the range:
 // with rho <= 1/5 (|X| >= 5 H + 1.25, and y2s >= -3/2), 1.3e-7 relative. The
 // coefficients of many lines add up, so a sum of such lines costs one polynomial per
-// point instead of one evaluation per line and point.
+// point instead of one evaluation per line and point. A looser budget eps takes
+// |X| >= kappa H + 1.25 with kappa = far_kappa(eps) (3.72 for eps = 1e-5).
 constexpr int kFarDeg = 11;
-constexpr float kFarKappa = 5.0f;
+constexpr float kFarKappa = 5.0f;     // the threshold at kTolDefault
 constexpr float kFarMargin = 1.25f;   // >= sqrt(3/2)
 
 // Whether a line at tile-centre x and half-width h (both Doppler units) may be expanded.
-XS_HD bool far_ok(float x, float h) { return fabsf(x) >= fmaf(kFarKappa, h, kFarMargin); }
+XS_HD bool far_ok(float x, float h, float kappa) {
+  return fabsf(x) >= fmaf(kappa, h, kFarMargin);
+}
+
+// The truncation bound above at rho, with the factor 1.05 raised to 1.15: at a looser
+// budget the shifted Lorentzian starts at |X| >= 19.7, where the two real roots of the
+// quadratic differ by up to 13 %.
+inline double far_tail_bound(double rho) {
+  double p = 1.0;
+  for (int k = 0; k <= kFarDeg; ++k) p *= rho;
+  return (1.0 + rho) * (1.0 + rho) * (kFarDeg + 2) * p * 1.15 / ((1.0 - rho) * (1.0 - rho));
+}
+
+// kappa for budget eps: kFarKappa at kTolDefault; otherwise the smallest kappa (to 1e-4)
+// whose bound stays within 0.65 eps (the rest of eps covers the FP32 recurrence), and
+// never above kFarKappa.
+inline float far_kappa(float eps) {
+  if (!(eps > kTolDefault)) return kFarKappa;
+  double lo = 1.0 / kFarKappa, hi = 0.5;   // far_tail_bound(lo) <= 0.65 eps < bound(hi)
+  for (int i = 0; i < 60; ++i) {
+    const double m = 0.5 * (lo + hi);
+    (far_tail_bound(m) <= 0.65 * (double)eps ? lo : hi) = m;
+  }
+  return fminf(kFarKappa, (float)(1.0 / lo) * 1.0001f);
+}
 
 // The recurrence: far_start gives alpha, beta, b_0 and b_1; far_next b_k from the two
 // before it.

@@ -68,7 +68,7 @@ class Opts(C.Structure):
     _fields_ = [("cutoff_kind", C.c_int), ("cut_cm1", C.c_double), ("fwhm_mult", C.c_double),
                 ("precision", C.c_int), ("pts_per_lane", C.c_int), ("split", C.c_int),
                 ("waves_per_simd", C.c_int), ("select_eps", C.c_double),
-                ("out_dtype", C.c_int), ("tile_group", C.c_int)]
+                ("out_dtype", C.c_int), ("tile_group", C.c_int), ("tol", C.c_double)]
 
 
 class ServeOpts(C.Structure):
@@ -147,10 +147,10 @@ _SIGS = {
                       C.c_int),
     "xs_eval_voigt_host": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p],
                            C.c_int),
-    "xs_eval_series_host": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p,
-                             C.c_void_p], C.c_int),
+    "xs_eval_series_host": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_double,
+                             C.c_void_p, C.c_void_p], C.c_int),
     "xs_eval_far_host": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
-                          C.c_void_p, C.c_void_p], C.c_int),
+                          C.c_double, C.c_void_p, C.c_void_p], C.c_int),
     "xs_eval_bounds_host": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p],
                             C.c_int),
     "xs_regrid": ([C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p, C.c_size_t, C.c_int,
@@ -200,30 +200,32 @@ def eval_voigt_host(x, y, precision: int = XS_FP32_KAHAN) -> np.ndarray:
     return out
 
 
-def eval_series_host(x, y, variant: int = -1):
+def eval_series_host(x, y, variant: int = -1, tol: float = 0.0):
     """The tile kernel's FP32 far-region forms on the host: (K, variant used per point).
     variant 0 = shifted Lorentzian, 1..4 = asymptotic series with 2, 3, 4, 6 terms, -1 =
-    the variant the kernel picks for a nearest point at (x, y)."""
+    the variant the kernel picks for a nearest point at (x, y) under error budget tol
+    (0: the default 2e-7)."""
     x = np.ascontiguousarray(x, np.float64)
     y = np.ascontiguousarray(y, np.float64)
     out = np.empty_like(x)
     var = np.empty(x.shape, np.int32)
-    rc = lib().xs_eval_series_host(_ptr(x), _ptr(y), x.size, int(variant), _ptr(out),
-                                   _ptr(var))
+    rc = lib().xs_eval_series_host(_ptr(x), _ptr(y), x.size, int(variant), float(tol),
+                                   _ptr(out), _ptr(var))
     if rc:
         raise XsError(rc, lib().xs_last_error(None).decode())
     return out, var
 
 
-def eval_far_host(X, H, y, t, with_kind: bool = False):
+def eval_far_host(X, H, y, t, with_kind: bool = False, tol: float = 0.0):
     """The tile kernel's polynomial for far lines on the host: K at x = X + H t from the
-    degree-11 expansion over a tile of half-width H centred at X (Doppler units); with
-    with_kind also the expansion taken per case (0 shifted, 1 doubly shifted Lorentzian)."""
+    degree-11 expansion over a tile of half-width H centred at X (Doppler units), with the
+    thresholds of error budget tol (0: the default 2e-7); with with_kind also the
+    expansion taken per case (0 shifted, 1 doubly shifted Lorentzian)."""
     X, H, y, t = (np.ascontiguousarray(a, np.float64) for a in np.broadcast_arrays(X, H, y, t))
     out = np.empty_like(X)
     kind = np.empty(X.shape, np.int32)
-    rc = lib().xs_eval_far_host(_ptr(X), _ptr(H), _ptr(y), _ptr(t), X.size, _ptr(out),
-                                _ptr(kind))
+    rc = lib().xs_eval_far_host(_ptr(X), _ptr(H), _ptr(y), _ptr(t), X.size, float(tol),
+                                _ptr(out), _ptr(kind))
     if rc:
         raise XsError(rc, lib().xs_last_error(None).decode())
     return (out, kind) if with_kind else out
@@ -518,9 +520,12 @@ class Context:
     def opts(cutoff_kind: int = XS_CUT_FIXED, cut_cm1: float = 25.0, fwhm_mult: float = 100.0,
              precision: int = XS_FP32_KAHAN, pts_per_lane: int = 0, split: int = 0,
              waves_per_simd: int = 0, select_eps: float = 0.0,
-             out_dtype: int = XS_F64, tile_group: int = 0) -> Opts:
+             out_dtype: int = XS_F64, tile_group: int = 0, tol: float = 0.0) -> Opts:
+        """Options of a computation (xs_opts). tol: the FP32 path's error budget of its far
+        forms relative to each contribution, 0 (the default 2e-7) or in [2e-7, 1e-5]."""
         return Opts(cutoff_kind, cut_cm1, fwhm_mult, precision, pts_per_lane, split,
-                    waves_per_simd, float(select_eps), int(out_dtype), int(tile_group))
+                    waves_per_simd, float(select_eps), int(out_dtype), int(tile_group),
+                    float(tol))
 
     @staticmethod
     def _pts(pts) -> C.Array:

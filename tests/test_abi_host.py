@@ -293,6 +293,85 @@ def test_far_line_polynomial_doubly_shifted():
     assert np.max(np.abs(K0 / ref0 - 1)) < 4e-7
 
 
+# The loosest error budget a launch may ask for (xs_opts.tol), and the far threshold kappa
+# the header gives for it.
+LOOSE_TOL, LOOSE_KAPPA = 1e-5, 3.72
+
+
+def _far_cases_loose(n, seed, ds):
+    # far lines from the loose budget's threshold |X| = kappa H + 1.25 outwards, nearest point
+    # inside the budget's region of the shifted (ds False) or only of the doubly shifted
+    # Lorentzian (ds True)
+    rng = np.random.default_rng(seed)
+    H = 10 ** rng.uniform(-1, 4, n)
+    y = 10 ** (rng.uniform(-0.5, 4.5, n) if ds else rng.uniform(-6, 3.3, n))
+    X = ((LOOSE_KAPPA + 10 ** rng.uniform(-6, 1.5, n)) * H + 1.25) * (1 + 1e-4)
+    X *= np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    t = rng.uniform(-1, 1, n)
+    t[:200], t[200:400] = -1.0, 1.0
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    xn = np.abs(f32(X)) - f32(H)
+    r2n = xn * xn + f32(y) ** 2
+    e1 = (1.5 + 2 * f32(y) ** 2) / r2n ** 2
+    ok = (xn >= 0) & (r2n * r2n * LOOSE_TOL >= 1.5 * (1 + 1e-5))
+    ok &= (e1 > LOOSE_TOL * 1.05) if ds else (e1 <= LOOSE_TOL * 0.95)
+    return X[ok], H[ok], y[ok], t[ok]
+
+
+def test_loose_budget_far_forms():
+    # Error budget 1e-5: the shifted Lorentzian where (3/2 + 2 y^2) / r^4 <= 1e-5, the
+    # doubly shifted one where 3/2 / r^4 <= 1e-5 (against wofz: within 1.013 times those
+    # bounds, so within the budget plus 1.3 %), and the far polynomials from
+    # |X| = 3.72 H + 1.25 (truncation within 0.65e-5, plus FP32 rounding)
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(51)
+    y = 10 ** rng.uniform(-6, 2, 300_000)
+    r2 = np.sqrt((1.5 + 2 * y * y) / LOOSE_TOL) * 10 ** rng.uniform(0, 2, y.size)
+    x = np.sqrt(np.maximum(r2 - y * y, 0.0))
+    x, y = f32(x), f32(y)
+    m = (x > 0) & (x * x + y * y >= 49.0)
+    x, y = x[m], y[m]
+    K, v = xsec.eval_series_host(x, y, -1, tol=LOOSE_TOL)
+    ref = wofz(x + 1j * y).real
+    rel = np.abs(K / ref - 1)
+    print(f"series forms at budget 1e-5: max {rel.max():.3e}, shifted Lorentzian share "
+          f"{np.mean(v == 0):.3f}")
+    assert rel.max() < 1.03 * LOOSE_TOL + 6e-7
+    assert np.mean(v == 0) > 0.95
+    # at the default budget the same points need the costlier variants more often
+    _, v0 = xsec.eval_series_host(x, y, -1)
+    assert np.all(v0 >= v) and np.mean(v0 == 0) < np.mean(v == 0)
+    for ds in (False, True):
+        X, H, yy, t = _far_cases_loose(400_000, 52 + ds, ds)
+        assert len(X) > 50_000
+        K, kind = xsec.eval_far_host(X, H, yy, t, with_kind=True, tol=LOOSE_TOL)
+        assert np.all(kind == ds)
+        Xf, Hf, yf, tf = f32(X), f32(H), f32(yy), f32(t)
+        xx = Xf + Hf * tf
+        r2 = xx * xx + yf * yf
+        closed = (yf / np.sqrt(np.pi)) / ((r2 - 1.5 + 2 * yf * yf / r2) if ds else (r2 - 1.5))
+        rc = np.abs(K / closed - 1)
+        sub = rng.choice(len(xx), 50_000, replace=False)
+        rw = np.abs(K[sub] / wofz(xx[sub] + 1j * yf[sub]).real - 1)
+        print(f"far polynomial at budget 1e-5 (ds={ds}): vs closed form {rc.max():.3e}, "
+              f"vs wofz {rw.max():.3e}")
+        assert rc.max() < 0.65 * LOOSE_TOL + 1e-6
+        assert rw.max() < 1.03 * LOOSE_TOL + 1e-6
+    # the threshold: just inside kappa H + 1.25 is refused, just outside accepted
+    H = 100.0
+    xsec.eval_far_host(LOOSE_KAPPA * H * 1.001 + 1.25, H, 1.0, 0.5, tol=LOOSE_TOL)
+    with pytest.raises(xsec.XsError):
+        xsec.eval_far_host(LOOSE_KAPPA * H * 0.999 + 1.25, H, 1.0, 0.5, tol=LOOSE_TOL)
+    with pytest.raises(xsec.XsError):   # not far at the default budget
+        xsec.eval_far_host(LOOSE_KAPPA * H * 1.001 + 1.25, H, 1.0, 0.5)
+    # budgets outside [2e-7, 1e-5] (other than 0, the default) are refused
+    for bad in (1e-7, 2e-5, -1e-6, float("nan")):
+        with pytest.raises(xsec.XsError):
+            xsec.eval_far_host(1e4, 10.0, 1.0, 0.0, tol=bad)
+        with pytest.raises(xsec.XsError):
+            xsec.eval_series_host([100.0], [1.0], -1, tol=bad)
+
+
 def test_series_variant_errors():
     with pytest.raises(xsec.XsError):
         xsec.eval_series_host([1.0], [1.0], 0)        # |z| < 7

@@ -161,10 +161,10 @@ def test_count_evals_fixed(ctx):
     ctx.free_grid(g)
 
 
-def _tiers_fp64(L, grid, P, T, mass, cut):
+def _tiers_fp64(L, grid, P, T, mass, cut, eps=2e-7):
     """Evaluation tier of every in-cut pair, classified in FP64 from the oracle's line
     parameters with the documented thresholds: far region x^2 + y^2 >= 49 split into the
-    shifted Lorentzian ((3/2 + 2 y^2) / r^4 <= 2e-7) and the asymptotic series with 2, 3,
+    shifted Lorentzian ((3/2 + 2 y^2) / r^4 <= eps, the error budget) and the asymptotic series with 2, 3,
     4, 6 terms (r^2 >= 6400, 400, 169, 49); the core by y (FP64 core with 16 terms for
     y >= 1, 24 for y >= 0.1, the FP32 small-y core below)."""
     par = O.line_parameters(L, P, T, mass, cut_cm1=cut)
@@ -177,7 +177,7 @@ def _tiers_fp64(L, grid, P, T, mass, cut):
         x = d / par["b_D"][None, :]
         yy = np.broadcast_to(y[None, :], x.shape)
         r2 = x * x + yy * yy
-        far = np.where((1.5 + 2 * yy * yy) / (r2 * r2) <= 2e-7, 0,
+        far = np.where((1.5 + 2 * yy * yy) / (r2 * r2) <= eps, 0,
                        np.where(r2 >= 6400, 1, np.where(r2 >= 400, 2,
                                 np.where(r2 >= 169, 3, 4))))
         core = np.where(yy >= 1.0, 5, np.where(yy >= 0.1, 6, 9))
@@ -584,9 +584,9 @@ def test_cia_regrid(ctx):
     ctx.free_grid(g)
 
 
-def _far_threshold_lines(grid, T, mass, per_tile, tile):
-    # centres at the far-line switch of every tile: (nu_c - nu0) = 5 h + 1.25 b_D(nu0) on
-    # the left, mirrored on the right, nudged by -1e-9 .. 1e-9 relative so that both
+def _far_threshold_lines(grid, T, mass, per_tile, tile, kappa=5.0):
+    # centres at the far-line switch of every tile: (nu_c - nu0) = kappa h + 1.25 b_D(nu0)
+    # on the left, mirrored on the right, nudged by -1e-9 .. 1e-9 relative so that both
     # sides of the switch occur; nu_c and h over the tile's valid points
     k = O.doppler_width(1.0, T, mass)
     out = []
@@ -594,8 +594,8 @@ def _far_threshold_lines(grid, T, mass, per_tile, tile):
     for j0 in range(0, len(grid), tile):
         g = grid[j0:j0 + tile]
         nc, h = 0.5 * (g[0] + g[-1]), 0.5 * (g[-1] - g[0])
-        left = (nc - 5.0 * h) / (1.0 + 1.25 * k)
-        right = (nc + 5.0 * h) / (1.0 - 1.25 * k)
+        left = (nc - kappa * h) / (1.0 + 1.25 * k)
+        right = (nc + kappa * h) / (1.0 - 1.25 * k)
         for c in (left, right):
             out.append(c * (1.0 + rng.uniform(-1e-9, 1e-9, per_tile)))
     return np.concatenate(out)
@@ -671,6 +671,79 @@ def test_grouped_far_field(ctx, gridkind):
         bad.tile_group = 4
         with pytest.raises(X.XsError) as e:
             ctx.compute(h, g, [(0.1, 1500.0)], bad)
+        assert e.value.code == X.XS_EINVAL
+    ctx.unload_lines(h)
+    ctx.free_grid(g)
+
+
+# The loosest error budget (xs_opts.tol) and its far threshold kappa, as the header states
+# them; sigma then stays within tol + 2e-6 of the oracle.
+LOOSE_TOL, LOOSE_KAPPA = 1e-5, 3.72
+
+
+def test_loose_error_budget(ctx):
+    """tol = 1e-5: the shifted forms and the far polynomials take over closer to the lines.
+    Dense lines around a ln grid (ragged last group), with extra lines at the loose far
+    switch of every tile, low to high pressure, per-tile and grouped far field, 1 and 2
+    points per lane, splits 1 and 3: against the oracle within 1e-5 + 2e-6, bitwise
+    repeatable, and different from the default budget's result (the looser forms ran)."""
+    grid = np.exp(np.linspace(np.log(990.0), np.log(1010.0), 5 * 256 + 129))
+    mass = 16.0
+    base = synth.make_lines(synth.ListSpec(80_000, grid[0] - 30.0, grid[-1] + 30.0, 81))
+    bound = LOOSE_TOL + 2e-6
+    for (P, T) in ((1e-4, 500.0), (0.1, 1500.0), (6.3, 3000.0), (100.0, 2500.0)):
+        L = {k: v.copy() for k, v in base.items()}
+        extra = _far_threshold_lines(grid, T, mass, 32, 64, kappa=LOOSE_KAPPA)
+        src = np.random.default_rng(82).integers(0, len(L["nu0"]), len(extra))
+        for key in L:
+            L[key] = np.concatenate([L[key], L[key][src] if key != "nu0" else extra])
+        order = np.argsort(L["nu0"], kind="stable")
+        L = {key: v[order] for key, v in L.items()}
+        h = ctx.load_lines(L, mass)
+        g = ctx.set_grid(grid)
+        ref = O.sigma(L, grid, P, T, mass, cut_cm1=25.0)
+        strict = ctx.compute(h, g, [(P, T)], _opts(P=1, split=1))[0]
+        for Pl, split, grp in ((1, 1, 1), (2, 3, 1), (1, 1, 4), (2, 3, 4), (0, 0, 0)):
+            o = _opts(P=Pl, split=split)
+            o.tile_group = grp
+            o.tol = LOOSE_TOL
+            sig = ctx.compute(h, g, [(P, T)], o)[0]
+            st = _check(sig, ref, bound, f"tol 1e-5 P={P} T={T} pts/lane {Pl} split {split} "
+                                         f"group {grp}")
+            assert st["max_rel"] < bound
+            assert not np.array_equal(sig, strict)
+            assert np.array_equal(ctx.compute(h, g, [(P, T)], o)[0], sig)
+        ctx.unload_lines(h)
+        ctx.free_grid(g)
+
+
+def test_loose_error_budget_tiers_and_errors(ctx):
+    """The tier counts follow the budget (more pairs take the shifted Lorentzian, the total
+    is unchanged), and budgets outside [2e-7, 1e-5] other than 0 are refused."""
+    X = _xsec()
+    W, L, grid = _tiny()
+    grid = grid[:3000]
+    h = ctx.load_lines(L, W.mass_amu)
+    g = ctx.set_grid(grid)
+    pts = [(1e-4, 300.0), (1.0, 1000.0), (60.0, 2500.0)]
+    o = _opts(cut=10.0)
+    o.tol = LOOSE_TOL
+    tiers = ctx.count_evals_by_tier(h, g, pts, o)
+    strict = ctx.count_evals_by_tier(h, g, pts, _opts(cut=10.0))
+    for k, (P, T) in enumerate(pts):
+        assert int(tiers[k].sum()) == int(strict[k].sum())
+        assert tiers[k][0] >= strict[k][0]
+        ref = _tiers_fp64(L, grid, P, T, W.mass_amu, 10.0, eps=LOOSE_TOL)
+        diff = np.abs(tiers[k].astype(np.int64) - ref)
+        print(f"[tiers tol 1e-5] P={P} T={T} {tiers[k].tolist()} ref {ref.tolist()}",
+              flush=True)
+        assert np.all(diff <= 2 + 1e-5 * ref.sum()), (P, T, tiers[k], ref)
+    assert sum(int(tiers[k][0]) for k in range(3)) > sum(int(strict[k][0]) for k in range(3))
+    for bad in (1e-7, 2e-5, -1e-6, float("nan")):
+        o = _opts(cut=10.0)
+        o.tol = bad
+        with pytest.raises(X.XsError) as e:
+            ctx.compute(h, g, [(1.0, 1000.0)], o)
         assert e.value.code == X.XS_EINVAL
     ctx.unload_lines(h)
     ctx.free_grid(g)
