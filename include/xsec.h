@@ -191,8 +191,8 @@ typedef struct { double P_bar, T_K; } xs_pt;
  * profile to the implementation): 0 is the default budget 2e-7; otherwise tol must lie
  * in [2e-7, 1e-5] (XS_EINVAL). It sets where the shifted Lorentzian
  * (3/2 + 2 y^2) / r^4 <= tol, the doubly shifted Lorentzian 3/2 / r^4 <= tol and the
- * far-line polynomials |X| >= kappa H + 1.25 take over, kappa = 5 at the default and
- * 3.72 at 1e-5 (the polynomial's truncation within 0.65 tol, the rest for its FP32
+ * far-line polynomials |X| >= kappa H + 1.25 take over, kappa = 4.09 at the default and
+ * 3.16 at 1e-5 (the polynomial's truncation within 0.65 tol, the rest for its FP32
  * recurrence); the other forms keep their own error (within 6e-7), and the FP32 sums add
  * theirs (below 1e-6). So sigma's relative error stays below tol + 2e-6. The FP64 path
  * ignores it. */
@@ -468,10 +468,10 @@ int xs_eval_bounds_host(const double *x, const double *y, size_t n, double *K_lo
  * inputs rounded to FP32). A line whose doubly shifted Lorentzian K = (y / sqrt(pi)) /
  * (r^2 - 3/2 + 2 y^2 / r^2), r^2 = x^2 + y^2, holds over a whole tile (3/2 / r^4 <= eps at
  * its nearest point, any y: r^2 >= 2738.6 at the default budget), with every point of the
- * tile inside the cut, is summed as a polynomial of degree 11 in the tile coordinate
+ * tile inside the cut, is summed as a polynomial of degree 13 in the tile coordinate
  * t in [-1, 1] when |X| >= kappa H + 1.25, X being x at the tile's centre and H the tile's
  * half-width in Doppler units; eps and kappa are those of budget `tol` (as xs_opts.tol: 0
- * the default, eps = 2e-7 and kappa = 5) (section
+ * the default, eps = 2e-7 and kappa = 4.09) (section
  * "Functionality of pyROX": the profile of every line inside the cutoff, here summed per
  * tile instead of per point). Where the shifted Lorentzian (y / sqrt(pi)) /
  * (x^2 + y^2 - 3/2) also holds at the nearest point, its expansion (truncation within

@@ -191,13 +191,13 @@ XS_HD float asym_scaled_v(int v, float y2, float r2) {
 // alpha = 2 X H / Q0, beta = H^2 / Q0. The roots of the quadratic lie at |t| >= 1 / rho,
 // rho = H / (|X| - sqrt(max(-y2s, 0))), which bounds |b_k| <= 1.05 (k + 1) rho^k b_0, and
 // the sum truncated after degree kFarDeg is within
-// (1 + rho)^2 (kFarDeg + 2) rho^(kFarDeg + 1) / (1 - rho)^2 (x 1.05) of f on the range:
-// with rho <= 1/5 (|X| >= 5 H + 1.25, and y2s >= -3/2), 1.3e-7 relative. The
-// coefficients of many lines add up, so a sum of such lines costs one polynomial per
-// point instead of one evaluation per line and point. A looser budget eps takes
-// |X| >= kappa H + 1.25 with kappa = far_kappa(eps) (3.72 for eps = 1e-5).
-constexpr int kFarDeg = 11;
-constexpr float kFarKappa = 5.0f;     // the threshold at kTolDefault
+// (1 + rho)^2 (kFarDeg + 2) rho^(kFarDeg + 1) / (1 - rho)^2 (x 1.05) of f on the range.
+// A line qualifies where |X| >= kappa H + 1.25 (rho <= 1 / kappa, as y2s >= -3/2), kappa =
+// far_kappa(eps) keeping the bound within 0.65 eps of the error budget eps: 4.09 at the
+// default 2e-7, 3.16 at 1e-5 (degree 13). The coefficients of many lines add up, so a sum
+// of such lines costs one polynomial per point instead of one evaluation per line and
+// point.
+constexpr int kFarDeg = 13;
 constexpr float kFarMargin = 1.25f;   // >= sqrt(3/2)
 
 // Whether a line at tile-centre x and half-width h (both Doppler units) may be expanded.
@@ -214,17 +214,15 @@ inline double far_tail_bound(double rho) {
   return (1.0 + rho) * (1.0 + rho) * (kFarDeg + 2) * p * 1.15 / ((1.0 - rho) * (1.0 - rho));
 }
 
-// kappa for budget eps: kFarKappa at kTolDefault; otherwise the smallest kappa (to 1e-4)
-// whose bound stays within 0.65 eps (the rest of eps covers the FP32 recurrence), and
-// never above kFarKappa.
+// kappa for budget eps (kTolDefault .. kTolMax): the smallest kappa (to 1e-4) whose bound
+// stays within 0.65 eps (the rest of eps covers the FP32 recurrence).
 inline float far_kappa(float eps) {
-  if (!(eps > kTolDefault)) return kFarKappa;
-  double lo = 1.0 / kFarKappa, hi = 0.5;   // far_tail_bound(lo) <= 0.65 eps < bound(hi)
+  double lo = 0.1, hi = 0.5;   // far_tail_bound(lo) <= 0.65 eps < far_tail_bound(hi)
   for (int i = 0; i < 60; ++i) {
     const double m = 0.5 * (lo + hi);
     (far_tail_bound(m) <= 0.65 * (double)eps ? lo : hi) = m;
   }
-  return fminf(kFarKappa, (float)(1.0 / lo) * 1.0001f);
+  return (float)(1.0 / lo) * 1.0001f;
 }
 
 // The recurrence: far_start gives alpha, beta, b_0 and b_1; far_next b_k from the two
@@ -262,10 +260,10 @@ XS_HD void far_coeffs(float c1, float x, float h, float y2s, float (&b)[kFarDeg 
 // (1, r1, r2, 0, ...). The roots of R^2 - 3/2 R + 2 y^2 in R are real and in (0, 3/2)
 // for y^2 < 9/32, else complex with |R| = sqrt(2) y; the four poles in t solve
 // (X + H t)^2 = R - y^2, and every such X + H t has a real part of magnitude at most
-// sqrt(3/2) (below 0.71 in the complex case), so |X| >= 5 H + 1.25 keeps them at
-// |t| >= 5 as for the shifted Lorentzian. Truncation after kFarDeg: measured
-// below 6.3e-8 in FP64 over tile half-widths of 0.1-1e4 Doppler widths and y up to 3e4;
-// FP32 rounding of the four-term recurrence brings the total to 5.3e-7.
+// sqrt(3/2) (below 0.71 in the complex case), so |X| >= kappa H + 1.25 keeps them at
+// |t| >= kappa as for the shifted Lorentzian. Truncation after degree 11 at kappa = 5:
+// measured below 6.3e-8 in FP64 over tile half-widths of 0.1-1e4 Doppler widths and y up
+// to 3e4; FP32 rounding of the four-term recurrence brought the total to 5.3e-7.
 struct FarRecD {
   float d1, d2, d3, d4, b0, b1, b2, b3;
 };

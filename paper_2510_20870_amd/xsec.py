@@ -218,7 +218,7 @@ def eval_series_host(x, y, variant: int = -1, tol: float = 0.0):
 
 def eval_far_host(X, H, y, t, with_kind: bool = False, tol: float = 0.0):
     """The tile kernel's polynomial for far lines on the host: K at x = X + H t from the
-    degree-11 expansion over a tile of half-width H centred at X (Doppler units), with the
+    degree-13 expansion over a tile of half-width H centred at X (Doppler units), with the
     thresholds of error budget tol (0: the default 2e-7); with with_kind also the
     expansion taken per case (0 shifted, 1 doubly shifted Lorentzian)."""
     X, H, y, t = (np.ascontiguousarray(a, np.float64) for a in np.broadcast_arrays(X, H, y, t))

@@ -183,14 +183,18 @@ def test_selection_bounds_enclose_k():
         xsec.eval_bounds_host([1.0], [0.0])
 
 
+# The far polynomials' threshold kappa at the default error budget, as the header states it.
+DEFAULT_KAPPA = 4.09
+
+
 def _far_cases(n, seed):
     # far lines as the tile kernel meets them: tile half-widths of 0.1..1e4 Doppler widths,
-    # centres from the expansion's threshold |X| = 5 H + 1.25 outwards, both sides, any t,
-    # kept where the nearest point of the tile takes the shifted Lorentzian
+    # centres from the expansion's threshold |X| = kappa H + 1.25 outwards, both sides, any
+    # t, kept where the nearest point of the tile takes the shifted Lorentzian
     rng = np.random.default_rng(seed)
     H = 10 ** rng.uniform(-1, 4, n)
     y = 10 ** rng.uniform(-6, 3.3, n)
-    X = ((5 + 10 ** rng.uniform(-6, 1.5, n)) * H + 1.25) * (1 + 1e-6)
+    X = ((DEFAULT_KAPPA + 10 ** rng.uniform(-6, 1.5, n)) * H + 1.25) * (1 + 1e-4)
     X *= np.where(rng.random(n) < 0.5, -1.0, 1.0)
     t = rng.uniform(-1, 1, n)
     t[:200], t[200:400] = -1.0, 1.0
@@ -202,7 +206,7 @@ def _far_cases(n, seed):
 
 
 def test_far_line_polynomial():
-    # the degree-11 polynomial that sums far lines over a tile against the function it
+    # the degree-13 polynomial that sums far lines over a tile against the function it
     # expands, the shifted Lorentzian (closed form, FP64 at the same FP32-rounded inputs),
     # and against K itself (wofz): truncation <= 1.3e-7 plus FP32 rounding
     X, H, y, t = _far_cases(400_000, 31)
@@ -229,7 +233,7 @@ def test_far_line_polynomial():
     # cases the kernel never expands are refused: inside the threshold, t outside the
     # tile, the nearest point inside |z| = 52.3 (where no form with one term holds),
     # y <= 0
-    for args in ((4.9 * 100 + 1.25, 100.0, 1.0, 0.0), (1e4, 10.0, 1.0, 1.01),
+    for args in ((4.0 * 100 + 1.25, 100.0, 1.0, 0.0), (1e4, 10.0, 1.0, 1.01),
                  (52.0, 0.5, 0.1, 0.0), (1e4, 10.0, 0.0, 0.0)):
         with pytest.raises(xsec.XsError):
             xsec.eval_far_host(*args)
@@ -254,7 +258,7 @@ def _far_cases_ds(n, seed):
     rng = np.random.default_rng(seed)
     H = 10 ** rng.uniform(-1, 4, n)
     y = 10 ** rng.uniform(-0.5, 4.5, n)
-    X = ((5 + 10 ** rng.uniform(-6, 1.5, n)) * H + 1.25) * (1 + 1e-6)
+    X = ((DEFAULT_KAPPA + 10 ** rng.uniform(-6, 1.5, n)) * H + 1.25) * (1 + 1e-4)
     X *= np.where(rng.random(n) < 0.5, -1.0, 1.0)
     t = rng.uniform(-1, 1, n)
     t[:200], t[200:400] = -1.0, 1.0
@@ -280,7 +284,9 @@ def test_far_line_polynomial_doubly_shifted():
     ds = (yf / np.sqrt(np.pi)) / (r2 - 1.5 + 2 * yf * yf / r2)
     rel = np.abs(K / ds - 1)
     print(f"doubly shifted far polynomial vs closed form: max {rel.max():.3e}")
-    assert rel.max() < 6e-7
+    # truncation within 1.3e-7; FP32 rounding of the four-term recurrence over 13 steps,
+    # whose terms reach (1 + rho)^2 / (1 - rho)^2 = 2.7 times the value at rho = 1 / 4.09
+    assert rel.max() < 7e-7
     sub = np.random.default_rng(44).choice(len(x), 50_000, replace=False)
     ref = wofz(x[sub] + 1j * yf[sub]).real
     assert np.max(np.abs(K[sub] / ref - 1)) < 7e-7
@@ -295,7 +301,7 @@ def test_far_line_polynomial_doubly_shifted():
 
 # The loosest error budget a launch may ask for (xs_opts.tol), and the far threshold kappa
 # the header gives for it.
-LOOSE_TOL, LOOSE_KAPPA = 1e-5, 3.72
+LOOSE_TOL, LOOSE_KAPPA = 1e-5, 3.16
 
 
 def _far_cases_loose(n, seed, ds):
@@ -322,7 +328,7 @@ def test_loose_budget_far_forms():
     # Error budget 1e-5: the shifted Lorentzian where (3/2 + 2 y^2) / r^4 <= 1e-5, the
     # doubly shifted one where 3/2 / r^4 <= 1e-5 (against wofz: within 1.013 times those
     # bounds, so within the budget plus 1.3 %), and the far polynomials from
-    # |X| = 3.72 H + 1.25 (truncation within 0.65e-5, plus FP32 rounding)
+    # |X| = 3.16 H + 1.25 (truncation within 0.65e-5, plus FP32 rounding)
     f32 = lambda a: a.astype(np.float32).astype(np.float64)
     rng = np.random.default_rng(51)
     y = 10 ** rng.uniform(-6, 2, 300_000)
@@ -357,7 +363,12 @@ def test_loose_budget_far_forms():
               f"vs wofz {rw.max():.3e}")
         assert rc.max() < 0.65 * LOOSE_TOL + 1e-6
         assert rw.max() < 1.03 * LOOSE_TOL + 1e-6
-    # the threshold: just inside kappa H + 1.25 is refused, just outside accepted
+    # the threshold: just inside kappa H + 1.25 is refused, just outside accepted; the
+    # thresholds the header states for the default and the loosest budget
+    for tol, kappa in ((0.0, DEFAULT_KAPPA), (LOOSE_TOL, LOOSE_KAPPA)):
+        xsec.eval_far_host(kappa * 1.002 * 1000.0 + 1.25, 1000.0, 1.0, 0.5, tol=tol)
+        with pytest.raises(xsec.XsError):
+            xsec.eval_far_host(kappa * 0.998 * 1000.0 + 1.25, 1000.0, 1.0, 0.5, tol=tol)
     H = 100.0
     xsec.eval_far_host(LOOSE_KAPPA * H * 1.001 + 1.25, H, 1.0, 0.5, tol=LOOSE_TOL)
     with pytest.raises(xsec.XsError):
