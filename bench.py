@@ -95,6 +95,21 @@ def counter_profile(path=None):
     return out
 
 
+def headline_profile(args):
+    """The counter profile when this run times what it was taken on: the headline workload,
+    all of its points, at the profile's error budget; else None (the tier model prices the
+    run instead)."""
+    if args.workload != "large" or args.points:
+        return None
+    prof = counter_profile()
+    if prof is None:
+        return None
+    tol = args.tol if args.tol else 2e-7
+    if abs(prof.get("error_budget_tol", -1.0) - tol) > 1e-6 * tol:
+        return None
+    return prof
+
+
 def copy_probe():
     """A plain device-to-device copy of 256 MiB, three times: the calibration run for the
     FETCH_SIZE / WRITE_SIZE counters (bytes per dispatch are known exactly)."""
@@ -442,7 +457,7 @@ def bench_large(args, torch, xsec, synth):
     del nu0
     log(f"{W.name}: {evals[0]:.4e} line-point evals per point, launch shape {shape}")
     flops_model = None
-    if counter_profile() is None:
+    if headline_profile(args) is None:
         # no counter profile of these kernel sources: price the first timed point's
         # evaluations by their tiers
         flops_model, mix, _ = model_flops(ctx, h, g, [pts[rotation(len(pts))[0]]], o32, xsec)
@@ -667,7 +682,7 @@ def main():
 
     H = bench_large(args, torch, xsec, synth)
     W, grid, pts = H["W"], H["grid"], H["pts"]
-    prof = counter_profile()
+    prof = headline_profile(args)
     roof = roofline(prof, H["evals_per_launch"], H["kernel_ms"], H.get("flops_model"))
 
     cpu, parity = None, None
