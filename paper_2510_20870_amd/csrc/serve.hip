@@ -245,7 +245,9 @@ void Server::finish(Request& r, int status, const std::string& err) {
 }
 
 // Enqueue the request's next step on the lane (staging its inputs first if this is its
-// first step) and record a completion event; the caller holds mu.
+// first step) and record a completion event. Called by the server thread without mu: the
+// request is admitted, so only this thread changes its dispatch state and frees it, and
+// other threads only read its timestamps or set its cancel flag under mu.
 int Server::enqueue_next(Request& r, Lane& ln) {
   char* blk = base + r.off;
   hipError_t e;
@@ -381,15 +383,17 @@ void Server::loop() {
           }
         }
         if (!best) break;
+        // the launches can block (a full hardware queue): submitters and pollers must not
+        // wait for them
+        lk.unlock();
         const int rc = enqueue_next(*best, ln);
+        // earlier parts of a failed step may be queued: let them drain first
+        if (rc && best->inflight == 0) (void)hipStreamSynchronize(ln.st);
+        lk.lock();
         if (rc) {
           best->fail_rc = rc;
           best->fail_msg = g_last_error;
-          if (best->inflight == 0) {
-            // earlier parts of the failed step may be queued: let them drain first
-            (void)hipStreamSynchronize(ln.st);
-            finish(*best, rc, best->fail_msg);
-          }
+          if (best->inflight == 0) finish(*best, rc, best->fail_msg);
           continue;
         }
         best->lane = (int)li;
