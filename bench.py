@@ -249,7 +249,10 @@ def serving_run(ctx, lists, reqs, opts, on_time=True):
     Latency runs from the scheduled arrival (on_time; the submitter's own lateness is
     counted) or from submission (a closed batch) to completion; returns the latencies,
     the span from the first arrival to the last completion and the largest lateness of a
-    submission behind its schedule."""
+    submission behind its schedule. Python's cyclic garbage collector is paused while the
+    submitter runs (after one full collection), so that a collection pass over the
+    benchmark process's objects does not hold a submission back."""
+    import gc
     import threading
     handles = [None] * len(reqs)
     sched = np.zeros(len(reqs))
@@ -269,9 +272,14 @@ def serving_run(ctx, lists, reqs, opts, on_time=True):
             handles[k] = ctx.submit_window(lists[r.list_id], r.nu_min, r.step, r.n_points,
                                            [(r.P_bar, r.T_K)], opts)
 
-    th = threading.Thread(target=submitter)
-    th.start()
-    th.join()
+    gc.collect()
+    gc.disable()
+    try:
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+    finally:
+        gc.enable()
     lat = np.zeros(len(reqs))
     last = -np.inf
     for k, h in enumerate(handles):
