@@ -69,12 +69,23 @@ COUNTER_PROFILE = os.path.join(PROFILE_DIR, "tile_kernel_large_counters.md")
 METRIC = "Voigt line-point evals/s at <=1e-4 rel err vs FP64; p50/p99 request latency"
 
 
+def _code_only(text: str) -> str:
+    """C++ source without its comments, trailing blanks and empty lines (the kernel
+    sources hold no comment markers inside string literals), so that a comment edit keeps
+    the hash."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def kernel_source_hash() -> str:
+    """sha256 over the code of the tile kernel's sources (comments left out), in
+    KERNEL_SOURCES order."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2510_20870_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2510_20870_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()
 
 

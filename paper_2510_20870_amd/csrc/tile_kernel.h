@@ -302,8 +302,9 @@ __device__ __forceinline__ bool decode_item(const TileArgs& A, int lane, ItemInf
 // cover only part of it on the right [i4, hi). "Far" is a distance R from the centre,
 // chosen from a bound of the window's Doppler widths so that every line beyond it meets
 // the conditions of the tile polynomial for the whole span: |X| >= kappa H + 1.25 in the
-// line's Doppler units (kappa = 5 at the default error budget), and the doubly shifted Lorentzian within its bound at the span's
-// nearest point (which holds for every y there). The two far ranges are summed as one polynomial over the span, their chunks
+// line's Doppler units (kappa = 4.09 at the default error budget), and the doubly shifted
+// Lorentzian within its bound at the span's nearest point (which holds for every y
+// there). The two far ranges are summed as one polynomial over the span, their chunks
 // dealt to the wavefronts in turn; the other three ranges go through each wavefront's
 // per-tile path (restricted to the lines that can reach its tile). The ranges depend on
 // nu0 alone, so each line is taken exactly once. A split divides the group window for

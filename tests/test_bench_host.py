@@ -52,3 +52,13 @@ def test_rotation_spreads_the_table():
     first = order[:6]
     assert len({i // 4 for i in first}) >= 5 and len({i % 4 for i in first}) == 4
     assert bench.rotation(1) == [0] and sorted(bench.rotation(120)) == list(range(120))
+
+
+def test_code_hash_ignores_comments():
+    # the profile's source hash covers the code only: comment and blank-line edits keep it,
+    # a code edit changes it
+    a = "int f(int x) {  // one\n  return x + 1; /* two\n three */\n}\n"
+    b = "// header\nint f(int x) {\n\n  return x + 1;\n}\n"
+    c = "int f(int x) {\n  return x + 2;\n}\n"
+    assert bench._code_only(a) == bench._code_only(b)
+    assert bench._code_only(a) != bench._code_only(c)
