@@ -175,7 +175,8 @@ typedef struct { double P_bar, T_K; } xs_pt;
  * the grid and (P, T) point, lines are dropped when the sum of their contributions' upper
  * bounds over the tile stays within select_eps times a lower bound of sigma over the tile,
  * so that sigma changes by at most select_eps * sigma at every point (plus the FP32
- * rounding of the kept lines); 0 computes every line. Must be in [0, 1).
+ * rounding and the error budget tol of the kept lines); 0 computes every line. Must be in
+ * [0, 1).
  * out_dtype: the element type of sigma outputs, XS_F64 (float64) or XS_F32 (float32, the
  * FP64 sum rounded once to nearest); the arithmetic is the same for both.
  * tile_group: how the tiles of a workgroup share work. 1: each wavefront sums the far
