@@ -383,6 +383,59 @@ def test_loose_budget_far_forms():
             xsec.eval_series_host([100.0], [1.0], -1, tol=bad)
 
 
+def _probe_kappa(tol):
+    # the far threshold where the host polynomial starts accepting a line, to 1e-9
+    lo, hi, H = 2.0, 6.0, 1000.0
+    for _ in range(32):
+        m = 0.5 * (lo + hi)
+        try:
+            xsec.eval_far_host(m * H + 1.25, H, 1.0, 0.0, tol=tol)
+            hi = m
+        except xsec.XsError:
+            lo = m
+    return hi
+
+
+def test_far_threshold_follows_the_stated_rule():
+    # kappa is the smallest threshold whose truncation bound
+    # (1 + rho)^2 15 rho^14 1.15 / (1 - rho)^2 at rho = 1 / kappa stays within 0.65 tol
+    # (degree 13), for every budget; looser budgets move it towards the tile
+    def bound(rho):
+        return (1 + rho) ** 2 * 15 * rho ** 14 * 1.15 / (1 - rho) ** 2
+    prev = None
+    for tol in (2e-7, 5e-7, 1e-6, 3e-6, 1e-5):
+        k = _probe_kappa(tol if tol != 2e-7 else 0.0)
+        assert bound(1 / k) <= 0.65 * tol * (1 + 1e-3)
+        assert bound(1 / (k * 0.999)) > 0.65 * tol
+        if prev is not None:
+            assert k < prev
+        prev = k
+
+
+def test_far_polynomial_within_budget_across_budgets():
+    # at intermediate budgets the far polynomials from their threshold outwards stay within
+    # the budget plus FP32 rounding of K (wofz)
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(57)
+    for tol in (1e-6, 3e-6):
+        k = _probe_kappa(tol)
+        n = 200_000
+        H = 10 ** rng.uniform(-1, 4, n)
+        y = 10 ** rng.uniform(-6, 3, n)
+        X = ((k + 10 ** rng.uniform(-6, 1.5, n)) * H + 1.25) * (1 + 1e-4)
+        X *= np.where(rng.random(n) < 0.5, -1.0, 1.0)
+        t = rng.uniform(-1, 1, n)
+        xn = np.abs(f32(X)) - f32(H)
+        ok = (xn >= 0) & ((xn * xn + f32(y) ** 2) ** 2 * tol >= 1.5 * (1 + 1e-5))
+        X, H, y, t = X[ok], H[ok], y[ok], t[ok]
+        K = xsec.eval_far_host(X, H, y, t, tol=tol)
+        x = f32(X) + f32(H) * f32(t)
+        sub = rng.choice(len(x), 40_000, replace=False)
+        rw = np.abs(K[sub] / wofz(x[sub] + 1j * f32(y)[sub]).real - 1)
+        print(f"far polynomial at budget {tol:g}: kappa {k:.4f}, vs wofz {rw.max():.3e}")
+        assert rw.max() < 1.03 * tol + 1e-6
+
+
 def test_series_variant_errors():
     with pytest.raises(xsec.XsError):
         xsec.eval_series_host([1.0], [1.0], 0)        # |z| < 7
